@@ -1,0 +1,161 @@
+"""Benchmark of the coupled hybrid LB step on one MI355X.
+
+Workload: the 128^3 chiral droplet (radius 32, q0 = 2 pi/24, zeta = 0.008),
+FP32 storage and arithmetic; the same box is also timed in FP64 and with FP16
+population storage.  A step is one pass of the whole coupled step over the box
+(stress, collide + stream, Q and phi updates).  Inputs are resident in HBM
+before the timed region starts.
+
+Prints one JSON line with MLUPS (whole job), the roofline of the dominant
+kernel (algorithmic bytes per launch / its mean HIP-event duration), and the
+FP64 CPU oracle's rate on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per site of each kernel of the step: the compulsory
+# traffic of the method (read + write of populations, Q and phi) that the
+# kernel is responsible for.  Values per site: populations 19 read + 19
+# written, Q 5 + 5, phi 1 + 1.
+ALGO_VALUES = {
+    "k_thermo": (0, 6),     # (population values, field values): reads Q, phi
+    "k_collide": (38, 0),   # reads and writes the 19 populations
+    "k_order": (0, 6),      # writes Q, phi
+    "k_lb_fused": (38, 6),  # populations + reads of Q, phi
+    "k_order_fused": (0, 6),
+}
+GS_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 2}
+FS_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 4}
+
+
+def step_bytes(prec: str) -> int:
+    return 38 * GS_BYTES[prec] + 12 * FS_BYTES[prec]
+
+
+def time_precision(prec, p, phi, q5, steps, warmup, stream):
+    import torch
+    from paper_2011_00287_amd.sim import Sim
+    sim = Sim(p, phi, q5, precision=prec, stream=stream)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return sim, dt
+
+
+def cpu_baseline(workload: str, nsteps: int = 2):
+    import torch
+    from oracle import core
+    from paper_2011_00287_amd import inputs
+    p = inputs.params_for(workload)
+    phi, q5 = inputs.workload_fields(workload)
+    phi_t, q5_t = torch.tensor(phi), torch.tensor(q5)
+    g = torch.zeros((19,) + phi.shape, dtype=torch.float64)
+    g, q5_t, phi_t = core.step(g, q5_t, phi_t, p)  # warm-up
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        g, q5_t, phi_t = core.step(g, q5_t, phi_t, p)
+    dt = time.perf_counter() - t0
+    n = phi.size
+    return {"value": n * nsteps / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"{workload} ({n} sites) FP64 oracle, {nsteps} timed steps after 1 warm-up from the initial droplet"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="droplet128")
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16s"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-side", action="store_true", help="skip the FP64 / FP16S side timings")
+    ap.add_argument("--profile-steps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the step runs the whole box on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2011_00287_amd import inputs
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    w = inputs.WORKLOADS[args.workload]
+    p = inputs.params_for(args.workload)
+    phi, q5 = inputs.workload_fields(args.workload)
+    n = phi.size
+    print(f"# workload {args.workload} {phi.shape} {args.precision}: warmup {args.warmup}, steps {args.steps}",
+          file=sys.stderr, flush=True)
+
+    sim, dt = time_precision(args.precision, p, phi, q5, args.steps, args.warmup, stream)
+    mlups = n * args.steps / dt / 1e6
+    print(f"# {args.precision}: {mlups:.1f} MLUPS ({dt / args.steps * 1e3:.4f} ms/step)", file=sys.stderr, flush=True)
+
+    prof = sim.profile(args.profile_steps)
+    dom = max(prof, key=prof.get)
+    gv, fv = ALGO_VALUES[dom]
+    algo_bytes = (gv * GS_BYTES[args.precision] + fv * FS_BYTES[args.precision]) * n
+    achieved = algo_bytes / (prof[dom] * 1e-3) / 1e9
+    totals = sim.totals()
+    sim.close()
+    print(f"# kernels (ms/launch): {prof}", file=sys.stderr, flush=True)
+
+    side = {}
+    if not args.no_side:
+        for prec in ("fp64", "fp16s"):
+            if prec == args.precision:
+                continue
+            ns = max(20, args.steps // (4 if prec == "fp64" else 1))
+            s2, dt2 = time_precision(prec, p, phi, q5, ns, 5, stream)
+            s2.close()
+            side[prec] = {"mlups": n * ns / dt2 / 1e6, "ms_per_step": dt2 / ns * 1e3,
+                          "step_hbm_frac": n * ns / dt2 * step_bytes(prec) / (HBM_PEAK_GBS * 1e9)}
+            print(f"# {prec}: {side[prec]['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
+
+    line = {
+        "metric": "coupled-step MLUPS at 128^3 FP32 vs FP64, % HBM peak; adjoint/forward time",
+        "value": mlups,
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp16s": "f16-storage/f32"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "box": list(phi.shape[::-1]), "droplet_radius": w["R"],
+                   "q0": w["q0"], "zeta": w["zeta"], "precision": args.precision, "lattice": "D3Q19"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                     "kernel_ms": prof[dom], "algorithmic_bytes_per_launch": algo_bytes},
+        "step_roofline": {"bytes_per_site": step_bytes(args.precision),
+                          "frac": mlups * 1e6 * step_bytes(args.precision) / (HBM_PEAK_GBS * 1e9)},
+        "kernel_ms": prof,
+        "side": side,
+        "totals_after_run": {k: totals[k] for k in ("mass", "phi_total", "free_energy")},
+    }
+    if not args.no_cpu_baseline:
+        print("# timing the FP64 CPU oracle on a bounded sample ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,169 @@
+/*
+ * lb_chiral.h -- C ABI of the coupled hybrid lattice-Boltzmann step for
+ * chiral active droplets (Carenza, Gonnella, Negro, "Lattice Boltzmann
+ * simulations of self-propelling chiral active droplets").
+ *
+ * One time step (Sec. 2 Eqs. (1)-(5), Sec. 3 Eqs. (6)-(11)):
+ *   - chemical potential mu = dF/dphi and molecular field H = -dF/dQ of the
+ *     free energy of Eq. (5) (second-order central stencils);
+ *   - stress sigma = passive (interfacial + Ericksen + Beris-Edwards reactive
+ *     + antisymmetric) + active -zeta*phi*Q (Eqs. (3)-(4));
+ *   - D3Q19 BGK collide + pull-stream of the populations (Eqs. (6)-(8), (11)),
+ *     forced by F = div(sigma) in the Guo form (force moments of Eq. (10));
+ *   - explicit Euler finite-difference Beris-Edwards update of Q (Eq. (2)) and
+ *     Cahn-Hilliard update of phi in conservative flux form (Eq. (1)).
+ *
+ * Conventions
+ *   - Periodic box nx x ny x nz, each >= 3.  Lattice spacing = time step = 1.
+ *   - Every host field array is float64, component-major [c][z][y][x] with x
+ *     fastest; N = nx*ny*nz sites.  Q is passed as its 5 independent
+ *     components (xx, xy, xz, yy, yz); Q_zz = -Q_xx - Q_yy.
+ *   - Populations are deviations g_i = f_i - w_i*rho0, D3Q19 order:
+ *     0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 = the 12 edge vectors in
+ *     opposite pairs (7,8) = (+x+y, -x-y), (9,10) = (+x-y, -x+y),
+ *     (11,12) = (+x+z, -x-z), (13,14) = (+x-z, -x+z), (15,16) = (+y+z, -y-z),
+ *     (17,18) = (+y-z, -y+z).
+ *   - The state at time t is (post-stream g, Q, phi).  u reported at t is
+ *     (sum_i c_i g_i + F/2)/rho.
+ *
+ * Ownership and streams
+ *   - The caller owns every host array: lb_init / lb_set_* copy in, lb_moments /
+ *     lb_populations copy out.  The library owns all device memory of a context.
+ *   - hip_stream is borrowed (NULL = the default stream) and must outlive the
+ *     context; every kernel of the context runs on it.  Device pointers passed
+ *     to lb_get_state / lb_set_state / lb_adjoint_* must be valid on the
+ *     context's device and ordered with respect to that stream by the caller.
+ *
+ * Errors
+ *   - Every call returns lb_status (0 = LB_OK); no exception crosses the ABI.
+ *     lb_last_error() gives a thread-local message for the last failure.
+ *   - lb_step only enqueues work; a launch failure returns LB_EDEVICE.
+ *     Non-finite values are reported by the next lb_free_energy
+ *     (LB_ENONFINITE).  After any error the context is still valid for
+ *     lb_destroy and for lb_set_state (recovery from a checkpoint).
+ */
+#ifndef LB_CHIRAL_H
+#define LB_CHIRAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LB_OK = 0,
+  LB_EINVAL = -1,     /* invalid argument or parameter                     */
+  LB_ENOMEM = -2,     /* device allocation failed or box too large          */
+  LB_EDEVICE = -3,    /* HIP runtime or kernel launch error                 */
+  LB_ENONFINITE = -4, /* NaN/Inf found in the state by a reduction          */
+  LB_ESTATE = -5      /* state buffer of the wrong size / context mismatch  */
+} lb_status;
+
+typedef enum {
+  LB_FP64 = 0,  /* populations, Q, phi stored and computed in float64        */
+  LB_FP32 = 1,  /* stored and computed in float32                            */
+  LB_FP16S = 2  /* populations stored as float16 (scaled by 64/w_i), Q and phi
+                   float32, all arithmetic float32                            */
+} lb_precision;
+
+/* Model parameters (Eqs. (1)-(5), (7)).  K is the single elastic constant
+ * K_Q of Eq. (5); Gamma is the rotational mobility multiplying H in the
+ * Beris-Edwards update; xi the flow-alignment parameter; zeta the activity
+ * (> 0 extensile).  chi(phi) = chi0 + chi_s*phi. */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t prec; /* lb_precision */
+  double tau, rho0;
+  double a, phi0, phi_cr, k_phi, M;
+  double A0, chi0, chi_s, K, q0, W;
+  double Gamma, xi, zeta;
+  double body_force[3]; /* uniform external force density, added to F */
+} lb_params;
+
+/* Global sums, accumulated in float64 on the device.  mass = N*rho0 + sum g;
+ * momentum = sum rho*u (u with F/2); free_energy = F_h (Eq. (5) on the
+ * lattice, forward differences in the squared-gradient terms); kinetic
+ * energy = sum rho |u|^2 / 2. */
+typedef struct {
+  double mass;
+  double momentum[3];
+  double phi_total;
+  double free_energy;
+  double kinetic_energy;
+  int64_t step;
+} lb_totals;
+
+typedef struct lb_ctx lb_ctx;
+
+/* Create a context: validates p (tau > 0.5, n >= 3, finite values), allocates
+ * the device state and uploads phi [N], q5 [5][N] and u0 [3][N] (NULL = 0).
+ * The populations start at the second-order equilibrium of (rho0, u0).
+ * Errors: LB_EINVAL, LB_ENOMEM, LB_EDEVICE; *out is NULL on error. */
+lb_status lb_init(const lb_params* p, const double* phi, const double* q5, const double* u0,
+                  void* hip_stream, lb_ctx** out);
+
+/* Enqueue nsteps coupled steps on the context's stream (nsteps >= 0). */
+lb_status lb_step(lb_ctx* c, int32_t nsteps);
+
+/* Replace the model parameters that do not change the allocation (every
+ * field except nx, ny, nz, prec, which must match).  Errors: LB_EINVAL. */
+lb_status lb_set_params(lb_ctx* c, const lb_params* p);
+
+/* Copy rho [N], u [3][N] (with F/2), phi [N] and q5 [5][N] at the current
+ * time to host float64 arrays; any pointer may be NULL.  Synchronises. */
+lb_status lb_moments(lb_ctx* c, double* rho, double* u3, double* phi, double* q5);
+
+/* Post-stream population deviations g [19][N] at the current time (float64
+ * host array).  Synchronises. */
+lb_status lb_populations(lb_ctx* c, double* g19);
+
+/* Overwrite the state at the current time from host float64 arrays:
+ * g19 [19][N] post-stream deviations, phi [N], q5 [5][N] (NULL = keep). */
+lb_status lb_set_fields(lb_ctx* c, const double* g19, const double* phi, const double* q5);
+
+/* Global float64 sums of the current state (see lb_totals).  Returns
+ * LB_ENONFINITE if any of them is not finite.  Synchronises. */
+lb_status lb_free_energy(lb_ctx* c, lb_totals* out);
+
+/* phi-weighted droplet centre.  out[0..2] = linear centre (x, y, z) with
+ * coordinates in [0, n); out[3..5] = circular-mean centre per axis,
+ * n/(2 pi) atan2(sum phi sin(2 pi x/n), sum phi cos(2 pi x/n)) in [0, n);
+ * *phi_total = sum phi.  float64 device sums.  Synchronises. */
+lb_status lb_centre(lb_ctx* c, double out[6], double* phi_total);
+
+/* Size in bytes of the opaque state buffer (populations, Q, phi in storage
+ * precision, plus the step counter). */
+size_t lb_state_bytes(const lb_ctx* c);
+
+/* Copy the state to / from a caller-owned device buffer of lb_state_bytes()
+ * bytes (checkpoint / resume; resuming is bitwise identical).  Ordered on the
+ * context's stream.  Errors: LB_ESTATE on a size mismatch. */
+lb_status lb_get_state(lb_ctx* c, void* dev_dst, size_t bytes);
+lb_status lb_set_state(lb_ctx* c, const void* dev_src, size_t bytes);
+
+/* Average device time per launch of each kernel of the step, measured with
+ * HIP events recorded on the context's stream around every launch of
+ * nsteps steps (the state advances by nsteps).  kernel_ms must hold
+ * LB_MAX_KERNELS entries; *count receives the number of kernels per step. */
+#define LB_MAX_KERNELS 8
+lb_status lb_profile_step(lb_ctx* c, int32_t nsteps, double* kernel_ms, int32_t* count);
+
+/* Name of kernel i of the step (as it appears in a kernel trace), or NULL. */
+const char* lb_kernel_name(const lb_ctx* c, int32_t i);
+
+/* Block until the context's stream is idle. */
+lb_status lb_sync(lb_ctx* c);
+
+/* Free the context (NULL-safe). */
+void lb_destroy(lb_ctx* c);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LB_CHIRAL_H */

@@ -1,0 +1,86 @@
+"""ctypes declarations of the C ABI in include/lb_chiral.h (marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "liblbchiral.so")
+
+LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ENONFINITE, LB_ESTATE = 0, -1, -2, -3, -4, -5
+LB_FP64, LB_FP32, LB_FP16S = 0, 1, 2
+PRECISIONS = {"fp64": LB_FP64, "fp32": LB_FP32, "fp16s": LB_FP16S}
+LB_MAX_KERNELS = 8
+
+
+class LbParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("prec", ctypes.c_int32),
+        ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
+        ("a", ctypes.c_double), ("phi0", ctypes.c_double), ("phi_cr", ctypes.c_double),
+        ("k_phi", ctypes.c_double), ("M", ctypes.c_double),
+        ("A0", ctypes.c_double), ("chi0", ctypes.c_double), ("chi_s", ctypes.c_double),
+        ("K", ctypes.c_double), ("q0", ctypes.c_double), ("W", ctypes.c_double),
+        ("Gamma", ctypes.c_double), ("xi", ctypes.c_double), ("zeta", ctypes.c_double),
+        ("body_force", ctypes.c_double * 3),
+    ]
+
+
+class LbTotals(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_double), ("momentum", ctypes.c_double * 3), ("phi_total", ctypes.c_double),
+        ("free_energy", ctypes.c_double), ("kinetic_energy", ctypes.c_double), ("step", ctypes.c_int64),
+    ]
+
+
+class LbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"lb status {status}: {msg}")
+        self.status = status
+
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+
+SIGNATURES = {
+    "lb_init": (ctypes.c_int, [ctypes.POINTER(LbParams), _D, _D, _D, _P, ctypes.POINTER(_P)]),
+    "lb_step": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "lb_set_params": (ctypes.c_int, [_P, ctypes.POINTER(LbParams)]),
+    "lb_moments": (ctypes.c_int, [_P, _D, _D, _D, _D]),
+    "lb_populations": (ctypes.c_int, [_P, _D]),
+    "lb_set_fields": (ctypes.c_int, [_P, _D, _D, _D]),
+    "lb_free_energy": (ctypes.c_int, [_P, ctypes.POINTER(LbTotals)]),
+    "lb_centre": (ctypes.c_int, [_P, _D, _D]),
+    "lb_state_bytes": (ctypes.c_size_t, [_P]),
+    "lb_get_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
+    "lb_set_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
+    "lb_profile_step": (ctypes.c_int, [_P, ctypes.c_int32, _D, ctypes.POINTER(ctypes.c_int32)]),
+    "lb_kernel_name": (ctypes.c_char_p, [_P, ctypes.c_int32]),
+    "lb_sync": (ctypes.c_int, [_P]),
+    "lb_destroy": (None, [_P]),
+    "lb_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the built HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} missing "
+                               "(run python -m paper_2011_00287_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != LB_OK:
+        msg = lib().lb_last_error()
+        raise LbError(status, msg.decode() if msg else "")

@@ -1,0 +1,176 @@
+// Global float64 reductions: conservation totals, the discrete free energy
+// F_h of Eq. (5), and the phi-weighted droplet centre.
+//
+// Each launch writes one partial vector per 256-thread block (wave64 shuffles,
+// then a fixed-order pass over the 4 waves); k_final_sum adds the block
+// partials in a fixed order, so results are bitwise reproducible.
+#pragma once
+#include "kernels_site.hpp"
+
+namespace lbc {
+
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* __restrict__ out) {
+  __shared__ double red[NV][4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_down(v[k], o, 64);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[k][wid] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    const int k = threadIdx.x;
+    out[k] = ((red[k][0] + red[k][1]) + red[k][2]) + red[k][3];
+  }
+}
+
+// out[k] = sum over blocks of partial[b*nv + k]; one block of 256 threads.
+__global__ void __launch_bounds__(256) k_final_sum(const double* __restrict__ partial, int nblocks, int nv,
+                                                   double* __restrict__ out) {
+  __shared__ double buf[256];
+  for (int k = 0; k < nv; ++k) {
+    double s = 0.0;
+    for (int bI = threadIdx.x; bI < nblocks; bI += 256) s += partial[(size_t)bI * nv + k];
+    buf[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = buf[0];
+    __syncthreads();
+  }
+}
+
+constexpr int NTOT = 8;  // mass, jx, jy, jz, phi, F_h, E_kin, non-finite count
+
+// Free-energy density of F_h at one site in float64: forward differences in
+// the squared-gradient terms, central differences in the chiral and
+// anchoring terms (the discretisation whose exact gradients are mu and -H).
+template <class FS>
+__device__ __forceinline__ double fh_density(const Box& b, const Params<double>& P, const FS* __restrict__ phi,
+                                             const FS* __restrict__ q, int x, int y, int z) {
+  const size_t N = b.N;
+  const int s0 = (z * b.ny + y) * b.nx + x;
+  const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  double qc[5], Q[3][3], dQ[3][3][3], dphi[3];
+  const double ph = double(phi[s0]);
+  for (int k = 0; k < 5; ++k) qc[k] = double(q[k * N + s0]);
+  full3(qc, Q);
+  double gp2 = 0.0, gq2 = 0.0;
+  for (int g = 0; g < 3; ++g) {
+    const int sp = sidx(b, x + off[g][0], y + off[g][1], z + off[g][2]);
+    const int sm = sidx(b, x - off[g][0], y - off[g][1], z - off[g][2]);
+    const double pp = double(phi[sp]), pm = double(phi[sm]);
+    dphi[g] = 0.5 * (pp - pm);
+    gp2 += (pp - ph) * (pp - ph);
+    double qp[5], qm[5], dqk[5];
+    for (int k = 0; k < 5; ++k) {
+      qp[k] = double(q[k * N + sp]);
+      qm[k] = double(q[k * N + sm]);
+      dqk[k] = 0.5 * (qp[k] - qm[k]);
+    }
+    full3(dqk, dQ[g]);
+    const double f[5] = {qp[0] - qc[0], qp[1] - qc[1], qp[2] - qc[2], qp[3] - qc[3], qp[4] - qc[4]};
+    const double fzz = -f[0] - f[3];
+    gq2 += f[0] * f[0] + f[3] * f[3] + fzz * fzz + 2.0 * (f[1] * f[1] + f[2] * f[2] + f[4] * f[4]);
+  }
+  double Q2[3][3], C[3][3];
+  matmul3(Q, Q, Q2);
+  const double tr2 = ddot3(Q, Q), tr3 = ddot3(Q2, Q);
+  curl3(dQ, C);
+  const double qcurl = ddot3(Q, C);
+  double anch = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c) anch += dphi[a] * Q[a][c] * dphi[c];
+  const double chi = P.chi0 + P.chi_s * ph;
+  const double dw = ph * (ph - P.phi0);
+  return 0.5 * P.a * dw * dw * P.inv_phicr2 +
+         P.A0 * (0.5 * (1.0 - chi / 3.0) * tr2 - chi / 3.0 * tr3 + chi / 4.0 * tr2 * tr2) +
+         2.0 * P.K * P.q0 * P.q0 * tr2 + 0.5 * P.k_phi * gp2 + 0.5 * P.K * gq2 + 2.0 * P.K * P.q0 * qcurl +
+         P.W * anch;
+}
+
+template <class R, class GS, class FS>
+__global__ void __launch_bounds__(256) k_totals(Box b, Params<double> P, const GS* __restrict__ B,
+                                                const FS* __restrict__ phi, const FS* __restrict__ q,
+                                                const R* __restrict__ sig, double* __restrict__ partial) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  double v[NTOT];
+#pragma unroll
+  for (int k = 0; k < NTOT; ++k) v[k] = 0.0;
+  if (s < b.N) {
+    int x, y, z;
+    coords(b, s, x, y, z);
+    const size_t N = b.N;
+    double sum = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 19; ++i) {
+      const double gi = double(GPol<GS>::template ld<R>(B, i * N + sidx(b, x - CX(i), y - CY(i), z - CZ(i)), i));
+      sum += gi;
+      j[0] += CX(i) * gi;
+      j[1] += CY(i) * gi;
+      j[2] += CZ(i) * gi;
+    }
+    const int sxp = sidx(b, x + 1, y, z), sxm = sidx(b, x - 1, y, z);
+    const int syp = sidx(b, x, y + 1, z), sym = sidx(b, x, y - 1, z);
+    const int szp = sidx(b, x, y, z + 1), szm = sidx(b, x, y, z - 1);
+    double mom[3];
+    for (int a = 0; a < 3; ++a) {
+      const R* sa = sig + (size_t)(a * 3) * N;
+      const double F = double(R(0.5) * (sa[sxp] - sa[sxm]) + R(0.5) * (sa[N + syp] - sa[N + sym]) +
+                              R(0.5) * (sa[2 * N + szp] - sa[2 * N + szm]) + R(P.bf[a]));
+      mom[a] = j[a] + 0.5 * F;
+    }
+    const double rho = P.rho0 + sum;
+    const double fh = fh_density(b, P, phi, q, x, y, z);
+    const double ph = double(phi[s]);
+    v[0] = sum;
+    v[1] = mom[0];
+    v[2] = mom[1];
+    v[3] = mom[2];
+    v[4] = ph;
+    v[5] = fh;
+    v[6] = 0.5 * (mom[0] * mom[0] + mom[1] * mom[1] + mom[2] * mom[2]) / rho;
+    double chk = sum + mom[0] + mom[1] + mom[2] + ph + fh;
+    for (int k = 0; k < 5; ++k) chk += double(q[k * N + s]);
+    v[7] = isfinite(chk) ? 0.0 : 1.0;
+  }
+  block_reduce_store<NTOT>(v, partial + (size_t)blockIdx.x * NTOT);
+}
+
+constexpr int NCEN = 10;  // phi x, phi y, phi z, phi, (phi sin, phi cos) per axis
+
+template <class FS>
+__global__ void __launch_bounds__(256) k_centre(Box b, const FS* __restrict__ phi, double* __restrict__ partial) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  double v[NCEN];
+#pragma unroll
+  for (int k = 0; k < NCEN; ++k) v[k] = 0.0;
+  if (s < b.N) {
+    int x, y, z;
+    coords(b, s, x, y, z);
+    const double ph = double(phi[s]);
+    v[0] = ph * x;
+    v[1] = ph * y;
+    v[2] = ph * z;
+    v[3] = ph;
+    double sn, cs;
+    sincospi(2.0 * x / b.nx, &sn, &cs);
+    v[4] = ph * sn;
+    v[5] = ph * cs;
+    sincospi(2.0 * y / b.ny, &sn, &cs);
+    v[6] = ph * sn;
+    v[7] = ph * cs;
+    sincospi(2.0 * z / b.nz, &sn, &cs);
+    v[8] = ph * sn;
+    v[9] = ph * cs;
+  }
+  block_reduce_store<NCEN>(v, partial + (size_t)blockIdx.x * NCEN);
+}
+
+}  // namespace lbc

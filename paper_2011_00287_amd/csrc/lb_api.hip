@@ -1,0 +1,600 @@
+// Host side of the C ABI declared in include/lb_chiral.h.
+//
+// A context owns the device state of one periodic box (ping-pong population,
+// Q and phi buffers, scratch fields, reduction partials) and enqueues every
+// kernel on the stream it was given.  The arithmetic type and the storage
+// types are template parameters of the backend: float64 throughout, float32
+// throughout, or float16 population storage with float32 arithmetic.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lb_chiral.h"
+#include "kernels_reduce.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct LbError {
+  lb_status st;
+  std::string msg;
+};
+
+[[noreturn]] void fail(lb_status st, const std::string& msg) { throw LbError{st, msg}; }
+
+#define HIPCHECK(expr)                                                                          \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess) fail(LB_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int TPB = 256;
+
+template <class T>
+T* dalloc(size_t n) {
+  void* p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(LB_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  }
+  return static_cast<T*>(p);
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+bool finite_params(const lb_params& p) {
+  const double v[] = {p.tau, p.rho0, p.a, p.phi0, p.phi_cr, p.k_phi, p.M, p.A0, p.chi0, p.chi_s, p.K,
+                      p.q0, p.W, p.Gamma, p.xi, p.zeta, p.body_force[0], p.body_force[1], p.body_force[2]};
+  for (double x : v)
+    if (!std::isfinite(x)) return false;
+  return true;
+}
+
+void validate(const lb_params& p) {
+  if (p.nx < 3 || p.ny < 3 || p.nz < 3) fail(LB_EINVAL, "box sides must be >= 3");
+  if (p.prec < LB_FP64 || p.prec > LB_FP16S) fail(LB_EINVAL, "unknown precision");
+  if (!finite_params(p)) fail(LB_EINVAL, "non-finite parameter");
+  if (!(p.tau > 0.5)) fail(LB_EINVAL, "tau must be > 0.5");
+  if (!(p.rho0 > 0.0)) fail(LB_EINVAL, "rho0 must be > 0");
+  if (!(p.phi_cr != 0.0)) fail(LB_EINVAL, "phi_cr must be nonzero");
+  const double n = double(p.nx) * double(p.ny) * double(p.nz);
+  if (n > double(1 << 30)) fail(LB_ENOMEM, "box exceeds 2^30 sites");
+}
+
+template <class R>
+lbc::Params<R> make_params(const lb_params& p) {
+  lbc::Params<R> P;
+  P.omega = R(1.0 / p.tau);
+  P.guo = R(1.0 - 0.5 / p.tau);
+  P.rho0 = R(p.rho0);
+  P.a = R(p.a);
+  P.phi0 = R(p.phi0);
+  P.inv_phicr2 = R(1.0 / (p.phi_cr * p.phi_cr));
+  P.k_phi = R(p.k_phi);
+  P.M = R(p.M);
+  P.A0 = R(p.A0);
+  P.chi0 = R(p.chi0);
+  P.chi_s = R(p.chi_s);
+  P.K = R(p.K);
+  P.q0 = R(p.q0);
+  P.W = R(p.W);
+  P.Gamma = R(p.Gamma);
+  P.xi = R(p.xi);
+  P.zeta = R(p.zeta);
+  for (int a = 0; a < 3; ++a) P.bf[a] = R(p.body_force[a]);
+  return P;
+}
+
+struct Backend {
+  virtual ~Backend() = default;
+  virtual void set_params(const lb_params& p) = 0;
+  virtual void upload(const double* phi, const double* q5, const double* u0) = 0;
+  virtual void set_fields(const double* g19, const double* phi, const double* q5) = 0;
+  virtual void step(int n) = 0;
+  virtual void profile(int n, double* ms, int* count) = 0;
+  virtual const char* kernel_name(int i) const = 0;
+  virtual void moments(double* rho, double* u3, double* phi, double* q5) = 0;
+  virtual void populations(double* g19) = 0;
+  virtual void totals(double out[lbc::NTOT]) = 0;
+  virtual void centre(double out[lbc::NCEN]) = 0;
+  virtual size_t state_bytes() const = 0;
+  virtual void get_state(void* dst, int64_t step) = 0;
+  virtual int64_t set_state(const void* src) = 0;
+};
+
+template <class R, class GS, class FS>
+struct BackendT final : Backend {
+  lbc::Box box;
+  hipStream_t stream;
+  lbc::Params<R> P;
+  lbc::Params<double> Pd;
+  size_t N;
+  unsigned nblk;
+  GS* B[2] = {nullptr, nullptr};
+  FS* Q[2] = {nullptr, nullptr};
+  FS* Ph[2] = {nullptr, nullptr};
+  int cur = 0;
+  R* mu = nullptr;
+  R* H = nullptr;
+  R* sig = nullptr;
+  R* u = nullptr;
+  double* partial = nullptr;
+  double* sums = nullptr;
+
+  BackendT(const lb_params& p, hipStream_t s) : stream(s) {
+    box.nx = p.nx;
+    box.ny = p.ny;
+    box.nz = p.nz;
+    N = size_t(p.nx) * p.ny * p.nz;
+    box.N = int(N);
+    nblk = unsigned((N + TPB - 1) / TPB);
+    set_params(p);
+    size_t need = 2 * (19 * N * sizeof(GS) + 6 * N * sizeof(FS)) + 18 * N * sizeof(R);
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need > free_b)
+      fail(LB_ENOMEM, "state needs " + std::to_string(need) + " bytes, " + std::to_string(free_b) + " free");
+    try {
+      for (int k = 0; k < 2; ++k) {
+        B[k] = dalloc<GS>(19 * N);
+        Q[k] = dalloc<FS>(5 * N);
+        Ph[k] = dalloc<FS>(N);
+      }
+      mu = dalloc<R>(N);
+      H = dalloc<R>(5 * N);
+      sig = dalloc<R>(9 * N);
+      u = dalloc<R>(3 * N);
+      partial = dalloc<double>(size_t(nblk) * 16);
+      sums = dalloc<double>(16);
+    } catch (...) {
+      release();
+      throw;
+    }
+  }
+  ~BackendT() override { release(); }
+  void release() {
+    for (int k = 0; k < 2; ++k) {
+      dfree(B[k]);
+      dfree(Q[k]);
+      dfree(Ph[k]);
+      B[k] = nullptr;
+      Q[k] = nullptr;
+      Ph[k] = nullptr;
+    }
+    dfree(mu);
+    dfree(H);
+    dfree(sig);
+    dfree(u);
+    dfree(partial);
+    dfree(sums);
+    mu = H = sig = u = nullptr;
+    partial = sums = nullptr;
+  }
+
+  void set_params(const lb_params& p) override {
+    P = make_params<R>(p);
+    Pd = make_params<double>(p);
+  }
+
+  void check_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) fail(LB_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  }
+
+  // host float64 -> device FS (via a float64 staging buffer)
+  template <class T>
+  void h2d_convert(const double* host, T* dev, size_t n) {
+    double* tmp = dalloc<double>(n);
+    try {
+      HIPCHECK(hipMemcpyAsync(tmp, host, n * sizeof(double), hipMemcpyHostToDevice, stream));
+      lbc::k_convert<T, double><<<unsigned((n + TPB - 1) / TPB), TPB, 0, stream>>>(n, tmp, dev);
+      check_launch();
+      HIPCHECK(hipStreamSynchronize(stream));
+    } catch (...) {
+      dfree(tmp);
+      throw;
+    }
+    dfree(tmp);
+  }
+  template <class T>
+  void d2h_convert(const T* dev, double* host, size_t n) {
+    double* tmp = dalloc<double>(n);
+    try {
+      lbc::k_convert<double, T><<<unsigned((n + TPB - 1) / TPB), TPB, 0, stream>>>(n, dev, tmp);
+      check_launch();
+      HIPCHECK(hipMemcpyAsync(host, tmp, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+      HIPCHECK(hipStreamSynchronize(stream));
+    } catch (...) {
+      dfree(tmp);
+      throw;
+    }
+    dfree(tmp);
+  }
+
+  void upload(const double* phi, const double* q5, const double* u0) override {
+    h2d_convert(phi, Ph[cur], N);
+    h2d_convert(q5, Q[cur], 5 * N);
+    double* du0 = nullptr;
+    double* g = dalloc<double>(19 * N);
+    try {
+      if (u0) {
+        du0 = dalloc<double>(3 * N);
+        HIPCHECK(hipMemcpyAsync(du0, u0, 3 * N * sizeof(double), hipMemcpyHostToDevice, stream));
+      }
+      lbc::k_equilibrium<<<nblk, TPB, 0, stream>>>(box, double(Pd.rho0), du0, g);
+      lbc::k_push<GS><<<nblk, TPB, 0, stream>>>(box, g, B[cur]);
+      check_launch();
+      HIPCHECK(hipStreamSynchronize(stream));
+    } catch (...) {
+      dfree(du0);
+      dfree(g);
+      throw;
+    }
+    dfree(du0);
+    dfree(g);
+  }
+
+  void set_fields(const double* g19, const double* phi, const double* q5) override {
+    if (phi) h2d_convert(phi, Ph[cur], N);
+    if (q5) h2d_convert(q5, Q[cur], 5 * N);
+    if (g19) {
+      double* g = dalloc<double>(19 * N);
+      try {
+        HIPCHECK(hipMemcpyAsync(g, g19, 19 * N * sizeof(double), hipMemcpyHostToDevice, stream));
+        lbc::k_push<GS><<<nblk, TPB, 0, stream>>>(box, g, B[cur]);
+        check_launch();
+        HIPCHECK(hipStreamSynchronize(stream));
+      } catch (...) {
+        dfree(g);
+        throw;
+      }
+      dfree(g);
+    }
+  }
+
+  // --- the step -----------------------------------------------------------
+  static constexpr int NK = 3;
+  const char* kernel_name(int i) const override {
+    static const char* names[NK] = {"k_thermo", "k_collide", "k_order"};
+    return (i >= 0 && i < NK) ? names[i] : nullptr;
+  }
+  void launch(int k) {
+    const int nx = cur ^ 1;
+    switch (k) {
+      case 0:
+        lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], mu, H, sig);
+        break;
+      case 1:
+        lbc::k_collide<R, GS><<<nblk, TPB, 0, stream>>>(box, P, B[cur], B[nx], sig, u);
+        break;
+      case 2:
+        lbc::k_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], u, H, mu, Ph[nx], Q[nx]);
+        cur = nx;
+        break;
+    }
+  }
+  void step(int n) override {
+    for (int s = 0; s < n; ++s)
+      for (int k = 0; k < NK; ++k) launch(k);
+    check_launch();
+  }
+  void profile(int n, double* ms, int* count) override {
+    *count = NK;
+    for (int k = 0; k < NK; ++k) ms[k] = 0.0;
+    const int chunk = 32;
+    std::vector<hipEvent_t> ev(size_t(chunk) * (NK + 1));
+    for (auto& e : ev) HIPCHECK(hipEventCreate(&e));
+    int done = 0;
+    try {
+      while (done < n) {
+        const int m = std::min(chunk, n - done);
+        for (int s = 0; s < m; ++s) {
+          for (int k = 0; k < NK; ++k) {
+            HIPCHECK(hipEventRecord(ev[size_t(s) * (NK + 1) + k], stream));
+            launch(k);
+          }
+          HIPCHECK(hipEventRecord(ev[size_t(s) * (NK + 1) + NK], stream));
+        }
+        check_launch();
+        HIPCHECK(hipStreamSynchronize(stream));
+        for (int s = 0; s < m; ++s)
+          for (int k = 0; k < NK; ++k) {
+            float t = 0.f;
+            HIPCHECK(hipEventElapsedTime(&t, ev[size_t(s) * (NK + 1) + k], ev[size_t(s) * (NK + 1) + k + 1]));
+            ms[k] += t;
+          }
+        done += m;
+      }
+    } catch (...) {
+      for (auto& e : ev) (void)hipEventDestroy(e);
+      throw;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    for (int k = 0; k < NK; ++k) ms[k] /= (n > 0 ? n : 1);
+  }
+
+  // --- observation -----------------------------------------------------------
+  void thermo_now() {
+    lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], mu, H, sig);
+    check_launch();
+  }
+  void moments(double* rho, double* u3, double* phi, double* q5) override {
+    if (rho || u3) {
+      thermo_now();
+      R* r = dalloc<R>(N);
+      R* uu = nullptr;
+      try {
+        uu = dalloc<R>(3 * N);
+        lbc::k_moments<R, GS><<<nblk, TPB, 0, stream>>>(box, P, B[cur], sig, r, uu);
+        check_launch();
+        if (rho) d2h_convert(r, rho, N);
+        if (u3) d2h_convert(uu, u3, 3 * N);
+      } catch (...) {
+        dfree(r);
+        dfree(uu);
+        throw;
+      }
+      dfree(r);
+      dfree(uu);
+    }
+    if (phi) d2h_convert(Ph[cur], phi, N);
+    if (q5) d2h_convert(Q[cur], q5, 5 * N);
+  }
+  void populations(double* g19) override {
+    R* g = dalloc<R>(19 * N);
+    try {
+      lbc::k_pull<R, GS><<<nblk, TPB, 0, stream>>>(box, B[cur], g);
+      check_launch();
+      d2h_convert(g, g19, 19 * N);
+    } catch (...) {
+      dfree(g);
+      throw;
+    }
+    dfree(g);
+  }
+  void totals(double out[lbc::NTOT]) override {
+    thermo_now();
+    lbc::k_totals<R, GS, FS><<<nblk, TPB, 0, stream>>>(box, Pd, B[cur], Ph[cur], Q[cur], sig, partial);
+    lbc::k_final_sum<<<1, TPB, 0, stream>>>(partial, int(nblk), lbc::NTOT, sums);
+    check_launch();
+    HIPCHECK(hipMemcpyAsync(out, sums, lbc::NTOT * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHECK(hipStreamSynchronize(stream));
+  }
+  void centre(double out[lbc::NCEN]) override {
+    lbc::k_centre<FS><<<nblk, TPB, 0, stream>>>(box, Ph[cur], partial);
+    lbc::k_final_sum<<<1, TPB, 0, stream>>>(partial, int(nblk), lbc::NCEN, sums);
+    check_launch();
+    HIPCHECK(hipMemcpyAsync(out, sums, lbc::NCEN * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHECK(hipStreamSynchronize(stream));
+  }
+
+  // --- checkpoint --------------------------------------------------------------
+  size_t off_q() const { return align256(19 * N * sizeof(GS)); }
+  size_t off_phi() const { return off_q() + align256(5 * N * sizeof(FS)); }
+  size_t off_step() const { return off_phi() + align256(N * sizeof(FS)); }
+  size_t state_bytes() const override { return off_step() + sizeof(int64_t); }
+  void get_state(void* dst, int64_t stepno) override {
+    char* d = static_cast<char*>(dst);
+    HIPCHECK(hipMemcpyAsync(d, B[cur], 19 * N * sizeof(GS), hipMemcpyDeviceToDevice, stream));
+    HIPCHECK(hipMemcpyAsync(d + off_q(), Q[cur], 5 * N * sizeof(FS), hipMemcpyDeviceToDevice, stream));
+    HIPCHECK(hipMemcpyAsync(d + off_phi(), Ph[cur], N * sizeof(FS), hipMemcpyDeviceToDevice, stream));
+    HIPCHECK(hipMemcpyAsync(d + off_step(), &stepno, sizeof(int64_t), hipMemcpyHostToDevice, stream));
+    HIPCHECK(hipStreamSynchronize(stream));
+  }
+  int64_t set_state(const void* src) override {
+    const char* s = static_cast<const char*>(src);
+    HIPCHECK(hipMemcpyAsync(B[cur], s, 19 * N * sizeof(GS), hipMemcpyDeviceToDevice, stream));
+    HIPCHECK(hipMemcpyAsync(Q[cur], s + off_q(), 5 * N * sizeof(FS), hipMemcpyDeviceToDevice, stream));
+    HIPCHECK(hipMemcpyAsync(Ph[cur], s + off_phi(), N * sizeof(FS), hipMemcpyDeviceToDevice, stream));
+    int64_t stepno = 0;
+    HIPCHECK(hipMemcpyAsync(&stepno, s + off_step(), sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    HIPCHECK(hipStreamSynchronize(stream));
+    return stepno;
+  }
+};
+
+}  // namespace
+
+struct lb_ctx {
+  lb_params p{};
+  hipStream_t stream = nullptr;
+  int64_t step = 0;
+  std::unique_ptr<Backend> be;
+};
+
+namespace {
+
+template <class F>
+lb_status guarded(F&& f) {
+  try {
+    f();
+    g_last_error.clear();
+    return LB_OK;
+  } catch (const LbError& e) {
+    g_last_error = e.msg;
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return LB_ENOMEM;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return LB_EDEVICE;
+  }
+}
+
+void need_ctx(const lb_ctx* c) {
+  if (!c || !c->be) fail(LB_EINVAL, "null context");
+}
+
+std::unique_ptr<Backend> make_backend(const lb_params& p, hipStream_t s) {
+  switch (p.prec) {
+    case LB_FP64:
+      return std::unique_ptr<Backend>(new BackendT<double, double, double>(p, s));
+    case LB_FP32:
+      return std::unique_ptr<Backend>(new BackendT<float, float, float>(p, s));
+    default:
+      return std::unique_ptr<Backend>(new BackendT<float, __half, float>(p, s));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+lb_status lb_init(const lb_params* p, const double* phi, const double* q5, const double* u0, void* hip_stream,
+                  lb_ctx** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!p || !phi || !q5 || !out) fail(LB_EINVAL, "null argument");
+    validate(*p);
+    std::unique_ptr<lb_ctx> c(new lb_ctx);
+    c->p = *p;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->be = make_backend(*p, c->stream);
+    c->be->upload(phi, q5, u0);
+    *out = c.release();
+  });
+}
+
+lb_status lb_step(lb_ctx* c, int32_t nsteps) {
+  return guarded([&] {
+    need_ctx(c);
+    if (nsteps < 0) fail(LB_EINVAL, "nsteps < 0");
+    c->be->step(nsteps);
+    c->step += nsteps;
+  });
+}
+
+lb_status lb_set_params(lb_ctx* c, const lb_params* p) {
+  return guarded([&] {
+    need_ctx(c);
+    if (!p) fail(LB_EINVAL, "null params");
+    validate(*p);
+    if (p->nx != c->p.nx || p->ny != c->p.ny || p->nz != c->p.nz || p->prec != c->p.prec)
+      fail(LB_EINVAL, "box size and precision cannot change");
+    c->p = *p;
+    c->be->set_params(*p);
+  });
+}
+
+lb_status lb_moments(lb_ctx* c, double* rho, double* u3, double* phi, double* q5) {
+  return guarded([&] {
+    need_ctx(c);
+    c->be->moments(rho, u3, phi, q5);
+  });
+}
+
+lb_status lb_populations(lb_ctx* c, double* g19) {
+  return guarded([&] {
+    need_ctx(c);
+    if (!g19) fail(LB_EINVAL, "null output");
+    c->be->populations(g19);
+  });
+}
+
+lb_status lb_set_fields(lb_ctx* c, const double* g19, const double* phi, const double* q5) {
+  return guarded([&] {
+    need_ctx(c);
+    c->be->set_fields(g19, phi, q5);
+  });
+}
+
+lb_status lb_free_energy(lb_ctx* c, lb_totals* out) {
+  return guarded([&] {
+    need_ctx(c);
+    if (!out) fail(LB_EINVAL, "null output");
+    double v[lbc::NTOT];
+    c->be->totals(v);
+    const double N = double(c->p.nx) * c->p.ny * c->p.nz;
+    out->mass = N * c->p.rho0 + v[0];
+    out->momentum[0] = v[1];
+    out->momentum[1] = v[2];
+    out->momentum[2] = v[3];
+    out->phi_total = v[4];
+    out->free_energy = v[5];
+    out->kinetic_energy = v[6];
+    out->step = c->step;
+    bool finite = v[7] == 0.0;
+    for (int k = 0; k < 7; ++k) finite = finite && std::isfinite(v[k]);
+    if (!finite) fail(LB_ENONFINITE, "non-finite value in the state");
+  });
+}
+
+lb_status lb_centre(lb_ctx* c, double out[6], double* phi_total) {
+  return guarded([&] {
+    need_ctx(c);
+    if (!out) fail(LB_EINVAL, "null output");
+    double v[lbc::NCEN];
+    c->be->centre(v);
+    const int n[3] = {c->p.nx, c->p.ny, c->p.nz};
+    for (int a = 0; a < 3; ++a) {
+      out[a] = v[a] / v[3];
+      double ang = std::atan2(v[4 + 2 * a], v[5 + 2 * a]);
+      double cc = ang * n[a] / (2.0 * M_PI);
+      if (cc < 0) cc += n[a];
+      out[3 + a] = cc;
+    }
+    if (phi_total) *phi_total = v[3];
+  });
+}
+
+size_t lb_state_bytes(const lb_ctx* c) { return (c && c->be) ? c->be->state_bytes() : 0; }
+
+lb_status lb_get_state(lb_ctx* c, void* dev_dst, size_t bytes) {
+  return guarded([&] {
+    need_ctx(c);
+    if (!dev_dst) fail(LB_EINVAL, "null buffer");
+    if (bytes != c->be->state_bytes()) fail(LB_ESTATE, "state buffer size mismatch");
+    c->be->get_state(dev_dst, c->step);
+  });
+}
+
+lb_status lb_set_state(lb_ctx* c, const void* dev_src, size_t bytes) {
+  return guarded([&] {
+    need_ctx(c);
+    if (!dev_src) fail(LB_EINVAL, "null buffer");
+    if (bytes != c->be->state_bytes()) fail(LB_ESTATE, "state buffer size mismatch");
+    c->step = c->be->set_state(dev_src);
+  });
+}
+
+lb_status lb_profile_step(lb_ctx* c, int32_t nsteps, double* kernel_ms, int32_t* count) {
+  return guarded([&] {
+    need_ctx(c);
+    if (!kernel_ms || !count || nsteps <= 0) fail(LB_EINVAL, "bad profile arguments");
+    int n = 0;
+    c->be->profile(nsteps, kernel_ms, &n);
+    *count = n;
+    c->step += nsteps;
+  });
+}
+
+const char* lb_kernel_name(const lb_ctx* c, int32_t i) { return (c && c->be) ? c->be->kernel_name(i) : nullptr; }
+
+lb_status lb_sync(lb_ctx* c) {
+  return guarded([&] {
+    need_ctx(c);
+    HIPCHECK(hipStreamSynchronize(c->stream));
+  });
+}
+
+void lb_destroy(lb_ctx* c) {
+  if (!c) return;
+  if (c->be) (void)hipStreamSynchronize(c->stream);
+  delete c;
+}
+
+const char* lb_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

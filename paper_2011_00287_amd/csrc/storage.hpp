@@ -1,0 +1,51 @@
+// Storage policies and lattice indexing shared by all kernels.
+#pragma once
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "physics.hpp"
+
+namespace lbc {
+
+// Population storage.  float64 / float32 store the deviation g_i itself;
+// float16 stores g_i * 64 / w_i, which keeps the typical O(1e-4 .. 1e-1)
+// values of g_i / w_i inside the normal range of the format.
+template <class GS>
+struct GPol {
+  template <class R>
+  __device__ __forceinline__ static R ld(const GS* p, size_t k, int) { return R(p[k]); }
+  template <class R>
+  __device__ __forceinline__ static void st(GS* p, size_t k, int, R v) { p[k] = GS(v); }
+};
+
+template <>
+struct GPol<__half> {
+  template <class R>
+  __device__ __forceinline__ static R ld(const __half* p, size_t k, int i) {
+    return R(__half2float(p[k])) * (WQ<R>(i) * R(1.0 / 64.0));
+  }
+  template <class R>
+  __device__ __forceinline__ static void st(__half* p, size_t k, int i, R v) {
+    p[k] = __float2half(float(v * (R(64) / WQ<R>(i))));
+  }
+};
+
+struct Box {
+  int nx, ny, nz;
+  int N;  // nx*ny*nz
+};
+
+__device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+__device__ __forceinline__ int sidx(const Box& b, int x, int y, int z) {
+  return (wrapi(z, b.nz) * b.ny + wrapi(y, b.ny)) * b.nx + wrapi(x, b.nx);
+}
+
+__device__ __forceinline__ void coords(const Box& b, int s, int& x, int& y, int& z) {
+  x = s % b.nx;
+  const int t = s / b.nx;
+  y = t % b.ny;
+  z = t / b.ny;
+}
+
+}  // namespace lbc

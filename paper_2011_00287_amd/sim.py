@@ -1,0 +1,176 @@
+"""Python handle on one simulation context of the HIP library.
+
+Argument marshalling only: every step of the method runs in the library's
+kernels.  torch is used for the device memory of checkpoints and for the
+stream the kernels run on.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+from ._lib import LbParams, LbTotals, check, lib
+
+_PARAM_KEYS = ("tau", "rho0", "a", "phi0", "phi_cr", "k_phi", "M", "A0", "chi0", "chi_s", "K", "q0", "W",
+               "Gamma", "xi", "zeta")
+
+
+def make_params(p: dict, shape, precision: str = "fp64") -> LbParams:
+    """LbParams from a parameter dict and a field shape (nz, ny, nx)."""
+    nz, ny, nx = shape
+    lp = LbParams()
+    lp.nx, lp.ny, lp.nz = int(nx), int(ny), int(nz)
+    lp.prec = _lib.PRECISIONS[precision]
+    for k in _PARAM_KEYS:
+        setattr(lp, k, float(p[k]))
+    bf = p.get("body_force", (0.0, 0.0, 0.0))
+    for a in range(3):
+        lp.body_force[a] = float(bf[a])
+    return lp
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _c64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Sim:
+    """One periodic box on the GPU.
+
+    phi: [nz, ny, nx]; q5: [5, nz, ny, nx] (xx, xy, xz, yy, yz); u0: [3, nz, ny, nx]
+    or None.  precision: 'fp64', 'fp32' or 'fp16s'.  stream: a torch.cuda.Stream,
+    a raw hipStream_t as int, or None for the default stream.
+    """
+
+    def __init__(self, params: dict, phi, q5, u0=None, precision: str = "fp64", stream=None):
+        phi = _c64(phi)
+        q5 = _c64(q5)
+        if q5.shape != (5,) + phi.shape:
+            raise ValueError(f"q5 shape {q5.shape} does not match phi {phi.shape}")
+        u0 = None if u0 is None else _c64(u0)
+        if u0 is not None and u0.shape != (3,) + phi.shape:
+            raise ValueError("u0 shape mismatch")
+        self.shape = phi.shape
+        self.precision = precision
+        self.params = dict(params)
+        self._lp = make_params(params, phi.shape, precision)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        check(lib().lb_init(ctypes.byref(self._lp), _dptr(phi), _dptr(q5), _dptr(u0),
+                            _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def n_sites(self) -> int:
+        nz, ny, nx = self.shape
+        return nx * ny * nz
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------------ stepping
+    def step(self, n: int = 1):
+        check(lib().lb_step(self._h, int(n)))
+
+    def sync(self):
+        check(lib().lb_sync(self._h))
+
+    def set_params(self, **changes):
+        self.params.update(changes)
+        self._lp = make_params(self.params, self.shape, self.precision)
+        check(lib().lb_set_params(self._h, ctypes.byref(self._lp)))
+
+    # --------------------------------------------------------------- observation
+    def moments(self):
+        """(rho, u, phi, q5) at the current time as float64 numpy arrays."""
+        rho = np.empty(self.shape)
+        u = np.empty((3,) + self.shape)
+        phi = np.empty(self.shape)
+        q5 = np.empty((5,) + self.shape)
+        check(lib().lb_moments(self._h, _dptr(rho), _dptr(u), _dptr(phi), _dptr(q5)))
+        return rho, u, phi, q5
+
+    def fields(self):
+        """(phi, q5) at the current time."""
+        phi = np.empty(self.shape)
+        q5 = np.empty((5,) + self.shape)
+        check(lib().lb_moments(self._h, None, None, _dptr(phi), _dptr(q5)))
+        return phi, q5
+
+    def populations(self) -> np.ndarray:
+        g = np.empty((19,) + self.shape)
+        check(lib().lb_populations(self._h, _dptr(g)))
+        return g
+
+    def set_fields(self, g=None, phi=None, q5=None):
+        g = None if g is None else _c64(g)
+        phi = None if phi is None else _c64(phi)
+        q5 = None if q5 is None else _c64(q5)
+        check(lib().lb_set_fields(self._h, _dptr(g), _dptr(phi), _dptr(q5)))
+
+    def totals(self) -> dict:
+        t = LbTotals()
+        check(lib().lb_free_energy(self._h, ctypes.byref(t)))
+        return dict(mass=t.mass, momentum=list(t.momentum), phi_total=t.phi_total, free_energy=t.free_energy,
+                    kinetic_energy=t.kinetic_energy, step=t.step)
+
+    def centre(self):
+        """(linear centre xyz, circular centre xyz, sum phi)."""
+        out = (ctypes.c_double * 6)()
+        tot = ctypes.c_double()
+        check(lib().lb_centre(self._h, out, ctypes.byref(tot)))
+        return np.array(out[:3]), np.array(out[3:]), tot.value
+
+    # ---------------------------------------------------------------- checkpoint
+    def state_bytes(self) -> int:
+        return int(lib().lb_state_bytes(self._h))
+
+    def get_state(self, buf=None):
+        """Copy the state into a torch uint8 device tensor (allocated if None)."""
+        import torch
+        nb = self.state_bytes()
+        if buf is None:
+            buf = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        check(lib().lb_get_state(self._h, ctypes.c_void_p(buf.data_ptr()), nb))
+        return buf
+
+    def set_state(self, buf):
+        check(lib().lb_set_state(self._h, ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()))
+
+    # ----------------------------------------------------------------- profiling
+    def profile(self, nsteps: int):
+        """{kernel name: average ms per launch} over nsteps steps (state advances)."""
+        ms = (ctypes.c_double * _lib.LB_MAX_KERNELS)()
+        cnt = ctypes.c_int32()
+        check(lib().lb_profile_step(self._h, int(nsteps), ms, ctypes.byref(cnt)))
+        return {lib().lb_kernel_name(self._h, i).decode(): ms[i] for i in range(cnt.value)}

@@ -1,0 +1,84 @@
+"""CPU checks of the C ABI: the built library loads and exports every function
+declared in include/lb_chiral.h, and the Python binding declares the same set.
+No compute call is made (there may be no GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lb_chiral.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(lb_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_four_core_calls():
+    names = declared_functions()
+    for n in ("lb_init", "lb_step", "lb_moments", "lb_free_energy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2011_00287_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("library not built: run python -m paper_2011_00287_amd.build")
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(L, n), n
+
+
+def test_binding_matches_header():
+    from paper_2011_00287_amd import _lib
+    assert sorted(_lib.SIGNATURES) == declared_functions()
+
+
+def test_param_struct_layout():
+    """Field order of lb_params in the header equals the ctypes struct."""
+    from paper_2011_00287_amd import _lib
+    text = open(HEADER).read()
+    body = re.search(r"typedef struct \{(.*?)\} lb_params;", text, flags=re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        names = decl.split(None, 1)[1]
+        for n in names.split(","):
+            fields.append(re.sub(r"\[.*\]", "", n).strip())
+    assert fields == [f[0] for f in _lib.LbParams._fields_]
+
+
+def test_last_error_is_empty_string_initially():
+    from paper_2011_00287_amd import _lib
+    assert _lib.lib().lb_last_error() in (b"",)
+
+
+def test_destroy_is_null_safe():
+    from paper_2011_00287_amd import _lib
+    _lib.lib().lb_destroy(None)
+
+
+def test_invalid_params_rejected_before_any_device_work():
+    """Validation runs on the host: a bad tau fails with LB_EINVAL even without a GPU."""
+    import numpy as np
+    from paper_2011_00287_amd import _lib, inputs, sim
+    p = dict(inputs.BASE_PARAMS, tau=0.4)
+    phi = np.zeros((4, 4, 4))
+    q5 = np.zeros((5, 4, 4, 4))
+    with pytest.raises(_lib.LbError) as e:
+        sim.Sim(p, phi, q5)
+    assert e.value.status == _lib.LB_EINVAL
+    p = dict(inputs.BASE_PARAMS)
+    with pytest.raises(_lib.LbError) as e:
+        sim.Sim(p, np.zeros((2, 4, 4)), np.zeros((5, 2, 4, 4)))
+    assert e.value.status == _lib.LB_EINVAL
+    with pytest.raises(_lib.LbError) as e:
+        sim.Sim(dict(p, zeta=float("nan")), phi, q5)
+    assert e.value.status == _lib.LB_EINVAL
