@@ -74,6 +74,28 @@ def cpu_baseline(workload: str, nsteps: int = 2):
             "sample": f"{workload} ({n} sites) FP64 oracle, {nsteps} timed steps after 1 warm-up from the initial droplet"}
 
 
+def copy_calibration(nbytes: int, reps: int):
+    """Device-to-device copy of a known size: achievable HBM bandwidth and the
+    reference for scaling hardware byte counters."""
+    import torch
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    line = {"metric": "device copy bandwidth", "value": 2 * n * 4 / (ms * 1e-3) / 1e9, "unit": "GB/s",
+            "bytes_read_per_launch": n * 4, "bytes_written_per_launch": n * 4, "ms_per_launch": ms,
+            "reps": reps, "peak": HBM_PEAK_GBS}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +106,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side", action="store_true", help="skip the FP64 / FP16S side timings")
     ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only time a device copy of this many MiB and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -94,6 +118,9 @@ def main():
     from paper_2011_00287_amd import inputs
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration << 20, max(1, args.steps))
+        return
     stream = torch.cuda.current_stream()
     w = inputs.WORKLOADS[args.workload]
     p = inputs.params_for(args.workload)

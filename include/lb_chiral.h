@@ -14,7 +14,8 @@
  *     Cahn-Hilliard update of phi in conservative flux form (Eq. (1)).
  *
  * Conventions
- *   - Periodic box nx x ny x nz, each >= 3.  Lattice spacing = time step = 1.
+ *   - Periodic box nx x ny x nz, each >= 3, at most 2^29 sites.  Lattice
+ *     spacing = time step = 1.
  *   - Every host field array is float64, component-major [c][z][y][x] with x
  *     fastest; N = nx*ny*nz sites.  Q is passed as its 5 independent
  *     components (xx, xy, xz, yy, yz); Q_zz = -Q_xx - Q_yy.

@@ -1,0 +1,416 @@
+// Fused kernels of the coupled step: two launches per step.
+//
+// k_lb_fused  : stress, force, pull-stream and Guo-forced BGK collision
+//               (Eqs. (3)-(4), (6)-(8), (10)-(11)) plus mu (Eq. (1));
+//               writes the post-collision populations, u and mu.
+// k_order_fused: molecular field H (Eq. (5)), Beris-Edwards update of Q
+//               (Eq. (2)) and Cahn-Hilliard update of phi (Eq. (1)).
+//
+// Both march along z over a slab of planes.  A workgroup owns a TX x TY tile
+// of the x-y plane; thread (lx, ly) owns one column of it.  Stencil inputs
+// are staged in LDS plane rings with a halo, so every neighbour read is an
+// LDS access at a compile-time offset.  Values a thread needs only along its
+// own column (the z-components of the stress, the in-plane force part, the
+// z-neighbours of u, mu, Q, phi) stay in registers.
+//
+// Workgroup ids are remapped so that each XCD (8 on MI355X, ids dealt
+// round-robin) receives a contiguous range of tiles, keeping the halos a
+// tile shares with its neighbours in the same L2.
+#pragma once
+#include "physics.hpp"
+#include "storage.hpp"
+
+namespace lbc {
+
+__device__ __forceinline__ int pmod(int a, int n) {
+  const int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+// Bijection of [0, nblk): XCD x (ids congruent to x mod 8) gets a contiguous range.
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7;
+  const int x = bid & 7, k = bid >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
+
+// ---------------------------------------------------------------------------
+// k_lb_fused
+//   phi and Q rings hold planes p-2..p+2 (phi) and p-1..p+1 (Q) on the tile
+//   plus a halo of 2; the stress is computed on the tile plus a halo of 1 at
+//   plane p (slots dealt round-robin to the threads); thread t owns column t
+//   of the tile for mu and for the collision of plane p-1, whose force needs
+//   the stress of planes p-2..p.  The global loads needed after the stress
+//   pass (the pull of plane p-1, the ring planes for p+1) are issued before
+//   it so that their latency overlaps the stress arithmetic.
+// ---------------------------------------------------------------------------
+template <class R, class GS, class FS, int TX, int TY, int MINW>
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(MINW)))
+k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ Bin, GS* __restrict__ Bout,
+           const FS* __restrict__ phi, const FS* __restrict__ q, R* __restrict__ u_out, R* __restrict__ mu_out) {
+  constexpr int NT = TX * TY;
+  constexpr int AX = TX + 4, AY = TY + 4, NA = AX * AY;  // phi / Q slots (halo 2)
+  constexpr int SX = TX + 2, SY = TY + 2, NS = SX * SY;  // stress slots (halo 1)
+  __shared__ R sPhi[5][NA];
+  __shared__ R sQ[3][5][NA];
+  __shared__ R sSig[6][NS];  // sigma_ax (a = 0..2), then sigma_ay
+  __shared__ R sSaz[3][NT];  // sigma_az at the tile sites
+  __shared__ int sGX[AX], sGY[AY];
+
+  const int l = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = l % ntx, ty = (l / ntx) % nty, sl = l / (ntx * nty);
+  const int x0 = tx * TX, y0 = ty * TY, z0 = sl * TZ;
+  const int z1 = min(z0 + TZ, b.nz);
+  const int tid = threadIdx.x;
+  const int lx = tid % TX, ly = tid / TX;
+  const int x = x0 + lx, y = y0 + ly;
+  const bool active = (x < b.nx) && (y < b.ny);
+  const size_t N = b.N;
+  const int plane = b.nx * b.ny;
+
+  for (int k = tid; k < AX; k += NT) sGX[k] = pmod(x0 - 2 + k, b.nx);
+  for (int k = tid; k < AY; k += NT) sGY[k] = pmod(y0 - 2 + k, b.ny);
+  __syncthreads();
+
+  // ring slots this thread refills each plane (fixed over the march)
+  constexpr int KR = (NA + NT - 1) / NT;
+  int rslot[KR];
+  uint32_t rcol[KR];  // byte offset of the slot's column within a plane (FS)
+#pragma unroll
+  for (int j = 0; j < KR; ++j) {
+    const int k = tid + j * NT;
+    rslot[j] = k < NA ? k : -1;
+    rcol[j] = k < NA ? uint32_t(sGY[k / AX] * b.nx + sGX[k % AX]) * uint32_t(sizeof(FS)) : 0u;
+  }
+  const uint32_t plane_fs = uint32_t(plane) * uint32_t(sizeof(FS));
+  auto fill = [&](int p, bool do_phi, bool do_q) {
+    const uint32_t bz = uint32_t(pmod(p, b.nz)) * plane_fs;
+    const int sph = pmod(p, 5), sq = pmod(p, 3);
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+      if (rslot[j] >= 0) {
+        if (do_phi) sPhi[sph][rslot[j]] = R(ldo(phi, bz + rcol[j]));
+        if (do_q) {
+#pragma unroll
+          for (int c = 0; c < 5; ++c) sQ[sq][c][rslot[j]] = R(ldo(q + size_t(c) * N, bz + rcol[j]));
+        }
+      }
+    }
+  };
+  // prefill for the first stress plane p = z0 - 1: phi z0-3..z0+1, Q z0-2..z0
+  fill(z0 - 3, true, false);
+  for (int p = z0 - 2; p <= z0; ++p) fill(p, true, true);
+  fill(z0 + 1, true, false);
+
+  // column registers: sigma_az at planes p-2, p-1 and the in-plane force part at p-1
+  R saz_m2[3] = {R(0), R(0), R(0)}, saz_m1[3] = {R(0), R(0), R(0)}, fin_m1[3] = {R(0), R(0), R(0)};
+
+  // pull offsets of the owned column: in-plane byte offsets of the 9 (x, y) neighbours
+  const int xw = active ? x : 0, yw = active ? y : 0;
+  const int xs[3] = {wrapi(xw - 1, b.nx), xw, wrapi(xw + 1, b.nx)};
+  const int ys[3] = {wrapi(yw - 1, b.ny), yw, wrapi(yw + 1, b.ny)};
+  uint32_t colb[3][3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) colb[j][i] = uint32_t(ys[j] * b.nx + xs[i]) * uint32_t(sizeof(GS));
+  const uint32_t plane_gs = uint32_t(plane) * uint32_t(sizeof(GS));
+  const uint32_t own_r = uint32_t(yw * b.nx + xw) * uint32_t(sizeof(R));
+  const uint32_t own_g = uint32_t(yw * b.nx + xw) * uint32_t(sizeof(GS));
+  const uint32_t plane_r = uint32_t(plane) * uint32_t(sizeof(R));
+
+  // loop-carried ring slots and wrapped plane indices (uniform)
+  int r0 = pmod(z0 - 1, 5), c0 = pmod(z0 - 1, 3);
+  int zph = pmod(z0 + 2, b.nz), zq = pmod(z0 + 1, b.nz);
+  int zc_m = pmod(z0 - 3, b.nz), zc_0 = pmod(z0 - 2, b.nz), zc_p = pmod(z0 - 1, b.nz);
+  for (int p = z0 - 1; p <= z1; ++p) {
+    __syncthreads();  // rings for plane p are complete; last plane's stress reads are done
+    const int rm = r0 == 0 ? 4 : r0 - 1, rp = r0 == 4 ? 0 : r0 + 1;
+    const int rm2 = rm == 0 ? 4 : rm - 1, rp2 = rp == 4 ? 0 : rp + 1;
+    const int cm = c0 == 0 ? 2 : c0 - 1, cp = c0 == 2 ? 0 : c0 + 1;
+    const int zc = p - 1;
+    const bool collide = active && zc >= z0 && zc < z1;
+
+    // ---- issue the global loads needed after the stress pass
+    R g[19];
+    if (collide) {
+      const uint32_t zb[3] = {uint32_t(zc_m) * plane_gs, uint32_t(zc_0) * plane_gs, uint32_t(zc_p) * plane_gs};
+#pragma unroll
+      for (int i = 0; i < 19; ++i)
+        g[i] = GPolO<GS>::template ld<R>(Bin + size_t(i) * N, zb[1 - CZ(i)] + colb[1 - CY(i)][1 - CX(i)], i);
+    }
+    const bool refill = p < z1;
+    R nphi[KR], nq[KR][5];
+    if (refill) {
+      const uint32_t bph = uint32_t(zph) * plane_fs, bq = uint32_t(zq) * plane_fs;
+#pragma unroll
+      for (int j = 0; j < KR; ++j) {
+        if (rslot[j] >= 0) {
+          nphi[j] = R(ldo(phi, bph + rcol[j]));
+#pragma unroll
+          for (int c = 0; c < 5; ++c) nq[j][c] = R(ldo(q + size_t(c) * N, bq + rcol[j]));
+        }
+      }
+    }
+
+    // ---- stress at plane p on the tile + halo 1
+    for (int s = tid; s < NS; s += NT) {
+      const int sx = s % SX, sy = s / SX;
+      const int a0 = (sy + 1) * AX + (sx + 1);  // phi / Q slot of this stress slot
+      Grad<R> G;
+      G.phi = sPhi[r0][a0];
+      G.dphi[0] = R(0.5) * (sPhi[r0][a0 + 1] - sPhi[r0][a0 - 1]);
+      G.dphi[1] = R(0.5) * (sPhi[r0][a0 + AX] - sPhi[r0][a0 - AX]);
+      G.dphi[2] = R(0.5) * (sPhi[rp][a0] - sPhi[rm][a0]);
+      G.lapphi = R(0);
+      G.divv = R(0);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        const R qc = sQ[c0][c][a0];
+        const R qxp = sQ[c0][c][a0 + 1], qxm = sQ[c0][c][a0 - 1];
+        const R qyp = sQ[c0][c][a0 + AX], qym = sQ[c0][c][a0 - AX];
+        const R qzp = sQ[cp][c][a0], qzm = sQ[cm][c][a0];
+        G.q[c] = qc;
+        G.dq[0][c] = R(0.5) * (qxp - qxm);
+        G.dq[1][c] = R(0.5) * (qyp - qym);
+        G.dq[2][c] = R(0.5) * (qzp - qzm);
+        G.lapq[c] = ((qxp + qxm) + (qyp + qym) + (qzp + qzm)) - R(6) * qc;
+      }
+      R h[5], sig[9];
+      sigma_site(P, G, sig, h);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        sSig[a][s] = sig[3 * a + 0];
+        sSig[3 + a][s] = sig[3 * a + 1];
+      }
+      if (sx >= 1 && sx <= TX && sy >= 1 && sy <= TY) {
+        const int t = (sy - 1) * TX + (sx - 1);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) sSaz[a][t] = sig[3 * a + 2];
+      }
+    }
+
+    // ---- mu at the owned site of plane p
+    if (active && p >= z0 && p < z1) {
+      const int a0 = (ly + 2) * AX + (lx + 2);
+      const R ph = sPhi[r0][a0];
+      const R lapphi = ((sPhi[r0][a0 + 1] + sPhi[r0][a0 - 1]) + (sPhi[r0][a0 + AX] + sPhi[r0][a0 - AX]) +
+                        (sPhi[rp][a0] + sPhi[rm][a0])) - R(6) * ph;
+      // v_a(y) = Q_ab(y) D0_b phi(y) at y = x +- e_a, divv = sum_a D0_a v_a
+      R divv = R(0);
+      {
+        // a = x: rows x of Q at x+-1 (plane p)
+        const int kp = a0 + 1, km = a0 - 1;
+        const R vp = sQ[c0][0][kp] * (R(0.5) * (sPhi[r0][kp + 1] - sPhi[r0][kp - 1])) +
+                     sQ[c0][1][kp] * (R(0.5) * (sPhi[r0][kp + AX] - sPhi[r0][kp - AX])) +
+                     sQ[c0][2][kp] * (R(0.5) * (sPhi[rp][kp] - sPhi[rm][kp]));
+        const R vm = sQ[c0][0][km] * (R(0.5) * (sPhi[r0][km + 1] - sPhi[r0][km - 1])) +
+                     sQ[c0][1][km] * (R(0.5) * (sPhi[r0][km + AX] - sPhi[r0][km - AX])) +
+                     sQ[c0][2][km] * (R(0.5) * (sPhi[rp][km] - sPhi[rm][km]));
+        divv += R(0.5) * (vp - vm);
+      }
+      {
+        // a = y: rows y at y+-1
+        const int kp = a0 + AX, km = a0 - AX;
+        const R vp = sQ[c0][1][kp] * (R(0.5) * (sPhi[r0][kp + 1] - sPhi[r0][kp - 1])) +
+                     sQ[c0][3][kp] * (R(0.5) * (sPhi[r0][kp + AX] - sPhi[r0][kp - AX])) +
+                     sQ[c0][4][kp] * (R(0.5) * (sPhi[rp][kp] - sPhi[rm][kp]));
+        const R vm = sQ[c0][1][km] * (R(0.5) * (sPhi[r0][km + 1] - sPhi[r0][km - 1])) +
+                     sQ[c0][3][km] * (R(0.5) * (sPhi[r0][km + AX] - sPhi[r0][km - AX])) +
+                     sQ[c0][4][km] * (R(0.5) * (sPhi[rp][km] - sPhi[rm][km]));
+        divv += R(0.5) * (vp - vm);
+      }
+      {
+        // a = z: rows z at z+-1 (Q planes p+-1, phi planes p, p+-2)
+        const R qxzp = sQ[cp][2][a0], qyzp = sQ[cp][4][a0], qzzp = -sQ[cp][0][a0] - sQ[cp][3][a0];
+        const R vp = qxzp * (R(0.5) * (sPhi[rp][a0 + 1] - sPhi[rp][a0 - 1])) +
+                     qyzp * (R(0.5) * (sPhi[rp][a0 + AX] - sPhi[rp][a0 - AX])) +
+                     qzzp * (R(0.5) * (sPhi[rp2][a0] - sPhi[r0][a0]));
+        const R qxzm = sQ[cm][2][a0], qyzm = sQ[cm][4][a0], qzzm = -sQ[cm][0][a0] - sQ[cm][3][a0];
+        const R vm = qxzm * (R(0.5) * (sPhi[rm][a0 + 1] - sPhi[rm][a0 - 1])) +
+                     qyzm * (R(0.5) * (sPhi[rm][a0 + AX] - sPhi[rm][a0 - AX])) +
+                     qzzm * (R(0.5) * (sPhi[r0][a0] - sPhi[rm2][a0]));
+        divv += R(0.5) * (vp - vm);
+      }
+      R qs[5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) qs[c] = sQ[c0][c][a0];
+      sto(mu_out, uint32_t(p) * plane_r + own_r, mu_site(P, ph, lapphi, divv, qs));
+    }
+    __syncthreads();  // stress of plane p is complete; ring slots of phi p-2 and Q p-1 are free
+
+    // ---- refill the rings for plane p+1 from the registers loaded above
+    if (refill) {
+#pragma unroll
+      for (int j = 0; j < KR; ++j) {
+        if (rslot[j] >= 0) {
+          sPhi[rm2][rslot[j]] = nphi[j];
+#pragma unroll
+          for (int c = 0; c < 5; ++c) sQ[cm][c][rslot[j]] = nq[j][c];
+        }
+      }
+    }
+
+    // ---- in-plane force part at plane p; collision of plane p-1
+    const int s0 = (ly + 1) * SX + (lx + 1);
+    R fin[3], saz[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      fin[a] = R(0.5) * (sSig[a][s0 + 1] - sSig[a][s0 - 1]) + R(0.5) * (sSig[3 + a][s0 + SX] - sSig[3 + a][s0 - SX]);
+      saz[a] = sSaz[a][tid];
+    }
+    if (collide) {
+      R F[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) F[a] = (fin_m1[a] + R(0.5) * (saz[a] - saz_m2[a])) + P.bf[a];
+      R u[3];
+      collide_site(P, g, F, u);
+      const uint32_t sg = uint32_t(zc) * plane_gs + own_g, sr = uint32_t(zc) * plane_r + own_r;
+#pragma unroll
+      for (int i = 0; i < 19; ++i) GPolO<GS>::template st<R>(Bout + size_t(i) * N, sg, i, g[i]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) sto(u_out + size_t(a) * N, sr, u[a]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      saz_m2[a] = saz_m1[a];
+      saz_m1[a] = saz[a];
+      fin_m1[a] = fin[a];
+    }
+    // advance the uniform indices to plane p+1
+    r0 = rp;
+    c0 = cp;
+    zph = zph + 1 == b.nz ? 0 : zph + 1;
+    zq = zq + 1 == b.nz ? 0 : zq + 1;
+    zc_m = zc_0;
+    zc_0 = zc_p;
+    zc_p = zc_p + 1 == b.nz ? 0 : zc_p + 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_order_fused
+//   LDS holds plane z of (Q, phi, u, mu) on the tile plus a halo of 1; the
+//   owned column keeps planes z-1, z, z+1 of the same fields in registers.
+// ---------------------------------------------------------------------------
+template <class R, class FS, int TX, int TY, int MINW>
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(MINW))) k_order_fused(Box b, Params<R> P, int TZ, int ntx, int nty,
+                                                        const FS* __restrict__ phi, const FS* __restrict__ q,
+                                                        const R* __restrict__ u, const R* __restrict__ mu,
+                                                        FS* __restrict__ phi_out, FS* __restrict__ q_out) {
+  constexpr int NT = TX * TY;
+  constexpr int SX = TX + 2, SY = TY + 2, NS = SX * SY;
+  constexpr int NH = NS - NT;  // halo slots
+  constexpr int NV = 10;       // q[5], phi, u[3], mu
+  __shared__ R sV[NV][NS];
+  __shared__ int sGX[SX], sGY[SY];
+
+  const int l = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = l % ntx, ty = (l / ntx) % nty, sl = l / (ntx * nty);
+  const int x0 = tx * TX, y0 = ty * TY, z0 = sl * TZ;
+  const int z1 = min(z0 + TZ, b.nz);
+  const int tid = threadIdx.x;
+  const int lx = tid % TX, ly = tid / TX;
+  const bool active = (x0 + lx < b.nx) && (y0 + ly < b.ny);
+  const size_t N = b.N;
+  const int plane = b.nx * b.ny;
+
+  for (int k = tid; k < SX; k += NT) sGX[k] = pmod(x0 - 1 + k, b.nx);
+  for (int k = tid; k < SY; k += NT) sGY[k] = pmod(y0 - 1 + k, b.ny);
+  __syncthreads();
+  const int x = sGX[lx + 1], y = sGY[ly + 1];  // wrapped coordinates of the column
+  const int col = y * b.nx + x;
+
+  auto load_col = [&](int zz, R v[NV]) {
+    const size_t k = size_t(pmod(zz, b.nz)) * plane + col;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) v[c] = R(q[c * N + k]);
+    v[5] = R(phi[k]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[6 + a] = u[a * N + k];
+    v[9] = mu[k];
+  };
+  R vm[NV], v0[NV], vp[NV];
+  load_col(z0 - 1, vm);
+  load_col(z0, v0);
+  load_col(z0 + 1, vp);
+
+  // halo slot s -> (slot index, wrapped column) pairs, fixed over the march
+  const int sc = (ly + 1) * SX + (lx + 1);
+  for (int zc = z0; zc < z1; ++zc) {
+    __syncthreads();  // previous plane's reads are done
+#pragma unroll
+    for (int c = 0; c < NV; ++c) sV[c][sc] = v0[c];
+    {
+      const size_t zoff = size_t(zc) * plane;
+      for (int h = tid; h < NH; h += NT) {
+        // enumerate the border of the SX x SY frame
+        int sx, sy;
+        if (h < SX) { sx = h; sy = 0; }
+        else if (h < 2 * SX) { sx = h - SX; sy = SY - 1; }
+        else { const int r = h - 2 * SX; sx = (r & 1) ? SX - 1 : 0; sy = 1 + (r >> 1); }
+        const int s = sy * SX + sx;
+        const size_t k = zoff + sGY[sy] * b.nx + sGX[sx];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) sV[c][s] = R(q[c * N + k]);
+        sV[5][s] = R(phi[k]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) sV[6 + a][s] = u[a * N + k];
+        sV[9][s] = mu[k];
+      }
+    }
+    __syncthreads();
+    if (active) {
+      // gradients: x, y from LDS, z from the column registers
+      Grad<R> G;
+      G.phi = v0[5];
+      G.dphi[0] = R(0.5) * (sV[5][sc + 1] - sV[5][sc - 1]);
+      G.dphi[1] = R(0.5) * (sV[5][sc + SX] - sV[5][sc - SX]);
+      G.dphi[2] = R(0.5) * (vp[5] - vm[5]);
+      G.lapphi = R(0);
+      G.divv = R(0);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        const R qxp = sV[c][sc + 1], qxm = sV[c][sc - 1];
+        const R qyp = sV[c][sc + SX], qym = sV[c][sc - SX];
+        G.q[c] = v0[c];
+        G.dq[0][c] = R(0.5) * (qxp - qxm);
+        G.dq[1][c] = R(0.5) * (qyp - qym);
+        G.dq[2][c] = R(0.5) * (vp[c] - vm[c]);
+        G.lapq[c] = ((qxp + qxm) + (qyp + qym) + (vp[c] + vm[c])) - R(6) * v0[c];
+      }
+      R h[5];
+      h_site(P, G, h);
+      // velocity gradient W_ab = D0_b u_a, conservative phi flux, laplacian of mu
+      R W[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        W[a][0] = R(0.5) * (sV[6 + a][sc + 1] - sV[6 + a][sc - 1]);
+        W[a][1] = R(0.5) * (sV[6 + a][sc + SX] - sV[6 + a][sc - SX]);
+        W[a][2] = R(0.5) * (vp[6 + a] - vm[6 + a]);
+      }
+      const R flux = R(0.5) * (sV[6][sc + 1] * sV[5][sc + 1] - sV[6][sc - 1] * sV[5][sc - 1]) +
+                     R(0.5) * (sV[7][sc + SX] * sV[5][sc + SX] - sV[7][sc - SX] * sV[5][sc - SX]) +
+                     R(0.5) * (vp[8] * vp[5] - vm[8] * vm[5]);
+      const R lapmu = ((sV[9][sc + 1] + sV[9][sc - 1]) + (sV[9][sc + SX] + sV[9][sc - SX]) + (vp[9] + vm[9])) -
+                      R(6) * v0[9];
+      R S[5];
+      corotation_site(P.xi, G.q, W, S);
+      const size_t site = size_t(zc) * plane + col;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const R adv = v0[6] * G.dq[0][k] + v0[7] * G.dq[1][k] + v0[8] * G.dq[2][k];
+        q_out[k * N + site] = FS(v0[k] + (-adv + S[k] + P.Gamma * h[k]));
+      }
+      phi_out[site] = FS(v0[5] - flux + P.M * lapmu);
+    }
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      vm[c] = v0[c];
+      v0[c] = vp[c];
+    }
+    if (zc + 1 < z1) load_col(zc + 2, vp);
+  }
+}
+
+}  // namespace lbc

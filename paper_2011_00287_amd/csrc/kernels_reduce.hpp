@@ -47,6 +47,19 @@ __global__ void __launch_bounds__(256) k_final_sum(const double* __restrict__ pa
   }
 }
 
+// Plain 3x3 helpers for the float64 free-energy density (off the step path).
+__device__ __forceinline__ void full3d(const double q[5], double Q[3][3]) {
+  Q[0][0] = q[0]; Q[0][1] = q[1]; Q[0][2] = q[2];
+  Q[1][0] = q[1]; Q[1][1] = q[3]; Q[1][2] = q[4];
+  Q[2][0] = q[2]; Q[2][1] = q[4]; Q[2][2] = -q[0] - q[3];
+}
+__device__ __forceinline__ double ddot3d(const double A[3][3], const double B[3][3]) {
+  double s = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) s += A[a][b] * B[a][b];
+  return s;
+}
+
 constexpr int NTOT = 8;  // mass, jx, jy, jz, phi, F_h, E_kin, non-finite count
 
 // Free-energy density of F_h at one site in float64: forward differences in
@@ -61,7 +74,7 @@ __device__ __forceinline__ double fh_density(const Box& b, const Params<double>&
   double qc[5], Q[3][3], dQ[3][3][3], dphi[3];
   const double ph = double(phi[s0]);
   for (int k = 0; k < 5; ++k) qc[k] = double(q[k * N + s0]);
-  full3(qc, Q);
+  full3d(qc, Q);
   double gp2 = 0.0, gq2 = 0.0;
   for (int g = 0; g < 3; ++g) {
     const int sp = sidx(b, x + off[g][0], y + off[g][1], z + off[g][2]);
@@ -75,16 +88,21 @@ __device__ __forceinline__ double fh_density(const Box& b, const Params<double>&
       qm[k] = double(q[k * N + sm]);
       dqk[k] = 0.5 * (qp[k] - qm[k]);
     }
-    full3(dqk, dQ[g]);
+    full3d(dqk, dQ[g]);
     const double f[5] = {qp[0] - qc[0], qp[1] - qc[1], qp[2] - qc[2], qp[3] - qc[3], qp[4] - qc[4]};
     const double fzz = -f[0] - f[3];
     gq2 += f[0] * f[0] + f[3] * f[3] + fzz * fzz + 2.0 * (f[1] * f[1] + f[2] * f[2] + f[4] * f[4]);
   }
   double Q2[3][3], C[3][3];
-  matmul3(Q, Q, Q2);
-  const double tr2 = ddot3(Q, Q), tr3 = ddot3(Q2, Q);
-  curl3(dQ, C);
-  const double qcurl = ddot3(Q, C);
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c) Q2[a][c] = Q[a][0] * Q[0][c] + Q[a][1] * Q[1][c] + Q[a][2] * Q[2][c];
+  const double tr2 = ddot3d(Q, Q), tr3 = ddot3d(Q2, Q);
+  for (int c = 0; c < 3; ++c) {  // C_ab = eps_agd D0_g Q_db
+    C[0][c] = dQ[1][2][c] - dQ[2][1][c];
+    C[1][c] = dQ[2][0][c] - dQ[0][2][c];
+    C[2][c] = dQ[0][1][c] - dQ[1][0][c];
+  }
+  const double qcurl = ddot3d(Q, C);
   double anch = 0.0;
   for (int a = 0; a < 3; ++a)
     for (int c = 0; c < 3; ++c) anch += dphi[a] * Q[a][c] * dphi[c];

@@ -86,20 +86,16 @@ __global__ void __launch_bounds__(256) k_thermo(Box b, Params<R> P, const FS* __
   coords(b, s, x, y, z);
   Grad<R> G;
   gather_grad<R>(b, phi, q, x, y, z, G);
-  R mu, h[5], fc, sig[3][3];
-  thermo_site(P, G, mu, h, fc);
-  stress_site(P, G, h, fc, sig);
+  R h[5], sig[9];
+  sigma_site(P, G, sig, h);
   const size_t N = b.N;
-  mu_out[s] = mu;
+  mu_out[s] = mu_site(P, G.phi, G.lapphi, G.divv, G.q);
 #pragma unroll
   for (int k = 0; k < 5; ++k) h_out[k * N + s] = h[k];
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) sig_out[(a * 3 + c) * N + s] = sig[a][c];
+  for (int k = 0; k < 9; ++k) sig_out[k * N + s] = sig[k];
 }
 
-// F_a = sum_b D0_b sigma_ab + body force, at site (x, y, z).
 template <class R>
 __device__ __forceinline__ void force_at(const Box& b, const Params<R>& P, const R* __restrict__ sig, int x, int y,
                                          int z, R F[3]) {
@@ -169,15 +165,12 @@ __global__ void __launch_bounds__(256) k_order(Box b, Params<R> P, const FS* __r
     lapmu += mu[sp] + mu[sm];
   }
   lapmu -= R(6) * muc;
-  R Q[3][3], S[3][3];
-  full3(qc, Q);
-  corotation_site(P.xi, Q, W, S);
-  const int ia[5] = {0, 0, 0, 1, 1};
-  const int ib[5] = {0, 1, 2, 1, 2};
+  R S[5];
+  corotation_site(P.xi, qc, W, S);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     const R adv = uc[0] * dq[0][k] + uc[1] * dq[1][k] + uc[2] * dq[2][k];
-    q_out[k * N + s] = FS(qc[k] + (-adv + S[ia[k]][ib[k]] + P.Gamma * h[k * N + s]));
+    q_out[k * N + s] = FS(qc[k] + (-adv + S[k] + P.Gamma * h[k * N + s]));
   }
   phi_out[s] = FS(R(phi[s]) - flux + P.M * lapmu);
 }

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -15,6 +16,7 @@
 #include <vector>
 
 #include "lb_chiral.h"
+#include "kernels_fused.hpp"
 #include "kernels_reduce.hpp"
 
 namespace {
@@ -54,6 +56,30 @@ void dfree(void* p) {
 
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return (v && *v) ? std::atoi(v) : dflt;
+}
+
+// x-y tiles of the fused kernels.  The stress kernel computes the stress on
+// the (TX+2) x (TY+2) frame of a TX x TY tile; LDS per workgroup is about
+// 20 (TX+4)(TY+4) + 6 (TX+2)(TY+2) + 3 TX TY values.  The variant is chosen at context
+// creation (LBC_LB_TILE / LBC_OR_TILE select another one for tuning).
+struct TileCfg {
+  int tx, ty;
+};
+constexpr TileCfg kLbTiles[] = {{32, 8}, {32, 16}, {64, 4}, {16, 16}, {16, 8}};
+constexpr TileCfg kOrTiles[] = {{32, 8}, {64, 4}, {32, 16}, {64, 8}};
+
+template <class R>
+struct DefaultTile {
+  static constexpr int lb = 0, order = 0;
+};
+template <>
+struct DefaultTile<double> {
+  static constexpr int lb = 4, order = 0;
+};
+
 bool finite_params(const lb_params& p) {
   const double v[] = {p.tau, p.rho0, p.a, p.phi0, p.phi_cr, p.k_phi, p.M, p.A0, p.chi0, p.chi_s, p.K,
                       p.q0, p.W, p.Gamma, p.xi, p.zeta, p.body_force[0], p.body_force[1], p.body_force[2]};
@@ -70,7 +96,7 @@ void validate(const lb_params& p) {
   if (!(p.rho0 > 0.0)) fail(LB_EINVAL, "rho0 must be > 0");
   if (!(p.phi_cr != 0.0)) fail(LB_EINVAL, "phi_cr must be nonzero");
   const double n = double(p.nx) * double(p.ny) * double(p.nz);
-  if (n > double(1 << 30)) fail(LB_ENOMEM, "box exceeds 2^30 sites");
+  if (n > double(1 << 29)) fail(LB_ENOMEM, "box exceeds 2^29 sites");
 }
 
 template <class R>
@@ -132,6 +158,10 @@ struct BackendT final : Backend {
   R* u = nullptr;
   double* partial = nullptr;
   double* sums = nullptr;
+  bool site_path = false;  // three site-parallel kernels instead of the fused pair
+  int tz_lb = 8, tz_or = 8;
+  int lb_tile = 0, or_tile = 0;
+  int lb_ntx, lb_nty, lb_blocks, or_ntx, or_nty, or_blocks;
 
   BackendT(const lb_params& p, hipStream_t s) : stream(s) {
     box.nx = p.nx;
@@ -141,6 +171,20 @@ struct BackendT final : Backend {
     box.N = int(N);
     nblk = unsigned((N + TPB - 1) / TPB);
     set_params(p);
+    site_path = env_int("LBC_SITE_KERNELS", 0) != 0;
+    tz_lb = std::max(1, env_int("LBC_TZ_LB", 16));
+    tz_or = std::max(1, env_int("LBC_TZ_ORDER", 8));
+    lb_tile = env_int("LBC_LB_TILE", DefaultTile<R>::lb);
+    or_tile = env_int("LBC_OR_TILE", DefaultTile<R>::order);
+    if (lb_tile < 0 || lb_tile >= int(sizeof(kLbTiles) / sizeof(kLbTiles[0]))) lb_tile = DefaultTile<R>::lb;
+    if (or_tile < 0 || or_tile >= int(sizeof(kOrTiles) / sizeof(kOrTiles[0]))) or_tile = DefaultTile<R>::order;
+    const TileCfg lt = kLbTiles[lb_tile], ot = kOrTiles[or_tile];
+    lb_ntx = (p.nx + lt.tx - 1) / lt.tx;
+    lb_nty = (p.ny + lt.ty - 1) / lt.ty;
+    lb_blocks = lb_ntx * lb_nty * ((p.nz + tz_lb - 1) / tz_lb);
+    or_ntx = (p.nx + ot.tx - 1) / ot.tx;
+    or_nty = (p.ny + ot.ty - 1) / ot.ty;
+    or_blocks = or_ntx * or_nty * ((p.nz + tz_or - 1) / tz_or);
     size_t need = 2 * (19 * N * sizeof(GS) + 6 * N * sizeof(FS)) + 18 * N * sizeof(R);
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need > free_b)
@@ -264,32 +308,66 @@ struct BackendT final : Backend {
   }
 
   // --- the step -----------------------------------------------------------
-  static constexpr int NK = 3;
+  int nkernels() const { return site_path ? 3 : 2; }
   const char* kernel_name(int i) const override {
-    static const char* names[NK] = {"k_thermo", "k_collide", "k_order"};
-    return (i >= 0 && i < NK) ? names[i] : nullptr;
+    static const char* site_names[3] = {"k_thermo", "k_collide", "k_order"};
+    static const char* fused_names[2] = {"k_lb_fused", "k_order_fused"};
+    if (i < 0 || i >= nkernels()) return nullptr;
+    return site_path ? site_names[i] : fused_names[i];
   }
   void launch(int k) {
     const int nx = cur ^ 1;
-    switch (k) {
-      case 0:
-        lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], mu, H, sig);
-        break;
-      case 1:
-        lbc::k_collide<R, GS><<<nblk, TPB, 0, stream>>>(box, P, B[cur], B[nx], sig, u);
-        break;
-      case 2:
-        lbc::k_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], u, H, mu, Ph[nx], Q[nx]);
-        cur = nx;
-        break;
+    if (site_path) {
+      switch (k) {
+        case 0:
+          lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], mu, H, sig);
+          break;
+        case 1:
+          lbc::k_collide<R, GS><<<nblk, TPB, 0, stream>>>(box, P, B[cur], B[nx], sig, u);
+          break;
+        case 2:
+          lbc::k_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], u, H, mu, Ph[nx], Q[nx]);
+          cur = nx;
+          break;
+      }
+      return;
+    }
+    if (k == 0) {
+      switch (lb_tile) {
+        case 0: launch_lb<32, 8, 2>(); break;
+        case 1: launch_lb<32, 16, (sizeof(R) == 4 ? 2 : 1)>(); break;
+        case 2: launch_lb<64, 4, 2>(); break;
+        case 3: launch_lb<16, 16, 2>(); break;
+        default: launch_lb<16, 8, 1>(); break;
+      }
+    } else {
+      switch (or_tile) {
+        case 0: launch_or<32, 8, 2>(); break;
+        case 1: launch_or<64, 4, 2>(); break;
+        case 2: launch_or<32, 16, 2>(); break;
+        default: launch_or<64, 8, 2>(); break;
+      }
+      cur = nx;
     }
   }
+  template <int TX, int TY, int MINW>
+  void launch_lb() {
+    lbc::k_lb_fused<R, GS, FS, TX, TY, MINW><<<lb_blocks, TX * TY, 0, stream>>>(
+        box, P, tz_lb, lb_ntx, lb_nty, B[cur], B[cur ^ 1], Ph[cur], Q[cur], u, mu);
+  }
+  template <int TX, int TY, int MINW>
+  void launch_or() {
+    lbc::k_order_fused<R, FS, TX, TY, MINW><<<or_blocks, TX * TY, 0, stream>>>(
+        box, P, tz_or, or_ntx, or_nty, Ph[cur], Q[cur], u, mu, Ph[cur ^ 1], Q[cur ^ 1]);
+  }
   void step(int n) override {
+    const int nk = nkernels();
     for (int s = 0; s < n; ++s)
-      for (int k = 0; k < NK; ++k) launch(k);
+      for (int k = 0; k < nk; ++k) launch(k);
     check_launch();
   }
   void profile(int n, double* ms, int* count) override {
+    const int NK = nkernels();
     *count = NK;
     for (int k = 0; k < NK; ++k) ms[k] = 0.0;
     const int chunk = 32;

@@ -2,6 +2,9 @@
 //
 // Every function here is pure register math on values a kernel has already
 // gathered; the kernels decide where the values come from (HBM, L2, LDS).
+// Symmetric traceless tensors are handled through their 5 stored components
+// (xx, xy, xz, yy, yz; zz = -xx - yy) with explicit scalar formulas, so no
+// work is spent on entries that symmetry already fixes.
 //
 // Free energy (Eq. (5)), with chi(phi) = chi0 + chi_s*phi and the one-constant
 // elastic term written on a periodic box as
@@ -44,183 +47,226 @@ __host__ __device__ constexpr R WQ(int i) {
   return i == 0 ? R(1) / R(3) : (i <= 6 ? R(1) / R(18) : R(1) / R(36));
 }
 
-// ------------------------------------------------------------- tensor helpers
 template <class R>
-__device__ __forceinline__ void full3(const R q[5], R Q[3][3]) {
-  Q[0][0] = q[0]; Q[0][1] = q[1]; Q[0][2] = q[2];
-  Q[1][0] = q[1]; Q[1][1] = q[3]; Q[1][2] = q[4];
-  Q[2][0] = q[2]; Q[2][1] = q[4]; Q[2][2] = -q[0] - q[3];
-}
-
-template <class R>
-__device__ __forceinline__ void matmul3(const R A[3][3], const R B[3][3], R C[3][3]) {
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) C[a][b] = A[a][0] * B[0][b] + A[a][1] * B[1][b] + A[a][2] * B[2][b];
-}
-
-// A:B = sum_ab A_ab B_ab
-template <class R>
-__device__ __forceinline__ R ddot3(const R A[3][3], const R B[3][3]) {
-  R s = R(0);
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) s += A[a][b] * B[a][b];
-  return s;
-}
-
-// curl(Q)_ab = eps_agd dQ[g][d][b]; dQ[g] = D0_g Q.
-template <class R>
-__device__ __forceinline__ void curl3(const R dQ[3][3][3], R C[3][3]) {
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    C[0][b] = dQ[1][2][b] - dQ[2][1][b];
-    C[1][b] = dQ[2][0][b] - dQ[0][2][b];
-    C[2][b] = dQ[0][1][b] - dQ[1][0][b];
-  }
-}
+struct C3 {
+  static constexpr R third = R(1) / R(3);
+  static constexpr R sixth = R(1) / R(6);
+};
 
 // Local gradient data of one site, gathered by a kernel.
 template <class R>
 struct Grad {
   R phi;          // phi(x)
   R dphi[3];      // D0 phi
-  R lapphi;       // 7-point laplacian of phi
-  R divv;         // sum_a D0_a (Q_ab D0_b phi)
+  R lapphi;       // 7-point laplacian of phi (mu only)
+  R divv;         // sum_a D0_a (Q_ab D0_b phi) (mu only)
   R q[5];         // stored Q components at x
   R dq[3][5];     // D0_g of the stored components
   R lapq[5];      // laplacian of the stored components
 };
 
-// mu, H (stored 5 components) and the central-difference free-energy density.
+// Quantities shared by H, the free-energy density and the stress.
 template <class R>
-__device__ __forceinline__ void thermo_site(const Params<R>& P, const Grad<R>& G, R& mu, R h[5], R& fc) {
-  R Q[3][3], dQ[3][3][3], Q2[3][3], C[3][3];
-  full3(G.q, Q);
-#pragma unroll
-  for (int g = 0; g < 3; ++g) full3(G.dq[g], dQ[g]);
-  matmul3(Q, Q, Q2);
-  R tr2 = ddot3(Q, Q);
-  R tr3 = ddot3(Q2, Q);
-  const R phi = G.phi;
-  const R chi = P.chi0 + P.chi_s * phi;
-  const R dp2 = G.dphi[0] * G.dphi[0] + G.dphi[1] * G.dphi[1] + G.dphi[2] * G.dphi[2];
+struct Local {
+  R xx, xy, xz, yy, yz, zz;                        // Q
+  R q2xx, q2xy, q2xz, q2yy, q2yz, q2zz, tr2, tr3;  // Q.Q and invariants
+  R cxx, cyy, sxy, sxz, syz;                       // C_xx, C_yy, (C + C^T) off-diagonals
+  R qc;                                            // Q : curl(Q)
+  R dp2, chi;
+  R h[5];                                          // molecular field
+};
 
-  mu = P.a * phi * (phi - P.phi0) * (R(2) * phi - P.phi0) * P.inv_phicr2
-     + P.A0 * P.chi_s * (-tr2 / R(6) - tr3 / R(3) + tr2 * tr2 / R(4))
-     - P.k_phi * G.lapphi - R(2) * P.W * G.divv;
+template <class R>
+__device__ __forceinline__ void local_thermo(const Params<R>& P, const Grad<R>& G, Local<R>& L) {
+  const R xx = G.q[0], xy = G.q[1], xz = G.q[2], yy = G.q[3], yz = G.q[4], zz = -xx - yy;
+  L.xx = xx; L.xy = xy; L.xz = xz; L.yy = yy; L.yz = yz; L.zz = zz;
+  L.q2xx = xx * xx + xy * xy + xz * xz;
+  L.q2xy = xx * xy + xy * yy + xz * yz;
+  L.q2xz = xx * xz + xy * yz + xz * zz;
+  L.q2yy = xy * xy + yy * yy + yz * yz;
+  L.q2yz = xy * xz + yy * yz + yz * zz;
+  L.q2zz = xz * xz + yz * yz + zz * zz;
+  L.tr2 = L.q2xx + L.q2yy + L.q2zz;
+  L.tr3 = xx * L.q2xx + yy * L.q2yy + zz * L.q2zz + R(2) * (xy * L.q2xy + xz * L.q2xz + yz * L.q2yz);
+  // d[g] = D0_g Q;  C_ab = eps_agd d[g]_db
+  const R* d0 = G.dq[0];
+  const R* d1 = G.dq[1];
+  const R* d2 = G.dq[2];
+  const R d0zz = -d0[0] - d0[3], d1zz = -d1[0] - d1[3];
+  L.cxx = d1[2] - d2[1];
+  L.cyy = d2[1] - d0[4];
+  const R czz = -L.cxx - L.cyy;
+  L.sxy = (d1[4] - d2[3]) + (d2[0] - d0[2]);
+  L.sxz = (d1zz - d2[4]) + (d0[1] - d1[0]);
+  L.syz = (d2[2] - d0zz) + (d0[3] - d1[1]);
+  L.qc = xx * L.cxx + yy * L.cyy + zz * czz + xy * L.sxy + xz * L.sxz + yz * L.syz;
 
-  curl3(dQ, C);
-  const R c1 = R(1) - chi / R(3);
+  const R dx = G.dphi[0], dy = G.dphi[1], dz = G.dphi[2];
+  L.dp2 = dx * dx + dy * dy + dz * dz;
+  L.chi = P.chi0 + P.chi_s * G.phi;
   const R kq = R(2) * P.K * P.q0;
   const R kq2 = R(4) * P.K * P.q0 * P.q0;
-  // stored components: (0,0) (0,1) (0,2) (1,1) (1,2)
-  const int ia[5] = {0, 0, 0, 1, 1};
-  const int ib[5] = {0, 1, 2, 1, 2};
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    const int a = ia[k], b = ib[k];
-    const R de = (a == b) ? R(1) : R(0);
-    h[k] = -P.A0 * (c1 * Q[a][b] - chi * (Q2[a][b] - de * tr2 / R(3)) + chi * Q[a][b] * tr2)
-         + P.K * G.lapq[k] - kq * (C[a][b] + C[b][a]) - kq2 * Q[a][b]
-         - P.W * (G.dphi[a] * G.dphi[b] - de * dp2 / R(3));
-  }
+  const R c1 = R(1) - L.chi * C3<R>::third;
+  const R alpha = -P.A0 * (c1 + L.chi * L.tr2) - kq2;
+  const R beta = P.A0 * L.chi;
+  const R t3 = L.tr2 * C3<R>::third;
+  const R dd3 = L.dp2 * C3<R>::third;
+  L.h[0] = alpha * xx + beta * (L.q2xx - t3) + P.K * G.lapq[0] - kq * (R(2) * L.cxx) - P.W * (dx * dx - dd3);
+  L.h[1] = alpha * xy + beta * L.q2xy + P.K * G.lapq[1] - kq * L.sxy - P.W * (dx * dy);
+  L.h[2] = alpha * xz + beta * L.q2xz + P.K * G.lapq[2] - kq * L.sxz - P.W * (dx * dz);
+  L.h[3] = alpha * yy + beta * (L.q2yy - t3) + P.K * G.lapq[3] - kq * (R(2) * L.cyy) - P.W * (dy * dy - dd3);
+  L.h[4] = alpha * yz + beta * L.q2yz + P.K * G.lapq[4] - kq * L.syz - P.W * (dy * dz);
+}
 
-  R gq2 = R(0);
+// Molecular field only (5 stored components).
+template <class R>
+__device__ __forceinline__ void h_site(const Params<R>& P, const Grad<R>& G, R h[5]) {
+  Local<R> L;
+  local_thermo(P, G, L);
 #pragma unroll
-  for (int g = 0; g < 3; ++g) gq2 += ddot3(dQ[g], dQ[g]);
-  R qc = ddot3(Q, C);
-  R anch = R(0);
+  for (int k = 0; k < 5; ++k) h[k] = L.h[k];
+}
+
+// A:B for symmetric traceless tensors given by 5 components.
+template <class R>
+__device__ __forceinline__ R sdot(const R* A, const R* B) {
+  const R azz = -A[0] - A[3], bzz = -B[0] - B[3];
+  return A[0] * B[0] + A[3] * B[3] + azz * bzz + R(2) * (A[1] * B[1] + A[2] * B[2] + A[4] * B[4]);
+}
+
+// Full stress sig[3*a + b] (a = force component, b = derivative index) and the
+// molecular field h (5 components) of one site.
+template <class R>
+__device__ __forceinline__ void sigma_site(const Params<R>& P, const Grad<R>& G, R sig[9], R h[5]) {
+  Local<R> L;
+  local_thermo(P, G, L);
+  const R xx = L.xx, xy = L.xy, xz = L.xz, yy = L.yy, yz = L.yz, zz = L.zz;
+  const R dp[3] = {G.dphi[0], G.dphi[1], G.dphi[2]};
+  const R kq = R(2) * P.K * P.q0;
+  const R kq2 = R(4) * P.K * P.q0 * P.q0;
+
+  // Ericksen (Q) part: D_ab = dQ[a]:dQ[b]; ax[a]_b = eps_bgl (dQ[a] Q)_gl
+  R D[3][3], ax[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) anch += G.dphi[a] * Q[a][b] * G.dphi[b];
-  const R dw = phi * (phi - P.phi0);
-  fc = R(0.5) * P.a * dw * dw * P.inv_phicr2
-     + P.A0 * (R(0.5) * c1 * tr2 - chi / R(3) * tr3 + chi / R(4) * tr2 * tr2)
-     + R(0.5) * kq2 * tr2 + R(0.5) * P.k_phi * dp2 + R(0.5) * P.K * gq2 + kq * qc + P.W * anch;
-}
-
-// Full 3x3 stress (row a = force component, column b = derivative index).
-template <class R>
-__device__ __forceinline__ void stress_site(const Params<R>& P, const Grad<R>& G, const R h[5], R fc,
-                                            R sig[3][3]) {
-  R Q[3][3], H[3][3], dQ[3][3][3];
-  full3(G.q, Q);
-  full3(h, H);
-#pragma unroll
-  for (int g = 0; g < 3; ++g) full3(G.dq[g], dQ[g]);
-  R Qd[3];
-#pragma unroll
-  for (int b = 0; b < 3; ++b) Qd[b] = Q[b][0] * G.dphi[0] + Q[b][1] * G.dphi[1] + Q[b][2] * G.dphi[2];
-  R QH[3][3], HQ[3][3];
-  matmul3(Q, H, QH);
-  matmul3(H, Q, HQ);
-  const R qh = ddot3(Q, H);
-  const R xi = P.xi;
-  const R kq = R(2) * P.K * P.q0;
+    for (int b = a; b < 3; ++b) {
+      D[a][b] = sdot(G.dq[a], G.dq[b]);
+      D[b][a] = D[a][b];
+    }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    // Ericksen (Q): -K dQ[a]:dQ[b] - 2 K q0 axial_b(dQ[a] Q), axial_b(M) = eps_bgl M_gl
-    R M[3][3];
-    matmul3(dQ[a], Q, M);
-    const R ax[3] = {M[1][2] - M[2][1], M[2][0] - M[0][2], M[0][1] - M[1][0]};
+    const R dxx = G.dq[a][0], dxy = G.dq[a][1], dxz = G.dq[a][2], dyy = G.dq[a][3], dyz = G.dq[a][4];
+    const R dzz = -dxx - dyy;
+    ax[a][0] = (dxy * xz + dyy * yz + dyz * zz) - (dxz * xy + dyz * yy + dzz * yz);
+    ax[a][1] = (dxz * xx + dyz * xy + dzz * xz) - (dxx * xz + dxy * yz + dxz * zz);
+    ax[a][2] = (dxx * xy + dxy * yy + dxz * yz) - (dxy * xx + dyy * xy + dyz * xz);
+  }
+  // free-energy density (central differences)
+  const R Qd[3] = {xx * dp[0] + xy * dp[1] + xz * dp[2], xy * dp[0] + yy * dp[1] + yz * dp[2],
+                   xz * dp[0] + yz * dp[1] + zz * dp[2]};
+  const R anch = dp[0] * Qd[0] + dp[1] * Qd[1] + dp[2] * Qd[2];
+  const R dw = G.phi * (G.phi - P.phi0);
+  const R c1 = R(1) - L.chi * C3<R>::third;
+  const R fc = R(0.5) * P.a * dw * dw * P.inv_phicr2 +
+               P.A0 * (R(0.5) * c1 * L.tr2 - L.chi * C3<R>::third * L.tr3 + R(0.25) * L.chi * L.tr2 * L.tr2) +
+               R(0.5) * kq2 * L.tr2 + R(0.5) * P.k_phi * L.dp2 + R(0.5) * P.K * (D[0][0] + D[1][1] + D[2][2]) +
+               kq * L.qc + P.W * anch;
+  // reactive + antisymmetric:
+  //   -(xi+1) (QH)^T + (1-xi) QH - (2xi/3) H + (2xi/3)(Q:H) I + 2 xi (Q:H) Q
+  const R hxx = L.h[0], hxy = L.h[1], hxz = L.h[2], hyy = L.h[3], hyz = L.h[4], hzz = -hxx - hyy;
+  const R Qm[3][3] = {{xx, xy, xz}, {xy, yy, yz}, {xz, yz, zz}};
+  const R Hm[3][3] = {{hxx, hxy, hxz}, {hxy, hyy, hyz}, {hxz, hyz, hzz}};
+  R QH[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) QH[a][b] = Qm[a][0] * Hm[0][b] + Qm[a][1] * Hm[1][b] + Qm[a][2] * Hm[2][b];
+  const R qh = QH[0][0] + QH[1][1] + QH[2][2];
+  const R xi = P.xi;
+  const R cA = -(xi + R(1)), cB = R(1) - xi, cH = -R(2) * xi * C3<R>::third;
+  const R cQ = R(2) * xi * qh - P.zeta * G.phi;
+  const R iso = fc - cH * qh;  // fc + (2 xi/3) qh
+  const R t[3] = {P.k_phi * dp[0] + R(2) * P.W * Qd[0], P.k_phi * dp[1] + R(2) * P.W * Qd[1],
+                  P.k_phi * dp[2] + R(2) * P.W * Qd[2]};
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const R de = (a == b) ? R(1) : R(0);
-      const R P_ab = Q[a][b] + de / R(3);
-      R s = fc * de - G.dphi[a] * (P.k_phi * G.dphi[b] + R(2) * P.W * Qd[b]);
-      s -= P.K * ddot3(dQ[a], dQ[b]) + kq * ax[b];
-      s += -xi * (HQ[a][b] + QH[a][b] + R(2) * H[a][b] / R(3)) + R(2) * xi * P_ab * qh + (QH[a][b] - HQ[a][b]);
-      s -= P.zeta * G.phi * Q[a][b];
-      sig[a][b] = s;
+      R s = -dp[a] * t[b] - P.K * D[a][b] - kq * ax[a][b] + cA * QH[b][a] + cB * QH[a][b] + cH * Hm[a][b] +
+            cQ * Qm[a][b];
+      if (a == b) s += iso;
+      sig[3 * a + b] = s;
     }
-  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) h[k] = L.h[k];
 }
 
-// Traceless co-rotational term S of the Beris-Edwards material derivative
-// (Eq. (2)), from the velocity gradient W_ab = D0_b u_a.
+// Chemical potential mu = dF/dphi from phi, its laplacian, the anchoring
+// divergence divv = D0_a(Q_ab D0_b phi) and the stored Q components.
 template <class R>
-__device__ __forceinline__ void corotation_site(R xi, const R Q[3][3], const R W[3][3], R S[3][3]) {
-  R A[3][3], B[3][3], Pm[3][3];
+__device__ __forceinline__ R mu_site(const Params<R>& P, R phi, R lapphi, R divv, const R q[5]) {
+  const R xx = q[0], xy = q[1], xz = q[2], yy = q[3], yz = q[4], zz = -xx - yy;
+  const R q2xx = xx * xx + xy * xy + xz * xz;
+  const R q2xy = xx * xy + xy * yy + xz * yz;
+  const R q2xz = xx * xz + xy * yz + xz * zz;
+  const R q2yy = xy * xy + yy * yy + yz * yz;
+  const R q2yz = xy * xz + yy * yz + yz * zz;
+  const R q2zz = xz * xz + yz * yz + zz * zz;
+  const R tr2 = q2xx + q2yy + q2zz;
+  const R tr3 = xx * q2xx + yy * q2yy + zz * q2zz + R(2) * (xy * q2xy + xz * q2xz + yz * q2yz);
+  return P.a * phi * (phi - P.phi0) * (R(2) * phi - P.phi0) * P.inv_phicr2 +
+         P.A0 * P.chi_s * (-tr2 * C3<R>::sixth - tr3 * C3<R>::third + R(0.25) * tr2 * tr2) - P.k_phi * lapphi -
+         R(2) * P.W * divv;
+}
+
+// Traceless co-rotational term of the Beris-Edwards material derivative
+// (Eq. (2)) as 5 stored components, from the velocity gradient W_ab = D0_b u_a:
+// S = A P + P A^T - 2 xi P tr(Q W), A = xi D + Om, P = Q + I/3, minus its trace/3.
+template <class R>
+__device__ __forceinline__ void corotation_site(R xi, const R q[5], const R W[3][3], R s5[5]) {
+  const R xx = q[0], xy = q[1], xz = q[2], yy = q[3], yz = q[4], zz = -xx - yy;
+  const R Pm[3][3] = {{xx + C3<R>::third, xy, xz}, {xy, yy + C3<R>::third, yz}, {xz, yz, zz + C3<R>::third}};
+  const R Qm[3][3] = {{xx, xy, xz}, {xy, yy, yz}, {xz, yz, zz}};
+  R A[3][3];
   R trQW = R(0);
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const R D = R(0.5) * (W[a][b] + W[b][a]);
-      const R O = R(0.5) * (W[a][b] - W[b][a]);
-      A[a][b] = xi * D + O;
-      B[a][b] = xi * D - O;
-      Pm[a][b] = Q[a][b] + ((a == b) ? R(1) / R(3) : R(0));
-      trQW += Q[a][b] * W[b][a];
+      A[a][b] = R(0.5) * ((xi + R(1)) * W[a][b] + (xi - R(1)) * W[b][a]);
+      trQW += Qm[a][b] * W[b][a];
     }
-  R AP[3][3], PB[3][3];
-  matmul3(A, Pm, AP);
-  matmul3(Pm, B, PB);
+  R M[3][3];  // A P
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) S[a][b] = AP[a][b] + PB[a][b] - R(2) * xi * Pm[a][b] * trQW;
-  const R tr = (S[0][0] + S[1][1] + S[2][2]) / R(3);
-  S[0][0] -= tr; S[1][1] -= tr; S[2][2] -= tr;
+    for (int b = 0; b < 3; ++b) M[a][b] = A[a][0] * Pm[0][b] + A[a][1] * Pm[1][b] + A[a][2] * Pm[2][b];
+  const R c = R(2) * xi * trQW;
+  const R sxx = R(2) * M[0][0] - c * Pm[0][0];
+  const R syy = R(2) * M[1][1] - c * Pm[1][1];
+  const R szz = R(2) * M[2][2] - c * Pm[2][2];
+  const R tr = (sxx + syy + szz) * C3<R>::third;
+  s5[0] = sxx - tr;
+  s5[1] = (M[0][1] + M[1][0]) - c * Pm[0][1];
+  s5[2] = (M[0][2] + M[2][0]) - c * Pm[0][2];
+  s5[3] = syy - tr;
+  s5[4] = (M[1][2] + M[2][1]) - c * Pm[1][2];
 }
 
 // BGK collision with Guo forcing on the 19 deviations g (in place).
-// rho = rho0 + sum g, u = (sum c g + F/2)/rho; returns u.
+// rho = rho0 + sum g, u = (sum c g + F/2)/rho; returns u.  Opposite pairs
+// (i, i+1) share the even part of g_eq and of the source.
 template <class R>
 __device__ __forceinline__ void collide_site(const Params<R>& P, R g[19], const R F[3], R u[3]) {
-  R s = R(0), jx = R(0), jy = R(0), jz = R(0);
+  R drho = g[0];
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    s += g[i];
-    if (CX(i)) jx += CX(i) > 0 ? g[i] : -g[i];
-    if (CY(i)) jy += CY(i) > 0 ? g[i] : -g[i];
-    if (CZ(i)) jz += CZ(i) > 0 ? g[i] : -g[i];
-  }
-  const R drho = s;
+  for (int i = 1; i < 19; ++i) drho += g[i];
+  const R e1 = g[1] - g[2], e3 = g[3] - g[4], e5 = g[5] - g[6], e7 = g[7] - g[8], e9 = g[9] - g[10];
+  const R e11 = g[11] - g[12], e13 = g[13] - g[14], e15 = g[15] - g[16], e17 = g[17] - g[18];
+  const R jx = e1 + e7 + e9 + e11 + e13;
+  const R jy = e3 + e7 - e9 + e15 + e17;
+  const R jz = e5 + e11 - e13 + e15 - e17;
   const R rho = P.rho0 + drho;
   const R inv = R(1) / rho;
   u[0] = (jx + R(0.5) * F[0]) * inv;
@@ -228,14 +274,22 @@ __device__ __forceinline__ void collide_site(const Params<R>& P, R g[19], const 
   u[2] = (jz + R(0.5) * F[2]) * inv;
   const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   const R uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+  const R om = P.omega, om1 = R(1) - P.omega;
+  // g_eq_i = w (A + 3 rho cu + 4.5 rho cu^2); src_i = guo w (Bs + 3 cF + 9 cu cF)
+  const R A = drho - R(1.5) * rho * uu;
+  const R Bs = R(-3) * uF;
+  const R r3 = R(3) * rho, r45 = R(4.5) * rho;
+  g[0] = om1 * g[0] + WQ<R>(0) * (om * A + P.guo * Bs);
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
+  for (int i = 1; i < 19; i += 2) {
     const R cu = R(CX(i)) * u[0] + R(CY(i)) * u[1] + R(CZ(i)) * u[2];
     const R cF = R(CX(i)) * F[0] + R(CY(i)) * F[1] + R(CZ(i)) * F[2];
     const R w = WQ<R>(i);
-    const R geq = w * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
-    const R src = P.guo * w * (R(3) * (cF - uF) + R(9) * cu * cF);
-    g[i] = g[i] - (g[i] - geq) * P.omega + src;
+    const R even = w * (om * (A + r45 * cu * cu) + P.guo * (Bs + R(9) * cu * cF));
+    const R odd = w * (om * (r3 * cu) + P.guo * (R(3) * cF));
+    const R gi = g[i], gj = g[i + 1];
+    g[i] = om1 * gi + (even + odd);
+    g[i + 1] = om1 * gj + (even - odd);
   }
 }
 

@@ -7,6 +7,18 @@
 
 namespace lbc {
 
+// Global access as a uniform base pointer plus a 32-bit per-lane byte offset
+// (the SGPR-base + VGPR-offset addressing form); every component array of
+// a context is below 4 GiB (sites <= 2^29).
+template <class T>
+__device__ __forceinline__ T ldo(const T* __restrict__ base, uint32_t byteoff) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byteoff);
+}
+template <class T>
+__device__ __forceinline__ void sto(T* __restrict__ base, uint32_t byteoff, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byteoff) = v;
+}
+
 // Population storage.  float64 / float32 store the deviation g_i itself;
 // float16 stores g_i * 64 / w_i, which keeps the typical O(1e-4 .. 1e-1)
 // values of g_i / w_i inside the normal range of the format.
@@ -16,6 +28,26 @@ struct GPol {
   __device__ __forceinline__ static R ld(const GS* p, size_t k, int) { return R(p[k]); }
   template <class R>
   __device__ __forceinline__ static void st(GS* p, size_t k, int, R v) { p[k] = GS(v); }
+};
+
+template <class GS>
+struct GPolO {
+  // element k of the population array starting at base, by byte offset
+  template <class R>
+  __device__ __forceinline__ static R ld(const GS* base, uint32_t off, int) { return R(ldo(base, off)); }
+  template <class R>
+  __device__ __forceinline__ static void st(GS* base, uint32_t off, int, R v) { sto(base, off, GS(v)); }
+};
+template <>
+struct GPolO<__half> {
+  template <class R>
+  __device__ __forceinline__ static R ld(const __half* base, uint32_t off, int i) {
+    return R(__half2float(ldo(base, off))) * (WQ<R>(i) * R(1.0 / 64.0));
+  }
+  template <class R>
+  __device__ __forceinline__ static void st(__half* base, uint32_t off, int i, R v) {
+    sto(base, off, __float2half(float(v * (R(64) / WQ<R>(i)))));
+  }
 };
 
 template <>
