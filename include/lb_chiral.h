@@ -144,6 +144,33 @@ size_t lb_state_bytes(const lb_ctx* c);
 lb_status lb_get_state(lb_ctx* c, void* dev_dst, size_t bytes);
 lb_status lb_set_state(lb_ctx* c, const void* dev_src, size_t bytes);
 
+/* ---------------------------------------------------------------------------
+ * Adjoint (reverse mode) of the coupled step.
+ *
+ * The adjoint of a state is a device buffer of lb_adjoint_bytes() bytes in the
+ * context's arithmetic type (double for LB_FP64, float otherwise), laid out
+ * as g_bar [19][N] (adjoint of the post-stream population deviations),
+ * q_bar [5][N] (adjoint of the 5 stored Q components) and phi_bar [N].
+ * The caller owns it (e.g. a torch tensor on the context's device).
+ * ------------------------------------------------------------------------- */
+size_t lb_adjoint_bytes(const lb_ctx* c);
+
+/* One reverse step.  dev_state_t is the forward state at time t in the
+ * lb_get_state format (state_bytes = lb_state_bytes()).  On entry dev_adj
+ * holds the adjoint of the state at t+1; on return the adjoint of the state at
+ * t (the vector-Jacobian product of one coupled step with the context's
+ * current parameters).  *zeta_bar and *q0_bar (may be NULL) are incremented by
+ * the step's contribution to dL/dzeta and dL/dq0, summed in float64 on the
+ * device.  The context's current state becomes the state at t.
+ * Errors: LB_ESTATE on a buffer size mismatch, LB_EDEVICE.  Synchronises. */
+lb_status lb_adjoint_step(lb_ctx* c, const void* dev_state_t, size_t state_bytes, void* dev_adj,
+                          size_t adj_bytes, double* zeta_bar, double* q0_bar);
+
+/* Seed of the droplet-displacement loss L = (z_c - z_ref)^2 with z_c the
+ * phi-weighted linear centre along z of the current state (the loss of a
+ * differentiable rollout).  Writes dL/d(state) into dev_adj and L into *loss. */
+lb_status lb_adjoint_seed_centre(lb_ctx* c, double z_ref, void* dev_adj, size_t adj_bytes, double* loss);
+
 /* Average device time per launch of each kernel of the step, measured with
  * HIP events recorded on the context's stream around every launch of
  * nsteps steps (the state advances by nsteps).  kernel_ms must hold

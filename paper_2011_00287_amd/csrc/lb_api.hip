@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "lb_chiral.h"
+#include "kernels_adjoint.hpp"
 #include "kernels_fused.hpp"
 #include "kernels_reduce.hpp"
 
@@ -138,6 +139,9 @@ struct Backend {
   virtual size_t state_bytes() const = 0;
   virtual void get_state(void* dst, int64_t step) = 0;
   virtual int64_t set_state(const void* src) = 0;
+  virtual size_t adjoint_bytes() const = 0;
+  virtual int64_t adjoint_step(const void* state, void* adj, double* zeta_bar, double* q0_bar) = 0;
+  virtual double seed_centre(double z_ref, void* adj) = 0;
 };
 
 template <class R, class GS, class FS>
@@ -158,6 +162,17 @@ struct BackendT final : Backend {
   R* u = nullptr;
   double* partial = nullptr;
   double* sums = nullptr;
+  // adjoint scratch (allocated on first use)
+  R* aF = nullptr;
+  R* amub = nullptr;
+  R* aWb = nullptr;
+  R* aubp = nullptr;
+  R* aqbp = nullptr;
+  R* aphibp = nullptr;
+  R* ahb = nullptr;
+  R* aFb = nullptr;
+  R* agbar = nullptr;
+  R* agnew = nullptr;
   bool site_path = false;  // three site-parallel kernels instead of the fused pair
   int tz_lb = 8, tz_or = 8;
   int lb_tile = 0, or_tile = 0;
@@ -224,6 +239,11 @@ struct BackendT final : Backend {
     dfree(sums);
     mu = H = sig = u = nullptr;
     partial = sums = nullptr;
+    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &ahb, &aFb, &agbar, &agnew};
+    for (R** a : adj) {
+      dfree(*a);
+      *a = nullptr;
+    }
   }
 
   void set_params(const lb_params& p) override {
@@ -480,6 +500,67 @@ struct BackendT final : Backend {
     HIPCHECK(hipStreamSynchronize(stream));
     return stepno;
   }
+
+  // --- adjoint ---------------------------------------------------------------
+  // adjoint buffer: g_bar [19][N], q_bar [5][N], phi_bar [N] in R
+  size_t adjoint_bytes() const override { return 25 * N * sizeof(R); }
+  void ensure_adjoint() {
+    if (aF) return;
+    try {
+      aF = dalloc<R>(3 * N);
+      amub = dalloc<R>(N);
+      aWb = dalloc<R>(9 * N);
+      aubp = dalloc<R>(3 * N);
+      aqbp = dalloc<R>(5 * N);
+      aphibp = dalloc<R>(N);
+      ahb = dalloc<R>(5 * N);
+      aFb = dalloc<R>(3 * N);
+      agbar = dalloc<R>(size_t(lbc::NGB) * N);
+      agnew = dalloc<R>(19 * N);
+    } catch (...) {
+      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &ahb, &aFb, &agbar, &agnew};
+      for (R** a : adj) {
+        dfree(*a);
+        *a = nullptr;
+      }
+      throw;
+    }
+  }
+  int64_t adjoint_step(const void* state, void* adj, double* zeta_bar, double* q0_bar) override {
+    ensure_adjoint();
+    const int64_t stepno = set_state(state);
+    R* ag = static_cast<R*>(adj);
+    R* aq = ag + 19 * N;
+    R* ap = ag + 24 * N;
+    // forward quantities of time t
+    lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], mu, H, sig);
+    lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, B[cur], sig, aF, u);
+    // reverse
+    lbc::k_adj_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], u, ap, aq, amub, aWb, aubp, aqbp,
+                                                       aphibp, ahb);
+    lbc::k_adj_collide<R, GS><<<nblk, TPB, 0, stream>>>(box, P, B[cur], aF, aWb, aubp, ag, agnew, aFb);
+    lbc::k_adj_stress<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], aFb, ahb, amub, agbar, partial);
+    lbc::k_final_sum<<<1, TPB, 0, stream>>>(partial, int(nblk), 2, sums);
+    lbc::k_adj_divv<R, FS><<<nblk, TPB, 0, stream>>>(box, Ph[cur], Q[cur], agbar);
+    lbc::k_adj_gather<R><<<nblk, TPB, 0, stream>>>(box, agbar, aphibp, aqbp, ap, aq);
+    check_launch();
+    HIPCHECK(hipMemcpyAsync(ag, agnew, 19 * N * sizeof(R), hipMemcpyDeviceToDevice, stream));
+    double pv[2] = {0.0, 0.0};
+    HIPCHECK(hipMemcpyAsync(pv, sums, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHECK(hipStreamSynchronize(stream));
+    if (zeta_bar) *zeta_bar += pv[0];
+    if (q0_bar) *q0_bar += pv[1];
+    return stepno;
+  }
+  double seed_centre(double z_ref, void* adj) override {
+    double v[lbc::NCEN];
+    centre(v);
+    const double zc = v[2] / v[3];
+    lbc::k_seed_centre<R><<<nblk, TPB, 0, stream>>>(box, zc, z_ref, v[3], static_cast<R*>(adj));
+    check_launch();
+    HIPCHECK(hipStreamSynchronize(stream));
+    return (zc - z_ref) * (zc - z_ref);
+  }
 };
 
 }  // namespace
@@ -644,6 +725,29 @@ lb_status lb_set_state(lb_ctx* c, const void* dev_src, size_t bytes) {
     if (!dev_src) fail(LB_EINVAL, "null buffer");
     if (bytes != c->be->state_bytes()) fail(LB_ESTATE, "state buffer size mismatch");
     c->step = c->be->set_state(dev_src);
+  });
+}
+
+size_t lb_adjoint_bytes(const lb_ctx* c) { return (c && c->be) ? c->be->adjoint_bytes() : 0; }
+
+lb_status lb_adjoint_step(lb_ctx* c, const void* dev_state_t, size_t state_bytes, void* dev_adj, size_t adj_bytes,
+                          double* zeta_bar, double* q0_bar) {
+  return guarded([&] {
+    need_ctx(c);
+    if (!dev_state_t || !dev_adj) fail(LB_EINVAL, "null buffer");
+    if (state_bytes != c->be->state_bytes()) fail(LB_ESTATE, "state buffer size mismatch");
+    if (adj_bytes != c->be->adjoint_bytes()) fail(LB_ESTATE, "adjoint buffer size mismatch");
+    c->step = c->be->adjoint_step(dev_state_t, dev_adj, zeta_bar, q0_bar);
+  });
+}
+
+lb_status lb_adjoint_seed_centre(lb_ctx* c, double z_ref, void* dev_adj, size_t adj_bytes, double* loss) {
+  return guarded([&] {
+    need_ctx(c);
+    if (!dev_adj) fail(LB_EINVAL, "null buffer");
+    if (adj_bytes != c->be->adjoint_bytes()) fail(LB_ESTATE, "adjoint buffer size mismatch");
+    const double L = c->be->seed_centre(z_ref, dev_adj);
+    if (loss) *loss = L;
   });
 }
 

@@ -77,7 +77,7 @@ struct Local {
 };
 
 template <class R>
-__device__ __forceinline__ void local_thermo(const Params<R>& P, const Grad<R>& G, Local<R>& L) {
+__host__ __device__ __forceinline__ void local_thermo(const Params<R>& P, const Grad<R>& G, Local<R>& L) {
   const R xx = G.q[0], xy = G.q[1], xz = G.q[2], yy = G.q[3], yz = G.q[4], zz = -xx - yy;
   L.xx = xx; L.xy = xy; L.xz = xz; L.yy = yy; L.yz = yz; L.zz = zz;
   L.q2xx = xx * xx + xy * xy + xz * xz;
@@ -120,7 +120,7 @@ __device__ __forceinline__ void local_thermo(const Params<R>& P, const Grad<R>& 
 
 // Molecular field only (5 stored components).
 template <class R>
-__device__ __forceinline__ void h_site(const Params<R>& P, const Grad<R>& G, R h[5]) {
+__host__ __device__ __forceinline__ void h_site(const Params<R>& P, const Grad<R>& G, R h[5]) {
   Local<R> L;
   local_thermo(P, G, L);
 #pragma unroll
@@ -129,7 +129,7 @@ __device__ __forceinline__ void h_site(const Params<R>& P, const Grad<R>& G, R h
 
 // A:B for symmetric traceless tensors given by 5 components.
 template <class R>
-__device__ __forceinline__ R sdot(const R* A, const R* B) {
+__host__ __device__ __forceinline__ R sdot(const R* A, const R* B) {
   const R azz = -A[0] - A[3], bzz = -B[0] - B[3];
   return A[0] * B[0] + A[3] * B[3] + azz * bzz + R(2) * (A[1] * B[1] + A[2] * B[2] + A[4] * B[4]);
 }
@@ -137,7 +137,7 @@ __device__ __forceinline__ R sdot(const R* A, const R* B) {
 // Full stress sig[3*a + b] (a = force component, b = derivative index) and the
 // molecular field h (5 components) of one site.
 template <class R>
-__device__ __forceinline__ void sigma_site(const Params<R>& P, const Grad<R>& G, R sig[9], R h[5]) {
+__host__ __device__ __forceinline__ void sigma_site(const Params<R>& P, const Grad<R>& G, R sig[9], R h[5]) {
   Local<R> L;
   local_thermo(P, G, L);
   const R xx = L.xx, xy = L.xy, xz = L.xz, yy = L.yy, yz = L.yz, zz = L.zz;
@@ -205,7 +205,7 @@ __device__ __forceinline__ void sigma_site(const Params<R>& P, const Grad<R>& G,
 // Chemical potential mu = dF/dphi from phi, its laplacian, the anchoring
 // divergence divv = D0_a(Q_ab D0_b phi) and the stored Q components.
 template <class R>
-__device__ __forceinline__ R mu_site(const Params<R>& P, R phi, R lapphi, R divv, const R q[5]) {
+__host__ __device__ __forceinline__ R mu_site(const Params<R>& P, R phi, R lapphi, R divv, const R q[5]) {
   const R xx = q[0], xy = q[1], xz = q[2], yy = q[3], yz = q[4], zz = -xx - yy;
   const R q2xx = xx * xx + xy * xy + xz * xz;
   const R q2xy = xx * xy + xy * yy + xz * yz;
@@ -224,7 +224,7 @@ __device__ __forceinline__ R mu_site(const Params<R>& P, R phi, R lapphi, R divv
 // (Eq. (2)) as 5 stored components, from the velocity gradient W_ab = D0_b u_a:
 // S = A P + P A^T - 2 xi P tr(Q W), A = xi D + Om, P = Q + I/3, minus its trace/3.
 template <class R>
-__device__ __forceinline__ void corotation_site(R xi, const R q[5], const R W[3][3], R s5[5]) {
+__host__ __device__ __forceinline__ void corotation_site(R xi, const R q[5], const R W[3][3], R s5[5]) {
   const R xx = q[0], xy = q[1], xz = q[2], yy = q[3], yz = q[4], zz = -xx - yy;
   const R Pm[3][3] = {{xx + C3<R>::third, xy, xz}, {xy, yy + C3<R>::third, yz}, {xz, yz, zz + C3<R>::third}};
   const R Qm[3][3] = {{xx, xy, xz}, {xy, yy, yz}, {xz, yz, zz}};
@@ -258,7 +258,7 @@ __device__ __forceinline__ void corotation_site(R xi, const R q[5], const R W[3]
 // rho = rho0 + sum g, u = (sum c g + F/2)/rho; returns u.  Opposite pairs
 // (i, i+1) share the even part of g_eq and of the source.
 template <class R>
-__device__ __forceinline__ void collide_site(const Params<R>& P, R g[19], const R F[3], R u[3]) {
+__host__ __device__ __forceinline__ void collide_site(const Params<R>& P, R g[19], const R F[3], R u[3]) {
   R drho = g[0];
 #pragma unroll
   for (int i = 1; i < 19; ++i) drho += g[i];

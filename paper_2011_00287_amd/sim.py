@@ -167,6 +167,43 @@ class Sim:
     def set_state(self, buf):
         check(lib().lb_set_state(self._h, ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()))
 
+    # ------------------------------------------------------------------- adjoint
+    @property
+    def compute_dtype(self):
+        import torch
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    def adjoint_buffer(self):
+        """Zeroed device tensor holding (g_bar [19][N], q_bar [5][N], phi_bar [N])."""
+        import torch
+        nb = int(lib().lb_adjoint_bytes(self._h))
+        esz = 8 if self.precision == "fp64" else 4
+        return torch.zeros(nb // esz, dtype=self.compute_dtype, device="cuda")
+
+    def adjoint_parts(self, adj):
+        """Views (g_bar [19,nz,ny,nx], q_bar [5,...], phi_bar [...]) of an adjoint buffer."""
+        n = self.n_sites
+        return (adj[:19 * n].view((19,) + self.shape), adj[19 * n:24 * n].view((5,) + self.shape),
+                adj[24 * n:].view(self.shape))
+
+    def seed_centre(self, z_ref: float, adj) -> float:
+        """adj <- dL/d(state) of L = (z_c - z_ref)^2 at the current state; returns L."""
+        loss = ctypes.c_double()
+        check(lib().lb_adjoint_seed_centre(self._h, ctypes.c_double(z_ref), ctypes.c_void_p(adj.data_ptr()),
+                                           adj.numel() * adj.element_size(), ctypes.byref(loss)))
+        return loss.value
+
+    def adjoint_step(self, state, adj, zeta_bar: float = 0.0, q0_bar: float = 0.0):
+        """adj (adjoint at t+1) <- adjoint at t, given the forward state at t.
+
+        Returns the updated (zeta_bar, q0_bar) accumulators."""
+        zb = ctypes.c_double(zeta_bar)
+        qb = ctypes.c_double(q0_bar)
+        check(lib().lb_adjoint_step(self._h, ctypes.c_void_p(state.data_ptr()), state.numel() * state.element_size(),
+                                    ctypes.c_void_p(adj.data_ptr()), adj.numel() * adj.element_size(),
+                                    ctypes.byref(zb), ctypes.byref(qb)))
+        return zb.value, qb.value
+
     # ----------------------------------------------------------------- profiling
     def profile(self, nsteps: int):
         """{kernel name: average ms per launch} over nsteps steps (state advances)."""
