@@ -56,6 +56,40 @@ def time_precision(prec, p, phi, q5, steps, warmup, stream):
     return sim, dt
 
 
+def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream):
+    """(backward incl. segment recompute) / (plain forward) over the same steps."""
+    import torch
+    from paper_2011_00287_amd.autograd import backward_segments, run_segments
+    from paper_2011_00287_amd.sim import Sim
+    sim = Sim(p, phi, q5, precision=prec, stream=stream)
+    s0 = sim.get_state()
+    sim.step(3)
+    sim.set_state(s0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    t_fwd = time.perf_counter() - t0
+    sim.set_state(s0)
+    zc0 = float(sim.centre()[0][2])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ckpts = run_segments(sim, steps, checkpoint)
+    sim.sync()
+    t_fwd_ck = time.perf_counter() - t0
+    adj = sim.adjoint_buffer()
+    sim.seed_centre(zc0, adj)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    backward_segments(sim, ckpts, steps, checkpoint, adj)
+    sim.sync()
+    t_bwd = time.perf_counter() - t0
+    sim.close()
+    return {"steps": steps, "checkpoint": checkpoint, "precision": prec, "forward_ms": t_fwd * 1e3,
+            "forward_with_checkpoints_ms": t_fwd_ck * 1e3, "backward_ms": t_bwd * 1e3,
+            "adjoint_over_forward": t_bwd / t_fwd, "total_over_forward": (t_fwd_ck + t_bwd) / t_fwd}
+
+
 def cpu_baseline(workload: str, nsteps: int = 2):
     import torch
     from oracle import core
@@ -106,6 +140,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side", action="store_true", help="skip the FP64 / FP16S side timings")
     ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--adjoint-steps", type=int, default=50, help="0 = skip the adjoint timing")
+    ap.add_argument("--adjoint-checkpoint", type=int, default=10)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only time a device copy of this many MiB and exit")
     args = ap.parse_args()
@@ -154,6 +190,11 @@ def main():
                           "step_hbm_frac": n * ns / dt2 * step_bytes(prec) / (HBM_PEAK_GBS * 1e9)}
             print(f"# {prec}: {side[prec]['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
 
+    adjoint = None
+    if args.adjoint_steps > 0:
+        adjoint = time_adjoint(args.precision, p, phi, q5, args.adjoint_steps, args.adjoint_checkpoint, stream)
+        print(f"# adjoint/forward: {adjoint['adjoint_over_forward']:.2f}", file=sys.stderr, flush=True)
+
     line = {
         "metric": "coupled-step MLUPS at 128^3 FP32 vs FP64, % HBM peak; adjoint/forward time",
         "value": mlups,
@@ -176,6 +217,7 @@ def main():
                           "frac": mlups * 1e6 * step_bytes(args.precision) / (HBM_PEAK_GBS * 1e9)},
         "kernel_ms": prof,
         "side": side,
+        "adjoint": adjoint,
         "totals_after_run": {k: totals[k] for k in ("mass", "phi_total", "free_energy")},
     }
     if not args.no_cpu_baseline:

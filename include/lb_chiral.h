@@ -155,16 +155,28 @@ lb_status lb_set_state(lb_ctx* c, const void* dev_src, size_t bytes);
  * ------------------------------------------------------------------------- */
 size_t lb_adjoint_bytes(const lb_ctx* c);
 
-/* One reverse step.  dev_state_t is the forward state at time t in the
- * lb_get_state format (state_bytes = lb_state_bytes()).  On entry dev_adj
- * holds the adjoint of the state at t+1; on return the adjoint of the state at
- * t (the vector-Jacobian product of one coupled step with the context's
- * current parameters).  *zeta_bar and *q0_bar (may be NULL) are incremented by
- * the step's contribution to dL/dzeta and dL/dq0, summed in float64 on the
- * device.  The context's current state becomes the state at t.
- * Errors: LB_ESTATE on a buffer size mismatch, LB_EDEVICE.  Synchronises. */
-lb_status lb_adjoint_step(lb_ctx* c, const void* dev_state_t, size_t state_bytes, void* dev_adj,
-                          size_t adj_bytes, double* zeta_bar, double* q0_bar);
+/* Size of a step record: u [3][N] and F [3][N] (the velocity with F/2 and the
+ * force of Eq. (3)) of one time t, in the context's arithmetic type. */
+size_t lb_record_bytes(const lb_ctx* c);
+
+/* One forward step from the state buffer dev_state_in (time t, lb_get_state
+ * format) into dev_state_out (time t+1, a different buffer), writing u and F
+ * of time t into dev_rec_out.  The context's own state is not touched.  This is
+ * the replay of a checkpoint segment before its reverse steps. */
+lb_status lb_step_record(lb_ctx* c, const void* dev_state_in, void* dev_state_out, void* dev_rec_out,
+                         size_t state_bytes, size_t rec_bytes);
+
+/* One reverse step: dev_adj_out <- (d step / d state_t)^T dev_adj_in, the
+ * vector-Jacobian product of one coupled step at the forward state dev_state_t
+ * with the context's current parameters.  dev_rec_t is that step's record
+ * from lb_step_record (NULL: u and F are recomputed).  *zeta_bar and *q0_bar
+ * (may be NULL) are incremented by the step's contribution to dL/dzeta and
+ * dL/dq0, summed in float64 on the device.  adj_in and adj_out must differ.
+ * Errors: LB_ESTATE on a buffer size mismatch, LB_EINVAL, LB_EDEVICE.
+ * Synchronises. */
+lb_status lb_adjoint_step(lb_ctx* c, const void* dev_state_t, size_t state_bytes, const void* dev_rec_t,
+                          size_t rec_bytes, const void* dev_adj_in, void* dev_adj_out, size_t adj_bytes,
+                          double* zeta_bar, double* q0_bar);
 
 /* Seed of the droplet-displacement loss L = (z_c - z_ref)^2 with z_c the
  * phi-weighted linear centre along z of the current state (the loss of a

@@ -30,22 +30,32 @@ def run_segments(sim: Sim, steps: int, checkpoint: int):
 
 
 def backward_segments(sim: Sim, ckpts, steps: int, checkpoint: int, adj):
-    """Reverse pass over the checkpointed segments; returns (zeta_bar, q0_bar)."""
+    """Reverse pass over the checkpointed segments.
+
+    adj holds the adjoint of the final state on entry and the adjoint of the
+    initial state on return.  Each segment is replayed from its checkpoint with
+    recording steps (state buffers and u, F records), then reversed step by
+    step.  Returns (zeta_bar, q0_bar)."""
     zb = qb = 0.0
-    nseg = len(ckpts)
-    states = [None] * checkpoint
-    for s in reversed(range(nseg)):
+    states = [None] * (checkpoint + 1)
+    recs = [None] * checkpoint
+    other = torch.empty_like(adj)
+    cur, nxt = adj, other
+    for s in reversed(range(len(ckpts))):
         t0 = s * checkpoint
         n = min(checkpoint, steps - t0)
-        sim.set_state(ckpts[s])
         states[0] = ckpts[s]
-        for j in range(1, n):
-            sim.step(1)
-            if states[j] is None:
-                states[j] = torch.empty_like(ckpts[s])
-            sim.get_state(states[j])
+        for j in range(n):
+            if states[j + 1] is None:
+                states[j + 1] = torch.empty_like(ckpts[s])
+            if recs[j] is None:
+                recs[j] = sim.record_buffer()
+            sim.step_record(states[j], states[j + 1], recs[j])
         for j in reversed(range(n)):
-            zb, qb = sim.adjoint_step(states[j], adj, zb, qb)
+            zb, qb = sim.adjoint_step(states[j], cur, nxt, rec=recs[j], zeta_bar=zb, q0_bar=qb)
+            cur, nxt = nxt, cur
+    if cur is not adj:
+        adj.copy_(cur)
     return zb, qb
 
 

@@ -7,13 +7,13 @@
 // stencils used: (D0)^T = -D0, (lap)^T = lap, and the transpose of the pull
 // stream g'_i(x) = g*_i(x - c_i) is the push gs_bar_i(x) = g'_bar_i(x + c_i).
 //
-// Order (each a launch; the forward quantities of time t are recomputed by
-// k_thermo and k_fwd_force first):
+// Order (each a launch; the forward u and F of time t come from a recording
+// step, or are recomputed by k_thermo and k_fwd_force):
 //   k_adj_order   : phi, Q updates (Eqs. (1), (2))  -> mu_bar, W_bar, partial u_bar, Q_bar, phi_bar, H_bar
 //   k_adj_collide : collision + stream (Eqs. (6)-(8), (10)-(11)) -> g_bar(t), F_bar
 //   k_adj_stress  : stress, H, mu (Eqs. (3)-(5)) -> gradient-data adjoints, zeta / q0 partials
-//   k_adj_divv    : the anchoring divergence D0_a(Q_ab D0_b phi) of mu
-//   k_adj_gather  : stencil transposes of the gradient data -> Q_bar(t), phi_bar(t)
+//   k_adj_gather  : stencil transposes of the gradient data, including the
+//                   anchoring divergence D0_a(Q_ab D0_b phi) of mu -> Q_bar(t), phi_bar(t)
 #pragma once
 #include "adjoint.hpp"
 #include "kernels_reduce.hpp"
@@ -218,45 +218,20 @@ __global__ void __launch_bounds__(256) k_adj_stress(Box b, Params<R> P, const FS
   block_reduce_store<2>(v, partial + size_t(blockIdx.x) * 2);
 }
 
-// Reverse of divv = sum_a D0_a v_a, v_a = Q_ab D0_b phi: adds to the dphi and
-// q adjoints of the gradient data (in place; reads divv_bar at neighbours).
+// Stencil transposes of the gradient data; writes Q_bar(t), phi_bar(t).
+// Includes the reverse of divv = sum_a D0_a v_a, v_a = Q_ab D0_b phi:
+// v_bar_a = -D0_a divv_bar, which adds v_bar_a D0_b phi to Q_bar_ab and
+// Q_ab v_bar_a to the adjoint of D0_b phi (gathered at the neighbours).
 template <class R, class FS>
-__global__ void __launch_bounds__(256) k_adj_divv(Box b, const FS* __restrict__ phi, const FS* __restrict__ q,
-                                                  R* __restrict__ gbar) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= b.N) return;
-  int x, y, z;
-  coords(b, s, x, y, z);
-  const size_t N = b.N;
-  const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
-  const R* divvb = gbar + size_t(GB_DIVV) * N;
-  R vb[3], dp[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int sp = sidx(b, x + off[a][0], y + off[a][1], z + off[a][2]);
-    const int sm = sidx(b, x - off[a][0], y - off[a][1], z - off[a][2]);
-    vb[a] = -R(0.5) * (divvb[sp] - divvb[sm]);
-    dp[a] = R(0.5) * (R(phi[sp]) - R(phi[sm]));
-  }
-  const R xx = R(q[s]), xy = R(q[N + s]), xz = R(q[2 * N + s]), yy = R(q[3 * N + s]), yz = R(q[4 * N + s]);
-  const R Qm[3][3] = {{xx, xy, xz}, {xy, yy, yz}, {xz, yz, -xx - yy}};
-  R Qb[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) Qb[a][c] = vb[a] * dp[c];
-  R qb5[5] = {R(0), R(0), R(0), R(0), R(0)};
-  full_to_stored(Qb, qb5);
-#pragma unroll
-  for (int k = 0; k < 5; ++k) gbar[size_t(GB_Q + k) * N + s] += qb5[k];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-    gbar[size_t(GB_DPHI + c) * N + s] += Qm[0][c] * vb[0] + Qm[1][c] * vb[1] + Qm[2][c] * vb[2];
+__device__ __forceinline__ void vbar_at(const Box& b, const R* __restrict__ divvb, int x, int y, int z, R vb[3]) {
+  vb[0] = -R(0.5) * (divvb[sidx(b, x + 1, y, z)] - divvb[sidx(b, x - 1, y, z)]);
+  vb[1] = -R(0.5) * (divvb[sidx(b, x, y + 1, z)] - divvb[sidx(b, x, y - 1, z)]);
+  vb[2] = -R(0.5) * (divvb[sidx(b, x, y, z + 1)] - divvb[sidx(b, x, y, z - 1)]);
 }
 
-// Stencil transposes of the gradient data; writes Q_bar(t), phi_bar(t).
-template <class R>
-__global__ void __launch_bounds__(256) k_adj_gather(Box b, const R* __restrict__ gbar, const R* __restrict__ phibp,
+template <class R, class FS>
+__global__ void __launch_bounds__(256) k_adj_gather(Box b, const FS* __restrict__ phi, const FS* __restrict__ q,
+                                                    const R* __restrict__ gbar, const R* __restrict__ phibp,
                                                     const R* __restrict__ qbp, R* __restrict__ adj_phi,
                                                     R* __restrict__ adj_q) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -265,16 +240,42 @@ __global__ void __launch_bounds__(256) k_adj_gather(Box b, const R* __restrict__
   coords(b, s, x, y, z);
   const size_t N = b.N;
   const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  const R* divvb = gbar + size_t(GB_DIVV) * N;
   R pb = phibp[s] + gbar[size_t(GB_PHI) * N + s];
   R qb[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) qb[k] = qbp[k * N + s] + gbar[size_t(GB_Q + k) * N + s];
+  // anchoring divergence, local part: Q_bar_ab += v_bar_a D0_b phi
+  {
+    R vb[3], dp[3];
+    vbar_at<R, FS>(b, divvb, x, y, z, vb);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      dp[c] = R(0.5) * (R(phi[sidx(b, x + off[c][0], y + off[c][1], z + off[c][2])]) -
+                        R(phi[sidx(b, x - off[c][0], y - off[c][1], z - off[c][2])]));
+    R Qb[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Qb[a][c] = vb[a] * dp[c];
+    full_to_stored(Qb, qb);
+  }
   R lp = R(0), lq[5] = {R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
   for (int g = 0; g < 3; ++g) {
-    const int sp = sidx(b, x + off[g][0], y + off[g][1], z + off[g][2]);
-    const int sm = sidx(b, x - off[g][0], y - off[g][1], z - off[g][2]);
-    pb -= R(0.5) * (gbar[size_t(GB_DPHI + g) * N + sp] - gbar[size_t(GB_DPHI + g) * N + sm]);
+    const int xp = x + off[g][0], yp = y + off[g][1], zp = z + off[g][2];
+    const int xm = x - off[g][0], ym = y - off[g][1], zm = z - off[g][2];
+    const int sp = sidx(b, xp, yp, zp), sm = sidx(b, xm, ym, zm);
+    // adjoint of D0_g phi at the neighbours: gradient-data part + anchoring part Q_ag v_bar_a
+    R vp[3], vm[3];
+    vbar_at<R, FS>(b, divvb, xp, yp, zp, vp);
+    vbar_at<R, FS>(b, divvb, xm, ym, zm, vm);
+    R qrp[3], qrm[3];  // column g of Q at the neighbours (Q symmetric)
+    qrow<R>(q, N, sp, g, qrp);
+    qrow<R>(q, N, sm, g, qrm);
+    const R dpp = gbar[size_t(GB_DPHI + g) * N + sp] + (qrp[0] * vp[0] + qrp[1] * vp[1] + qrp[2] * vp[2]);
+    const R dpm = gbar[size_t(GB_DPHI + g) * N + sm] + (qrm[0] * vm[0] + qrm[1] * vm[1] + qrm[2] * vm[2]);
+    pb -= R(0.5) * (dpp - dpm);
     lp += gbar[size_t(GB_LAPPHI) * N + sp] + gbar[size_t(GB_LAPPHI) * N + sm];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
@@ -286,6 +287,11 @@ __global__ void __launch_bounds__(256) k_adj_gather(Box b, const R* __restrict__
   adj_phi[s] = pb;
 #pragma unroll
   for (int k = 0; k < 5; ++k) adj_q[k * N + s] = qb[k] + lq[k] - R(6) * gbar[size_t(GB_LAPQ + k) * N + s];
+}
+
+// out = in + 1 for the step counter of a recorded state (one thread, vector memory).
+__global__ void k_step_count(const int64_t* __restrict__ in, int64_t* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = in[0] + 1;
 }
 
 // Seed of the displacement loss L = (z_c - z_ref)^2, z_c = sum phi z / sum phi:

@@ -2,7 +2,8 @@
 //
 // k_lb_fused  : stress, force, pull-stream and Guo-forced BGK collision
 //               (Eqs. (3)-(4), (6)-(8), (10)-(11)) plus mu (Eq. (1));
-//               writes the post-collision populations, u and mu.
+//               writes the post-collision populations, u and mu (and the
+//               force F when a recording step asks for it).
 // k_order_fused: molecular field H (Eq. (5)), Beris-Edwards update of Q
 //               (Eq. (2)) and Cahn-Hilliard update of phi (Eq. (1)).
 //
@@ -47,7 +48,8 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
 template <class R, class GS, class FS, int TX, int TY, int MINW>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(MINW)))
 k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ Bin, GS* __restrict__ Bout,
-           const FS* __restrict__ phi, const FS* __restrict__ q, R* __restrict__ u_out, R* __restrict__ mu_out) {
+           const FS* __restrict__ phi, const FS* __restrict__ q, R* __restrict__ u_out, R* __restrict__ mu_out,
+           R* __restrict__ F_out) {
   constexpr int NT = TX * TY;
   constexpr int AX = TX + 4, AY = TY + 4, NA = AX * AY;  // phi / Q slots (halo 2)
   constexpr int SX = TX + 2, SY = TY + 2, NS = SX * SY;  // stress slots (halo 1)
@@ -270,6 +272,10 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
       for (int i = 0; i < 19; ++i) GPolO<GS>::template st<R>(Bout + size_t(i) * N, sg, i, g[i]);
 #pragma unroll
       for (int a = 0; a < 3; ++a) sto(u_out + size_t(a) * N, sr, u[a]);
+      if (F_out) {  // recording step (adjoint replay): keep the force of this plane
+#pragma unroll
+        for (int a = 0; a < 3; ++a) sto(F_out + size_t(a) * N, sr, F[a]);
+      }
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {

@@ -140,7 +140,10 @@ struct Backend {
   virtual void get_state(void* dst, int64_t step) = 0;
   virtual int64_t set_state(const void* src) = 0;
   virtual size_t adjoint_bytes() const = 0;
-  virtual int64_t adjoint_step(const void* state, void* adj, double* zeta_bar, double* q0_bar) = 0;
+  virtual size_t record_bytes() const = 0;
+  virtual void step_record(const void* state_in, void* state_out, void* rec_out) = 0;
+  virtual void adjoint_step(const void* state, const void* rec, const void* adj_in, void* adj_out,
+                            double* zeta_bar, double* q0_bar) = 0;
   virtual double seed_centre(double z_ref, void* adj) = 0;
 };
 
@@ -172,7 +175,6 @@ struct BackendT final : Backend {
   R* ahb = nullptr;
   R* aFb = nullptr;
   R* agbar = nullptr;
-  R* agnew = nullptr;
   bool site_path = false;  // three site-parallel kernels instead of the fused pair
   int tz_lb = 8, tz_or = 8;
   int lb_tile = 0, or_tile = 0;
@@ -239,7 +241,7 @@ struct BackendT final : Backend {
     dfree(sums);
     mu = H = sig = u = nullptr;
     partial = sums = nullptr;
-    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &ahb, &aFb, &agbar, &agnew};
+    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &ahb, &aFb, &agbar};
     for (R** a : adj) {
       dfree(*a);
       *a = nullptr;
@@ -352,33 +354,62 @@ struct BackendT final : Backend {
       }
       return;
     }
+    const Io io = cur_io();
     if (k == 0) {
       switch (lb_tile) {
-        case 0: launch_lb<32, 8, 2>(); break;
-        case 1: launch_lb<32, 16, (sizeof(R) == 4 ? 2 : 1)>(); break;
-        case 2: launch_lb<64, 4, 2>(); break;
-        case 3: launch_lb<16, 16, 2>(); break;
-        default: launch_lb<16, 8, 1>(); break;
+        case 0: launch_lb<32, 8, 2>(io); break;
+        case 1: launch_lb<32, 16, (sizeof(R) == 4 ? 2 : 1)>(io); break;
+        case 2: launch_lb<64, 4, 2>(io); break;
+        case 3: launch_lb<16, 16, 2>(io); break;
+        default: launch_lb<16, 8, 1>(io); break;
       }
     } else {
       switch (or_tile) {
-        case 0: launch_or<32, 8, 2>(); break;
-        case 1: launch_or<64, 4, 2>(); break;
-        case 2: launch_or<32, 16, 2>(); break;
-        default: launch_or<64, 8, 2>(); break;
+        case 0: launch_or<32, 8, 2>(io); break;
+        case 1: launch_or<64, 4, 2>(io); break;
+        case 2: launch_or<32, 16, 2>(io); break;
+        default: launch_or<64, 8, 2>(io); break;
       }
       cur = nx;
     }
   }
+  // buffers of one step: in / out state, u (and optionally F) output
+  struct Io {
+    const GS* Bi;
+    GS* Bo;
+    const FS* phi_i;
+    const FS* q_i;
+    FS* phi_o;
+    FS* q_o;
+    R* u;
+    R* F;
+  };
+  Io cur_io() { return Io{B[cur], B[cur ^ 1], Ph[cur], Q[cur], Ph[cur ^ 1], Q[cur ^ 1], u, nullptr}; }
   template <int TX, int TY, int MINW>
-  void launch_lb() {
+  void launch_lb(const Io& io) {
     lbc::k_lb_fused<R, GS, FS, TX, TY, MINW><<<lb_blocks, TX * TY, 0, stream>>>(
-        box, P, tz_lb, lb_ntx, lb_nty, B[cur], B[cur ^ 1], Ph[cur], Q[cur], u, mu);
+        box, P, tz_lb, lb_ntx, lb_nty, io.Bi, io.Bo, io.phi_i, io.q_i, io.u, mu, io.F);
   }
   template <int TX, int TY, int MINW>
-  void launch_or() {
+  void launch_or(const Io& io) {
     lbc::k_order_fused<R, FS, TX, TY, MINW><<<or_blocks, TX * TY, 0, stream>>>(
-        box, P, tz_or, or_ntx, or_nty, Ph[cur], Q[cur], u, mu, Ph[cur ^ 1], Q[cur ^ 1]);
+        box, P, tz_or, or_ntx, or_nty, io.phi_i, io.q_i, io.u, mu, io.phi_o, io.q_o);
+  }
+  // the fused pair on explicit buffers
+  void fused_step(const Io& io) {
+    switch (lb_tile) {
+      case 0: launch_lb<32, 8, 2>(io); break;
+      case 1: launch_lb<32, 16, (sizeof(R) == 4 ? 2 : 1)>(io); break;
+      case 2: launch_lb<64, 4, 2>(io); break;
+      case 3: launch_lb<16, 16, 2>(io); break;
+      default: launch_lb<16, 8, 1>(io); break;
+    }
+    switch (or_tile) {
+      case 0: launch_or<32, 8, 2>(io); break;
+      case 1: launch_or<64, 4, 2>(io); break;
+      case 2: launch_or<32, 16, 2>(io); break;
+      default: launch_or<64, 8, 2>(io); break;
+    }
   }
   void step(int n) override {
     const int nk = nkernels();
@@ -516,9 +547,8 @@ struct BackendT final : Backend {
       ahb = dalloc<R>(5 * N);
       aFb = dalloc<R>(3 * N);
       agbar = dalloc<R>(size_t(lbc::NGB) * N);
-      agnew = dalloc<R>(19 * N);
     } catch (...) {
-      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &ahb, &aFb, &agbar, &agnew};
+      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &ahb, &aFb, &agbar};
       for (R** a : adj) {
         dfree(*a);
         *a = nullptr;
@@ -526,31 +556,73 @@ struct BackendT final : Backend {
       throw;
     }
   }
-  int64_t adjoint_step(const void* state, void* adj, double* zeta_bar, double* q0_bar) override {
-    ensure_adjoint();
-    const int64_t stepno = set_state(state);
-    R* ag = static_cast<R*>(adj);
-    R* aq = ag + 19 * N;
-    R* ap = ag + 24 * N;
-    // forward quantities of time t
-    lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], mu, H, sig);
-    lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, B[cur], sig, aF, u);
-    // reverse
-    lbc::k_adj_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], u, ap, aq, amub, aWb, aubp, aqbp,
-                                                       aphibp, ahb);
-    lbc::k_adj_collide<R, GS><<<nblk, TPB, 0, stream>>>(box, P, B[cur], aF, aWb, aubp, ag, agnew, aFb);
-    lbc::k_adj_stress<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], aFb, ahb, amub, agbar, partial);
-    lbc::k_final_sum<<<1, TPB, 0, stream>>>(partial, int(nblk), 2, sums);
-    lbc::k_adj_divv<R, FS><<<nblk, TPB, 0, stream>>>(box, Ph[cur], Q[cur], agbar);
-    lbc::k_adj_gather<R><<<nblk, TPB, 0, stream>>>(box, agbar, aphibp, aqbp, ap, aq);
+  // record buffer: u [3][N] and F [3][N] of the step that leaves the state
+  size_t record_bytes() const override { return 6 * N * sizeof(R); }
+  struct StateView {
+    const GS* B;
+    const FS* q;
+    const FS* phi;
+    const int64_t* step;
+  };
+  StateView view(const void* st) const {
+    const char* c = static_cast<const char*>(st);
+    return StateView{reinterpret_cast<const GS*>(c), reinterpret_cast<const FS*>(c + off_q()),
+                     reinterpret_cast<const FS*>(c + off_phi()), reinterpret_cast<const int64_t*>(c + off_step())};
+  }
+  // One forward step from a state buffer into another, recording u and F of
+  // the input time (the replay of a checkpoint segment for the adjoint).
+  void step_record(const void* state_in, void* state_out, void* rec_out) override {
+    const StateView vi = view(state_in);
+    char* co = static_cast<char*>(state_out);
+    GS* Bo = reinterpret_cast<GS*>(co);
+    FS* qo = reinterpret_cast<FS*>(co + off_q());
+    FS* po = reinterpret_cast<FS*>(co + off_phi());
+    R* ru = static_cast<R*>(rec_out);
+    R* rF = ru + 3 * N;
+    if (site_path) {
+      lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, vi.phi, vi.q, mu, H, sig);
+      lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, vi.B, sig, rF, ru);
+      lbc::k_collide<R, GS><<<nblk, TPB, 0, stream>>>(box, P, vi.B, Bo, sig, ru);
+      lbc::k_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, vi.phi, vi.q, ru, H, mu, po, qo);
+    } else {
+      fused_step(Io{vi.B, Bo, vi.phi, vi.q, po, qo, ru, rF});
+    }
+    lbc::k_step_count<<<1, 64, 0, stream>>>(vi.step, reinterpret_cast<int64_t*>(co + off_step()));
     check_launch();
-    HIPCHECK(hipMemcpyAsync(ag, agnew, 19 * N * sizeof(R), hipMemcpyDeviceToDevice, stream));
+  }
+  void adjoint_step(const void* state, const void* rec, const void* adj_in, void* adj_out, double* zeta_bar,
+                    double* q0_bar) override {
+    ensure_adjoint();
+    const StateView v = view(state);
+    const R* gi = static_cast<const R*>(adj_in);
+    const R* qi = gi + 19 * N;
+    const R* pi = gi + 24 * N;
+    R* go = static_cast<R*>(adj_out);
+    R* qo = go + 19 * N;
+    R* po = go + 24 * N;
+    const R* uu;
+    const R* FF;
+    if (rec) {
+      uu = static_cast<const R*>(rec);
+      FF = uu + 3 * N;
+    } else {  // recompute u and F of time t
+      lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, mu, H, sig);
+      lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, v.B, sig, aF, u);
+      uu = u;
+      FF = aF;
+    }
+    lbc::k_adj_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp,
+                                                       ahb);
+    lbc::k_adj_collide<R, GS><<<nblk, TPB, 0, stream>>>(box, P, v.B, FF, aWb, aubp, gi, go, aFb);
+    lbc::k_adj_stress<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, aFb, ahb, amub, agbar, partial);
+    lbc::k_final_sum<<<1, TPB, 0, stream>>>(partial, int(nblk), 2, sums);
+    lbc::k_adj_gather<R, FS><<<nblk, TPB, 0, stream>>>(box, v.phi, v.q, agbar, aphibp, aqbp, po, qo);
+    check_launch();
     double pv[2] = {0.0, 0.0};
     HIPCHECK(hipMemcpyAsync(pv, sums, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
     HIPCHECK(hipStreamSynchronize(stream));
     if (zeta_bar) *zeta_bar += pv[0];
     if (q0_bar) *q0_bar += pv[1];
-    return stepno;
   }
   double seed_centre(double z_ref, void* adj) override {
     double v[lbc::NCEN];
@@ -730,14 +802,31 @@ lb_status lb_set_state(lb_ctx* c, const void* dev_src, size_t bytes) {
 
 size_t lb_adjoint_bytes(const lb_ctx* c) { return (c && c->be) ? c->be->adjoint_bytes() : 0; }
 
-lb_status lb_adjoint_step(lb_ctx* c, const void* dev_state_t, size_t state_bytes, void* dev_adj, size_t adj_bytes,
+size_t lb_record_bytes(const lb_ctx* c) { return (c && c->be) ? c->be->record_bytes() : 0; }
+
+lb_status lb_step_record(lb_ctx* c, const void* dev_state_in, void* dev_state_out, void* dev_rec_out,
+                         size_t state_bytes, size_t rec_bytes) {
+  return guarded([&] {
+    need_ctx(c);
+    if (!dev_state_in || !dev_state_out || !dev_rec_out) fail(LB_EINVAL, "null buffer");
+    if (dev_state_in == dev_state_out) fail(LB_EINVAL, "state_in and state_out must differ");
+    if (state_bytes != c->be->state_bytes()) fail(LB_ESTATE, "state buffer size mismatch");
+    if (rec_bytes != c->be->record_bytes()) fail(LB_ESTATE, "record buffer size mismatch");
+    c->be->step_record(dev_state_in, dev_state_out, dev_rec_out);
+  });
+}
+
+lb_status lb_adjoint_step(lb_ctx* c, const void* dev_state_t, size_t state_bytes, const void* dev_rec_t,
+                          size_t rec_bytes, const void* dev_adj_in, void* dev_adj_out, size_t adj_bytes,
                           double* zeta_bar, double* q0_bar) {
   return guarded([&] {
     need_ctx(c);
-    if (!dev_state_t || !dev_adj) fail(LB_EINVAL, "null buffer");
+    if (!dev_state_t || !dev_adj_in || !dev_adj_out) fail(LB_EINVAL, "null buffer");
+    if (dev_adj_in == dev_adj_out) fail(LB_EINVAL, "adj_in and adj_out must differ");
     if (state_bytes != c->be->state_bytes()) fail(LB_ESTATE, "state buffer size mismatch");
+    if (dev_rec_t && rec_bytes != c->be->record_bytes()) fail(LB_ESTATE, "record buffer size mismatch");
     if (adj_bytes != c->be->adjoint_bytes()) fail(LB_ESTATE, "adjoint buffer size mismatch");
-    c->step = c->be->adjoint_step(dev_state_t, dev_adj, zeta_bar, q0_bar);
+    c->be->adjoint_step(dev_state_t, dev_rec_t, dev_adj_in, dev_adj_out, zeta_bar, q0_bar);
   });
 }
 

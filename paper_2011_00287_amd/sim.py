@@ -193,14 +193,30 @@ class Sim:
                                            adj.numel() * adj.element_size(), ctypes.byref(loss)))
         return loss.value
 
-    def adjoint_step(self, state, adj, zeta_bar: float = 0.0, q0_bar: float = 0.0):
-        """adj (adjoint at t+1) <- adjoint at t, given the forward state at t.
+    def record_buffer(self):
+        """Device tensor for one step record (u [3][N], F [3][N])."""
+        import torch
+        nb = int(lib().lb_record_bytes(self._h))
+        esz = 8 if self.precision == "fp64" else 4
+        return torch.empty(nb // esz, dtype=self.compute_dtype, device="cuda")
 
-        Returns the updated (zeta_bar, q0_bar) accumulators."""
+    def step_record(self, state_in, state_out, rec_out):
+        """state_out <- one step of state_in; rec_out <- (u, F) of state_in's time."""
+        check(lib().lb_step_record(self._h, ctypes.c_void_p(state_in.data_ptr()),
+                                   ctypes.c_void_p(state_out.data_ptr()), ctypes.c_void_p(rec_out.data_ptr()),
+                                   state_in.numel() * state_in.element_size(),
+                                   rec_out.numel() * rec_out.element_size()))
+
+    def adjoint_step(self, state, adj_in, adj_out, rec=None, zeta_bar: float = 0.0, q0_bar: float = 0.0):
+        """adj_out <- adjoint at t from adj_in (adjoint at t+1), given the forward state at t
+        (and its step record, or None to recompute).  Returns the updated (zeta_bar, q0_bar)."""
         zb = ctypes.c_double(zeta_bar)
         qb = ctypes.c_double(q0_bar)
+        recp = ctypes.c_void_p(rec.data_ptr()) if rec is not None else None
+        recb = rec.numel() * rec.element_size() if rec is not None else 0
         check(lib().lb_adjoint_step(self._h, ctypes.c_void_p(state.data_ptr()), state.numel() * state.element_size(),
-                                    ctypes.c_void_p(adj.data_ptr()), adj.numel() * adj.element_size(),
+                                    recp, recb, ctypes.c_void_p(adj_in.data_ptr()),
+                                    ctypes.c_void_p(adj_out.data_ptr()), adj_in.numel() * adj_in.element_size(),
                                     ctypes.byref(zb), ctypes.byref(qb)))
         return zb.value, qb.value
 
