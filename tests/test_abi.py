@@ -82,3 +82,19 @@ def test_invalid_params_rejected_before_any_device_work():
     with pytest.raises(_lib.LbError) as e:
         sim.Sim(dict(p, zeta=float("nan")), phi, q5)
     assert e.value.status == _lib.LB_EINVAL
+
+
+def test_oversize_box_rejected_before_allocation():
+    """A box above 2^29 sites is refused with LB_ENOMEM during validation."""
+    import numpy as np
+    from paper_2011_00287_amd import _lib, inputs, sim
+    p = dict(inputs.BASE_PARAMS)
+    lp = sim.make_params(p, (1024, 1024, 1024), "fp32")
+    import ctypes
+    h = ctypes.c_void_p()
+    phi = np.zeros(1)
+    q5 = np.zeros(5)
+    st = _lib.lib().lb_init(ctypes.byref(lp), phi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                            q5.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, None, ctypes.byref(h))
+    assert st == _lib.LB_ENOMEM
+    assert not h.value
