@@ -38,6 +38,29 @@ GS_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 2}
 FS_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 4}
 
 
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources; traffic counters are valid only for the source they were taken on."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2011_00287_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str, prec: str):
+    """HBM bytes per launch from the committed counter summary, if it matches the current source."""
+    f = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{prec}.json")
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
 def step_bytes(prec: str) -> int:
     return 38 * GS_BYTES[prec] + 12 * FS_BYTES[prec]
 
@@ -109,25 +132,27 @@ def cpu_baseline(workload: str, nsteps: int = 2):
 
 
 def copy_calibration(nbytes: int, reps: int):
-    """Device-to-device copy of a known size: achievable HBM bandwidth and the
-    reference for scaling hardware byte counters."""
+    """Device-to-device copies of a known size: achievable HBM bandwidth and the
+    reference for scaling hardware byte counters.  Two kernels: the runtime's
+    copy (copy_) and an elementwise multiply (reads n*4 bytes, writes n*4)."""
     import torch
     n = nbytes // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    line = {"metric": "device copy bandwidth", "value": 2 * n * 4 / (ms * 1e-3) / 1e9, "unit": "GB/s",
-            "bytes_read_per_launch": n * 4, "bytes_written_per_launch": n * 4, "ms_per_launch": ms,
-            "reps": reps, "peak": HBM_PEAK_GBS}
-    print(json.dumps(line), flush=True)
+    for name, fn in (("copy", lambda: dst.copy_(src)), ("mul", lambda: torch.mul(src, 1.0, out=dst))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        line = {"metric": f"device {name} bandwidth", "value": 2 * n * 4 / (ms * 1e-3) / 1e9, "unit": "GB/s",
+                "bytes_read_per_launch": n * 4, "bytes_written_per_launch": n * 4, "ms_per_launch": ms,
+                "reps": reps, "peak": HBM_PEAK_GBS}
+        print(json.dumps(line), flush=True)
 
 
 def main():
@@ -211,11 +236,13 @@ def main():
         "config": {"workload": args.workload, "box": list(phi.shape[::-1]), "droplet_radius": w["R"],
                    "q0": w["q0"], "zeta": w["zeta"], "precision": args.precision, "lattice": "D3Q19"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom, args.workload, args.precision), "kernel": dom,
                      "kernel_ms": prof[dom], "algorithmic_bytes_per_launch": algo_bytes},
         "step_roofline": {"bytes_per_site": step_bytes(args.precision),
                           "frac": mlups * 1e6 * step_bytes(args.precision) / (HBM_PEAK_GBS * 1e9)},
         "kernel_ms": prof,
+        "kernel_source_hash": kernel_source_hash(),
         "side": side,
         "adjoint": adjoint,
         "totals_after_run": {k: totals[k] for k in ("mass", "phi_total", "free_energy")},
