@@ -14,7 +14,7 @@ Per-field error: ||X - X64||_2 / ||X64||_2 and max|X - X64| / max|X64| for
 X in rho - rho0, u, phi, Q.  Droplet velocity: displacement of the
 circular-mean centre over the last 1000 steps / 1000.  The FP64 GPU path is
 the reference (it matches the FP64 oracle to 1e-12 per field on the 16^3
-droplet over 100 steps and on 64^3 over 50 steps).
+droplet over 100 steps and on 64^3 over 30 steps).
 """
 from __future__ import annotations
 
