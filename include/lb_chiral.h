@@ -169,11 +169,16 @@ lb_status lb_step_record(lb_ctx* c, const void* dev_state_in, void* dev_state_ou
 /* One reverse step: dev_adj_out <- (d step / d state_t)^T dev_adj_in, the
  * vector-Jacobian product of one coupled step at the forward state dev_state_t
  * with the context's current parameters.  dev_rec_t is that step's record
- * from lb_step_record (NULL: u and F are recomputed).  *zeta_bar and *q0_bar
- * (may be NULL) are incremented by the step's contribution to dL/dzeta and
- * dL/dq0, summed in float64 on the device.  adj_in and adj_out must differ.
- * Errors: LB_ESTATE on a buffer size mismatch, LB_EINVAL, LB_EDEVICE.
- * Synchronises. */
+ * from lb_step_record (NULL: u and F are recomputed).  adj_in and adj_out
+ * must differ.
+ * The step's contributions to dL/dzeta and dL/dq0 are summed in float64 on
+ * the device and kept there across calls.  When zeta_bar or q0_bar is
+ * non-NULL, every contribution kept since the last such call (this one's
+ * included) is added to *zeta_bar and *q0_bar (a NULL one is dropped), the
+ * device sums are cleared, and the call synchronises the stream.  With both
+ * NULL the call only enqueues work, so a reverse sweep passes pointers on its
+ * last step only.
+ * Errors: LB_ESTATE on a buffer size mismatch, LB_EINVAL, LB_EDEVICE. */
 lb_status lb_adjoint_step(lb_ctx* c, const void* dev_state_t, size_t state_bytes, const void* dev_rec_t,
                           size_t rec_bytes, const void* dev_adj_in, void* dev_adj_out, size_t adj_bytes,
                           double* zeta_bar, double* q0_bar);

@@ -52,7 +52,8 @@ def backward_segments(sim: Sim, ckpts, steps: int, checkpoint: int, adj):
                 recs[j] = sim.record_buffer()
             sim.step_record(states[j], states[j + 1], recs[j])
         for j in reversed(range(n)):
-            zb, qb = sim.adjoint_step(states[j], cur, nxt, rec=recs[j], zeta_bar=zb, q0_bar=qb)
+            last = s == 0 and j == 0  # the parameter sums are fetched once, after the last reverse step
+            zb, qb = sim.adjoint_step(states[j], cur, nxt, rec=recs[j], zeta_bar=zb, q0_bar=qb, fetch=last)
             cur, nxt = nxt, cur
     if cur is not adj:
         adj.copy_(cur)

@@ -9,11 +9,16 @@
 //
 // Order (each a launch; the forward u and F of time t come from a recording
 // step, or are recomputed by k_thermo and k_fwd_force):
-//   k_adj_order   : phi, Q updates (Eqs. (1), (2))  -> mu_bar, W_bar, partial u_bar, Q_bar, phi_bar, H_bar
+//   k_adj_order   : phi, Q updates (Eqs. (1), (2))  -> mu_bar, W_bar, partial u_bar, Q_bar, phi_bar
 //   k_adj_collide : collision + stream (Eqs. (6)-(8), (10)-(11)) -> g_bar(t), F_bar
-//   k_adj_stress  : stress, H, mu (Eqs. (3)-(5)) -> gradient-data adjoints, zeta / q0 partials
-//   k_adj_gather  : stencil transposes of the gradient data, including the
-//                   anchoring divergence D0_a(Q_ab D0_b phi) of mu -> Q_bar(t), phi_bar(t)
+//   k_adj_stress  : stress, H, mu (Eqs. (3)-(5)), including the anchoring
+//                   divergence D0_a(Q_ab D0_b phi) of mu, whose adjoint
+//                   v_bar_a = W (mu_bar(x + e_a) - mu_bar(x - e_a)) is formed
+//                   from mu_bar at the neighbours -> gradient-data adjoints
+//                   (the site-local ones already summed with the Q, phi
+//                   adjoints of k_adj_order), zeta / q0 block partials
+//   k_adj_gather  : stencil transposes of the gradient data -> Q_bar(t), phi_bar(t)
+// H_bar = Gamma Q_bar(t+1) is formed where it is used.
 #pragma once
 #include "adjoint.hpp"
 #include "kernels_reduce.hpp"
@@ -58,7 +63,7 @@ __global__ void __launch_bounds__(256) k_adj_order(Box b, Params<R> P, const FS*
                                                    const R* __restrict__ adj_phi, const R* __restrict__ adj_q,
                                                    R* __restrict__ mub, R* __restrict__ Wb_out,
                                                    R* __restrict__ ubp, R* __restrict__ qbp,
-                                                   R* __restrict__ phibp, R* __restrict__ hb) {
+                                                   R* __restrict__ phibp) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= b.N) return;
   int x, y, z;
@@ -115,10 +120,7 @@ __global__ void __launch_bounds__(256) k_adj_order(Box b, Params<R> P, const FS*
 #pragma unroll
   for (int a = 0; a < 3; ++a) ubp[a * N + s] = ub[a];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    qbp[k * N + s] = qb_out[k];
-    hb[k * N + s] = P.Gamma * qbar[k];
-  }
+  for (int k = 0; k < 5; ++k) qbp[k * N + s] = qb_out[k];
   phibp[s] = phib;
 }
 
@@ -162,29 +164,37 @@ __global__ void __launch_bounds__(256) k_adj_collide(Box b, Params<R> P, const G
 }
 
 // Number of per-site gradient-data adjoint values stored between kernels.
-constexpr int NGB = 31;  // phi, dphi[3], lapphi, divv, q[5], dq[3][5], lapq[5]
+constexpr int NGB = 30;  // phi, dphi[3], lapphi, q[5], dq[3][5], lapq[5]
+// offsets of the fields in the gradient-data adjoint buffer
+constexpr int GB_PHI = 0, GB_DPHI = 1, GB_LAPPHI = 4, GB_Q = 5, GB_DQ = 10, GB_LAPQ = 25;
 
 template <class R>
 __device__ __forceinline__ void store_gb(const GradBar<R>& Gb, R* __restrict__ out, size_t N, int s) {
-  int n = 0;
-  out[(n++) * N + s] = Gb.phi;
-  for (int g = 0; g < 3; ++g) out[(n++) * N + s] = Gb.dphi[g];
-  out[(n++) * N + s] = Gb.lapphi;
-  out[(n++) * N + s] = Gb.divv;
-  for (int k = 0; k < 5; ++k) out[(n++) * N + s] = Gb.q[k];
+  out[GB_PHI * N + s] = Gb.phi;
+#pragma unroll
+  for (int g = 0; g < 3; ++g) out[(GB_DPHI + g) * N + s] = Gb.dphi[g];
+  out[GB_LAPPHI * N + s] = Gb.lapphi;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) out[(GB_Q + k) * N + s] = Gb.q[k];
+#pragma unroll
   for (int g = 0; g < 3; ++g)
-    for (int k = 0; k < 5; ++k) out[(n++) * N + s] = Gb.dq[g][k];
-  for (int k = 0; k < 5; ++k) out[(n++) * N + s] = Gb.lapq[k];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) out[(GB_DQ + 5 * g + k) * N + s] = Gb.dq[g][k];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) out[(GB_LAPQ + k) * N + s] = Gb.lapq[k];
 }
-// offsets of the fields in the gradient-data adjoint buffer
-constexpr int GB_PHI = 0, GB_DPHI = 1, GB_LAPPHI = 4, GB_DIVV = 5, GB_Q = 6, GB_DQ = 11, GB_LAPQ = 26;
 
 // Reverse of the stress (through H), of H as used by the Q update and of mu.
+// qbp, phibp: the site-local Q and phi adjoints from k_adj_order, added to
+// the gradient data's own.  partial: one float64 pair (zeta, q0) per block,
+// overwritten (accumulate = 0) or added to (accumulate = 1).
 template <class R, class FS>
 __global__ void __launch_bounds__(256) k_adj_stress(Box b, Params<R> P, const FS* __restrict__ phi,
                                                     const FS* __restrict__ q, const R* __restrict__ Fb,
-                                                    const R* __restrict__ hb, const R* __restrict__ mub,
-                                                    R* __restrict__ gbar, double* __restrict__ partial) {
+                                                    const R* __restrict__ adj_q, const R* __restrict__ mub,
+                                                    const R* __restrict__ qbp, const R* __restrict__ phibp,
+                                                    R* __restrict__ gbar, double* __restrict__ partial,
+                                                    int accumulate) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   double v[2] = {0.0, 0.0};
   if (s < b.N) {
@@ -192,47 +202,53 @@ __global__ void __launch_bounds__(256) k_adj_stress(Box b, Params<R> P, const FS
     coords(b, s, x, y, z);
     const size_t N = b.N;
     const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
-    // sigma_bar_ab = -D0_b F_bar_a
-    R sb[9];
+    // sigma_bar_ab = -D0_b F_bar_a;  v_bar_a = -D0_a divv_bar with divv_bar = -2 W mu_bar
+    R sb[9], vb[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int sp = sidx(b, x + off[c][0], y + off[c][1], z + off[c][2]);
       const int sm = sidx(b, x - off[c][0], y - off[c][1], z - off[c][2]);
 #pragma unroll
       for (int a = 0; a < 3; ++a) sb[3 * a + c] = -R(0.5) * (Fb[a * N + sp] - Fb[a * N + sm]);
+      vb[c] = P.W * (mub[sp] - mub[sm]);
     }
     Grad<R> G;
     gather_grad<R>(b, phi, q, x, y, z, G);
     R hbs[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) hbs[k] = hb[k * N + s];
+    for (int k = 0; k < 5; ++k) hbs[k] = P.Gamma * adj_q[k * N + s];
     GradBar<R> Gb;
     Gb.zero();
     ParBar<R> Pb{R(0), R(0), R(0)};
     sigma_site_bwd(P, G, sb, hbs, Gb, Pb);
     mu_site_bwd(P, G.phi, G.q, mub[s], Gb.phi, Gb.lapphi, Gb.divv, Gb.q);
+    // anchoring divergence: v_a = Q_ab D0_b phi  ->  Q_bar_ab += v_bar_a D0_b phi,
+    // (D0_b phi)_bar += Q_ab v_bar_a
+    {
+      R Qb[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Qb[a][c] = vb[a] * G.dphi[c];
+      full_to_stored(Qb, Gb.q);
+      const R xx = G.q[0], xy = G.q[1], xz = G.q[2], yy = G.q[3], yz = G.q[4], zz = -xx - yy;
+      Gb.dphi[0] += xx * vb[0] + xy * vb[1] + xz * vb[2];
+      Gb.dphi[1] += xy * vb[0] + yy * vb[1] + yz * vb[2];
+      Gb.dphi[2] += xz * vb[0] + yz * vb[1] + zz * vb[2];
+    }
+    Gb.phi += phibp[s];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Gb.q[k] += qbp[k * N + s];
     store_gb(Gb, gbar, N, s);
     v[0] = double(Pb.zeta);
     v[1] = 2.0 * double(P.K) * double(Pb.kq) + 8.0 * double(P.K) * double(P.q0) * double(Pb.kq2);
   }
-  block_reduce_store<2>(v, partial + size_t(blockIdx.x) * 2);
+  block_reduce_store<2>(v, partial + size_t(blockIdx.x) * 2, accumulate != 0);
 }
 
 // Stencil transposes of the gradient data; writes Q_bar(t), phi_bar(t).
-// Includes the reverse of divv = sum_a D0_a v_a, v_a = Q_ab D0_b phi:
-// v_bar_a = -D0_a divv_bar, which adds v_bar_a D0_b phi to Q_bar_ab and
-// Q_ab v_bar_a to the adjoint of D0_b phi (gathered at the neighbours).
-template <class R, class FS>
-__device__ __forceinline__ void vbar_at(const Box& b, const R* __restrict__ divvb, int x, int y, int z, R vb[3]) {
-  vb[0] = -R(0.5) * (divvb[sidx(b, x + 1, y, z)] - divvb[sidx(b, x - 1, y, z)]);
-  vb[1] = -R(0.5) * (divvb[sidx(b, x, y + 1, z)] - divvb[sidx(b, x, y - 1, z)]);
-  vb[2] = -R(0.5) * (divvb[sidx(b, x, y, z + 1)] - divvb[sidx(b, x, y, z - 1)]);
-}
-
-template <class R, class FS>
-__global__ void __launch_bounds__(256) k_adj_gather(Box b, const FS* __restrict__ phi, const FS* __restrict__ q,
-                                                    const R* __restrict__ gbar, const R* __restrict__ phibp,
-                                                    const R* __restrict__ qbp, R* __restrict__ adj_phi,
+template <class R>
+__global__ void __launch_bounds__(256) k_adj_gather(Box b, const R* __restrict__ gbar, R* __restrict__ adj_phi,
                                                     R* __restrict__ adj_q) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= b.N) return;
@@ -240,42 +256,16 @@ __global__ void __launch_bounds__(256) k_adj_gather(Box b, const FS* __restrict_
   coords(b, s, x, y, z);
   const size_t N = b.N;
   const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
-  const R* divvb = gbar + size_t(GB_DIVV) * N;
-  R pb = phibp[s] + gbar[size_t(GB_PHI) * N + s];
+  R pb = gbar[size_t(GB_PHI) * N + s];
   R qb[5];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) qb[k] = qbp[k * N + s] + gbar[size_t(GB_Q + k) * N + s];
-  // anchoring divergence, local part: Q_bar_ab += v_bar_a D0_b phi
-  {
-    R vb[3], dp[3];
-    vbar_at<R, FS>(b, divvb, x, y, z, vb);
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      dp[c] = R(0.5) * (R(phi[sidx(b, x + off[c][0], y + off[c][1], z + off[c][2])]) -
-                        R(phi[sidx(b, x - off[c][0], y - off[c][1], z - off[c][2])]));
-    R Qb[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) Qb[a][c] = vb[a] * dp[c];
-    full_to_stored(Qb, qb);
-  }
+  for (int k = 0; k < 5; ++k) qb[k] = gbar[size_t(GB_Q + k) * N + s];
   R lp = R(0), lq[5] = {R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
   for (int g = 0; g < 3; ++g) {
-    const int xp = x + off[g][0], yp = y + off[g][1], zp = z + off[g][2];
-    const int xm = x - off[g][0], ym = y - off[g][1], zm = z - off[g][2];
-    const int sp = sidx(b, xp, yp, zp), sm = sidx(b, xm, ym, zm);
-    // adjoint of D0_g phi at the neighbours: gradient-data part + anchoring part Q_ag v_bar_a
-    R vp[3], vm[3];
-    vbar_at<R, FS>(b, divvb, xp, yp, zp, vp);
-    vbar_at<R, FS>(b, divvb, xm, ym, zm, vm);
-    R qrp[3], qrm[3];  // column g of Q at the neighbours (Q symmetric)
-    qrow<R>(q, N, sp, g, qrp);
-    qrow<R>(q, N, sm, g, qrm);
-    const R dpp = gbar[size_t(GB_DPHI + g) * N + sp] + (qrp[0] * vp[0] + qrp[1] * vp[1] + qrp[2] * vp[2]);
-    const R dpm = gbar[size_t(GB_DPHI + g) * N + sm] + (qrm[0] * vm[0] + qrm[1] * vm[1] + qrm[2] * vm[2]);
-    pb -= R(0.5) * (dpp - dpm);
+    const int sp = sidx(b, x + off[g][0], y + off[g][1], z + off[g][2]);
+    const int sm = sidx(b, x - off[g][0], y - off[g][1], z - off[g][2]);
+    pb -= R(0.5) * (gbar[size_t(GB_DPHI + g) * N + sp] - gbar[size_t(GB_DPHI + g) * N + sm]);
     lp += gbar[size_t(GB_LAPPHI) * N + sp] + gbar[size_t(GB_LAPPHI) * N + sm];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {

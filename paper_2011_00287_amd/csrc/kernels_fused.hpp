@@ -38,8 +38,9 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
 // ---------------------------------------------------------------------------
 // k_lb_fused
 //   phi and Q rings hold planes p-2..p+2 (phi) and p-1..p+1 (Q) on the tile
-//   plus a halo of 2; the stress is computed on the tile plus a halo of 1 at
-//   plane p (slots dealt round-robin to the threads); thread t owns column t
+//   plus a halo of 2; the stress is computed on the tile plus the halo of 1
+//   the force reads at plane p (each thread its own site, then the halo
+//   slots on rotating waves); thread t owns column t
 //   of the tile for mu and for the collision of plane p-1, whose force needs
 //   the stress of planes p-2..p.  The global loads needed after the stress
 //   pass (the pull of plane p-1, the ring planes for p+1) are issued before
@@ -55,8 +56,9 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
   constexpr int SX = TX + 2, SY = TY + 2, NS = SX * SY;  // stress slots (halo 1)
   __shared__ R sPhi[5][NA];
   __shared__ R sQ[3][5][NA];
+  constexpr int NHALO = 2 * (TX + TY);                  // halo stress slots the force reads
+  static_assert(NHALO <= NT && NT % 64 == 0, "one halo slot per thread, whole waves");
   __shared__ R sSig[6][NS];  // sigma_ax (a = 0..2), then sigma_ay
-  __shared__ R sSaz[3][NT];  // sigma_az at the tile sites
   __shared__ int sGX[AX], sGY[AY];
 
   const int l = xcd_remap(blockIdx.x, gridDim.x);
@@ -155,40 +157,65 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
       }
     }
 
-    // ---- stress at plane p on the tile + halo 1
-    for (int s = tid; s < NS; s += NT) {
-      const int sx = s % SX, sy = s / SX;
-      const int a0 = (sy + 1) * AX + (sx + 1);  // phi / Q slot of this stress slot
-      Grad<R> G;
-      G.phi = sPhi[r0][a0];
-      G.dphi[0] = R(0.5) * (sPhi[r0][a0 + 1] - sPhi[r0][a0 - 1]);
-      G.dphi[1] = R(0.5) * (sPhi[r0][a0 + AX] - sPhi[r0][a0 - AX]);
-      G.dphi[2] = R(0.5) * (sPhi[rp][a0] - sPhi[rm][a0]);
-      G.lapphi = R(0);
-      G.divv = R(0);
+    // ---- stress at plane p: round 0 is the owned site (its sigma_az stays in
+    // registers), round 1 the halo slots the in-plane force reads (rows
+    // y0-1, y0+TY and columns x0-1, x0+TX; corners are not needed).  The halo
+    // slots go to whole waves, starting at a wave that rotates with the plane
+    // and the workgroup, so the extra round is spread over the SIMDs.
+    R saz[3];
+    {
+      constexpr int NW = NT / 64 > 0 ? NT / 64 : 1;
+      const int shift = ((p + 1 + l) % NW) * 64;
+      const int hslot = tid >= shift ? tid - shift : tid - shift + NT;
+#pragma unroll 1
+      for (int r = 0; r < 2; ++r) {
+        int sx, sy;
+        if (r == 0) {
+          sx = lx + 1;
+          sy = ly + 1;
+        } else {
+          if (hslot >= NHALO) break;
+          if (hslot < 2 * TX) {
+            sx = 1 + (hslot % TX);
+            sy = hslot < TX ? 0 : SY - 1;
+          } else {
+            const int h2 = hslot - 2 * TX;
+            sx = h2 < TY ? 0 : SX - 1;
+            sy = 1 + (h2 % TY);
+          }
+        }
+        const int s = sy * SX + sx;
+        const int a0 = (sy + 1) * AX + (sx + 1);  // phi / Q slot of this stress slot
+        Grad<R> G;
+        G.phi = sPhi[r0][a0];
+        G.dphi[0] = R(0.5) * (sPhi[r0][a0 + 1] - sPhi[r0][a0 - 1]);
+        G.dphi[1] = R(0.5) * (sPhi[r0][a0 + AX] - sPhi[r0][a0 - AX]);
+        G.dphi[2] = R(0.5) * (sPhi[rp][a0] - sPhi[rm][a0]);
+        G.lapphi = R(0);
+        G.divv = R(0);
 #pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        const R qc = sQ[c0][c][a0];
-        const R qxp = sQ[c0][c][a0 + 1], qxm = sQ[c0][c][a0 - 1];
-        const R qyp = sQ[c0][c][a0 + AX], qym = sQ[c0][c][a0 - AX];
-        const R qzp = sQ[cp][c][a0], qzm = sQ[cm][c][a0];
-        G.q[c] = qc;
-        G.dq[0][c] = R(0.5) * (qxp - qxm);
-        G.dq[1][c] = R(0.5) * (qyp - qym);
-        G.dq[2][c] = R(0.5) * (qzp - qzm);
-        G.lapq[c] = ((qxp + qxm) + (qyp + qym) + (qzp + qzm)) - R(6) * qc;
-      }
-      R h[5], sig[9];
-      sigma_site(P, G, sig, h);
+        for (int c = 0; c < 5; ++c) {
+          const R qc = sQ[c0][c][a0];
+          const R qxp = sQ[c0][c][a0 + 1], qxm = sQ[c0][c][a0 - 1];
+          const R qyp = sQ[c0][c][a0 + AX], qym = sQ[c0][c][a0 - AX];
+          const R qzp = sQ[cp][c][a0], qzm = sQ[cm][c][a0];
+          G.q[c] = qc;
+          G.dq[0][c] = R(0.5) * (qxp - qxm);
+          G.dq[1][c] = R(0.5) * (qyp - qym);
+          G.dq[2][c] = R(0.5) * (qzp - qzm);
+          G.lapq[c] = ((qxp + qxm) + (qyp + qym) + (qzp + qzm)) - R(6) * qc;
+        }
+        R h[5], sig[9];
+        sigma_site(P, G, sig, h);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        sSig[a][s] = sig[3 * a + 0];
-        sSig[3 + a][s] = sig[3 * a + 1];
-      }
-      if (sx >= 1 && sx <= TX && sy >= 1 && sy <= TY) {
-        const int t = (sy - 1) * TX + (sx - 1);
+        for (int a = 0; a < 3; ++a) {
+          sSig[a][s] = sig[3 * a + 0];
+          sSig[3 + a][s] = sig[3 * a + 1];
+        }
+        if (r == 0) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) sSaz[a][t] = sig[3 * a + 2];
+          for (int a = 0; a < 3; ++a) saz[a] = sig[3 * a + 2];
+        }
       }
     }
 
@@ -255,12 +282,10 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
 
     // ---- in-plane force part at plane p; collision of plane p-1
     const int s0 = (ly + 1) * SX + (lx + 1);
-    R fin[3], saz[3];
+    R fin[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < 3; ++a)
       fin[a] = R(0.5) * (sSig[a][s0 + 1] - sSig[a][s0 - 1]) + R(0.5) * (sSig[3 + a][s0 + SX] - sSig[3 + a][s0 - SX]);
-      saz[a] = sSaz[a][tid];
-    }
     if (collide) {
       R F[3];
 #pragma unroll

@@ -9,8 +9,10 @@
 
 namespace lbc {
 
+// Block sum of NV doubles into out[0..NV) (added to out when accumulate).
 template <int NV>
-__device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* __restrict__ out) {
+__device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* __restrict__ out,
+                                                   bool accumulate = false) {
   __shared__ double red[NV][4];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -25,7 +27,8 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* __re
   __syncthreads();
   if (threadIdx.x < NV) {
     const int k = threadIdx.x;
-    out[k] = ((red[k][0] + red[k][1]) + red[k][2]) + red[k][3];
+    const double bs = ((red[k][0] + red[k][1]) + red[k][2]) + red[k][3];
+    out[k] = accumulate ? out[k] + bs : bs;
   }
 }
 

@@ -172,9 +172,10 @@ struct BackendT final : Backend {
   R* aubp = nullptr;
   R* aqbp = nullptr;
   R* aphibp = nullptr;
-  R* ahb = nullptr;
   R* aFb = nullptr;
   R* agbar = nullptr;
+  double* apart = nullptr;   // per-block (zeta, q0) adjoint partials, kept across reverse steps
+  bool apart_live = false;   // apart holds sums not yet fetched by the caller
   bool site_path = false;  // three site-parallel kernels instead of the fused pair
   int tz_lb = 8, tz_or = 8;
   int lb_tile = 0, or_tile = 0;
@@ -241,11 +242,13 @@ struct BackendT final : Backend {
     dfree(sums);
     mu = H = sig = u = nullptr;
     partial = sums = nullptr;
-    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &ahb, &aFb, &agbar};
+    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar};
     for (R** a : adj) {
       dfree(*a);
       *a = nullptr;
     }
+    dfree(apart);
+    apart = nullptr;
   }
 
   void set_params(const lb_params& p) override {
@@ -544,15 +547,18 @@ struct BackendT final : Backend {
       aubp = dalloc<R>(3 * N);
       aqbp = dalloc<R>(5 * N);
       aphibp = dalloc<R>(N);
-      ahb = dalloc<R>(5 * N);
       aFb = dalloc<R>(3 * N);
       agbar = dalloc<R>(size_t(lbc::NGB) * N);
+      apart = dalloc<double>(size_t(nblk) * 2);
+      apart_live = false;
     } catch (...) {
-      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &ahb, &aFb, &agbar};
+      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar};
       for (R** a : adj) {
         dfree(*a);
         *a = nullptr;
       }
+      dfree(apart);
+      apart = nullptr;
       throw;
     }
   }
@@ -611,13 +617,17 @@ struct BackendT final : Backend {
       uu = u;
       FF = aF;
     }
-    lbc::k_adj_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp,
-                                                       ahb);
+    lbc::k_adj_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp);
     lbc::k_adj_collide<R, GS><<<nblk, TPB, 0, stream>>>(box, P, v.B, FF, aWb, aubp, gi, go, aFb);
-    lbc::k_adj_stress<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, aFb, ahb, amub, agbar, partial);
-    lbc::k_final_sum<<<1, TPB, 0, stream>>>(partial, int(nblk), 2, sums);
-    lbc::k_adj_gather<R, FS><<<nblk, TPB, 0, stream>>>(box, v.phi, v.q, agbar, aphibp, aqbp, po, qo);
+    lbc::k_adj_stress<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, aFb, qi, amub, aqbp, aphibp, agbar, apart,
+                                                        apart_live ? 1 : 0);
+    apart_live = true;
+    lbc::k_adj_gather<R><<<nblk, TPB, 0, stream>>>(box, agbar, po, qo);
     check_launch();
+    if (!zeta_bar && !q0_bar) return;  // the parameter sums stay on the device
+    lbc::k_final_sum<<<1, TPB, 0, stream>>>(apart, int(nblk), 2, sums);
+    check_launch();
+    apart_live = false;
     double pv[2] = {0.0, 0.0};
     HIPCHECK(hipMemcpyAsync(pv, sums, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
     HIPCHECK(hipStreamSynchronize(stream));

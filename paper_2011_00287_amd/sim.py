@@ -207,17 +207,22 @@ class Sim:
                                    state_in.numel() * state_in.element_size(),
                                    rec_out.numel() * rec_out.element_size()))
 
-    def adjoint_step(self, state, adj_in, adj_out, rec=None, zeta_bar: float = 0.0, q0_bar: float = 0.0):
+    def adjoint_step(self, state, adj_in, adj_out, rec=None, zeta_bar: float = 0.0, q0_bar: float = 0.0,
+                     fetch: bool = True):
         """adj_out <- adjoint at t from adj_in (adjoint at t+1), given the forward state at t
-        (and its step record, or None to recompute).  Returns the updated (zeta_bar, q0_bar)."""
-        zb = ctypes.c_double(zeta_bar)
-        qb = ctypes.c_double(q0_bar)
+        (and its step record, or None to recompute).  Returns the updated (zeta_bar, q0_bar).
+
+        fetch=False leaves this step's parameter contributions summed on the
+        device (no synchronisation) and returns the inputs unchanged; the next
+        call with fetch=True adds every kept contribution."""
         recp = ctypes.c_void_p(rec.data_ptr()) if rec is not None else None
         recb = rec.numel() * rec.element_size() if rec is not None else 0
+        zb = ctypes.c_double(zeta_bar)
+        qb = ctypes.c_double(q0_bar)
         check(lib().lb_adjoint_step(self._h, ctypes.c_void_p(state.data_ptr()), state.numel() * state.element_size(),
                                     recp, recb, ctypes.c_void_p(adj_in.data_ptr()),
                                     ctypes.c_void_p(adj_out.data_ptr()), adj_in.numel() * adj_in.element_size(),
-                                    ctypes.byref(zb), ctypes.byref(qb)))
+                                    ctypes.byref(zb) if fetch else None, ctypes.byref(qb) if fetch else None))
         return zb.value, qb.value
 
     # ----------------------------------------------------------------- profiling

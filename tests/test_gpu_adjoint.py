@@ -66,8 +66,10 @@ def test_single_step_vjp_matches_oracle(shape):
         sim.step_record(state, nxt, rec)
         out2 = sim.adjoint_buffer()
         zb2, qb2 = sim.adjoint_step(state, adj, out2, rec=rec)
-        assert torch.equal(out, out2) or float((out - out2).abs().max()) <= 1e-15 * float(out.abs().max())
-        assert abs(zb2 - zb) <= 1e-15 * abs(zb) and abs(qb2 - qb) <= 1e-15 * abs(qb)
+        # the recorded u, F come from the fused kernels, the recomputed ones from the
+        # site kernels: equal up to float64 rounding of differently ordered sums
+        assert float((out - out2).abs().max()) <= 1e-13 * float(out.abs().max())
+        assert abs(zb2 - zb) <= 1e-13 * abs(zb) and abs(qb2 - qb) <= 1e-13 * abs(qb)
         # the recorded step equals an ordinary step (state buffers hold padding: compare fields)
         sim.set_state(state)
         sim.step(1)
@@ -166,3 +168,36 @@ def test_droplet32_adjoint_vs_central_differences(precision, tol):
         norms.append(abs(fd))
     errs, norms = np.array(errs), np.array(norms)
     assert np.linalg.norm(errs) <= tol * np.linalg.norm(norms), (errs, norms)
+
+
+def test_parameter_sums_kept_on_device_between_fetches():
+    """Reverse steps that leave the zeta / q0 sums on the device, fetched once at
+    the end, give the same totals (to float64 rounding) as fetching every step;
+    a fetch clears the device sums."""
+    p = _p(q0=2 * math.pi / 7, zeta=0.01)
+    g, phi, q5 = inputs.random_fields(7, 6, 5, seed=11, g_amp=2e-3, q_amp=0.2)
+    rng = np.random.default_rng(9)
+    with Sim(p, phi, q5, precision="fp64") as sim:
+        sim.set_fields(g=g)
+        states = [sim.get_state()]
+        for _ in range(3):
+            sim.step(1)
+            states.append(sim.get_state())
+        seed = sim.adjoint_buffer()
+        seed.copy_(torch.tensor(rng.normal(size=seed.numel())))
+
+        def sweep(fetch_every):
+            cur, nxt = seed.clone(), sim.adjoint_buffer()
+            zb = qb = 0.0
+            for j in (2, 1, 0):
+                zb, qb = sim.adjoint_step(states[j], cur, nxt, zeta_bar=zb, q0_bar=qb, fetch=fetch_every or j == 0)
+                cur, nxt = nxt, cur
+            return zb, qb, cur
+
+        z1, q1, a1 = sweep(True)
+        z2, q2, a2 = sweep(False)
+        z3, q3, _ = sweep(True)  # nothing left over from the previous sweep
+    assert torch.equal(a1, a2)
+    for a, b in ((z1, z2), (q1, q2), (z1, z3), (q1, q3)):
+        assert abs(a - b) <= 1e-13 * abs(a), (a, b)
+    assert z1 != 0.0 and q1 != 0.0
