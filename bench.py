@@ -79,38 +79,51 @@ def time_precision(prec, p, phi, q5, steps, warmup, stream):
     return sim, dt
 
 
-def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream):
-    """(backward incl. segment recompute) / (plain forward) over the same steps."""
+def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True):
+    """(reverse pass incl. segment replay) / (plain forward) over the same steps,
+    with states kept every `checkpoint` steps; with `recorded`, also the mode that
+    keeps every state and step record in the forward pass (reverse pass without
+    replay, steps x (state + record) bytes of device memory)."""
     import torch
-    from paper_2011_00287_amd.autograd import backward_segments, run_segments
+    from paper_2011_00287_amd.autograd import backward_recorded, backward_segments, run_recorded, run_segments
     from paper_2011_00287_amd.sim import Sim
     sim = Sim(p, phi, q5, precision=prec, stream=stream)
     s0 = sim.get_state()
     sim.step(3)
     sim.set_state(s0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(steps)
-    sim.sync()
-    t_fwd = time.perf_counter() - t0
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        sim.sync()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    _, t_fwd = timed(lambda: sim.step(steps))
     sim.set_state(s0)
     zc0 = float(sim.centre()[0][2])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ckpts = run_segments(sim, steps, checkpoint)
-    sim.sync()
-    t_fwd_ck = time.perf_counter() - t0
+    ckpts, t_fwd_ck = timed(lambda: run_segments(sim, steps, checkpoint))
     adj = sim.adjoint_buffer()
     sim.seed_centre(zc0, adj)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    backward_segments(sim, ckpts, steps, checkpoint, adj)
-    sim.sync()
-    t_bwd = time.perf_counter() - t0
+    _, t_bwd = timed(lambda: backward_segments(sim, ckpts, steps, checkpoint, adj))
+    del ckpts
+    out = {"steps": steps, "checkpoint": checkpoint, "precision": prec, "forward_ms": t_fwd * 1e3,
+           "forward_with_checkpoints_ms": t_fwd_ck * 1e3, "backward_ms": t_bwd * 1e3,
+           "adjoint_over_forward": t_bwd / t_fwd, "total_over_forward": (t_fwd_ck + t_bwd) / t_fwd}
+    if recorded:
+        sim.set_state(s0)
+        (states, recs), t_fwd_rec = timed(lambda: run_recorded(sim, steps))
+        adj = sim.adjoint_buffer()
+        sim.seed_centre(zc0, adj)
+        _, t_bwd_rec = timed(lambda: backward_recorded(sim, states, recs, adj))
+        nbytes = sum(t.numel() * t.element_size() for t in states + recs)
+        del states, recs
+        out["recorded"] = {"forward_recording_ms": t_fwd_rec * 1e3, "backward_ms": t_bwd_rec * 1e3,
+                           "adjoint_over_forward": t_bwd_rec / t_fwd,
+                           "total_over_forward": (t_fwd_rec + t_bwd_rec) / t_fwd, "device_bytes": nbytes}
     sim.close()
-    return {"steps": steps, "checkpoint": checkpoint, "precision": prec, "forward_ms": t_fwd * 1e3,
-            "forward_with_checkpoints_ms": t_fwd_ck * 1e3, "backward_ms": t_bwd * 1e3,
-            "adjoint_over_forward": t_bwd / t_fwd, "total_over_forward": (t_fwd_ck + t_bwd) / t_fwd}
+    return out
 
 
 def cpu_baseline(workload: str, nsteps: int = 2):
@@ -167,6 +180,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--adjoint-steps", type=int, default=50, help="0 = skip the adjoint timing")
     ap.add_argument("--adjoint-checkpoint", type=int, default=10)
+    ap.add_argument("--no-adjoint-recorded", action="store_true",
+                    help="skip the reverse pass over a fully recorded forward pass")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only time a device copy of this many MiB and exit")
     args = ap.parse_args()
@@ -217,8 +232,11 @@ def main():
 
     adjoint = None
     if args.adjoint_steps > 0:
-        adjoint = time_adjoint(args.precision, p, phi, q5, args.adjoint_steps, args.adjoint_checkpoint, stream)
-        print(f"# adjoint/forward: {adjoint['adjoint_over_forward']:.2f}", file=sys.stderr, flush=True)
+        adjoint = time_adjoint(args.precision, p, phi, q5, args.adjoint_steps, args.adjoint_checkpoint, stream,
+                               recorded=not args.no_adjoint_recorded)
+        print(f"# adjoint/forward: {adjoint['adjoint_over_forward']:.2f} (checkpoint {args.adjoint_checkpoint})"
+              + (f", {adjoint['recorded']['adjoint_over_forward']:.2f} (every step recorded)"
+                 if "recorded" in adjoint else ""), file=sys.stderr, flush=True)
 
     line = {
         "metric": "coupled-step MLUPS at 128^3 FP32 vs FP64, % HBM peak; adjoint/forward time",

@@ -7,7 +7,9 @@ adjoint of the step (lb_adjoint_step) in reverse, recomputing each segment of
 `checkpoint` steps from a stored state so that only about steps/checkpoint +
 checkpoint states are ever held in device memory.  Gradients: dL/dzeta,
 dL/dq0 (float64 device sums) and dL/dq5 (the initial Q field, 5 stored
-components); phi(0) and the initial populations are held fixed.
+components); phi(0) and the initial populations are held fixed.  With
+checkpoint = 0 every state and step record of the forward pass is kept
+instead, and the reverse pass runs no replay.
 """
 from __future__ import annotations
 
@@ -27,6 +29,34 @@ def run_segments(sim: Sim, steps: int, checkpoint: int):
         sim.step(n)
         t += n
     return ckpts
+
+
+def run_recorded(sim: Sim, steps: int):
+    """Advance `steps` steps keeping every state and step record (no replay in the
+    reverse pass; device memory grows as steps x (state + record) bytes).
+    Returns (states[0..steps], records[0..steps-1]); the context ends at states[-1]."""
+    states = [sim.get_state()]
+    recs = []
+    for _ in range(steps):
+        states.append(torch.empty_like(states[0]))
+        recs.append(sim.record_buffer())
+        sim.step_record(states[-2], states[-1], recs[-1])
+    sim.set_state(states[-1])
+    return states, recs
+
+
+def backward_recorded(sim: Sim, states, recs, adj):
+    """Reverse pass over a run_recorded history; adj as in backward_segments.
+    Returns (zeta_bar, q0_bar)."""
+    zb = qb = 0.0
+    other = torch.empty_like(adj)
+    cur, nxt = adj, other
+    for j in reversed(range(len(recs))):
+        zb, qb = sim.adjoint_step(states[j], cur, nxt, rec=recs[j], zeta_bar=zb, q0_bar=qb, fetch=j == 0)
+        cur, nxt = nxt, cur
+    if cur is not adj:
+        adj.copy_(cur)
+    return zb, qb
 
 
 def backward_segments(sim: Sim, ckpts, steps: int, checkpoint: int, adj):
@@ -68,7 +98,7 @@ class _DropletRollout(torch.autograd.Function):
         sim = Sim(p, np.asarray(phi, dtype=np.float64), q5_np, precision=precision,
                   stream=torch.cuda.current_stream())
         zc0 = float(sim.centre()[0][2])
-        ckpts = run_segments(sim, steps, checkpoint)
+        ckpts = run_recorded(sim, steps) if checkpoint == 0 else run_segments(sim, steps, checkpoint)
         zcT = float(sim.centre()[0][2])
         ctx.sim, ctx.ckpts, ctx.zc0 = sim, ckpts, zc0
         ctx.steps, ctx.checkpoint = steps, checkpoint
@@ -80,7 +110,10 @@ class _DropletRollout(torch.autograd.Function):
         sim = ctx.sim
         adj = sim.adjoint_buffer()
         sim.seed_centre(ctx.zc0, adj)
-        zb, qb = backward_segments(sim, ctx.ckpts, ctx.steps, ctx.checkpoint, adj)
+        if ctx.checkpoint == 0:
+            zb, qb = backward_recorded(sim, *ctx.ckpts, adj)
+        else:
+            zb, qb = backward_segments(sim, ctx.ckpts, ctx.steps, ctx.checkpoint, adj)
         _, qbar, _ = sim.adjoint_parts(adj)
         g = float(grad_out)
         dtype, device = ctx.q5_meta
@@ -97,5 +130,7 @@ def displacement_loss(zeta, q0, q5, *, params: dict, phi, steps: int, checkpoint
 
     zeta, q0: 0-dim tensors; q5: [5, nz, ny, nx] tensor (CPU or CUDA); phi: numpy
     [nz, ny, nx]; params: the model parameter dict (its zeta / q0 are replaced).
+    checkpoint: states kept every `checkpoint` steps and segments replayed in the
+    reverse pass; 0 keeps every state and step record instead (no replay).
     """
     return _DropletRollout.apply(zeta, q0, q5, params, phi, steps, checkpoint, precision)

@@ -30,7 +30,7 @@ template <class R, class GS>
 __global__ void __launch_bounds__(256) k_fwd_force(Box b, Params<R> P, const GS* __restrict__ B,
                                                    const R* __restrict__ sig, R* __restrict__ F_out,
                                                    R* __restrict__ u_out) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = site_xcd();
   if (s >= b.N) return;
   int x, y, z;
   coords(b, s, x, y, z);
@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(256) k_adj_order(Box b, Params<R> P, const FS*
                                                    R* __restrict__ mub, R* __restrict__ Wb_out,
                                                    R* __restrict__ ubp, R* __restrict__ qbp,
                                                    R* __restrict__ phibp) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = site_xcd();
   if (s >= b.N) return;
   int x, y, z;
   coords(b, s, x, y, z);
@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(256) k_adj_collide(Box b, Params<R> P, const G
                                                      const R* __restrict__ F, const R* __restrict__ Wb,
                                                      const R* __restrict__ ubp, const R* __restrict__ adj_g,
                                                      R* __restrict__ g_out, R* __restrict__ Fb_out) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = site_xcd();
   if (s >= b.N) return;
   int x, y, z;
   coords(b, s, x, y, z);
@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(256) k_adj_stress(Box b, Params<R> P, const FS
                                                     const R* __restrict__ qbp, const R* __restrict__ phibp,
                                                     R* __restrict__ gbar, double* __restrict__ partial,
                                                     int accumulate) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = site_xcd();
   double v[2] = {0.0, 0.0};
   if (s < b.N) {
     int x, y, z;
@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(256) k_adj_stress(Box b, Params<R> P, const FS
 template <class R>
 __global__ void __launch_bounds__(256) k_adj_gather(Box b, const R* __restrict__ gbar, R* __restrict__ adj_phi,
                                                     R* __restrict__ adj_q) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = site_xcd();
   if (s >= b.N) return;
   int x, y, z;
   coords(b, s, x, y, z);

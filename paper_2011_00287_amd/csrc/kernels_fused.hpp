@@ -23,18 +23,6 @@
 
 namespace lbc {
 
-__device__ __forceinline__ int pmod(int a, int n) {
-  const int r = a % n;
-  return r < 0 ? r + n : r;
-}
-
-// Bijection of [0, nblk): XCD x (ids congruent to x mod 8) gets a contiguous range.
-__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
-  const int q = nblk >> 3, r = nblk & 7;
-  const int x = bid & 7, k = bid >> 3;
-  return x * q + (x < r ? x : r) + k;
-}
-
 // ---------------------------------------------------------------------------
 // k_lb_fused
 //   phi and Q rings hold planes p-2..p+2 (phi) and p-1..p+1 (Q) on the tile

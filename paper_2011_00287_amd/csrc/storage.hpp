@@ -73,6 +73,25 @@ __device__ __forceinline__ int sidx(const Box& b, int x, int y, int z) {
   return (wrapi(z, b.nz) * b.ny + wrapi(y, b.ny)) * b.nx + wrapi(x, b.nx);
 }
 
+__device__ __forceinline__ int pmod(int a, int n) {
+  const int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+// Bijection of [0, nblk): XCD x (ids congruent to x mod 8 are dealt to it)
+// gets a contiguous range of logical block ids, so blocks that share stencil
+// neighbours share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7;
+  const int x = bid & 7, k = bid >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
+
+// Site of this thread in a site-parallel launch, blocks remapped by XCD.
+__device__ __forceinline__ int site_xcd() {
+  return xcd_remap(int(blockIdx.x), int(gridDim.x)) * int(blockDim.x) + int(threadIdx.x);
+}
+
 __device__ __forceinline__ void coords(const Box& b, int s, int& x, int& y, int& z) {
   x = s % b.nx;
   const int t = s / b.nx;

@@ -201,3 +201,23 @@ def test_parameter_sums_kept_on_device_between_fetches():
     for a, b in ((z1, z2), (q1, q2), (z1, z3), (q1, q3)):
         assert abs(a - b) <= 1e-13 * abs(a), (a, b)
     assert z1 != 0.0 and q1 != 0.0
+
+
+def test_recorded_rollout_equals_checkpointed():
+    """checkpoint = 0 keeps every state and step record instead of replaying
+    segments; the reverse pass sees the same states and records, so the
+    gradients agree to float64 rounding (only the device-sum order differs)."""
+    p = _p(q0=2 * math.pi / 8, zeta=0.02)
+    phi, q5 = inputs.droplet_fields(8, 8, 10, 2.5, p["q0"], seed=3)
+    grads = []
+    for ck in (3, 0):
+        zeta = torch.tensor(p["zeta"], dtype=DT, requires_grad=True)
+        q0 = torch.tensor(p["q0"], dtype=DT, requires_grad=True)
+        q5t = torch.tensor(q5, requires_grad=True)
+        L = displacement_loss(zeta, q0, q5t, params=p, phi=phi, steps=7, checkpoint=ck, precision="fp64")
+        L.backward()
+        grads.append((float(L.detach()), float(zeta.grad), float(q0.grad), q5t.grad.numpy()))
+    (L1, z1, c1, g1), (L2, z2, c2, g2) = grads
+    assert L1 == L2
+    assert abs(z1 - z2) <= 1e-13 * abs(z1) and abs(c1 - c2) <= 1e-13 * abs(c1)
+    assert np.array_equal(g1, g2)
