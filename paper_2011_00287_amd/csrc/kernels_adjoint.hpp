@@ -57,20 +57,20 @@ __global__ void __launch_bounds__(256) k_fwd_force(Box b, Params<R> P, const GS*
 // Reverse of the Q and phi updates at one site.
 //   phi' = phi - sum_g D0_g(u_g phi) + M lap(mu)
 //   q'   = q - u.D0 q + S(q, W(u)) + Gamma h
+// All loads of a site (own values and the 6 neighbours) are issued before the
+// arithmetic.
 template <class R, class FS>
-__global__ void __launch_bounds__(256) k_adj_order(Box b, Params<R> P, const FS* __restrict__ phi,
-                                                   const FS* __restrict__ q, const R* __restrict__ u,
-                                                   const R* __restrict__ adj_phi, const R* __restrict__ adj_q,
-                                                   R* __restrict__ mub, R* __restrict__ Wb_out,
-                                                   R* __restrict__ ubp, R* __restrict__ qbp,
-                                                   R* __restrict__ phibp) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4)))
+k_adj_order(Box b, Params<R> P, const FS* __restrict__ phi, const FS* __restrict__ q, const R* __restrict__ u,
+            const R* __restrict__ adj_phi, const R* __restrict__ adj_q, R* __restrict__ mub, R* __restrict__ Wb_out,
+            R* __restrict__ ubp, R* __restrict__ qbp, R* __restrict__ phibp) {
   const int s = site_xcd();
   if (s >= b.N) return;
   int x, y, z;
   coords(b, s, x, y, z);
   const size_t N = b.N;
   const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
-  R qc[5], qbar[5], W[3][3], uc[3], dq[3][5];
+  R qc[5], qbar[5], uc[3];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     qc[k] = R(q[k * N + s]);
@@ -80,28 +80,41 @@ __global__ void __launch_bounds__(256) k_adj_order(Box b, Params<R> P, const FS*
   for (int a = 0; a < 3; ++a) uc[a] = u[a * N + s];
   const R ph = R(phi[s]);
   const R pb0 = adj_phi[s];
-  R lap_pb = R(0), vb[3];
+  // neighbour values at x + e_g (d = 0) and x - e_g (d = 1)
+  R pbn[3][2], un[3][2][3], qn[3][2][5], aqn[3][2][5];
+#pragma unroll
+  for (int g = 0; g < 3; ++g)
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int sg = d == 0 ? 1 : -1;
+      const int sn = sidx(b, x + sg * off[g][0], y + sg * off[g][1], z + sg * off[g][2]);
+      pbn[g][d] = adj_phi[sn];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) un[g][d][a] = u[a * N + sn];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        qn[g][d][k] = R(q[k * N + sn]);
+        aqn[g][d][k] = adj_q[k * N + sn];
+      }
+    }
+  R lap_pb = -R(6) * pb0, vb[3], W[3][3], dq[3][5];
   R qb_out[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) qb_out[k] = qbar[k];
 #pragma unroll
   for (int g = 0; g < 3; ++g) {
-    const int sp = sidx(b, x + off[g][0], y + off[g][1], z + off[g][2]);
-    const int sm = sidx(b, x - off[g][0], y - off[g][1], z - off[g][2]);
-    const R pbp = adj_phi[sp], pbm = adj_phi[sm];
-    lap_pb += pbp + pbm;
-    vb[g] = R(0.5) * (pbp - pbm);  // adjoint of u_g phi at this site
+    lap_pb += pbn[g][0] + pbn[g][1];
+    vb[g] = R(0.5) * (pbn[g][0] - pbn[g][1]);  // adjoint of u_g phi at this site
 #pragma unroll
-    for (int a = 0; a < 3; ++a) W[a][g] = R(0.5) * (u[a * N + sp] - u[a * N + sm]);
-    const R ugp = u[g * N + sp], ugm = u[g * N + sm];
+    for (int a = 0; a < 3; ++a) W[a][g] = R(0.5) * (un[g][0][a] - un[g][1][a]);
+    const R ugp = un[g][0][g], ugm = un[g][1][g];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      dq[g][k] = R(0.5) * (R(q[k * N + sp]) - R(q[k * N + sm]));
+      dq[g][k] = R(0.5) * (qn[g][0][k] - qn[g][1][k]);
       // transpose of the advection: D0_g (u_g q_bar_k)
-      qb_out[k] += R(0.5) * (ugp * adj_q[k * N + sp] - ugm * adj_q[k * N + sm]);
+      qb_out[k] += R(0.5) * (ugp * aqn[g][0][k] - ugm * aqn[g][1][k]);
     }
   }
-  lap_pb -= R(6) * pb0;
   mub[s] = P.M * lap_pb;
   R ub[3], phib = pb0;
 #pragma unroll
@@ -189,12 +202,10 @@ __device__ __forceinline__ void store_gb(const GradBar<R>& Gb, R* __restrict__ o
 // the gradient data's own.  partial: one float64 pair (zeta, q0) per block,
 // overwritten (accumulate = 0) or added to (accumulate = 1).
 template <class R, class FS>
-__global__ void __launch_bounds__(256) k_adj_stress(Box b, Params<R> P, const FS* __restrict__ phi,
-                                                    const FS* __restrict__ q, const R* __restrict__ Fb,
-                                                    const R* __restrict__ adj_q, const R* __restrict__ mub,
-                                                    const R* __restrict__ qbp, const R* __restrict__ phibp,
-                                                    R* __restrict__ gbar, double* __restrict__ partial,
-                                                    int accumulate) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3)))
+k_adj_stress(Box b, Params<R> P, const FS* __restrict__ phi, const FS* __restrict__ q, const R* __restrict__ Fb,
+             const R* __restrict__ adj_q, const R* __restrict__ mub, const R* __restrict__ qbp,
+             const R* __restrict__ phibp, R* __restrict__ gbar, double* __restrict__ partial, int accumulate) {
   const int s = site_xcd();
   double v[2] = {0.0, 0.0};
   if (s < b.N) {
@@ -202,26 +213,75 @@ __global__ void __launch_bounds__(256) k_adj_stress(Box b, Params<R> P, const FS
     coords(b, s, x, y, z);
     const size_t N = b.N;
     const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    int sn[3][2];
+#pragma unroll
+    for (int g = 0; g < 3; ++g)
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const int sg = d == 0 ? 1 : -1;
+        sn[g][d] = sidx(b, x + sg * off[g][0], y + sg * off[g][1], z + sg * off[g][2]);
+      }
+    // ---- every load of the site first
+    R ph0 = R(phi[s]), q0[5], aq[5], qp[5];
+    const R mb0 = mub[s], pbp = phibp[s];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      q0[k] = R(q[k * N + s]);
+      aq[k] = adj_q[k * N + s];
+      qp[k] = qbp[k * N + s];
+    }
+    R phn[3][2], mbn[3][2], qn[3][2][5], Fn[3][2][3];
+#pragma unroll
+    for (int g = 0; g < 3; ++g)
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const int t = sn[g][d];
+        phn[g][d] = R(phi[t]);
+        mbn[g][d] = mub[t];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) qn[g][d][k] = R(q[k * N + t]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Fn[g][d][a] = Fb[a * N + t];
+      }
+    // ---- gradient data of the site (as the forward gathers it)
+    Grad<R> G;
+    G.phi = ph0;
+    R lap = R(0);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      G.q[k] = q0[k];
+      G.lapq[k] = R(0);
+    }
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      G.dphi[g] = R(0.5) * (phn[g][0] - phn[g][1]);
+      lap += phn[g][0] + phn[g][1];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        G.dq[g][k] = R(0.5) * (qn[g][0][k] - qn[g][1][k]);
+        G.lapq[k] += qn[g][0][k] + qn[g][1][k];
+      }
+    }
+    G.lapphi = lap - R(6) * G.phi;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) G.lapq[k] -= R(6) * G.q[k];
+    G.divv = R(0);  // mu's anchoring divergence is reversed below through v_bar
     // sigma_bar_ab = -D0_b F_bar_a;  v_bar_a = -D0_a divv_bar with divv_bar = -2 W mu_bar
     R sb[9], vb[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const int sp = sidx(b, x + off[c][0], y + off[c][1], z + off[c][2]);
-      const int sm = sidx(b, x - off[c][0], y - off[c][1], z - off[c][2]);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) sb[3 * a + c] = -R(0.5) * (Fb[a * N + sp] - Fb[a * N + sm]);
-      vb[c] = P.W * (mub[sp] - mub[sm]);
+      for (int a = 0; a < 3; ++a) sb[3 * a + c] = -R(0.5) * (Fn[c][0][a] - Fn[c][1][a]);
+      vb[c] = P.W * (mbn[c][0] - mbn[c][1]);
     }
-    Grad<R> G;
-    gather_grad<R>(b, phi, q, x, y, z, G);
     R hbs[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) hbs[k] = P.Gamma * adj_q[k * N + s];
+    for (int k = 0; k < 5; ++k) hbs[k] = P.Gamma * aq[k];
     GradBar<R> Gb;
     Gb.zero();
     ParBar<R> Pb{R(0), R(0), R(0)};
     sigma_site_bwd(P, G, sb, hbs, Gb, Pb);
-    mu_site_bwd(P, G.phi, G.q, mub[s], Gb.phi, Gb.lapphi, Gb.divv, Gb.q);
+    mu_site_bwd(P, G.phi, G.q, mb0, Gb.phi, Gb.lapphi, Gb.divv, Gb.q);
     // anchoring divergence: v_a = Q_ab D0_b phi  ->  Q_bar_ab += v_bar_a D0_b phi,
     // (D0_b phi)_bar += Q_ab v_bar_a
     {
@@ -236,9 +296,9 @@ __global__ void __launch_bounds__(256) k_adj_stress(Box b, Params<R> P, const FS
       Gb.dphi[1] += xy * vb[0] + yy * vb[1] + yz * vb[2];
       Gb.dphi[2] += xz * vb[0] + yz * vb[1] + zz * vb[2];
     }
-    Gb.phi += phibp[s];
+    Gb.phi += pbp;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) Gb.q[k] += qbp[k * N + s];
+    for (int k = 0; k < 5; ++k) Gb.q[k] += qp[k];
     store_gb(Gb, gbar, N, s);
     v[0] = double(Pb.zeta);
     v[1] = 2.0 * double(P.K) * double(Pb.kq) + 8.0 * double(P.K) * double(P.q0) * double(Pb.kq2);
@@ -247,36 +307,54 @@ __global__ void __launch_bounds__(256) k_adj_stress(Box b, Params<R> P, const FS
 }
 
 // Stencil transposes of the gradient data; writes Q_bar(t), phi_bar(t).
+// All 84 loads of a site are issued before any arithmetic (a wave keeps them
+// in flight together; the register budget allows 4 waves per SIMD).
 template <class R>
-__global__ void __launch_bounds__(256) k_adj_gather(Box b, const R* __restrict__ gbar, R* __restrict__ adj_phi,
-                                                    R* __restrict__ adj_q) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4)))
+k_adj_gather(Box b, const R* __restrict__ gbar, R* __restrict__ adj_phi, R* __restrict__ adj_q) {
   const int s = site_xcd();
   if (s >= b.N) return;
   int x, y, z;
   coords(b, s, x, y, z);
   const size_t N = b.N;
   const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
-  R pb = gbar[size_t(GB_PHI) * N + s];
-  R qb[5];
+  // own: phi, q[5], lapphi, lapq[5]; neighbour +-e_g: dphi_g, lapphi, dq_g[5], lapq[5]
+  constexpr int NF = 12;
+  R own[NF], nb[3][2][NF];
+  own[0] = gbar[size_t(GB_PHI) * N + s];
+  own[6] = gbar[size_t(GB_LAPPHI) * N + s];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) qb[k] = gbar[size_t(GB_Q + k) * N + s];
-  R lp = R(0), lq[5] = {R(0), R(0), R(0), R(0), R(0)};
-#pragma unroll
-  for (int g = 0; g < 3; ++g) {
-    const int sp = sidx(b, x + off[g][0], y + off[g][1], z + off[g][2]);
-    const int sm = sidx(b, x - off[g][0], y - off[g][1], z - off[g][2]);
-    pb -= R(0.5) * (gbar[size_t(GB_DPHI + g) * N + sp] - gbar[size_t(GB_DPHI + g) * N + sm]);
-    lp += gbar[size_t(GB_LAPPHI) * N + sp] + gbar[size_t(GB_LAPPHI) * N + sm];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      qb[k] -= R(0.5) * (gbar[size_t(GB_DQ + 5 * g + k) * N + sp] - gbar[size_t(GB_DQ + 5 * g + k) * N + sm]);
-      lq[k] += gbar[size_t(GB_LAPQ + k) * N + sp] + gbar[size_t(GB_LAPQ + k) * N + sm];
-    }
+  for (int k = 0; k < 5; ++k) {
+    own[1 + k] = gbar[size_t(GB_Q + k) * N + s];
+    own[7 + k] = gbar[size_t(GB_LAPQ + k) * N + s];
   }
-  pb += lp - R(6) * gbar[size_t(GB_LAPPHI) * N + s];
+#pragma unroll
+  for (int g = 0; g < 3; ++g)
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int sg = d == 0 ? 1 : -1;
+      const int sn = sidx(b, x + sg * off[g][0], y + sg * off[g][1], z + sg * off[g][2]);
+      R* v = nb[g][d];
+      v[0] = gbar[size_t(GB_DPHI + g) * N + sn];
+      v[1] = gbar[size_t(GB_LAPPHI) * N + sn];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        v[2 + k] = gbar[size_t(GB_DQ + 5 * g + k) * N + sn];
+        v[7 + k] = gbar[size_t(GB_LAPQ + k) * N + sn];
+      }
+    }
+  R pb = own[0] - R(6) * own[6];
+#pragma unroll
+  for (int g = 0; g < 3; ++g) pb += (nb[g][0][1] + nb[g][1][1]) - R(0.5) * (nb[g][0][0] - nb[g][1][0]);
   adj_phi[s] = pb;
 #pragma unroll
-  for (int k = 0; k < 5; ++k) adj_q[k * N + s] = qb[k] + lq[k] - R(6) * gbar[size_t(GB_LAPQ + k) * N + s];
+  for (int k = 0; k < 5; ++k) {
+    R qb = own[1 + k] - R(6) * own[7 + k];
+#pragma unroll
+    for (int g = 0; g < 3; ++g)
+      qb += (nb[g][0][7 + k] + nb[g][1][7 + k]) - R(0.5) * (nb[g][0][2 + k] - nb[g][1][2 + k]);
+    adj_q[k * N + s] = qb;
+  }
 }
 
 // out = in + 1 for the step counter of a recorded state (one thread, vector memory).

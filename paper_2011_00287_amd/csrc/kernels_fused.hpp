@@ -1,7 +1,8 @@
 // Fused kernels of the coupled step: two launches per step.
 //
 // k_lb_fused  : stress, force, pull-stream and Guo-forced BGK collision
-//               (Eqs. (3)-(4), (6)-(8), (10)-(11)) plus mu (Eq. (1));
+//               (Eqs. (3)-(4), (6)-(8), (10)-(11)) plus mu (Eq. (1), with the
+//               anchoring vector v = Q D0 phi taken from the stress pass);
 //               writes the post-collision populations, u and mu (and the
 //               force F when a recording step asks for it).
 // k_order_fused: molecular field H (Eq. (5)), Beris-Edwards update of Q
@@ -47,6 +48,7 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
   constexpr int NHALO = 2 * (TX + TY);                  // halo stress slots the force reads
   static_assert(NHALO <= NT && NT % 64 == 0, "one halo slot per thread, whole waves");
   __shared__ R sSig[6][NS];  // sigma_ax (a = 0..2), then sigma_ay
+  __shared__ R sV[2][2][NS];  // anchoring vector v_x, v_y of the stress slots, planes by parity
   __shared__ int sGX[AX], sGY[AY];
 
   const int l = xcd_remap(blockIdx.x, gridDim.x);
@@ -96,6 +98,7 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
 
   // column registers: sigma_az at planes p-2, p-1 and the in-plane force part at p-1
   R saz_m2[3] = {R(0), R(0), R(0)}, saz_m1[3] = {R(0), R(0), R(0)}, fin_m1[3] = {R(0), R(0), R(0)};
+  R vz_m2 = R(0), vz_m1 = R(0);  // v_z of the owned column at planes p-2, p-1
 
   // pull offsets of the owned column: in-plane byte offsets of the 9 (x, y) neighbours
   const int xw = active ? x : 0, yw = active ? y : 0;
@@ -150,7 +153,8 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
     // y0-1, y0+TY and columns x0-1, x0+TX; corners are not needed).  The halo
     // slots go to whole waves, starting at a wave that rotates with the plane
     // and the workgroup, so the extra round is spread over the SIMDs.
-    R saz[3];
+    R saz[3], vz = R(0);
+    const int vbuf = p & 1;
     {
       constexpr int NW = NT / 64 > 0 ? NT / 64 : 1;
       const int shift = ((p + 1 + l) % NW) * 64;
@@ -193,66 +197,40 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
           G.dq[2][c] = R(0.5) * (qzp - qzm);
           G.lapq[c] = ((qxp + qxm) + (qyp + qym) + (qzp + qzm)) - R(6) * qc;
         }
-        R h[5], sig[9];
-        sigma_site(P, G, sig, h);
+        R h[5], sig[9], vq[3];
+        sigma_site(P, G, sig, h, vq);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           sSig[a][s] = sig[3 * a + 0];
           sSig[3 + a][s] = sig[3 * a + 1];
         }
+        sV[vbuf][0][s] = vq[0];
+        sV[vbuf][1][s] = vq[1];
         if (r == 0) {
 #pragma unroll
           for (int a = 0; a < 3; ++a) saz[a] = sig[3 * a + 2];
+          vz = vq[2];
         }
       }
     }
 
-    // ---- mu at the owned site of plane p
-    if (active && p >= z0 && p < z1) {
+    // ---- mu at the owned site of plane p-1 (the collision plane): its
+    // anchoring divergence D0_a v_a takes v_x, v_y of plane p-1 from the
+    // stress slots and v_z of planes p-2, p from the column registers.  It
+    // reads phi p-2 and Q p-1, so it runs before the rings are refilled.
+    if (collide) {
       const int a0 = (ly + 2) * AX + (lx + 2);
-      const R ph = sPhi[r0][a0];
-      const R lapphi = ((sPhi[r0][a0 + 1] + sPhi[r0][a0 - 1]) + (sPhi[r0][a0 + AX] + sPhi[r0][a0 - AX]) +
-                        (sPhi[rp][a0] + sPhi[rm][a0])) - R(6) * ph;
-      // v_a(y) = Q_ab(y) D0_b phi(y) at y = x +- e_a, divv = sum_a D0_a v_a
-      R divv = R(0);
-      {
-        // a = x: rows x of Q at x+-1 (plane p)
-        const int kp = a0 + 1, km = a0 - 1;
-        const R vp = sQ[c0][0][kp] * (R(0.5) * (sPhi[r0][kp + 1] - sPhi[r0][kp - 1])) +
-                     sQ[c0][1][kp] * (R(0.5) * (sPhi[r0][kp + AX] - sPhi[r0][kp - AX])) +
-                     sQ[c0][2][kp] * (R(0.5) * (sPhi[rp][kp] - sPhi[rm][kp]));
-        const R vm = sQ[c0][0][km] * (R(0.5) * (sPhi[r0][km + 1] - sPhi[r0][km - 1])) +
-                     sQ[c0][1][km] * (R(0.5) * (sPhi[r0][km + AX] - sPhi[r0][km - AX])) +
-                     sQ[c0][2][km] * (R(0.5) * (sPhi[rp][km] - sPhi[rm][km]));
-        divv += R(0.5) * (vp - vm);
-      }
-      {
-        // a = y: rows y at y+-1
-        const int kp = a0 + AX, km = a0 - AX;
-        const R vp = sQ[c0][1][kp] * (R(0.5) * (sPhi[r0][kp + 1] - sPhi[r0][kp - 1])) +
-                     sQ[c0][3][kp] * (R(0.5) * (sPhi[r0][kp + AX] - sPhi[r0][kp - AX])) +
-                     sQ[c0][4][kp] * (R(0.5) * (sPhi[rp][kp] - sPhi[rm][kp]));
-        const R vm = sQ[c0][1][km] * (R(0.5) * (sPhi[r0][km + 1] - sPhi[r0][km - 1])) +
-                     sQ[c0][3][km] * (R(0.5) * (sPhi[r0][km + AX] - sPhi[r0][km - AX])) +
-                     sQ[c0][4][km] * (R(0.5) * (sPhi[rp][km] - sPhi[rm][km]));
-        divv += R(0.5) * (vp - vm);
-      }
-      {
-        // a = z: rows z at z+-1 (Q planes p+-1, phi planes p, p+-2)
-        const R qxzp = sQ[cp][2][a0], qyzp = sQ[cp][4][a0], qzzp = -sQ[cp][0][a0] - sQ[cp][3][a0];
-        const R vp = qxzp * (R(0.5) * (sPhi[rp][a0 + 1] - sPhi[rp][a0 - 1])) +
-                     qyzp * (R(0.5) * (sPhi[rp][a0 + AX] - sPhi[rp][a0 - AX])) +
-                     qzzp * (R(0.5) * (sPhi[rp2][a0] - sPhi[r0][a0]));
-        const R qxzm = sQ[cm][2][a0], qyzm = sQ[cm][4][a0], qzzm = -sQ[cm][0][a0] - sQ[cm][3][a0];
-        const R vm = qxzm * (R(0.5) * (sPhi[rm][a0 + 1] - sPhi[rm][a0 - 1])) +
-                     qyzm * (R(0.5) * (sPhi[rm][a0 + AX] - sPhi[rm][a0 - AX])) +
-                     qzzm * (R(0.5) * (sPhi[r0][a0] - sPhi[rm2][a0]));
-        divv += R(0.5) * (vp - vm);
-      }
+      const int s0 = (ly + 1) * SX + (lx + 1);
+      const int vb = vbuf ^ 1;
+      const R ph = sPhi[rm][a0];
+      const R lapphi = ((sPhi[rm][a0 + 1] + sPhi[rm][a0 - 1]) + (sPhi[rm][a0 + AX] + sPhi[rm][a0 - AX]) +
+                        (sPhi[r0][a0] + sPhi[rm2][a0])) - R(6) * ph;
+      const R divv = R(0.5) * (sV[vb][0][s0 + 1] - sV[vb][0][s0 - 1]) +
+                     R(0.5) * (sV[vb][1][s0 + SX] - sV[vb][1][s0 - SX]) + R(0.5) * (vz - vz_m2);
       R qs[5];
 #pragma unroll
-      for (int c = 0; c < 5; ++c) qs[c] = sQ[c0][c][a0];
-      sto(mu_out, uint32_t(p) * plane_r + own_r, mu_site(P, ph, lapphi, divv, qs));
+      for (int c = 0; c < 5; ++c) qs[c] = sQ[cm][c][a0];
+      sto(mu_out, uint32_t(zc) * plane_r + own_r, mu_site(P, ph, lapphi, divv, qs));
     }
     __syncthreads();  // stress of plane p is complete; ring slots of phi p-2 and Q p-1 are free
 
@@ -296,6 +274,8 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
       saz_m1[a] = saz[a];
       fin_m1[a] = fin[a];
     }
+    vz_m2 = vz_m1;
+    vz_m1 = vz;
     // advance the uniform indices to plane p+1
     r0 = rp;
     c0 = cp;

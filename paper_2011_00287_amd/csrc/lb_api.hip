@@ -64,21 +64,30 @@ int env_int(const char* name, int dflt) {
 
 // x-y tiles of the fused kernels.  The stress kernel computes the stress on
 // the (TX+2) x (TY+2) frame of a TX x TY tile; LDS per workgroup is about
-// 20 (TX+4)(TY+4) + 6 (TX+2)(TY+2) + 3 TX TY values.  The variant is chosen at context
-// creation (LBC_LB_TILE / LBC_OR_TILE select another one for tuning).
+// 20 (TX+4)(TY+4) + 10 (TX+2)(TY+2) values.  The variant is chosen at context
+// creation (LBC_LB_TILE / LBC_OR_TILE select another one for tuning; in
+// double, the 32 x 16 tile is replaced by 16 x 16).
 struct TileCfg {
   int tx, ty;
 };
 constexpr TileCfg kLbTiles[] = {{32, 8}, {32, 16}, {64, 4}, {16, 16}, {16, 8}};
 constexpr TileCfg kOrTiles[] = {{32, 8}, {64, 4}, {32, 16}, {64, 8}};
 
-template <class R>
+// Default tiles and slab depths per storage (measured on the 128^3 droplet):
+// float 32 x 8 with 16-plane slabs; half populations 16 x 8 with 11-plane
+// slabs; double 16 x 8 with 16-plane slabs (its register and LDS footprint
+// leaves one or two small workgroups per CU).
+template <class R, class GS>
 struct DefaultTile {
-  static constexpr int lb = 0, order = 0;
+  static constexpr int lb = 0, order = 0, tz_lb = 16, tz_order = 8;
 };
 template <>
-struct DefaultTile<double> {
-  static constexpr int lb = 4, order = 0;
+struct DefaultTile<float, __half> {
+  static constexpr int lb = 4, order = 0, tz_lb = 11, tz_order = 8;
+};
+template <>
+struct DefaultTile<double, double> {
+  static constexpr int lb = 4, order = 0, tz_lb = 16, tz_order = 8;
 };
 
 bool finite_params(const lb_params& p) {
@@ -190,12 +199,14 @@ struct BackendT final : Backend {
     nblk = unsigned((N + TPB - 1) / TPB);
     set_params(p);
     site_path = env_int("LBC_SITE_KERNELS", 0) != 0;
-    tz_lb = std::max(1, env_int("LBC_TZ_LB", 16));
-    tz_or = std::max(1, env_int("LBC_TZ_ORDER", 8));
-    lb_tile = env_int("LBC_LB_TILE", DefaultTile<R>::lb);
-    or_tile = env_int("LBC_OR_TILE", DefaultTile<R>::order);
-    if (lb_tile < 0 || lb_tile >= int(sizeof(kLbTiles) / sizeof(kLbTiles[0]))) lb_tile = DefaultTile<R>::lb;
-    if (or_tile < 0 || or_tile >= int(sizeof(kOrTiles) / sizeof(kOrTiles[0]))) or_tile = DefaultTile<R>::order;
+    using D = DefaultTile<R, GS>;
+    tz_lb = std::max(1, env_int("LBC_TZ_LB", D::tz_lb));
+    tz_or = std::max(1, env_int("LBC_TZ_ORDER", D::tz_order));
+    lb_tile = env_int("LBC_LB_TILE", D::lb);
+    or_tile = env_int("LBC_OR_TILE", D::order);
+    if (lb_tile < 0 || lb_tile >= int(sizeof(kLbTiles) / sizeof(kLbTiles[0]))) lb_tile = D::lb;
+    if (sizeof(R) == 8 && lb_tile == 1) lb_tile = 3;  // 32 x 16 needs more than 160 KB of LDS in double
+    if (or_tile < 0 || or_tile >= int(sizeof(kOrTiles) / sizeof(kOrTiles[0]))) or_tile = D::order;
     const TileCfg lt = kLbTiles[lb_tile], ot = kOrTiles[or_tile];
     lb_ntx = (p.nx + lt.tx - 1) / lt.tx;
     lb_nty = (p.ny + lt.ty - 1) / lt.ty;
@@ -359,13 +370,7 @@ struct BackendT final : Backend {
     }
     const Io io = cur_io();
     if (k == 0) {
-      switch (lb_tile) {
-        case 0: launch_lb<32, 8, 2>(io); break;
-        case 1: launch_lb<32, 16, (sizeof(R) == 4 ? 2 : 1)>(io); break;
-        case 2: launch_lb<64, 4, 2>(io); break;
-        case 3: launch_lb<16, 16, 2>(io); break;
-        default: launch_lb<16, 8, 1>(io); break;
-      }
+      launch_lb_tile(io);
     } else {
       switch (or_tile) {
         case 0: launch_or<32, 8, 2>(io); break;
@@ -388,6 +393,17 @@ struct BackendT final : Backend {
     R* F;
   };
   Io cur_io() { return Io{B[cur], B[cur ^ 1], Ph[cur], Q[cur], Ph[cur ^ 1], Q[cur ^ 1], u, nullptr}; }
+  void launch_lb_tile(const Io& io) {
+    switch (lb_tile) {
+      case 0: launch_lb<32, 8, 2>(io); break;
+      case 1:  // float only: the double 32 x 16 frame does not fit the LDS (mapped to 16 x 16 at creation)
+        if constexpr (sizeof(R) == 4) launch_lb<32, 16, 2>(io);
+        break;
+      case 2: launch_lb<64, 4, 2>(io); break;
+      case 3: launch_lb<16, 16, 2>(io); break;
+      default: launch_lb<16, 8, 1>(io); break;
+    }
+  }
   template <int TX, int TY, int MINW>
   void launch_lb(const Io& io) {
     lbc::k_lb_fused<R, GS, FS, TX, TY, MINW><<<lb_blocks, TX * TY, 0, stream>>>(
@@ -400,13 +416,7 @@ struct BackendT final : Backend {
   }
   // the fused pair on explicit buffers
   void fused_step(const Io& io) {
-    switch (lb_tile) {
-      case 0: launch_lb<32, 8, 2>(io); break;
-      case 1: launch_lb<32, 16, (sizeof(R) == 4 ? 2 : 1)>(io); break;
-      case 2: launch_lb<64, 4, 2>(io); break;
-      case 3: launch_lb<16, 16, 2>(io); break;
-      default: launch_lb<16, 8, 1>(io); break;
-    }
+    launch_lb_tile(io);
     switch (or_tile) {
       case 0: launch_or<32, 8, 2>(io); break;
       case 1: launch_or<64, 4, 2>(io); break;

@@ -134,10 +134,12 @@ __host__ __device__ __forceinline__ R sdot(const R* A, const R* B) {
   return A[0] * B[0] + A[3] * B[3] + azz * bzz + R(2) * (A[1] * B[1] + A[2] * B[2] + A[4] * B[4]);
 }
 
-// Full stress sig[3*a + b] (a = force component, b = derivative index) and the
-// molecular field h (5 components) of one site.
+// Full stress sig[3*a + b] (a = force component, b = derivative index), the
+// molecular field h (5 components) and the anchoring vector vq_a = Q_ab D0_b phi
+// (whose divergence enters mu) of one site.
 template <class R>
-__host__ __device__ __forceinline__ void sigma_site(const Params<R>& P, const Grad<R>& G, R sig[9], R h[5]) {
+__host__ __device__ __forceinline__ void sigma_site(const Params<R>& P, const Grad<R>& G, R sig[9], R h[5],
+                                                   R vq[3]) {
   Local<R> L;
   local_thermo(P, G, L);
   const R xx = L.xx, xy = L.xy, xz = L.xz, yy = L.yy, yz = L.yz, zz = L.zz;
@@ -200,6 +202,14 @@ __host__ __device__ __forceinline__ void sigma_site(const Params<R>& P, const Gr
     }
 #pragma unroll
   for (int k = 0; k < 5; ++k) h[k] = L.h[k];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) vq[a] = Qd[a];
+}
+
+template <class R>
+__host__ __device__ __forceinline__ void sigma_site(const Params<R>& P, const Grad<R>& G, R sig[9], R h[5]) {
+  R vq[3];
+  sigma_site(P, G, sig, h, vq);
 }
 
 // Chemical potential mu = dF/dphi from phi, its laplacian, the anchoring
@@ -255,8 +265,13 @@ __host__ __device__ __forceinline__ void corotation_site(R xi, const R q[5], con
 }
 
 // BGK collision with Guo forcing on the 19 deviations g (in place).
-// rho = rho0 + sum g, u = (sum c g + F/2)/rho; returns u.  Opposite pairs
-// (i, i+1) share the even part of g_eq and of the source.
+// rho = rho0 + sum g, u = (sum c g + F/2)/rho; returns u.  With cu = c_i.u,
+// cF = c_i.F, the equilibrium and source of population i are
+//   g_eq_i = w (A + 3 rho cu + 4.5 rho cu^2),  A = (rho - rho0) - 1.5 rho u.u
+//   src_i  = guo w (-3 u.F + 3 cF + 9 cu cF)
+// and opposite pairs (i, i+1) share the even part in cu and differ in the
+// sign of the odd part.  The weight w and the relaxation factors are folded
+// into per-class constants, so a pair costs a few fused multiply-adds.
 template <class R>
 __host__ __device__ __forceinline__ void collide_site(const Params<R>& P, R g[19], const R F[3], R u[3]) {
   R drho = g[0];
@@ -275,21 +290,31 @@ __host__ __device__ __forceinline__ void collide_site(const Params<R>& P, R g[19
   const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   const R uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
   const R om = P.omega, om1 = R(1) - P.omega;
-  // g_eq_i = w (A + 3 rho cu + 4.5 rho cu^2); src_i = guo w (Bs + 3 cF + 9 cu cF)
-  const R A = drho - R(1.5) * rho * uu;
-  const R Bs = R(-3) * uF;
-  const R r3 = R(3) * rho, r45 = R(4.5) * rho;
-  g[0] = om1 * g[0] + WQ<R>(0) * (om * A + P.guo * Bs);
+  // w-free coefficients: even = w (base + cu (a45 cu + g9 cF)), odd = w (r3 cu + g3 cF)
+  const R base = om * (drho - R(1.5) * rho * uu) - R(3) * P.guo * uF;
+  const R a45 = R(4.5) * om * rho, g9 = R(9) * P.guo;
+  const R r3 = R(3) * om * rho, g3 = R(3) * P.guo;
+  R cb[2], ca[2], cg9[2], cr[2], cg3[2];  // class 0: axis (w = 1/18), class 1: edge (w = 1/36)
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const R w = WQ<R>(k == 0 ? 1 : 7);
+    cb[k] = w * base;
+    ca[k] = w * a45;
+    cg9[k] = w * g9;
+    cr[k] = w * r3;
+    cg3[k] = w * g3;
+  }
+  g[0] = om1 * g[0] + WQ<R>(0) * base;
 #pragma unroll
   for (int i = 1; i < 19; i += 2) {
+    const int k = i < 7 ? 0 : 1;
     const R cu = R(CX(i)) * u[0] + R(CY(i)) * u[1] + R(CZ(i)) * u[2];
     const R cF = R(CX(i)) * F[0] + R(CY(i)) * F[1] + R(CZ(i)) * F[2];
-    const R w = WQ<R>(i);
-    const R even = w * (om * (A + r45 * cu * cu) + P.guo * (Bs + R(9) * cu * cF));
-    const R odd = w * (om * (r3 * cu) + P.guo * (R(3) * cF));
+    const R even = cb[k] + cu * (ca[k] * cu + cg9[k] * cF);
+    const R odd = cr[k] * cu + cg3[k] * cF;
     const R gi = g[i], gj = g[i + 1];
-    g[i] = om1 * gi + (even + odd);
-    g[i + 1] = om1 * gj + (even - odd);
+    g[i] = (om1 * gi + even) + odd;
+    g[i + 1] = (om1 * gj + even) - odd;
   }
 }
 
