@@ -289,8 +289,10 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
 
 // ---------------------------------------------------------------------------
 // k_order_fused
-//   LDS holds plane z of (Q, phi, u, mu) on the tile plus a halo of 1; the
+//   LDS holds plane z of (Q, phi, u, mu) on the tile plus the halo the
+//   stencils read (rows y0-1, y0+TY and columns x0-1, x0+TX; no corners); the
 //   owned column keeps planes z-1, z, z+1 of the same fields in registers.
+//   The halo of plane z+1 is loaded into registers while plane z is computed.
 // ---------------------------------------------------------------------------
 template <class R, class FS, int TX, int TY, int MINW>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(MINW))) k_order_fused(Box b, Params<R> P, int TZ, int ntx, int nty,
@@ -299,8 +301,9 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(MIN
                                                         FS* __restrict__ phi_out, FS* __restrict__ q_out) {
   constexpr int NT = TX * TY;
   constexpr int SX = TX + 2, SY = TY + 2, NS = SX * SY;
-  constexpr int NH = NS - NT;  // halo slots
-  constexpr int NV = 10;       // q[5], phi, u[3], mu
+  constexpr int NH = 2 * (TX + TY);  // halo slots read by the stencils
+  static_assert(NH <= NT, "one halo slot per thread");
+  constexpr int NV = 10;             // q[5], phi, u[3], mu
   __shared__ R sV[NV][NS];
   __shared__ int sGX[SX], sGY[SY];
 
@@ -320,8 +323,7 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(MIN
   const int x = sGX[lx + 1], y = sGY[ly + 1];  // wrapped coordinates of the column
   const int col = y * b.nx + x;
 
-  auto load_col = [&](int zz, R v[NV]) {
-    const size_t k = size_t(pmod(zz, b.nz)) * plane + col;
+  auto load_at = [&](size_t k, R v[NV]) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) v[c] = R(q[c * N + k]);
     v[5] = R(phi[k]);
@@ -329,34 +331,40 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(MIN
     for (int a = 0; a < 3; ++a) v[6 + a] = u[a * N + k];
     v[9] = mu[k];
   };
+  auto load_col = [&](int zz, R v[NV]) { load_at(size_t(pmod(zz, b.nz)) * plane + col, v); };
   R vm[NV], v0[NV], vp[NV];
   load_col(z0 - 1, vm);
   load_col(z0, v0);
   load_col(z0 + 1, vp);
 
-  // halo slot s -> (slot index, wrapped column) pairs, fixed over the march
+  // this thread's halo slot (rows first, then columns), fixed over the march
+  const bool has_halo = tid < NH;
+  int hs = 0, hcol = 0;
+  if (has_halo) {
+    int hx, hy;
+    if (tid < 2 * TX) {
+      hx = 1 + (tid % TX);
+      hy = tid < TX ? 0 : SY - 1;
+    } else {
+      const int r = tid - 2 * TX;
+      hx = r < TY ? 0 : SX - 1;
+      hy = 1 + (r % TY);
+    }
+    hs = hy * SX + hx;
+    hcol = sGY[hy] * b.nx + sGX[hx];
+  }
+  R hv[NV];
+  if (has_halo) load_at(size_t(z0) * plane + hcol, hv);
+
   const int sc = (ly + 1) * SX + (lx + 1);
   for (int zc = z0; zc < z1; ++zc) {
     __syncthreads();  // previous plane's reads are done
 #pragma unroll
     for (int c = 0; c < NV; ++c) sV[c][sc] = v0[c];
-    {
-      const size_t zoff = size_t(zc) * plane;
-      for (int h = tid; h < NH; h += NT) {
-        // enumerate the border of the SX x SY frame
-        int sx, sy;
-        if (h < SX) { sx = h; sy = 0; }
-        else if (h < 2 * SX) { sx = h - SX; sy = SY - 1; }
-        else { const int r = h - 2 * SX; sx = (r & 1) ? SX - 1 : 0; sy = 1 + (r >> 1); }
-        const int s = sy * SX + sx;
-        const size_t k = zoff + sGY[sy] * b.nx + sGX[sx];
+    if (has_halo) {
 #pragma unroll
-        for (int c = 0; c < 5; ++c) sV[c][s] = R(q[c * N + k]);
-        sV[5][s] = R(phi[k]);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) sV[6 + a][s] = u[a * N + k];
-        sV[9][s] = mu[k];
-      }
+      for (int c = 0; c < NV; ++c) sV[c][hs] = hv[c];
+      if (zc + 1 < z1) load_at(size_t(zc + 1) * plane + hcol, hv);  // next plane's halo
     }
     __syncthreads();
     if (active) {

@@ -66,28 +66,31 @@ int env_int(const char* name, int dflt) {
 // the (TX+2) x (TY+2) frame of a TX x TY tile; LDS per workgroup is about
 // 20 (TX+4)(TY+4) + 10 (TX+2)(TY+2) values.  The variant is chosen at context
 // creation (LBC_LB_TILE / LBC_OR_TILE select another one for tuning; in
-// double, the 32 x 16 tile is replaced by 16 x 16).
+// double, the 32 x 16 stress tile is replaced by 16 x 16 and the 64 x 16
+// order tile by 64 x 8).
 struct TileCfg {
   int tx, ty;
 };
 constexpr TileCfg kLbTiles[] = {{32, 8}, {32, 16}, {64, 4}, {16, 16}, {16, 8}};
-constexpr TileCfg kOrTiles[] = {{32, 8}, {64, 4}, {32, 16}, {64, 8}};
+constexpr TileCfg kOrTiles[] = {{32, 8}, {64, 4}, {32, 16}, {64, 8}, {64, 16}};
 
-// Default tiles and slab depths per storage (measured on the 128^3 droplet):
-// float 32 x 8 with 16-plane slabs; half populations 16 x 8 with 11-plane
-// slabs; double 16 x 8 with 16-plane slabs (its register and LDS footprint
-// leaves one or two small workgroups per CU).
+// Default tiles and slab depths per storage (measured on the 128^3 and
+// 256^3 droplets): stress kernel float 32 x 8 with 16-plane slabs, half
+// populations 16 x 8 with 11-plane slabs, double 16 x 8 with 16-plane slabs
+// (its register and LDS footprint leaves one or two small workgroups per
+// CU); order kernel 64 x 8 with the deepest slab of at most 16 planes that
+// still gives two workgroups per CU (tz_order = 0 selects it).
 template <class R, class GS>
 struct DefaultTile {
-  static constexpr int lb = 0, order = 0, tz_lb = 16, tz_order = 8;
+  static constexpr int lb = 0, order = 3, tz_lb = 16, tz_order = 0;
 };
 template <>
 struct DefaultTile<float, __half> {
-  static constexpr int lb = 4, order = 0, tz_lb = 11, tz_order = 8;
+  static constexpr int lb = 4, order = 3, tz_lb = 11, tz_order = 0;
 };
 template <>
 struct DefaultTile<double, double> {
-  static constexpr int lb = 4, order = 0, tz_lb = 16, tz_order = 8;
+  static constexpr int lb = 4, order = 3, tz_lb = 16, tz_order = 0;
 };
 
 bool finite_params(const lb_params& p) {
@@ -201,18 +204,25 @@ struct BackendT final : Backend {
     site_path = env_int("LBC_SITE_KERNELS", 0) != 0;
     using D = DefaultTile<R, GS>;
     tz_lb = std::max(1, env_int("LBC_TZ_LB", D::tz_lb));
-    tz_or = std::max(1, env_int("LBC_TZ_ORDER", D::tz_order));
+    tz_or = std::max(0, env_int("LBC_TZ_ORDER", D::tz_order));
     lb_tile = env_int("LBC_LB_TILE", D::lb);
     or_tile = env_int("LBC_OR_TILE", D::order);
     if (lb_tile < 0 || lb_tile >= int(sizeof(kLbTiles) / sizeof(kLbTiles[0]))) lb_tile = D::lb;
     if (sizeof(R) == 8 && lb_tile == 1) lb_tile = 3;  // 32 x 16 needs more than 160 KB of LDS in double
     if (or_tile < 0 || or_tile >= int(sizeof(kOrTiles) / sizeof(kOrTiles[0]))) or_tile = D::order;
+    if (sizeof(R) == 8 && or_tile == 4) or_tile = 3;  // 64 x 16 would spill in double
     const TileCfg lt = kLbTiles[lb_tile], ot = kOrTiles[or_tile];
     lb_ntx = (p.nx + lt.tx - 1) / lt.tx;
     lb_nty = (p.ny + lt.ty - 1) / lt.ty;
     lb_blocks = lb_ntx * lb_nty * ((p.nz + tz_lb - 1) / tz_lb);
     or_ntx = (p.nx + ot.tx - 1) / ot.tx;
     or_nty = (p.ny + ot.ty - 1) / ot.ty;
+    if (tz_or == 0) {  // deepest slab (<= 16 planes, >= 4) with two workgroups per CU
+      int dev = 0, ncu = 256;
+      if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+      tz_or = 16;
+      while (tz_or > 4 && size_t(or_ntx) * or_nty * ((p.nz + tz_or - 1) / tz_or) < size_t(2 * ncu)) tz_or /= 2;
+    }
     or_blocks = or_ntx * or_nty * ((p.nz + tz_or - 1) / tz_or);
     size_t need = 2 * (19 * N * sizeof(GS) + 6 * N * sizeof(FS)) + 18 * N * sizeof(R);
     size_t free_b = 0, total_b = 0;
@@ -372,12 +382,7 @@ struct BackendT final : Backend {
     if (k == 0) {
       launch_lb_tile(io);
     } else {
-      switch (or_tile) {
-        case 0: launch_or<32, 8, 2>(io); break;
-        case 1: launch_or<64, 4, 2>(io); break;
-        case 2: launch_or<32, 16, 2>(io); break;
-        default: launch_or<64, 8, 2>(io); break;
-      }
+      launch_or_tile(io);
       cur = nx;
     }
   }
@@ -409,6 +414,17 @@ struct BackendT final : Backend {
     lbc::k_lb_fused<R, GS, FS, TX, TY, MINW><<<lb_blocks, TX * TY, 0, stream>>>(
         box, P, tz_lb, lb_ntx, lb_nty, io.Bi, io.Bo, io.phi_i, io.q_i, io.u, mu, io.F);
   }
+  void launch_or_tile(const Io& io) {
+    switch (or_tile) {
+      case 0: launch_or<32, 8, 2>(io); break;
+      case 1: launch_or<64, 4, 2>(io); break;
+      case 2: launch_or<32, 16, 2>(io); break;
+      case 3: launch_or<64, 8, 2>(io); break;
+      default:  // float only: 1024 threads need <= 128 VGPRs (double: mapped to 64 x 8 at creation)
+        if constexpr (sizeof(R) == 4) launch_or<64, 16, 4>(io);
+        break;
+    }
+  }
   template <int TX, int TY, int MINW>
   void launch_or(const Io& io) {
     lbc::k_order_fused<R, FS, TX, TY, MINW><<<or_blocks, TX * TY, 0, stream>>>(
@@ -417,12 +433,7 @@ struct BackendT final : Backend {
   // the fused pair on explicit buffers
   void fused_step(const Io& io) {
     launch_lb_tile(io);
-    switch (or_tile) {
-      case 0: launch_or<32, 8, 2>(io); break;
-      case 1: launch_or<64, 4, 2>(io); break;
-      case 2: launch_or<32, 16, 2>(io); break;
-      default: launch_or<64, 8, 2>(io); break;
-    }
+    launch_or_tile(io);
   }
   void step(int n) override {
     const int nk = nkernels();
