@@ -218,8 +218,10 @@ struct BackendT final : Backend {
     or_ntx = (p.nx + ot.tx - 1) / ot.tx;
     or_nty = (p.ny + ot.ty - 1) / ot.ty;
     if (tz_or == 0) {  // deepest slab (<= 16 planes, >= 4) with two workgroups per CU
-      int dev = 0, ncu = 256;
-      if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+      int dev = 0, ncu = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+        ncu = 256;
       tz_or = 16;
       while (tz_or > 4 && size_t(or_ntx) * or_nty * ((p.nz + tz_or - 1) / tz_or) < size_t(2 * ncu)) tz_or /= 2;
     }

@@ -30,16 +30,30 @@ struct GPol {
   __device__ __forceinline__ static void st(GS* p, size_t k, int, R v) { p[k] = GS(v); }
 };
 
+// Non-temporal (streaming) access for 32- and 64-bit populations: each value
+// is pulled once and the post-collision values are not read again within the
+// step, so their traffic is marked to leave the caches to the fields the
+// kernels re-read (u, mu, Q, phi and their halos).
+template <class T>
+__device__ __forceinline__ T ldo_nt(const T* __restrict__ base, uint32_t byteoff) {
+  return __builtin_nontemporal_load(reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byteoff));
+}
+template <class T>
+__device__ __forceinline__ void sto_nt(T* __restrict__ base, uint32_t byteoff, T v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byteoff));
+}
+
 template <class GS>
 struct GPolO {
-  // element k of the population array starting at base, by byte offset
+  // element of the population array starting at base, by byte offset (streaming)
   template <class R>
-  __device__ __forceinline__ static R ld(const GS* base, uint32_t off, int) { return R(ldo(base, off)); }
+  __device__ __forceinline__ static R ld(const GS* base, uint32_t off, int) { return R(ldo_nt(base, off)); }
   template <class R>
-  __device__ __forceinline__ static void st(GS* base, uint32_t off, int, R v) { sto(base, off, GS(v)); }
+  __device__ __forceinline__ static void st(GS* base, uint32_t off, int, R v) { sto_nt(base, off, GS(v)); }
 };
 template <>
 struct GPolO<__half> {
+  // ordinary (cached) access: 16-bit streaming accesses measured much slower
   template <class R>
   __device__ __forceinline__ static R ld(const __half* base, uint32_t off, int i) {
     return R(__half2float(ldo(base, off))) * (WQ<R>(i) * R(1.0 / 64.0));
