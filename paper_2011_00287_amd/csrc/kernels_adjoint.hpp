@@ -163,15 +163,21 @@ __global__ void __launch_bounds__(256) k_adj_collide(Box b, Params<R> P, const G
   R g[19], gsb[19], Fs[3];
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
-    g[i] = GPol<GS>::template ld<R>(B, i * N + sidx(b, x - CX(i), y - CY(i), z - CZ(i)), i);
-    gsb[i] = adj_g[i * N + sidx(b, x + CX(i), y + CY(i), z + CZ(i))];
+    // pulled populations and pushed adjoints are read once: streaming loads
+    // (32/64-bit storage; half storage keeps ordinary loads)
+    const int sp = sidx(b, x - CX(i), y - CY(i), z - CZ(i));
+    if constexpr (sizeof(GS) >= 4)
+      g[i] = R(__builtin_nontemporal_load(B + i * N + sp));
+    else
+      g[i] = GPol<GS>::template ld<R>(B, i * N + sp, i);
+    gsb[i] = __builtin_nontemporal_load(adj_g + i * N + sidx(b, x + CX(i), y + CY(i), z + CZ(i)));
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) Fs[a] = F[a * N + s];
   R gb[19], Fb[3] = {R(0), R(0), R(0)};
   collide_site_bwd(P, g, Fs, gsb, ub, gb, Fb);
 #pragma unroll
-  for (int i = 0; i < 19; ++i) g_out[i * N + s] = gb[i];
+  for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(gb[i], g_out + i * N + s);
 #pragma unroll
   for (int a = 0; a < 3; ++a) Fb_out[a * N + s] = Fb[a];
 }
