@@ -1,4 +1,4 @@
-// Site-parallel kernels of the adjoint (reverse) of one coupled step.
+// Kernels of the adjoint (reverse) of one coupled step.
 //
 // Given the state at time t and the adjoint of the state at t+1 (adjoints of
 // the post-stream populations g, the 5 stored Q components and phi), the
@@ -10,6 +10,7 @@
 // Order (each a launch; the forward u and F of time t come from a recording
 // step, or are recomputed by k_thermo and k_fwd_force):
 //   k_adj_order   : phi, Q updates (Eqs. (1), (2))  -> mu_bar, W_bar, partial u_bar, Q_bar, phi_bar
+//                   (site-parallel, or z-marching over LDS tiles: k_adj_order_fused)
 //   k_adj_collide : collision + stream (Eqs. (6)-(8), (10)-(11)) -> g_bar(t), F_bar
 //   k_adj_stress  : stress, H, mu (Eqs. (3)-(5)), including the anchoring
 //                   divergence D0_a(Q_ab D0_b phi) of mu, whose adjoint
@@ -57,8 +58,67 @@ __global__ void __launch_bounds__(256) k_fwd_force(Box b, Params<R> P, const GS*
 // Reverse of the Q and phi updates at one site.
 //   phi' = phi - sum_g D0_g(u_g phi) + M lap(mu)
 //   q'   = q - u.D0 q + S(q, W(u)) + Gamma h
-// All loads of a site (own values and the 6 neighbours) are issued before the
-// arithmetic.
+// Own values: qc, u, phi at x; qbar, pb0 the adjoints of q', phi' at x.
+// Neighbour values at x + e_g (index [g][0]) and x - e_g ([g][1]): phi
+// adjoint pbn, u, q and q adjoint aqn.  Outputs: mu_bar, W_bar (3x3),
+// the local parts of u_bar, Q_bar, phi_bar.
+template <class R>
+__device__ __forceinline__ void adj_order_site(const Params<R>& P, const R qc[5], const R qbar[5], const R uc[3], R ph,
+                                               R pb0, const R pbn[3][2], const R un[3][2][3], const R qn[3][2][5],
+                                               const R aqn[3][2][5], R& mub, R Wb[3][3], R ub[3], R qb_out[5],
+                                               R& phib) {
+  R lap_pb = -R(6) * pb0, vb[3], W[3][3], dq[3][5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) qb_out[k] = qbar[k];
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    lap_pb += pbn[g][0] + pbn[g][1];
+    vb[g] = R(0.5) * (pbn[g][0] - pbn[g][1]);  // adjoint of u_g phi at this site
+#pragma unroll
+    for (int a = 0; a < 3; ++a) W[a][g] = R(0.5) * (un[g][0][a] - un[g][1][a]);
+    const R ugp = un[g][0][g], ugm = un[g][1][g];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      dq[g][k] = R(0.5) * (qn[g][0][k] - qn[g][1][k]);
+      // transpose of the advection: D0_g (u_g q_bar_k)
+      qb_out[k] += R(0.5) * (ugp * aqn[g][0][k] - ugm * aqn[g][1][k]);
+    }
+  }
+  mub = P.M * lap_pb;
+  phib = pb0;
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    ub[g] = vb[g] * ph;
+    phib += vb[g] * uc[g];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) ub[g] -= qbar[k] * dq[g][k];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Wb[a][c] = R(0);
+  corotation_site_bwd(P.xi, qc, W, qbar, qb_out, Wb);
+}
+
+template <class R>
+__device__ __forceinline__ void store_adj_order(size_t N, size_t s, R mub, const R Wb[3][3], const R ub[3],
+                                                const R qb[5], R phib, R* __restrict__ mub_out,
+                                                R* __restrict__ Wb_out, R* __restrict__ ubp, R* __restrict__ qbp,
+                                                R* __restrict__ phibp) {
+  mub_out[s] = mub;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Wb_out[(a * 3 + c) * N + s] = Wb[a][c];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ubp[a * N + s] = ub[a];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) qbp[k * N + s] = qb[k];
+  phibp[s] = phib;
+}
+
+// Site-parallel form: all loads of a site (own values and the 6 neighbours)
+// are issued before the arithmetic.
 template <class R, class FS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4)))
 k_adj_order(Box b, Params<R> P, const FS* __restrict__ phi, const FS* __restrict__ q, const R* __restrict__ u,
@@ -80,7 +140,6 @@ k_adj_order(Box b, Params<R> P, const FS* __restrict__ phi, const FS* __restrict
   for (int a = 0; a < 3; ++a) uc[a] = u[a * N + s];
   const R ph = R(phi[s]);
   const R pb0 = adj_phi[s];
-  // neighbour values at x + e_g (d = 0) and x - e_g (d = 1)
   R pbn[3][2], un[3][2][3], qn[3][2][5], aqn[3][2][5];
 #pragma unroll
   for (int g = 0; g < 3; ++g)
@@ -97,44 +156,140 @@ k_adj_order(Box b, Params<R> P, const FS* __restrict__ phi, const FS* __restrict
         aqn[g][d][k] = adj_q[k * N + sn];
       }
     }
-  R lap_pb = -R(6) * pb0, vb[3], W[3][3], dq[3][5];
-  R qb_out[5];
+  R m, Wb[3][3], ub[3], qb[5], pb;
+  adj_order_site(P, qc, qbar, uc, ph, pb0, pbn, un, qn, aqn, m, Wb, ub, qb, pb);
+  store_adj_order(N, size_t(s), m, Wb, ub, qb, pb, mub, Wb_out, ubp, qbp, phibp);
+}
+
+// z-marching form of k_adj_order: LDS holds plane z of the 14 stencil fields
+// (q[5], u[3], phi adjoint, q adjoint[5]) on a TX x TY tile plus the halo the
+// stencils read (no corners), the owned column keeps planes z-1, z, z+1 in
+// registers, and the halo of plane z+1 is loaded while plane z is computed.
+template <class R, class FS, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY)
+k_adj_order_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__ phi,
+                  const FS* __restrict__ q, const R* __restrict__ u, const R* __restrict__ adj_phi,
+                  const R* __restrict__ adj_q, R* __restrict__ mub, R* __restrict__ Wb_out, R* __restrict__ ubp,
+                  R* __restrict__ qbp, R* __restrict__ phibp) {
+  constexpr int NT = TX * TY;
+  constexpr int SX = TX + 2, SY = TY + 2, NS = SX * SY;
+  constexpr int NH = 2 * (TX + TY);
+  static_assert(NH <= NT, "one halo slot per thread");
+  constexpr int NV = 14;  // q[5], u[3], phi adjoint, q adjoint[5]
+  __shared__ R sV[NV][NS];
+  __shared__ int sGX[SX], sGY[SY];
+
+  const int l = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = l % ntx, ty = (l / ntx) % nty, sl = l / (ntx * nty);
+  const int x0 = tx * TX, y0 = ty * TY, z0 = sl * TZ;
+  const int z1 = min(z0 + TZ, b.nz);
+  const int tid = threadIdx.x;
+  const int lx = tid % TX, ly = tid / TX;
+  const bool active = (x0 + lx < b.nx) && (y0 + ly < b.ny);
+  const size_t N = b.N;
+  const int plane = b.nx * b.ny;
+
+  for (int k = tid; k < SX; k += NT) sGX[k] = pmod(x0 - 1 + k, b.nx);
+  for (int k = tid; k < SY; k += NT) sGY[k] = pmod(y0 - 1 + k, b.ny);
+  __syncthreads();
+  const int col = sGY[ly + 1] * b.nx + sGX[lx + 1];
+
+  auto load_at = [&](size_t k, R v[NV]) {
 #pragma unroll
-  for (int k = 0; k < 5; ++k) qb_out[k] = qbar[k];
+    for (int c = 0; c < 5; ++c) v[c] = R(q[c * N + k]);
 #pragma unroll
-  for (int g = 0; g < 3; ++g) {
-    lap_pb += pbn[g][0] + pbn[g][1];
-    vb[g] = R(0.5) * (pbn[g][0] - pbn[g][1]);  // adjoint of u_g phi at this site
+    for (int a = 0; a < 3; ++a) v[5 + a] = u[a * N + k];
+    v[8] = adj_phi[k];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) W[a][g] = R(0.5) * (un[g][0][a] - un[g][1][a]);
-    const R ugp = un[g][0][g], ugm = un[g][1][g];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      dq[g][k] = R(0.5) * (qn[g][0][k] - qn[g][1][k]);
-      // transpose of the advection: D0_g (u_g q_bar_k)
-      qb_out[k] += R(0.5) * (ugp * aqn[g][0][k] - ugm * aqn[g][1][k]);
+    for (int c = 0; c < 5; ++c) v[9 + c] = adj_q[c * N + k];
+  };
+  auto load_col = [&](int zz, R v[NV]) { load_at(size_t(pmod(zz, b.nz)) * plane + col, v); };
+  R vm[NV], v0[NV], vp[NV];
+  load_col(z0 - 1, vm);
+  load_col(z0, v0);
+  load_col(z0 + 1, vp);
+
+  const bool has_halo = tid < NH;
+  int hs = 0, hcol = 0;
+  if (has_halo) {
+    int hx, hy;
+    if (tid < 2 * TX) {
+      hx = 1 + (tid % TX);
+      hy = tid < TX ? 0 : SY - 1;
+    } else {
+      const int r = tid - 2 * TX;
+      hx = r < TY ? 0 : SX - 1;
+      hy = 1 + (r % TY);
     }
+    hs = hy * SX + hx;
+    hcol = sGY[hy] * b.nx + sGX[hx];
   }
-  mub[s] = P.M * lap_pb;
-  R ub[3], phib = pb0;
+  R hv[NV];
+  if (has_halo) load_at(size_t(z0) * plane + hcol, hv);
+
+  const int sc = (ly + 1) * SX + (lx + 1);
+  for (int zc = z0; zc < z1; ++zc) {
+    __syncthreads();  // previous plane's reads are done
 #pragma unroll
-  for (int g = 0; g < 3; ++g) {
-    ub[g] = vb[g] * ph;
-    phib += vb[g] * uc[g];
+    for (int c = 0; c < NV; ++c) sV[c][sc] = v0[c];
+    if (has_halo) {
 #pragma unroll
-    for (int k = 0; k < 5; ++k) ub[g] -= qbar[k] * dq[g][k];
+      for (int c = 0; c < NV; ++c) sV[c][hs] = hv[c];
+      if (zc + 1 < z1) load_at(size_t(zc + 1) * plane + hcol, hv);  // next plane's halo
+    }
+    __syncthreads();
+    if (active) {
+      const size_t site = size_t(zc) * plane + col;
+      const R ph = R(phi[site]);
+      R qc[5], qbar[5], uc[3];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        qc[k] = v0[k];
+        qbar[k] = v0[9 + k];
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) uc[a] = v0[5 + a];
+      R pbn[3][2], un[3][2][3], qn[3][2][5], aqn[3][2][5];
+      const int nb[2][2] = {{sc + 1, sc - 1}, {sc + SX, sc - SX}};
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+          const int t = nb[g][d];
+          pbn[g][d] = sV[8][t];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) un[g][d][a] = sV[5 + a][t];
+#pragma unroll
+          for (int k = 0; k < 5; ++k) {
+            qn[g][d][k] = sV[k][t];
+            aqn[g][d][k] = sV[9 + k][t];
+          }
+        }
+      pbn[2][0] = vp[8];
+      pbn[2][1] = vm[8];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        un[2][0][a] = vp[5 + a];
+        un[2][1][a] = vm[5 + a];
+      }
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        qn[2][0][k] = vp[k];
+        qn[2][1][k] = vm[k];
+        aqn[2][0][k] = vp[9 + k];
+        aqn[2][1][k] = vm[9 + k];
+      }
+      R m, Wb[3][3], ub[3], qb[5], pb;
+      adj_order_site(P, qc, qbar, uc, ph, v0[8], pbn, un, qn, aqn, m, Wb, ub, qb, pb);
+      store_adj_order(N, site, m, Wb, ub, qb, pb, mub, Wb_out, ubp, qbp, phibp);
+    }
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      vm[c] = v0[c];
+      v0[c] = vp[c];
+    }
+    if (zc + 1 < z1) load_col(zc + 2, vp);
   }
-  R Wb[3][3] = {};
-  corotation_site_bwd(P.xi, qc, W, qbar, qb_out, Wb);
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) Wb_out[(a * 3 + c) * N + s] = Wb[a][c];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) ubp[a * N + s] = ub[a];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) qbp[k * N + s] = qb_out[k];
-  phibp[s] = phib;
 }
 
 // Reverse of the collision and the pull stream at one site.
@@ -312,9 +467,26 @@ k_adj_stress(Box b, Params<R> P, const FS* __restrict__ phi, const FS* __restric
   block_reduce_store<2>(v, partial + size_t(blockIdx.x) * 2, accumulate != 0);
 }
 
-// Stencil transposes of the gradient data; writes Q_bar(t), phi_bar(t).
-// All 84 loads of a site are issued before any arithmetic (a wave keeps them
-// in flight together; the register budget allows 4 waves per SIMD).
+// Stencil transposes of the gradient data at one site.
+// own: phi, q[5], lapphi, lapq[5] of the site; nb[g][d] at x + e_g (d = 0) and
+// x - e_g (d = 1): dphi_g, lapphi, dq_g[5], lapq[5].
+template <class R>
+__device__ __forceinline__ void gather_site(const R own[12], const R nb[3][2][12], R& pb, R qb[5]) {
+  pb = own[0] - R(6) * own[6];
+#pragma unroll
+  for (int g = 0; g < 3; ++g) pb += (nb[g][0][1] + nb[g][1][1]) - R(0.5) * (nb[g][0][0] - nb[g][1][0]);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    qb[k] = own[1 + k] - R(6) * own[7 + k];
+#pragma unroll
+    for (int g = 0; g < 3; ++g)
+      qb[k] += (nb[g][0][7 + k] + nb[g][1][7 + k]) - R(0.5) * (nb[g][0][2 + k] - nb[g][1][2 + k]);
+  }
+}
+
+// Site-parallel form: all 84 loads of a site are issued before any
+// arithmetic (a wave keeps them in flight together; the register budget
+// allows 4 waves per SIMD).
 template <class R>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4)))
 k_adj_gather(Box b, const R* __restrict__ gbar, R* __restrict__ adj_phi, R* __restrict__ adj_q) {
@@ -324,9 +496,7 @@ k_adj_gather(Box b, const R* __restrict__ gbar, R* __restrict__ adj_phi, R* __re
   coords(b, s, x, y, z);
   const size_t N = b.N;
   const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
-  // own: phi, q[5], lapphi, lapq[5]; neighbour +-e_g: dphi_g, lapphi, dq_g[5], lapq[5]
-  constexpr int NF = 12;
-  R own[NF], nb[3][2][NF];
+  R own[12], nb[3][2][12];
   own[0] = gbar[size_t(GB_PHI) * N + s];
   own[6] = gbar[size_t(GB_LAPPHI) * N + s];
 #pragma unroll
@@ -349,18 +519,11 @@ k_adj_gather(Box b, const R* __restrict__ gbar, R* __restrict__ adj_phi, R* __re
         v[7 + k] = gbar[size_t(GB_LAPQ + k) * N + sn];
       }
     }
-  R pb = own[0] - R(6) * own[6];
-#pragma unroll
-  for (int g = 0; g < 3; ++g) pb += (nb[g][0][1] + nb[g][1][1]) - R(0.5) * (nb[g][0][0] - nb[g][1][0]);
+  R pb, qb[5];
+  gather_site(own, nb, pb, qb);
   adj_phi[s] = pb;
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    R qb = own[1 + k] - R(6) * own[7 + k];
-#pragma unroll
-    for (int g = 0; g < 3; ++g)
-      qb += (nb[g][0][7 + k] + nb[g][1][7 + k]) - R(0.5) * (nb[g][0][2 + k] - nb[g][1][2 + k]);
-    adj_q[k * N + s] = qb;
-  }
+  for (int k = 0; k < 5; ++k) adj_q[k * N + s] = qb[k];
 }
 
 // out = in + 1 for the step counter of a recorded state (one thread, vector memory).

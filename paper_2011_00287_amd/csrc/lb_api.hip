@@ -74,6 +74,18 @@ struct TileCfg {
 constexpr TileCfg kLbTiles[] = {{32, 8}, {32, 16}, {64, 4}, {16, 16}, {16, 8}};
 constexpr TileCfg kOrTiles[] = {{32, 8}, {64, 4}, {32, 16}, {64, 8}, {64, 16}};
 
+// Deepest z-slab (<= 16 planes, >= 4) that still gives two workgroups per
+// CU for a grid of ntx x nty tiles.
+int auto_slab(int ntx, int nty, int nz) {
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+    ncu = 256;
+  int tz = 16;
+  while (tz > 4 && size_t(ntx) * nty * ((nz + tz - 1) / tz) < size_t(2 * ncu)) tz /= 2;
+  return tz;
+}
+
 // Default tiles and slab depths per storage (measured on the 128^3 and
 // 256^3 droplets): stress kernel float 32 x 8 with 16-plane slabs, half
 // populations 16 x 8 with 11-plane slabs, double 16 x 8 with 16-plane slabs
@@ -192,6 +204,8 @@ struct BackendT final : Backend {
   int tz_lb = 8, tz_or = 8;
   int lb_tile = 0, or_tile = 0;
   int lb_ntx, lb_nty, lb_blocks, or_ntx, or_nty, or_blocks;
+  static constexpr int kAoTX = 32, kAoTY = 8;  // tile of the z-marching adjoint order kernel
+  int ao_ntx, ao_nty, ao_tz, ao_blocks;
 
   BackendT(const lb_params& p, hipStream_t s) : stream(s) {
     box.nx = p.nx;
@@ -217,15 +231,12 @@ struct BackendT final : Backend {
     lb_blocks = lb_ntx * lb_nty * ((p.nz + tz_lb - 1) / tz_lb);
     or_ntx = (p.nx + ot.tx - 1) / ot.tx;
     or_nty = (p.ny + ot.ty - 1) / ot.ty;
-    if (tz_or == 0) {  // deepest slab (<= 16 planes, >= 4) with two workgroups per CU
-      int dev = 0, ncu = 0;
-      if (hipGetDevice(&dev) != hipSuccess ||
-          hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
-        ncu = 256;
-      tz_or = 16;
-      while (tz_or > 4 && size_t(or_ntx) * or_nty * ((p.nz + tz_or - 1) / tz_or) < size_t(2 * ncu)) tz_or /= 2;
-    }
+    if (tz_or == 0) tz_or = auto_slab(or_ntx, or_nty, p.nz);
     or_blocks = or_ntx * or_nty * ((p.nz + tz_or - 1) / tz_or);
+    ao_ntx = (p.nx + kAoTX - 1) / kAoTX;
+    ao_nty = (p.ny + kAoTY - 1) / kAoTY;
+    ao_tz = auto_slab(ao_ntx, ao_nty, p.nz);
+    ao_blocks = ao_ntx * ao_nty * ((p.nz + ao_tz - 1) / ao_tz);
     size_t need = 2 * (19 * N * sizeof(GS) + 6 * N * sizeof(FS)) + 18 * N * sizeof(R);
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need > free_b)
@@ -640,7 +651,11 @@ struct BackendT final : Backend {
       uu = u;
       FF = aF;
     }
-    lbc::k_adj_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp);
+    if (site_path)
+      lbc::k_adj_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp);
+    else
+      lbc::k_adj_order_fused<R, FS, kAoTX, kAoTY><<<ao_blocks, kAoTX * kAoTY, 0, stream>>>(
+          box, P, ao_tz, ao_ntx, ao_nty, v.phi, v.q, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp);
     lbc::k_adj_collide<R, GS><<<nblk, TPB, 0, stream>>>(box, P, v.B, FF, aWb, aubp, gi, go, aFb);
     lbc::k_adj_stress<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, aFb, qi, amub, aqbp, aphibp, agbar, apart,
                                                         apart_live ? 1 : 0);
