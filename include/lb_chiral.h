@@ -101,6 +101,10 @@ typedef struct lb_ctx lb_ctx;
 /* Create a context: validates p (tau > 0.5, n >= 3, finite values), allocates
  * the device state and uploads phi [N], q5 [5][N] and u0 [3][N] (NULL = 0).
  * The populations start at the second-order equilibrium of (rho0, u0).
+ * Device memory: two buffers of populations, Q and phi, plus u and mu, i.e.
+ * 2 (19 s_g + 6 s_f) + 4 s bytes per site (s_g, s_f, s: population, field and
+ * arithmetic sizes; 232 B in LB_FP32).  lb_moments (rho, u), lb_free_energy
+ * and the adjoint's recomputation allocate 14 s more per site on first use.
  * Errors: LB_EINVAL, LB_ENOMEM, LB_EDEVICE; *out is NULL on error. */
 lb_status lb_init(const lb_params* p, const double* phi, const double* q5, const double* u0,
                   void* hip_stream, lb_ctx** out);
@@ -113,7 +117,8 @@ lb_status lb_step(lb_ctx* c, int32_t nsteps);
 lb_status lb_set_params(lb_ctx* c, const lb_params* p);
 
 /* Copy rho [N], u [3][N] (with F/2), phi [N] and q5 [5][N] at the current
- * time to host float64 arrays; any pointer may be NULL.  Synchronises. */
+ * time to host float64 arrays; any pointer may be NULL.  Synchronises.
+ * Errors: LB_ENOMEM when device scratch for rho, u cannot be allocated. */
 lb_status lb_moments(lb_ctx* c, double* rho, double* u3, double* phi, double* q5);
 
 /* Post-stream population deviations g [19][N] at the current time (float64
@@ -125,7 +130,8 @@ lb_status lb_populations(lb_ctx* c, double* g19);
 lb_status lb_set_fields(lb_ctx* c, const double* g19, const double* phi, const double* q5);
 
 /* Global float64 sums of the current state (see lb_totals).  Returns
- * LB_ENONFINITE if any of them is not finite.  Synchronises. */
+ * LB_ENONFINITE if any of them is not finite, LB_ENOMEM if device scratch
+ * cannot be allocated.  Synchronises. */
 lb_status lb_free_energy(lb_ctx* c, lb_totals* out);
 
 /* phi-weighted droplet centre.  out[0..2] = linear centre (x, y, z) with

@@ -26,10 +26,10 @@ namespace lbc {
 
 // ---------------------------------------------------------------------------
 // k_lb_fused
-//   phi and Q rings hold planes p-2..p+2 (phi) and p-1..p+1 (Q) on the tile
-//   plus a halo of 2; the stress is computed on the tile plus the halo of 1
-//   the force reads at plane p (each thread its own site, then the halo
-//   slots on rotating waves); thread t owns column t
+//   Iteration p of the march: phi and Q rings hold planes p-2..p+2 (phi) and
+//   p-1..p+1 (Q) on the tile plus a halo of 2.  The stress is computed at
+//   plane p on the tile plus the halo of 1 the force reads (each thread its
+//   own site, then the halo slots on rotating waves).  Thread t owns column t
 //   of the tile for mu and for the collision of plane p-1, whose force needs
 //   the stress of planes p-2..p.  The global loads needed after the stress
 //   pass (the pull of plane p-1, the ring planes for p+1) are issued before

@@ -237,7 +237,7 @@ struct BackendT final : Backend {
     ao_nty = (p.ny + kAoTY - 1) / kAoTY;
     ao_tz = auto_slab(ao_ntx, ao_nty, p.nz);
     ao_blocks = ao_ntx * ao_nty * ((p.nz + ao_tz - 1) / ao_tz);
-    size_t need = 2 * (19 * N * sizeof(GS) + 6 * N * sizeof(FS)) + 18 * N * sizeof(R);
+    size_t need = 2 * (19 * N * sizeof(GS) + 6 * N * sizeof(FS)) + 4 * N * sizeof(R);
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need > free_b)
       fail(LB_ENOMEM, "state needs " + std::to_string(need) + " bytes, " + std::to_string(free_b) + " free");
@@ -248,15 +248,28 @@ struct BackendT final : Backend {
         Ph[k] = dalloc<FS>(N);
       }
       mu = dalloc<R>(N);
-      H = dalloc<R>(5 * N);
-      sig = dalloc<R>(9 * N);
       u = dalloc<R>(3 * N);
       partial = dalloc<double>(size_t(nblk) * 16);
       sums = dalloc<double>(16);
+      if (site_path) ensure_thermo();
     } catch (...) {
       release();
       throw;
     }
+  }
+  // H [5][N] and sigma [9][N]: used by the site-parallel step, by observation
+  // (u and rho need the force) and by the adjoint's recomputation of u and F,
+  // never by the fused step; allocated on first use.
+  void ensure_thermo() {
+    if (H) return;
+    R* h = dalloc<R>(5 * N);
+    try {
+      sig = dalloc<R>(9 * N);
+    } catch (...) {
+      dfree(h);
+      throw;
+    }
+    H = h;
   }
   ~BackendT() override { release(); }
   void release() {
@@ -492,6 +505,7 @@ struct BackendT final : Backend {
 
   // --- observation -----------------------------------------------------------
   void thermo_now() {
+    ensure_thermo();
     lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], mu, H, sig);
     check_launch();
   }
@@ -620,6 +634,7 @@ struct BackendT final : Backend {
     R* ru = static_cast<R*>(rec_out);
     R* rF = ru + 3 * N;
     if (site_path) {
+      ensure_thermo();
       lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, vi.phi, vi.q, mu, H, sig);
       lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, vi.B, sig, rF, ru);
       lbc::k_collide<R, GS><<<nblk, TPB, 0, stream>>>(box, P, vi.B, Bo, sig, ru);
@@ -646,6 +661,7 @@ struct BackendT final : Backend {
       uu = static_cast<const R*>(rec);
       FF = uu + 3 * N;
     } else {  // recompute u and F of time t
+      ensure_thermo();
       lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, mu, H, sig);
       lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, v.B, sig, aF, u);
       uu = u;
