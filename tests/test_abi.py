@@ -98,3 +98,16 @@ def test_oversize_box_rejected_before_allocation():
                             q5.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, None, ctypes.byref(h))
     assert st == _lib.LB_ENOMEM
     assert not h.value
+
+
+def test_header_is_plain_c_and_links():
+    """A C11 program using only include/lb_chiral.h compiles without warnings
+    and links against the built library (it runs in the GPU tests)."""
+    import tempfile
+    from c_abi_build import compile_c_consumer
+    from paper_2011_00287_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("library not built: run python -m paper_2011_00287_amd.build")
+    with tempfile.TemporaryDirectory() as d:
+        exe = compile_c_consumer(d)
+        assert os.path.exists(exe)
