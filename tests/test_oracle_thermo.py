@@ -4,7 +4,9 @@
   H = 0 there, and the isotropic-nematic coexistence at chi = 2.7 that the
   paper states as the liquid-crystal threshold;
 * the double well: minima at phi = 0 and phi0, and the tanh interface of the
-  continuum theory (mu = 0 on it);
+  continuum theory (mu = 0 on it); the excess free energy of planar
+  interfaces tends to the closed-form surface tension sqrt(a k_phi) phi0^3 / 6
+  per unit area, at second order in the interface resolution;
 * mu and H are the exact lattice gradients of the discrete free energy
   (brute-force central differences on a 4^3 box);
 * the cholesteric term: free energy per site of a lattice helix in closed
@@ -125,6 +127,32 @@ BASIS = [np.array(m, dtype=float) for m in (
     [[0, 0, 0], [0, 1, 0], [0, 0, -1]],
     [[0, 0, 0], [0, 0, 1], [0, 1, 0]],
 )]
+
+
+def _planar_interfaces_ratio(k_phi):
+    """F_h of two planar tanh interfaces (Q = 0) over 2 sigma A, sigma = sqrt(a k_phi) phi0^3 / 6."""
+    p = _p(q0=0.0, zeta=0.0, W=0.0, k_phi=k_phi)
+    kappa = p["phi0"] * math.sqrt(p["a"] / p["k_phi"]) / 2.0
+    sigma = math.sqrt(p["a"] * p["k_phi"]) * p["phi0"] ** 3 / 6.0
+    nx, ny, nz = 128, 3, 3
+    x = np.arange(nx)
+    prof = 0.5 * p["phi0"] * (np.tanh(kappa * (x - nx / 4 - 0.3)) - np.tanh(kappa * (x - 3 * nx / 4 - 0.3)))
+    phi = torch.tensor(np.broadcast_to(prof[None, None, :], (nz, ny, nx)).copy(), dtype=DT)
+    Q = core.q_full(torch.zeros((5, nz, ny, nx), dtype=DT))
+    return float(core.free_energy(phi, Q, p)) / (2.0 * sigma * ny * nz), kappa
+
+
+def test_interface_tension_closed_form():
+    """Bulk phases at phi = 0 and phi0 cost nothing, so F_h is the interfaces' excess:
+    2 sigma A in the continuum.  On the lattice the error is O(kappa^2): it must
+    shrink about 4-fold each time the interface width doubles (k_phi x 4)."""
+    errs = []
+    for k_phi in (0.1, 0.4, 1.6):
+        ratio, kappa = _planar_interfaces_ratio(k_phi)
+        errs.append(abs(ratio - 1.0))
+    assert errs[0] < 0.03 and errs[2] < 2e-3, errs
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 3.5 < e0 / e1 < 4.5, errs
 
 
 def test_mu_and_h_are_exact_gradients_of_free_energy():
