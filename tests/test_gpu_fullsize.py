@@ -8,6 +8,12 @@ benchmark times (default tiles and slab depths).
   is exact.  Tolerance: FP32 rounding of the step, 2e-6 absolute on g, Q, phi.
 * 64^3 droplet, FP64: 30 steps against the oracle on the whole box, 1e-12.
 * 256^3 droplet, FP32, 100 steps: mass and sum(phi) conserved (float64 sums).
+* 256^3 droplet, FP32: one step at sampled sites against 13^3 oracle patches,
+  and one reverse step (through the recorded path the benchmark times) at
+  sampled sites against the oracle's autograd on 17^3 patches.  The adjoint
+  seed is a smooth closed-form field; a site's reverse value depends on the
+  seed within 4 sites, whose forward values in turn need 4 more, so the centre
+  of a 17^3 patch with the seed kept on the central 9^3 cube is exact.
 """
 import numpy as np
 import pytest
@@ -70,6 +76,85 @@ def test_fp64_64_full_box_vs_oracle():
         assert l2 <= 1e-12 and mx <= 1e-12, (name, l2, mx)
     l2, mx = rel_err(gs, go)
     assert l2 <= 1e-12 and mx <= 1e-12
+
+
+def _sites(n, R):
+    c = n // 2
+    return [(c, c, c), (c, c, c + int(R)), (c + int(R), c, c), (c, c - int(R) + 1, c), (0, 0, 0),
+            (n - 1, n - 1, n - 1), (0, c, n - 1), (c + 20, c - 17, c + 9), (3, n // 2, n - 1), (n - 1, 0, n // 2)]
+
+
+def test_fp32_256_sampled_sites_vs_oracle():
+    p = inputs.params_for("droplet256")
+    phi, q5 = inputs.workload_fields("droplet256")
+    n = phi.shape[0]
+    with Sim(p, phi, q5, precision="fp32") as s:
+        s.step(1)
+        g1 = s.populations()
+        _, _, phi1, q1 = s.moments()
+    r = 6
+    g0 = np.zeros((19, 2 * r + 1, 2 * r + 1, 2 * r + 1))
+    worst = {"g": 0.0, "Q": 0.0, "phi": 0.0}
+    for (z, y, x) in _sites(n, inputs.WORKLOADS["droplet256"]["R"]):
+        go, qo, po = oracle_run(p, g0, _patch(q5, z, y, x, r), _patch(phi, z, y, x, r), 1)
+        worst["g"] = max(worst["g"], float(np.abs(go[:, r, r, r] - g1[:, z, y, x]).max()))
+        worst["Q"] = max(worst["Q"], float(np.abs(qo[:, r, r, r] - q1[:, z, y, x]).max()))
+        worst["phi"] = max(worst["phi"], float(abs(po[r, r, r] - phi1[z, y, x])))
+    print(worst)
+    assert all(v <= 2e-6 for v in worst.values()), worst
+
+
+def _seed_field(z, y, x, comps):
+    """Smooth adjoint seed: component c at (z, y, x); broadcasts over index arrays."""
+    c = comps.reshape((-1,) + (1,) * np.ndim(z))
+    return np.sin(0.37 * x + 0.91 * y + 1.3 * z + 0.7 * c) * np.cos(0.23 * x - 0.5 * z + c)
+
+
+def test_fp32_256_adjoint_sampled_sites_vs_oracle():
+    p = inputs.params_for("droplet256")
+    phi, q5 = inputs.workload_fields("droplet256")
+    n = phi.shape[0]
+    sites = _sites(n, inputs.WORKLOADS["droplet256"]["R"])[:6]
+    with Sim(p, phi, q5, precision="fp32") as sim:
+        state = sim.get_state()
+        rec = sim.record_buffer()
+        nxt = torch.empty_like(state)
+        sim.step_record(state, nxt, rec)
+        del nxt
+        adj = sim.adjoint_buffer()
+        a5 = adj.view(25, n, n, n)
+        zz = torch.arange(n, device="cuda", dtype=torch.float64).view(n, 1, 1)
+        yy = zz.view(1, n, 1)
+        xx = zz.view(1, 1, n)
+        for c in range(25):  # the same closed form as _seed_field, built on the device
+            a5[c] = (torch.sin(0.37 * xx + 0.91 * yy + 1.3 * zz + 0.7 * c) * torch.cos(0.23 * xx - 0.5 * zz + c)).float()
+        out = sim.adjoint_buffer()
+        sim.adjoint_step(state, adj, out, rec=rec)
+        o5 = out.view(25, n, n, n)
+        gpu = [o5[:, z, y, x].double().cpu().numpy() for (z, y, x) in sites]
+    R, r = 8, 4
+    m = 2 * R + 1
+    worst = 0.0
+    for (z, y, x), gv in zip(sites, gpu):
+        iz = (np.arange(z - R, z + R + 1)) % n
+        iy = (np.arange(y - R, y + R + 1)) % n
+        ix = (np.arange(x - R, x + R + 1)) % n
+        seed = _seed_field(iz[:, None, None], iy[None, :, None], ix[None, None, :], np.arange(25))
+        mask = np.zeros((m, m, m))
+        mask[R - r:R + r + 1, R - r:R + r + 1, R - r:R + r + 1] = 1.0
+        seed = seed * mask
+        gt = torch.zeros((19, m, m, m), dtype=torch.float64, requires_grad=True)
+        qt = torch.tensor(_patch(q5, z, y, x, R), requires_grad=True)
+        pt = torch.tensor(_patch(phi, z, y, x, R), requires_grad=True)
+        go, qo, po = core.step(gt, qt, pt, p)
+        tot = (go * torch.tensor(seed[:19])).sum() + (qo * torch.tensor(seed[19:24])).sum() + \
+            (po * torch.tensor(seed[24])).sum()
+        tot.backward()
+        orc = np.concatenate([gt.grad[:, R, R, R].numpy(), qt.grad[:, R, R, R].numpy(), [pt.grad[R, R, R].item()]])
+        err = float(np.abs(orc - gv).max() / np.abs(orc).max())
+        worst = max(worst, err)
+    print("worst relative reverse-step error", worst)
+    assert worst <= 1e-4, worst
 
 
 def test_fp32_256_conservation():
