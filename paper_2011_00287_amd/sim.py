@@ -55,7 +55,10 @@ class Sim:
 
     phi: [nz, ny, nx]; q5: [5, nz, ny, nx] (xx, xy, xz, yy, yz); u0: [3, nz, ny, nx]
     or None.  precision: 'fp64', 'fp32' or 'fp16s'.  stream: a torch.cuda.Stream,
-    a raw hipStream_t as int, or None for the default stream.
+    a raw hipStream_t as int, or None for the default stream.  The device tensors
+    this class allocates (state, adjoint and record buffers) are created and
+    zero-filled on torch's current stream, so pass that stream (or None while
+    torch uses the default stream) to keep them ordered with the library's work.
     """
 
     def __init__(self, params: dict, phi, q5, u0=None, precision: str = "fp64", stream=None):
@@ -106,9 +109,11 @@ class Sim:
         check(lib().lb_sync(self._h))
 
     def set_params(self, **changes):
-        self.params.update(changes)
-        self._lp = make_params(self.params, self.shape, self.precision)
-        check(lib().lb_set_params(self._h, ctypes.byref(self._lp)))
+        """Change model parameters (not the box or precision); kept only if the library accepts them."""
+        new = dict(self.params, **changes)
+        lp = make_params(new, self.shape, self.precision)
+        check(lib().lb_set_params(self._h, ctypes.byref(lp)))
+        self.params, self._lp = new, lp
 
     # --------------------------------------------------------------- observation
     def moments(self):
