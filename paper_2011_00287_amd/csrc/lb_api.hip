@@ -74,35 +74,38 @@ struct TileCfg {
 constexpr TileCfg kLbTiles[] = {{32, 8}, {32, 16}, {64, 4}, {16, 16}, {16, 8}};
 constexpr TileCfg kOrTiles[] = {{32, 8}, {64, 4}, {32, 16}, {64, 8}, {64, 16}};
 
-// Deepest z-slab (<= 16 planes, >= 4) that still gives two workgroups per
-// CU for a grid of ntx x nty tiles.
-int auto_slab(int ntx, int nty, int nz) {
+// Deepest z-slab of at most tz_max planes (halved down to tz_min) that still
+// gives per_cu workgroups per CU for a grid of ntx x nty tiles.  Small boxes
+// get shallow slabs: a deep slab on few tiles leaves most CUs idle while a
+// handful of workgroups march through the planes one after another.
+int auto_slab(int ntx, int nty, int nz, int tz_max, int tz_min, int per_cu) {
   int dev = 0, ncu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
     ncu = 256;
-  int tz = 16;
-  while (tz > 4 && size_t(ntx) * nty * ((nz + tz - 1) / tz) < size_t(2 * ncu)) tz /= 2;
+  int tz = tz_max;
+  while (tz > tz_min && size_t(ntx) * nty * ((nz + tz - 1) / tz) < size_t(per_cu) * ncu) tz /= 2;
   return tz;
 }
 
 // Default tiles and slab depths per storage (measured on the 128^3 and
-// 256^3 droplets): stress kernel float 32 x 8 with 16-plane slabs, half
-// populations 16 x 8 with 11-plane slabs, double 16 x 8 with 16-plane slabs
-// (its register and LDS footprint leaves one or two small workgroups per
-// CU); order kernel 64 x 8 with the deepest slab of at most 16 planes that
-// still gives two workgroups per CU (tz_order = 0 selects it).
+// 256^3 droplets): stress kernel float 32 x 8 with slabs of up to 16 planes,
+// half populations 16 x 8 with up to 11, double 16 x 8 with up to 16 (its
+// register and LDS footprint leaves one or two small workgroups per CU); the
+// slab is the deepest that still gives a workgroup per CU.  Order kernel
+// 64 x 8 with the deepest slab of at most 16 planes that gives two
+// workgroups per CU.  LBC_TZ_LB / LBC_TZ_ORDER fix a depth instead.
 template <class R, class GS>
 struct DefaultTile {
-  static constexpr int lb = 0, order = 3, tz_lb = 16, tz_order = 0;
+  static constexpr int lb = 0, order = 3, tz_lb_max = 16;
 };
 template <>
 struct DefaultTile<float, __half> {
-  static constexpr int lb = 4, order = 3, tz_lb = 11, tz_order = 0;
+  static constexpr int lb = 4, order = 3, tz_lb_max = 11;
 };
 template <>
 struct DefaultTile<double, double> {
-  static constexpr int lb = 4, order = 3, tz_lb = 16, tz_order = 0;
+  static constexpr int lb = 4, order = 3, tz_lb_max = 16;
 };
 
 bool finite_params(const lb_params& p) {
@@ -217,8 +220,8 @@ struct BackendT final : Backend {
     set_params(p);
     site_path = env_int("LBC_SITE_KERNELS", 0) != 0;
     using D = DefaultTile<R, GS>;
-    tz_lb = std::max(1, env_int("LBC_TZ_LB", D::tz_lb));
-    tz_or = std::max(0, env_int("LBC_TZ_ORDER", D::tz_order));
+    tz_lb = std::max(0, env_int("LBC_TZ_LB", 0));
+    tz_or = std::max(0, env_int("LBC_TZ_ORDER", 0));
     lb_tile = env_int("LBC_LB_TILE", D::lb);
     or_tile = env_int("LBC_OR_TILE", D::order);
     if (lb_tile < 0 || lb_tile >= int(sizeof(kLbTiles) / sizeof(kLbTiles[0]))) lb_tile = D::lb;
@@ -228,14 +231,15 @@ struct BackendT final : Backend {
     const TileCfg lt = kLbTiles[lb_tile], ot = kOrTiles[or_tile];
     lb_ntx = (p.nx + lt.tx - 1) / lt.tx;
     lb_nty = (p.ny + lt.ty - 1) / lt.ty;
+    if (tz_lb == 0) tz_lb = auto_slab(lb_ntx, lb_nty, p.nz, D::tz_lb_max, 1, 1);
     lb_blocks = lb_ntx * lb_nty * ((p.nz + tz_lb - 1) / tz_lb);
     or_ntx = (p.nx + ot.tx - 1) / ot.tx;
     or_nty = (p.ny + ot.ty - 1) / ot.ty;
-    if (tz_or == 0) tz_or = auto_slab(or_ntx, or_nty, p.nz);
+    if (tz_or == 0) tz_or = auto_slab(or_ntx, or_nty, p.nz, 16, 1, 2);
     or_blocks = or_ntx * or_nty * ((p.nz + tz_or - 1) / tz_or);
     ao_ntx = (p.nx + kAoTX - 1) / kAoTX;
     ao_nty = (p.ny + kAoTY - 1) / kAoTY;
-    ao_tz = auto_slab(ao_ntx, ao_nty, p.nz);
+    ao_tz = auto_slab(ao_ntx, ao_nty, p.nz, 16, 1, 2);
     ao_blocks = ao_ntx * ao_nty * ((p.nz + ao_tz - 1) / ao_tz);
     size_t need = 2 * (19 * N * sizeof(GS) + 6 * N * sizeof(FS)) + 4 * N * sizeof(R);
     size_t free_b = 0, total_b = 0;

@@ -222,3 +222,4 @@ def test_site_kernels_match_fused_kernels(monkeypatch, lb_tile, or_tile, tz, pre
                 assert l2 < tol and mx < tol
             l2, mx = rel_err(fused.populations(), site.populations())
             assert l2 < tol and mx < tol
+
