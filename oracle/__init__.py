@@ -2,6 +2,7 @@
 
 Only tests, the smoke check and the benchmark's CPU-baseline leg import this
 package.  It shares no code with the HIP path; see core.py for what it
-computes and brute.py for the per-site loop version used on tiny boxes.
+computes, brute.py for the per-site loop version used on tiny boxes and
+d3q15.py for the paper's own LB scheme (D3Q15, stress in the equilibrium).
 """
-from . import core, lattice  # noqa: F401
+from . import core, d3q15, lattice  # noqa: F401
