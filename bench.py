@@ -1,8 +1,9 @@
 """Benchmark of the coupled hybrid LB step on one MI355X.
 
 Workload: the 128^3 chiral droplet (radius 32, q0 = 2 pi/24, zeta = 0.008),
-FP32 storage and arithmetic; the same box is also timed in FP64 and with FP16
-population storage.  A step is one pass of the whole coupled step over the box
+FP32 storage and arithmetic, D3Q19 with the stress as a body force; the same
+box is also timed in FP64, with FP16 population storage, and with the paper's
+D3Q15 scheme (symmetric stress in the equilibrium) in FP32 and FP64.  A step is one pass of the whole coupled step over the box
 (stress, collide + stream, Q and phi updates).  Inputs are resident in HBM
 before the timed region starts.
 
@@ -25,15 +26,16 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per site of each kernel of the step: the compulsory
 # traffic of the method (read + write of populations, Q and phi) that the
-# kernel is responsible for.  Values per site: populations 19 read + 19
-# written, Q 5 + 5, phi 1 + 1.
+# kernel is responsible for.  Values per site: populations Q read + Q
+# written (Q = 19 or 15), Q-tensor 5 + 5, phi 1 + 1.
 ALGO_VALUES = {
-    "k_thermo": (0, 6),     # (population values, field values): reads Q, phi
-    "k_collide": (38, 0),   # reads and writes the 19 populations
+    "k_thermo": (0, 6),     # (population read+write passes, field values): reads Q, phi
+    "k_collide": (1, 0),    # reads and writes the populations
     "k_order": (0, 6),      # writes Q, phi
-    "k_lb_fused": (38, 6),  # populations + reads of Q, phi
+    "k_lb_fused": (1, 6),   # populations + reads of Q, phi
     "k_order_fused": (0, 6),
 }
+NQ = {"d3q19": 19, "d3q15": 15}
 GS_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 2}
 FS_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 4}
 
@@ -49,9 +51,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str, prec: str):
+def measured_traffic(kernel: str, workload: str, prec: str, lattice: str = "d3q19"):
     """HBM bytes per launch from the committed counter summary, if it matches the current source."""
-    f = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{prec}.json")
+    tag = "" if lattice == "d3q19" else f"_{lattice}"
+    f = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{prec}{tag}.json")
     if not os.path.exists(f):
         return None
     with open(f) as fh:
@@ -61,14 +64,14 @@ def measured_traffic(kernel: str, workload: str, prec: str):
     return d.get("hbm_bytes_per_launch")
 
 
-def step_bytes(prec: str) -> int:
-    return 38 * GS_BYTES[prec] + 12 * FS_BYTES[prec]
+def step_bytes(prec: str, lattice: str = "d3q19") -> int:
+    return 2 * NQ[lattice] * GS_BYTES[prec] + 12 * FS_BYTES[prec]
 
 
-def time_precision(prec, p, phi, q5, steps, warmup, stream):
+def time_precision(prec, p, phi, q5, steps, warmup, stream, lattice="d3q19"):
     import torch
     from paper_2011_00287_amd.sim import Sim
-    sim = Sim(p, phi, q5, precision=prec, stream=stream)
+    sim = Sim(p, phi, q5, precision=prec, stream=stream, lattice=lattice)
     sim.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -126,22 +129,24 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True):
     return out
 
 
-def cpu_baseline(workload: str, nsteps: int = 2):
+def cpu_baseline(workload: str, nsteps: int = 2, lattice: str = "d3q19"):
     import torch
-    from oracle import core
+    from oracle import core, d3q15
     from paper_2011_00287_amd import inputs
+    step = core.step if lattice == "d3q19" else d3q15.step
     p = inputs.params_for(workload)
     phi, q5 = inputs.workload_fields(workload)
     phi_t, q5_t = torch.tensor(phi), torch.tensor(q5)
-    g = torch.zeros((19,) + phi.shape, dtype=torch.float64)
-    g, q5_t, phi_t = core.step(g, q5_t, phi_t, p)  # warm-up
+    g = torch.zeros((NQ[lattice],) + phi.shape, dtype=torch.float64)
+    g, q5_t, phi_t = step(g, q5_t, phi_t, p)  # warm-up
     t0 = time.perf_counter()
     for _ in range(nsteps):
-        g, q5_t, phi_t = core.step(g, q5_t, phi_t, p)
+        g, q5_t, phi_t = step(g, q5_t, phi_t, p)
     dt = time.perf_counter() - t0
     n = phi.size
     return {"value": n * nsteps / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"{workload} ({n} sites) FP64 oracle, {nsteps} timed steps after 1 warm-up from the initial droplet"}
+            "sample": f"{workload} ({n} sites) FP64 oracle ({lattice.upper()}), {nsteps} timed steps after 1 "
+                      "warm-up from the initial droplet"}
 
 
 def copy_calibration(nbytes: int, reps: int):
@@ -175,6 +180,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="droplet128")
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16s"])
+    ap.add_argument("--lattice", default="d3q19", choices=["d3q19", "d3q15"],
+                    help="d3q19: stress as a body force; d3q15: the paper's scheme (forward only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side", action="store_true", help="skip the FP64 / FP16S side timings")
     ap.add_argument("--profile-steps", type=int, default=50)
@@ -202,17 +209,19 @@ def main():
     p = inputs.params_for(args.workload)
     phi, q5 = inputs.workload_fields(args.workload)
     n = phi.size
-    print(f"# workload {args.workload} {phi.shape} {args.precision}: warmup {args.warmup}, steps {args.steps}",
-          file=sys.stderr, flush=True)
+    print(f"# workload {args.workload} {phi.shape} {args.precision} {args.lattice}: warmup {args.warmup}, "
+          f"steps {args.steps}", file=sys.stderr, flush=True)
+    if args.lattice == "d3q15" and args.precision == "fp16s":
+        ap.error("float16 population storage is D3Q19-only")
 
-    sim, dt = time_precision(args.precision, p, phi, q5, args.steps, args.warmup, stream)
+    sim, dt = time_precision(args.precision, p, phi, q5, args.steps, args.warmup, stream, args.lattice)
     mlups = n * args.steps / dt / 1e6
     print(f"# {args.precision}: {mlups:.1f} MLUPS ({dt / args.steps * 1e3:.4f} ms/step)", file=sys.stderr, flush=True)
 
     prof = sim.profile(args.profile_steps)
     dom = max(prof, key=prof.get)
     gv, fv = ALGO_VALUES[dom]
-    algo_bytes = (gv * GS_BYTES[args.precision] + fv * FS_BYTES[args.precision]) * n
+    algo_bytes = (gv * 2 * NQ[args.lattice] * GS_BYTES[args.precision] + fv * FS_BYTES[args.precision]) * n
     achieved = algo_bytes / (prof[dom] * 1e-3) / 1e9
     totals = sim.totals()
     sim.close()
@@ -220,18 +229,20 @@ def main():
 
     side = {}
     if not args.no_side:
-        for prec in ("fp64", "fp16s"):
-            if prec == args.precision:
+        cases = [(prec, "d3q19") for prec in ("fp64", "fp16s")] + [(prec, "d3q15") for prec in ("fp32", "fp64")]
+        for prec, lat in cases:
+            if (prec, lat) == (args.precision, args.lattice):
                 continue
+            key = prec if lat == "d3q19" else f"{lat}_{prec}"
             ns = max(20, args.steps // (4 if prec == "fp64" else 1))
-            s2, dt2 = time_precision(prec, p, phi, q5, ns, 5, stream)
+            s2, dt2 = time_precision(prec, p, phi, q5, ns, 5, stream, lat)
             s2.close()
-            side[prec] = {"mlups": n * ns / dt2 / 1e6, "ms_per_step": dt2 / ns * 1e3,
-                          "step_hbm_frac": n * ns / dt2 * step_bytes(prec) / (HBM_PEAK_GBS * 1e9)}
-            print(f"# {prec}: {side[prec]['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
+            side[key] = {"mlups": n * ns / dt2 / 1e6, "ms_per_step": dt2 / ns * 1e3,
+                         "step_hbm_frac": n * ns / dt2 * step_bytes(prec, lat) / (HBM_PEAK_GBS * 1e9)}
+            print(f"# {key}: {side[key]['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
 
     adjoint = None
-    if args.adjoint_steps > 0:
+    if args.adjoint_steps > 0 and args.lattice == "d3q19":
         adjoint = time_adjoint(args.precision, p, phi, q5, args.adjoint_steps, args.adjoint_checkpoint, stream,
                                recorded=not args.no_adjoint_recorded)
         print(f"# adjoint/forward: {adjoint['adjoint_over_forward']:.2f} (checkpoint {args.adjoint_checkpoint})"
@@ -252,13 +263,14 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32", "fp16s": "f16-storage/f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": args.workload, "box": list(phi.shape[::-1]), "droplet_radius": w["R"],
-                   "q0": w["q0"], "zeta": w["zeta"], "precision": args.precision, "lattice": "D3Q19"},
+                   "q0": w["q0"], "zeta": w["zeta"], "precision": args.precision,
+                   "lattice": args.lattice.upper()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom, args.workload, args.precision), "kernel": dom,
+                     "traffic": measured_traffic(dom, args.workload, args.precision, args.lattice), "kernel": dom,
                      "kernel_ms": prof[dom], "algorithmic_bytes_per_launch": algo_bytes},
-        "step_roofline": {"bytes_per_site": step_bytes(args.precision),
-                          "frac": mlups * 1e6 * step_bytes(args.precision) / (HBM_PEAK_GBS * 1e9)},
+        "step_roofline": {"bytes_per_site": step_bytes(args.precision, args.lattice),
+                          "frac": mlups * 1e6 * step_bytes(args.precision, args.lattice) / (HBM_PEAK_GBS * 1e9)},
         "kernel_ms": prof,
         "kernel_source_hash": kernel_source_hash(),
         "side": side,
@@ -267,7 +279,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         print("# timing the FP64 CPU oracle on a bounded sample ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(args.workload)
+        line["cpu_baseline"] = cpu_baseline(args.workload, lattice=args.lattice)
     print(json.dumps(line), flush=True)
 
 

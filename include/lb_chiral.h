@@ -69,6 +69,14 @@ typedef enum {
                    float32, all arithmetic float32                            */
 } lb_precision;
 
+typedef enum {
+  LB_D3Q19 = 0, /* D3Q19; the whole stress acts as a Guo body force F = div(sigma) */
+  LB_D3Q15 = 1  /* the paper's scheme (Sec. 3): D3Q15 (Fig. 1), the symmetric
+                   stress in the second moment of the equilibrium (Eqs. (9),
+                   (11)), the antisymmetric stress as a Guo forcing term
+                   (Eq. (10)); float64 and float32 only, no adjoint          */
+} lb_lattice;
+
 /* Model parameters (Eqs. (1)-(5), (7)).  K is the single elastic constant
  * K_Q of Eq. (5); Gamma is the rotational mobility multiplying H in the
  * Beris-Edwards update; xi the flow-alignment parameter; zeta the activity
@@ -81,6 +89,7 @@ typedef struct {
   double A0, chi0, chi_s, K, q0, W;
   double Gamma, xi, zeta;
   double body_force[3]; /* uniform external force density, added to F */
+  int32_t lattice;      /* lb_lattice; 0 (a zero-initialised struct) = LB_D3Q19 */
 } lb_params;
 
 /* Global sums, accumulated in float64 on the device.  mass = N*rho0 + sum g;
@@ -121,12 +130,14 @@ lb_status lb_set_params(lb_ctx* c, const lb_params* p);
  * Errors: LB_ENOMEM when device scratch for rho, u cannot be allocated. */
 lb_status lb_moments(lb_ctx* c, double* rho, double* u3, double* phi, double* q5);
 
-/* Post-stream population deviations g [19][N] at the current time (float64
- * host array).  Synchronises. */
+/* Post-stream population deviations g [Q][N] at the current time (float64
+ * host array; Q = 19 for LB_D3Q19, 15 for LB_D3Q15, in the velocity order of
+ * the lattice).  Synchronises. */
 lb_status lb_populations(lb_ctx* c, double* g19);
 
 /* Overwrite the state at the current time from host float64 arrays:
- * g19 [19][N] post-stream deviations, phi [N], q5 [5][N] (NULL = keep). */
+ * g19 [Q][N] post-stream deviations (Q as in lb_populations), phi [N],
+ * q5 [5][N] (NULL = keep). */
 lb_status lb_set_fields(lb_ctx* c, const double* g19, const double* phi, const double* q5);
 
 /* Global float64 sums of the current state (see lb_totals).  Returns
@@ -158,6 +169,8 @@ lb_status lb_set_state(lb_ctx* c, const void* dev_src, size_t bytes);
  * as g_bar [19][N] (adjoint of the post-stream population deviations),
  * q_bar [5][N] (adjoint of the 5 stored Q components) and phi_bar [N].
  * The caller owns it (e.g. a torch tensor on the context's device).
+ * The adjoint is implemented for LB_D3Q19: with LB_D3Q15, lb_adjoint_bytes
+ * and lb_record_bytes return 0 and the calls below return LB_EINVAL.
  * ------------------------------------------------------------------------- */
 size_t lb_adjoint_bytes(const lb_ctx* c);
 

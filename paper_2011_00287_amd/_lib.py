@@ -10,6 +10,9 @@ LIB_PATH = os.path.join(_HERE, "lib", "liblbchiral.so")
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ENONFINITE, LB_ESTATE = 0, -1, -2, -3, -4, -5
 LB_FP64, LB_FP32, LB_FP16S = 0, 1, 2
 PRECISIONS = {"fp64": LB_FP64, "fp32": LB_FP32, "fp16s": LB_FP16S}
+LB_D3Q19, LB_D3Q15 = 0, 1
+LATTICES = {"d3q19": LB_D3Q19, "d3q15": LB_D3Q15}
+N_POPULATIONS = {"d3q19": 19, "d3q15": 15}
 LB_MAX_KERNELS = 8
 
 
@@ -22,7 +25,7 @@ class LbParams(ctypes.Structure):
         ("A0", ctypes.c_double), ("chi0", ctypes.c_double), ("chi_s", ctypes.c_double),
         ("K", ctypes.c_double), ("q0", ctypes.c_double), ("W", ctypes.c_double),
         ("Gamma", ctypes.c_double), ("xi", ctypes.c_double), ("zeta", ctypes.c_double),
-        ("body_force", ctypes.c_double * 3),
+        ("body_force", ctypes.c_double * 3), ("lattice", ctypes.c_int32),
     ]
 
 

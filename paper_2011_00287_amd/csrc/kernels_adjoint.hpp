@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(256) k_fwd_force(Box b, Params<R> P, const GS*
   coords(b, s, x, y, z);
   const size_t N = b.N;
   R F[3];
-  force_at(b, P, sig, x, y, z, F);
+  force_at<D3Q19>(b, P, sig, x, y, z, F);
   R sum = R(0), j[3] = {R(0), R(0), R(0)};
 #pragma unroll
   for (int i = 0; i < 19; ++i) {

@@ -2,7 +2,9 @@
 //
 // k_lb_fused  : stress, force, pull-stream and Guo-forced BGK collision
 //               (Eqs. (3)-(4), (6)-(8), (10)-(11)) plus mu (Eq. (1), with the
-//               anchoring vector v = Q D0 phi taken from the stress pass);
+//               anchoring vector v = Q D0 phi taken from the stress pass); on
+//               D3Q15 the symmetric stress enters the equilibrium (Eq. (9))
+//               and the force is that of the antisymmetric stress;
 //               writes the post-collision populations, u and mu (and the
 //               force F when a recording step asks for it).
 // k_order_fused: molecular field H (Eq. (5)), Beris-Edwards update of Q
@@ -35,7 +37,7 @@ namespace lbc {
 //   pass (the pull of plane p-1, the ring planes for p+1) are issued before
 //   it so that their latency overlaps the stress arithmetic.
 // ---------------------------------------------------------------------------
-template <class R, class GS, class FS, int TX, int TY, int MINW>
+template <class R, class GS, class FS, class L, int TX, int TY, int MINW>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(MINW)))
 k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ Bin, GS* __restrict__ Bout,
            const FS* __restrict__ phi, const FS* __restrict__ q, R* __restrict__ u_out, R* __restrict__ mu_out,
@@ -99,6 +101,8 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
   // column registers: sigma_az at planes p-2, p-1 and the in-plane force part at p-1
   R saz_m2[3] = {R(0), R(0), R(0)}, saz_m1[3] = {R(0), R(0), R(0)}, fin_m1[3] = {R(0), R(0), R(0)};
   R vz_m2 = R(0), vz_m1 = R(0);  // v_z of the owned column at planes p-2, p-1
+  // stress in the equilibrium (D3Q15): symmetric stress of the owned site at plane p-1
+  R ssym_m1[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
 
   // pull offsets of the owned column: in-plane byte offsets of the 9 (x, y) neighbours
   const int xw = active ? x : 0, yw = active ? y : 0;
@@ -127,12 +131,12 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
     const bool collide = active && zc >= z0 && zc < z1;
 
     // ---- issue the global loads needed after the stress pass
-    R g[19];
+    R g[L::Q];
     if (collide) {
       const uint32_t zb[3] = {uint32_t(zc_m) * plane_gs, uint32_t(zc_0) * plane_gs, uint32_t(zc_p) * plane_gs};
 #pragma unroll
-      for (int i = 0; i < 19; ++i)
-        g[i] = GPolO<GS>::template ld<R>(Bin + size_t(i) * N, zb[1 - CZ(i)] + colb[1 - CY(i)][1 - CX(i)], i);
+      for (int i = 0; i < L::Q; ++i)
+        g[i] = GPolO<GS>::template ld<R>(Bin + size_t(i) * N, zb[1 - L::cz(i)] + colb[1 - L::cy(i)][1 - L::cx(i)], i);
     }
     const bool refill = p < z1;
     R nphi[KR], nq[KR][5];
@@ -154,6 +158,7 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
     // slots go to whole waves, starting at a wave that rotates with the plane
     // and the workgroup, so the extra round is spread over the SIMDs.
     R saz[3], vz = R(0);
+    R ss[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};  // symmetric stress of the owned site (D3Q15)
     const int vbuf = p & 1;
     {
       constexpr int NW = NT / 64 > 0 ? NT / 64 : 1;
@@ -199,6 +204,25 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
         }
         R h[5], sig[9], vq[3];
         sigma_site(P, G, sig, h, vq);
+        if constexpr (L::kStressInEq) {
+          // the symmetric part goes to the equilibrium, the force stencil sees
+          // only the antisymmetric part A_ab = (sigma_ab - sigma_ba)/2
+          if (r == 0) {
+            ss[0] = sig[0];
+            ss[1] = R(0.5) * (sig[1] + sig[3]);
+            ss[2] = R(0.5) * (sig[2] + sig[6]);
+            ss[3] = sig[4];
+            ss[4] = R(0.5) * (sig[5] + sig[7]);
+            ss[5] = sig[8];
+          }
+          R A[9];
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) A[3 * a + c] = R(0.5) * (sig[3 * a + c] - sig[3 * c + a]);
+#pragma unroll
+          for (int k = 0; k < 9; ++k) sig[k] = A[k];
+        }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           sSig[a][s] = sig[3 * a + 0];
@@ -257,10 +281,13 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
 #pragma unroll
       for (int a = 0; a < 3; ++a) F[a] = (fin_m1[a] + R(0.5) * (saz[a] - saz_m2[a])) + P.bf[a];
       R u[3];
-      collide_site(P, g, F, u);
+      if constexpr (L::kStressInEq)
+        collide_site_eq(P, g, F, ssym_m1, u);
+      else
+        collide_site(P, g, F, u);
       const uint32_t sg = uint32_t(zc) * plane_gs + own_g, sr = uint32_t(zc) * plane_r + own_r;
 #pragma unroll
-      for (int i = 0; i < 19; ++i) GPolO<GS>::template st<R>(Bout + size_t(i) * N, sg, i, g[i]);
+      for (int i = 0; i < L::Q; ++i) GPolO<GS>::template st<R>(Bout + size_t(i) * N, sg, i, g[i]);
 #pragma unroll
       for (int a = 0; a < 3; ++a) sto(u_out + size_t(a) * N, sr, u[a]);
       if (F_out) {  // recording step (adjoint replay): keep the force of this plane
@@ -276,6 +303,10 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
     }
     vz_m2 = vz_m1;
     vz_m1 = vz;
+    if constexpr (L::kStressInEq) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) ssym_m1[k] = ss[k];
+    }
     // advance the uniform indices to plane p+1
     r0 = rp;
     c0 = cp;

@@ -117,7 +117,7 @@ __device__ __forceinline__ double fh_density(const Box& b, const Params<double>&
          P.W * anch;
 }
 
-template <class R, class GS, class FS>
+template <class R, class GS, class FS, class L>
 __global__ void __launch_bounds__(256) k_totals(Box b, Params<double> P, const GS* __restrict__ B,
                                                 const FS* __restrict__ phi, const FS* __restrict__ q,
                                                 const R* __restrict__ sig, double* __restrict__ partial) {
@@ -130,23 +130,18 @@ __global__ void __launch_bounds__(256) k_totals(Box b, Params<double> P, const G
     coords(b, s, x, y, z);
     const size_t N = b.N;
     double sum = 0.0, j[3] = {0.0, 0.0, 0.0};
-    for (int i = 0; i < 19; ++i) {
-      const double gi = double(GPol<GS>::template ld<R>(B, i * N + sidx(b, x - CX(i), y - CY(i), z - CZ(i)), i));
+    for (int i = 0; i < L::Q; ++i) {
+      const double gi =
+          double(GPol<GS>::template ld<R>(B, i * N + sidx(b, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i));
       sum += gi;
-      j[0] += CX(i) * gi;
-      j[1] += CY(i) * gi;
-      j[2] += CZ(i) * gi;
+      j[0] += L::cx(i) * gi;
+      j[1] += L::cy(i) * gi;
+      j[2] += L::cz(i) * gi;
     }
-    const int sxp = sidx(b, x + 1, y, z), sxm = sidx(b, x - 1, y, z);
-    const int syp = sidx(b, x, y + 1, z), sym = sidx(b, x, y - 1, z);
-    const int szp = sidx(b, x, y, z + 1), szm = sidx(b, x, y, z - 1);
+    R Fs[3];
+    force_sig<L>(b, sig, x, y, z, Fs);
     double mom[3];
-    for (int a = 0; a < 3; ++a) {
-      const R* sa = sig + (size_t)(a * 3) * N;
-      const double F = double(R(0.5) * (sa[sxp] - sa[sxm]) + R(0.5) * (sa[N + syp] - sa[N + sym]) +
-                              R(0.5) * (sa[2 * N + szp] - sa[2 * N + szm]) + R(P.bf[a]));
-      mom[a] = j[a] + 0.5 * F;
-    }
+    for (int a = 0; a < 3; ++a) mom[a] = j[a] + 0.5 * double(Fs[a] + R(P.bf[a]));
     const double rho = P.rho0 + sum;
     const double fh = fh_density(b, P, phi, q, x, y, z);
     const double ph = double(phi[s]);

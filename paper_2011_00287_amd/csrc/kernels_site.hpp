@@ -96,23 +96,40 @@ __global__ void __launch_bounds__(256) k_thermo(Box b, Params<R> P, const FS* __
   for (int k = 0; k < 9; ++k) sig_out[k * N + s] = sig[k];
 }
 
-template <class R>
-__device__ __forceinline__ void force_at(const Box& b, const Params<R>& P, const R* __restrict__ sig, int x, int y,
-                                         int z, R F[3]) {
+// sum_b D0_b of the stress components the lattice's forcing carries: the
+// whole stress (D3Q19), or its antisymmetric part (sigma_ab - sigma_ba)/2
+// (D3Q15, whose equilibrium carries the symmetric part).  No body force.
+template <class L, class R>
+__device__ __forceinline__ void force_sig(const Box& b, const R* __restrict__ sig, int x, int y, int z, R F[3]) {
   const size_t N = b.N;
-  const int sxp = sidx(b, x + 1, y, z), sxm = sidx(b, x - 1, y, z);
-  const int syp = sidx(b, x, y + 1, z), sym = sidx(b, x, y - 1, z);
-  const int szp = sidx(b, x, y, z + 1), szm = sidx(b, x, y, z - 1);
+  const int sp[3] = {sidx(b, x + 1, y, z), sidx(b, x, y + 1, z), sidx(b, x, y, z + 1)};
+  const int sm[3] = {sidx(b, x - 1, y, z), sidx(b, x, y - 1, z), sidx(b, x, y, z - 1)};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const R* sa = sig + (size_t)(a * 3) * N;
-    const R d = R(0.5) * (sa[sxp] - sa[sxm]) + R(0.5) * (sa[N + syp] - sa[N + sym]) +
-                R(0.5) * (sa[2 * N + szp] - sa[2 * N + szm]);
-    F[a] = d + P.bf[a];
+    R d = R(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const R* sac = sig + size_t(3 * a + c) * N;
+      if constexpr (L::kStressInEq) {
+        const R* sca = sig + size_t(3 * c + a) * N;
+        d += R(0.5) * (R(0.5) * (sac[sp[c]] - sca[sp[c]]) - R(0.5) * (sac[sm[c]] - sca[sm[c]]));
+      } else {
+        d += R(0.5) * (sac[sp[c]] - sac[sm[c]]);
+      }
+    }
+    F[a] = d;
   }
 }
 
-template <class R, class GS>
+template <class L, class R>
+__device__ __forceinline__ void force_at(const Box& b, const Params<R>& P, const R* __restrict__ sig, int x, int y,
+                                         int z, R F[3]) {
+  force_sig<L>(b, sig, x, y, z, F);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) F[a] += P.bf[a];
+}
+
+template <class R, class GS, class L>
 __global__ void __launch_bounds__(256) k_collide(Box b, Params<R> P, const GS* __restrict__ Bin,
                                                  GS* __restrict__ Bout, const R* __restrict__ sig,
                                                  R* __restrict__ u_out) {
@@ -122,15 +139,21 @@ __global__ void __launch_bounds__(256) k_collide(Box b, Params<R> P, const GS* _
   coords(b, s, x, y, z);
   const size_t N = b.N;
   R F[3];
-  force_at(b, P, sig, x, y, z, F);
-  R g[19];
+  force_at<L>(b, P, sig, x, y, z, F);
+  R g[L::Q];
 #pragma unroll
-  for (int i = 0; i < 19; ++i)
-    g[i] = GPol<GS>::template ld<R>(Bin, i * N + sidx(b, x - CX(i), y - CY(i), z - CZ(i)), i);
+  for (int i = 0; i < L::Q; ++i)
+    g[i] = GPol<GS>::template ld<R>(Bin, i * N + sidx(b, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i);
   R u[3];
-  collide_site(P, g, F, u);
+  if constexpr (L::kStressInEq) {
+    const R S[6] = {sig[s], R(0.5) * (sig[N + s] + sig[3 * N + s]), R(0.5) * (sig[2 * N + s] + sig[6 * N + s]),
+                    sig[4 * N + s], R(0.5) * (sig[5 * N + s] + sig[7 * N + s]), sig[8 * N + s]};
+    collide_site_eq(P, g, F, S, u);
+  } else {
+    collide_site(P, g, F, u);
+  }
 #pragma unroll
-  for (int i = 0; i < 19; ++i) GPol<GS>::template st<R>(Bout, i * N + s, i, g[i]);
+  for (int i = 0; i < L::Q; ++i) GPol<GS>::template st<R>(Bout, i * N + s, i, g[i]);
 #pragma unroll
   for (int a = 0; a < 3; ++a) u_out[a * N + s] = u[a];
 }
@@ -177,7 +200,7 @@ __global__ void __launch_bounds__(256) k_order(Box b, Params<R> P, const FS* __r
 
 // ------------------------------------------------------------ auxiliary kernels
 // Post-stream populations at time t (pull of B) converted to R.
-template <class R, class GS>
+template <class R, class GS, class L>
 __global__ void k_pull(Box b, const GS* __restrict__ B, R* __restrict__ g) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= b.N) return;
@@ -185,12 +208,12 @@ __global__ void k_pull(Box b, const GS* __restrict__ B, R* __restrict__ g) {
   coords(b, s, x, y, z);
   const size_t N = b.N;
 #pragma unroll
-  for (int i = 0; i < 19; ++i)
-    g[i * N + s] = GPol<GS>::template ld<R>(B, i * N + sidx(b, x - CX(i), y - CY(i), z - CZ(i)), i);
+  for (int i = 0; i < L::Q; ++i)
+    g[i * N + s] = GPol<GS>::template ld<R>(B, i * N + sidx(b, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i);
 }
 
 // B_i(x) = g_i(x + c_i): the inverse of the pull, from float64 deviations.
-template <class GS>
+template <class GS, class L>
 __global__ void k_push(Box b, const double* __restrict__ g, GS* __restrict__ B) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= b.N) return;
@@ -198,11 +221,13 @@ __global__ void k_push(Box b, const double* __restrict__ g, GS* __restrict__ B) 
   coords(b, s, x, y, z);
   const size_t N = b.N;
 #pragma unroll
-  for (int i = 0; i < 19; ++i)
-    GPol<GS>::template st<double>(B, i * N + s, i, g[i * N + sidx(b, x + CX(i), y + CY(i), z + CZ(i))]);
+  for (int i = 0; i < L::Q; ++i)
+    GPol<GS>::template st<double>(B, i * N + s, i, g[i * N + sidx(b, x + L::cx(i), y + L::cy(i), z + L::cz(i))]);
 }
 
-// Second-order equilibrium deviations of (rho0, u0) in float64 (Eq. (11), G = 0).
+// Second-order equilibrium deviations of (rho0, u0) in float64 (Eq. (11) with
+// no stress term).
+template <class L>
 __global__ void k_equilibrium(Box b, double rho0, const double* __restrict__ u0, double* __restrict__ g) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= b.N) return;
@@ -212,14 +237,14 @@ __global__ void k_equilibrium(Box b, double rho0, const double* __restrict__ u0,
     for (int a = 0; a < 3; ++a) u[a] = u0[a * N + s];
   const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    const double cu = CX(i) * u[0] + CY(i) * u[1] + CZ(i) * u[2];
-    g[i * N + s] = WQ<double>(i) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+  for (int i = 0; i < L::Q; ++i) {
+    const double cu = L::cx(i) * u[0] + L::cy(i) * u[1] + L::cz(i) * u[2];
+    g[i * N + s] = L::template w<double>(i) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
   }
 }
 
 // rho and u (with F/2) at time t.
-template <class R, class GS>
+template <class R, class GS, class L>
 __global__ void k_moments(Box b, Params<R> P, const GS* __restrict__ B, const R* __restrict__ sig,
                           R* __restrict__ rho_out, R* __restrict__ u_out) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -228,15 +253,15 @@ __global__ void k_moments(Box b, Params<R> P, const GS* __restrict__ B, const R*
   coords(b, s, x, y, z);
   const size_t N = b.N;
   R F[3];
-  force_at(b, P, sig, x, y, z, F);
+  force_at<L>(b, P, sig, x, y, z, F);
   R sum = R(0), j[3] = {R(0), R(0), R(0)};
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    const R gi = GPol<GS>::template ld<R>(B, i * N + sidx(b, x - CX(i), y - CY(i), z - CZ(i)), i);
+  for (int i = 0; i < L::Q; ++i) {
+    const R gi = GPol<GS>::template ld<R>(B, i * N + sidx(b, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i);
     sum += gi;
-    j[0] += R(CX(i)) * gi;
-    j[1] += R(CY(i)) * gi;
-    j[2] += R(CZ(i)) * gi;
+    j[0] += R(L::cx(i)) * gi;
+    j[1] += R(L::cy(i)) * gi;
+    j[2] += R(L::cz(i)) * gi;
   }
   const R rho = P.rho0 + sum;
   rho_out[s] = rho;

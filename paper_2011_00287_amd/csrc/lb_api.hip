@@ -119,6 +119,9 @@ bool finite_params(const lb_params& p) {
 void validate(const lb_params& p) {
   if (p.nx < 3 || p.ny < 3 || p.nz < 3) fail(LB_EINVAL, "box sides must be >= 3");
   if (p.prec < LB_FP64 || p.prec > LB_FP16S) fail(LB_EINVAL, "unknown precision");
+  if (p.lattice != LB_D3Q19 && p.lattice != LB_D3Q15) fail(LB_EINVAL, "unknown lattice");
+  if (p.lattice == LB_D3Q15 && p.prec == LB_FP16S)
+    fail(LB_EINVAL, "float16 population storage is scaled for the D3Q19 weights");
   if (!finite_params(p)) fail(LB_EINVAL, "non-finite parameter");
   if (!(p.tau > 0.5)) fail(LB_EINVAL, "tau must be > 0.5");
   if (!(p.rho0 > 0.0)) fail(LB_EINVAL, "rho0 must be > 0");
@@ -174,8 +177,9 @@ struct Backend {
   virtual double seed_centre(double z_ref, void* adj) = 0;
 };
 
-template <class R, class GS, class FS>
+template <class R, class GS, class FS, class L>
 struct BackendT final : Backend {
+  static constexpr int NQ = L::Q;  // populations per site
   lbc::Box box;
   hipStream_t stream;
   lbc::Params<R> P;
@@ -241,13 +245,13 @@ struct BackendT final : Backend {
     ao_nty = (p.ny + kAoTY - 1) / kAoTY;
     ao_tz = auto_slab(ao_ntx, ao_nty, p.nz, 16, 1, 2);
     ao_blocks = ao_ntx * ao_nty * ((p.nz + ao_tz - 1) / ao_tz);
-    size_t need = 2 * (19 * N * sizeof(GS) + 6 * N * sizeof(FS)) + 4 * N * sizeof(R);
+    size_t need = 2 * (NQ * N * sizeof(GS) + 6 * N * sizeof(FS)) + 4 * N * sizeof(R);
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need > free_b)
       fail(LB_ENOMEM, "state needs " + std::to_string(need) + " bytes, " + std::to_string(free_b) + " free");
     try {
       for (int k = 0; k < 2; ++k) {
-        B[k] = dalloc<GS>(19 * N);
+        B[k] = dalloc<GS>(NQ * N);
         Q[k] = dalloc<FS>(5 * N);
         Ph[k] = dalloc<FS>(N);
       }
@@ -346,14 +350,14 @@ struct BackendT final : Backend {
     h2d_convert(phi, Ph[cur], N);
     h2d_convert(q5, Q[cur], 5 * N);
     double* du0 = nullptr;
-    double* g = dalloc<double>(19 * N);
+    double* g = dalloc<double>(NQ * N);
     try {
       if (u0) {
         du0 = dalloc<double>(3 * N);
         HIPCHECK(hipMemcpyAsync(du0, u0, 3 * N * sizeof(double), hipMemcpyHostToDevice, stream));
       }
-      lbc::k_equilibrium<<<nblk, TPB, 0, stream>>>(box, double(Pd.rho0), du0, g);
-      lbc::k_push<GS><<<nblk, TPB, 0, stream>>>(box, g, B[cur]);
+      lbc::k_equilibrium<L><<<nblk, TPB, 0, stream>>>(box, double(Pd.rho0), du0, g);
+      lbc::k_push<GS, L><<<nblk, TPB, 0, stream>>>(box, g, B[cur]);
       check_launch();
       HIPCHECK(hipStreamSynchronize(stream));
     } catch (...) {
@@ -369,10 +373,10 @@ struct BackendT final : Backend {
     if (phi) h2d_convert(phi, Ph[cur], N);
     if (q5) h2d_convert(q5, Q[cur], 5 * N);
     if (g19) {
-      double* g = dalloc<double>(19 * N);
+      double* g = dalloc<double>(NQ * N);
       try {
-        HIPCHECK(hipMemcpyAsync(g, g19, 19 * N * sizeof(double), hipMemcpyHostToDevice, stream));
-        lbc::k_push<GS><<<nblk, TPB, 0, stream>>>(box, g, B[cur]);
+        HIPCHECK(hipMemcpyAsync(g, g19, NQ * N * sizeof(double), hipMemcpyHostToDevice, stream));
+        lbc::k_push<GS, L><<<nblk, TPB, 0, stream>>>(box, g, B[cur]);
         check_launch();
         HIPCHECK(hipStreamSynchronize(stream));
       } catch (...) {
@@ -399,7 +403,7 @@ struct BackendT final : Backend {
           lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], mu, H, sig);
           break;
         case 1:
-          lbc::k_collide<R, GS><<<nblk, TPB, 0, stream>>>(box, P, B[cur], B[nx], sig, u);
+          lbc::k_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, B[cur], B[nx], sig, u);
           break;
         case 2:
           lbc::k_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], u, H, mu, Ph[nx], Q[nx]);
@@ -441,7 +445,7 @@ struct BackendT final : Backend {
   }
   template <int TX, int TY, int MINW>
   void launch_lb(const Io& io) {
-    lbc::k_lb_fused<R, GS, FS, TX, TY, MINW><<<lb_blocks, TX * TY, 0, stream>>>(
+    lbc::k_lb_fused<R, GS, FS, L, TX, TY, MINW><<<lb_blocks, TX * TY, 0, stream>>>(
         box, P, tz_lb, lb_ntx, lb_nty, io.Bi, io.Bo, io.phi_i, io.q_i, io.u, mu, io.F);
   }
   void launch_or_tile(const Io& io) {
@@ -520,7 +524,7 @@ struct BackendT final : Backend {
       R* uu = nullptr;
       try {
         uu = dalloc<R>(3 * N);
-        lbc::k_moments<R, GS><<<nblk, TPB, 0, stream>>>(box, P, B[cur], sig, r, uu);
+        lbc::k_moments<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, B[cur], sig, r, uu);
         check_launch();
         if (rho) d2h_convert(r, rho, N);
         if (u3) d2h_convert(uu, u3, 3 * N);
@@ -536,11 +540,11 @@ struct BackendT final : Backend {
     if (q5) d2h_convert(Q[cur], q5, 5 * N);
   }
   void populations(double* g19) override {
-    R* g = dalloc<R>(19 * N);
+    R* g = dalloc<R>(NQ * N);
     try {
-      lbc::k_pull<R, GS><<<nblk, TPB, 0, stream>>>(box, B[cur], g);
+      lbc::k_pull<R, GS, L><<<nblk, TPB, 0, stream>>>(box, B[cur], g);
       check_launch();
-      d2h_convert(g, g19, 19 * N);
+      d2h_convert(g, g19, NQ * N);
     } catch (...) {
       dfree(g);
       throw;
@@ -549,7 +553,7 @@ struct BackendT final : Backend {
   }
   void totals(double out[lbc::NTOT]) override {
     thermo_now();
-    lbc::k_totals<R, GS, FS><<<nblk, TPB, 0, stream>>>(box, Pd, B[cur], Ph[cur], Q[cur], sig, partial);
+    lbc::k_totals<R, GS, FS, L><<<nblk, TPB, 0, stream>>>(box, Pd, B[cur], Ph[cur], Q[cur], sig, partial);
     lbc::k_final_sum<<<1, TPB, 0, stream>>>(partial, int(nblk), lbc::NTOT, sums);
     check_launch();
     HIPCHECK(hipMemcpyAsync(out, sums, lbc::NTOT * sizeof(double), hipMemcpyDeviceToHost, stream));
@@ -564,13 +568,13 @@ struct BackendT final : Backend {
   }
 
   // --- checkpoint --------------------------------------------------------------
-  size_t off_q() const { return align256(19 * N * sizeof(GS)); }
+  size_t off_q() const { return align256(NQ * N * sizeof(GS)); }
   size_t off_phi() const { return off_q() + align256(5 * N * sizeof(FS)); }
   size_t off_step() const { return off_phi() + align256(N * sizeof(FS)); }
   size_t state_bytes() const override { return off_step() + sizeof(int64_t); }
   void get_state(void* dst, int64_t stepno) override {
     char* d = static_cast<char*>(dst);
-    HIPCHECK(hipMemcpyAsync(d, B[cur], 19 * N * sizeof(GS), hipMemcpyDeviceToDevice, stream));
+    HIPCHECK(hipMemcpyAsync(d, B[cur], NQ * N * sizeof(GS), hipMemcpyDeviceToDevice, stream));
     HIPCHECK(hipMemcpyAsync(d + off_q(), Q[cur], 5 * N * sizeof(FS), hipMemcpyDeviceToDevice, stream));
     HIPCHECK(hipMemcpyAsync(d + off_phi(), Ph[cur], N * sizeof(FS), hipMemcpyDeviceToDevice, stream));
     HIPCHECK(hipMemcpyAsync(d + off_step(), &stepno, sizeof(int64_t), hipMemcpyHostToDevice, stream));
@@ -578,7 +582,7 @@ struct BackendT final : Backend {
   }
   int64_t set_state(const void* src) override {
     const char* s = static_cast<const char*>(src);
-    HIPCHECK(hipMemcpyAsync(B[cur], s, 19 * N * sizeof(GS), hipMemcpyDeviceToDevice, stream));
+    HIPCHECK(hipMemcpyAsync(B[cur], s, NQ * N * sizeof(GS), hipMemcpyDeviceToDevice, stream));
     HIPCHECK(hipMemcpyAsync(Q[cur], s + off_q(), 5 * N * sizeof(FS), hipMemcpyDeviceToDevice, stream));
     HIPCHECK(hipMemcpyAsync(Ph[cur], s + off_phi(), N * sizeof(FS), hipMemcpyDeviceToDevice, stream));
     int64_t stepno = 0;
@@ -588,8 +592,12 @@ struct BackendT final : Backend {
   }
 
   // --- adjoint ---------------------------------------------------------------
-  // adjoint buffer: g_bar [19][N], q_bar [5][N], phi_bar [N] in R
-  size_t adjoint_bytes() const override { return 25 * N * sizeof(R); }
+  // adjoint buffer: g_bar [19][N], q_bar [5][N], phi_bar [N] in R (D3Q19 only)
+  static constexpr bool kAdjoint = !L::kStressInEq;
+  void need_adjoint() const {
+    if (!kAdjoint) fail(LB_EINVAL, "the adjoint is implemented for the D3Q19 scheme");
+  }
+  size_t adjoint_bytes() const override { return kAdjoint ? 25 * N * sizeof(R) : 0; }
   void ensure_adjoint() {
     if (aF) return;
     try {
@@ -615,7 +623,7 @@ struct BackendT final : Backend {
     }
   }
   // record buffer: u [3][N] and F [3][N] of the step that leaves the state
-  size_t record_bytes() const override { return 6 * N * sizeof(R); }
+  size_t record_bytes() const override { return kAdjoint ? 6 * N * sizeof(R) : 0; }
   struct StateView {
     const GS* B;
     const FS* q;
@@ -630,6 +638,7 @@ struct BackendT final : Backend {
   // One forward step from a state buffer into another, recording u and F of
   // the input time (the replay of a checkpoint segment for the adjoint).
   void step_record(const void* state_in, void* state_out, void* rec_out) override {
+    need_adjoint();
     const StateView vi = view(state_in);
     char* co = static_cast<char*>(state_out);
     GS* Bo = reinterpret_cast<GS*>(co);
@@ -641,7 +650,7 @@ struct BackendT final : Backend {
       ensure_thermo();
       lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, vi.phi, vi.q, mu, H, sig);
       lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, vi.B, sig, rF, ru);
-      lbc::k_collide<R, GS><<<nblk, TPB, 0, stream>>>(box, P, vi.B, Bo, sig, ru);
+      lbc::k_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, vi.B, Bo, sig, ru);
       lbc::k_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, vi.phi, vi.q, ru, H, mu, po, qo);
     } else {
       fused_step(Io{vi.B, Bo, vi.phi, vi.q, po, qo, ru, rF});
@@ -651,6 +660,7 @@ struct BackendT final : Backend {
   }
   void adjoint_step(const void* state, const void* rec, const void* adj_in, void* adj_out, double* zeta_bar,
                     double* q0_bar) override {
+    need_adjoint();
     ensure_adjoint();
     const StateView v = view(state);
     const R* gi = static_cast<const R*>(adj_in);
@@ -693,6 +703,7 @@ struct BackendT final : Backend {
     if (q0_bar) *q0_bar += pv[1];
   }
   double seed_centre(double z_ref, void* adj) override {
+    need_adjoint();
     double v[lbc::NCEN];
     centre(v);
     const double zc = v[2] / v[3];
@@ -736,14 +747,21 @@ void need_ctx(const lb_ctx* c) {
   if (!c || !c->be) fail(LB_EINVAL, "null context");
 }
 
+void need_adjoint_ctx(const lb_ctx* c) {
+  need_ctx(c);
+  if (c->p.lattice != LB_D3Q19) fail(LB_EINVAL, "the adjoint is implemented for the D3Q19 scheme");
+}
+
 std::unique_ptr<Backend> make_backend(const lb_params& p, hipStream_t s) {
   switch (p.prec) {
     case LB_FP64:
-      return std::unique_ptr<Backend>(new BackendT<double, double, double>(p, s));
+      if (p.lattice == LB_D3Q15) return std::unique_ptr<Backend>(new BackendT<double, double, double, lbc::D3Q15>(p, s));
+      return std::unique_ptr<Backend>(new BackendT<double, double, double, lbc::D3Q19>(p, s));
     case LB_FP32:
-      return std::unique_ptr<Backend>(new BackendT<float, float, float>(p, s));
+      if (p.lattice == LB_D3Q15) return std::unique_ptr<Backend>(new BackendT<float, float, float, lbc::D3Q15>(p, s));
+      return std::unique_ptr<Backend>(new BackendT<float, float, float, lbc::D3Q19>(p, s));
     default:
-      return std::unique_ptr<Backend>(new BackendT<float, __half, float>(p, s));
+      return std::unique_ptr<Backend>(new BackendT<float, __half, float, lbc::D3Q19>(p, s));
   }
 }
 
@@ -780,8 +798,9 @@ lb_status lb_set_params(lb_ctx* c, const lb_params* p) {
     need_ctx(c);
     if (!p) fail(LB_EINVAL, "null params");
     validate(*p);
-    if (p->nx != c->p.nx || p->ny != c->p.ny || p->nz != c->p.nz || p->prec != c->p.prec)
-      fail(LB_EINVAL, "box size and precision cannot change");
+    if (p->nx != c->p.nx || p->ny != c->p.ny || p->nz != c->p.nz || p->prec != c->p.prec ||
+        p->lattice != c->p.lattice)
+      fail(LB_EINVAL, "box size, precision and lattice cannot change");
     c->p = *p;
     c->be->set_params(*p);
   });
@@ -875,7 +894,7 @@ size_t lb_record_bytes(const lb_ctx* c) { return (c && c->be) ? c->be->record_by
 lb_status lb_step_record(lb_ctx* c, const void* dev_state_in, void* dev_state_out, void* dev_rec_out,
                          size_t state_bytes, size_t rec_bytes) {
   return guarded([&] {
-    need_ctx(c);
+    need_adjoint_ctx(c);
     if (!dev_state_in || !dev_state_out || !dev_rec_out) fail(LB_EINVAL, "null buffer");
     if (dev_state_in == dev_state_out) fail(LB_EINVAL, "state_in and state_out must differ");
     if (state_bytes != c->be->state_bytes()) fail(LB_ESTATE, "state buffer size mismatch");
@@ -888,7 +907,7 @@ lb_status lb_adjoint_step(lb_ctx* c, const void* dev_state_t, size_t state_bytes
                           size_t rec_bytes, const void* dev_adj_in, void* dev_adj_out, size_t adj_bytes,
                           double* zeta_bar, double* q0_bar) {
   return guarded([&] {
-    need_ctx(c);
+    need_adjoint_ctx(c);
     if (!dev_state_t || !dev_adj_in || !dev_adj_out) fail(LB_EINVAL, "null buffer");
     if (dev_adj_in == dev_adj_out) fail(LB_EINVAL, "adj_in and adj_out must differ");
     if (state_bytes != c->be->state_bytes()) fail(LB_ESTATE, "state buffer size mismatch");
@@ -900,7 +919,7 @@ lb_status lb_adjoint_step(lb_ctx* c, const void* dev_state_t, size_t state_bytes
 
 lb_status lb_adjoint_seed_centre(lb_ctx* c, double z_ref, void* dev_adj, size_t adj_bytes, double* loss) {
   return guarded([&] {
-    need_ctx(c);
+    need_adjoint_ctx(c);
     if (!dev_adj) fail(LB_EINVAL, "null buffer");
     if (adj_bytes != c->be->adjoint_bytes()) fail(LB_ESTATE, "adjoint buffer size mismatch");
     const double L = c->be->seed_centre(z_ref, dev_adj);

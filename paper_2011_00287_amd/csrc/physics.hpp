@@ -47,6 +47,42 @@ __host__ __device__ constexpr R WQ(int i) {
   return i == 0 ? R(1) / R(3) : (i <= 6 ? R(1) / R(18) : R(1) / R(36));
 }
 
+// Velocity sets as traits.  D3Q19 (the order above) carries the whole stress as
+// a Guo body force.  D3Q15, the paper's lattice (Fig. 1), carries the symmetric
+// stress in the second moment of the equilibrium (Eqs. (9), (11)) and only the
+// antisymmetric stress as forcing (Eq. (10)).  D3Q15 order: 0 rest; 1-6 = +x,
+// -x, +y, -y, +z, -z; 7-14 = body diagonals in opposite pairs (+,+,+)/(-,-,-),
+// (+,+,-)/(-,-,+), (+,-,+)/(-,+,-), (-,+,+)/(+,-,-); weights 2/9, 1/9, 1/72.
+struct D3Q19 {
+  static constexpr int Q = 19;
+  static constexpr bool kStressInEq = false;
+  __host__ __device__ static constexpr int cx(int i) { return CX(i); }
+  __host__ __device__ static constexpr int cy(int i) { return CY(i); }
+  __host__ __device__ static constexpr int cz(int i) { return CZ(i); }
+  template <class R>
+  __host__ __device__ static constexpr R w(int i) { return WQ<R>(i); }
+};
+struct D3Q15 {
+  static constexpr int Q = 15;
+  static constexpr bool kStressInEq = true;
+  __host__ __device__ static constexpr int cx(int i) {
+    return (i == 1 || i == 7 || i == 9 || i == 11 || i == 14) ? 1
+         : (i == 2 || i == 8 || i == 10 || i == 12 || i == 13) ? -1 : 0;
+  }
+  __host__ __device__ static constexpr int cy(int i) {
+    return (i == 3 || i == 7 || i == 9 || i == 12 || i == 13) ? 1
+         : (i == 4 || i == 8 || i == 10 || i == 11 || i == 14) ? -1 : 0;
+  }
+  __host__ __device__ static constexpr int cz(int i) {
+    return (i == 5 || i == 7 || i == 10 || i == 11 || i == 13) ? 1
+         : (i == 6 || i == 8 || i == 9 || i == 12 || i == 14) ? -1 : 0;
+  }
+  template <class R>
+  __host__ __device__ static constexpr R w(int i) {
+    return i == 0 ? R(2) / R(9) : (i <= 6 ? R(1) / R(9) : R(1) / R(72));
+  }
+};
+
 template <class R>
 struct C3 {
   static constexpr R third = R(1) / R(3);
@@ -312,6 +348,55 @@ __host__ __device__ __forceinline__ void collide_site(const Params<R>& P, R g[19
     const R cF = R(CX(i)) * F[0] + R(CY(i)) * F[1] + R(CZ(i)) * F[2];
     const R even = cb[k] + cu * (ca[k] * cu + cg9[k] * cF);
     const R odd = cr[k] * cu + cg3[k] * cF;
+    const R gi = g[i], gj = g[i + 1];
+    g[i] = (om1 * gi + even) + odd;
+    g[i + 1] = (om1 * gj + even) - odd;
+  }
+}
+
+// BGK collision of the paper's scheme on the 15 D3Q15 deviations g (in place).
+// The symmetric stress S (xx, xy, xz, yy, yz, zz) sits in the equilibrium,
+//   g_eq_i = w (drho + 3 rho cu + 9/2 c.T.c - 3/2 tr T),  T = rho u u - S,
+// and F (the force of the antisymmetric stress plus the body force) enters as
+// the Guo source guo w (-3 u.F + 3 cF + 9 cu cF) with u = (sum c g + F/2)/rho.
+// Opposite pairs (i, i+1) share the even part, as in collide_site.
+template <class R>
+__host__ __device__ __forceinline__ void collide_site_eq(const Params<R>& P, R g[15], const R F[3], const R S[6],
+                                                         R u[3]) {
+  using L = D3Q15;
+  R drho = g[0];
+#pragma unroll
+  for (int i = 1; i < 15; ++i) drho += g[i];
+  R j[3] = {R(0), R(0), R(0)};
+#pragma unroll
+  for (int i = 1; i < 15; i += 2) {
+    const R e = g[i] - g[i + 1];
+    j[0] += R(L::cx(i)) * e;
+    j[1] += R(L::cy(i)) * e;
+    j[2] += R(L::cz(i)) * e;
+  }
+  const R rho = P.rho0 + drho;
+  const R inv = R(1) / rho;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) u[a] = (j[a] + R(0.5) * F[a]) * inv;
+  const R Txx = rho * u[0] * u[0] - S[0], Txy = rho * u[0] * u[1] - S[1], Txz = rho * u[0] * u[2] - S[2];
+  const R Tyy = rho * u[1] * u[1] - S[3], Tyz = rho * u[1] * u[2] - S[4], Tzz = rho * u[2] * u[2] - S[5];
+  const R trT = Txx + Tyy + Tzz;
+  const R uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+  const R om = P.omega, om1 = R(1) - P.omega;
+  const R base = om * (drho - R(1.5) * trT) - R(3) * P.guo * uF;
+  const R a45 = R(4.5) * om, g9 = R(9) * P.guo, r3 = R(3) * om * rho, g3 = R(3) * P.guo;
+  g[0] = om1 * g[0] + L::w<R>(0) * base;
+#pragma unroll
+  for (int i = 1; i < 15; i += 2) {
+    const int ex = L::cx(i), ey = L::cy(i), ez = L::cz(i);
+    const R cu = R(ex) * u[0] + R(ey) * u[1] + R(ez) * u[2];
+    const R cF = R(ex) * F[0] + R(ey) * F[1] + R(ez) * F[2];
+    const R cTc = R(ex * ex) * Txx + R(ey * ey) * Tyy + R(ez * ez) * Tzz +
+                  R(2) * (R(ex * ey) * Txy + R(ex * ez) * Txz + R(ey * ez) * Tyz);
+    const R w = L::w<R>(i);
+    const R even = w * (base + a45 * cTc + g9 * cu * cF);
+    const R odd = w * (r3 * cu + g3 * cF);
     const R gi = g[i], gj = g[i + 1];
     g[i] = (om1 * gi + even) + odd;
     g[i + 1] = (om1 * gj + even) - odd;

@@ -18,12 +18,13 @@ _PARAM_KEYS = ("tau", "rho0", "a", "phi0", "phi_cr", "k_phi", "M", "A0", "chi0",
                "Gamma", "xi", "zeta")
 
 
-def make_params(p: dict, shape, precision: str = "fp64") -> LbParams:
+def make_params(p: dict, shape, precision: str = "fp64", lattice: str = "d3q19") -> LbParams:
     """LbParams from a parameter dict and a field shape (nz, ny, nx)."""
     nz, ny, nx = shape
     lp = LbParams()
     lp.nx, lp.ny, lp.nz = int(nx), int(ny), int(nz)
     lp.prec = _lib.PRECISIONS[precision]
+    lp.lattice = _lib.LATTICES[lattice]
     for k in _PARAM_KEYS:
         setattr(lp, k, float(p[k]))
     bf = p.get("body_force", (0.0, 0.0, 0.0))
@@ -54,14 +55,17 @@ class Sim:
     """One periodic box on the GPU.
 
     phi: [nz, ny, nx]; q5: [5, nz, ny, nx] (xx, xy, xz, yy, yz); u0: [3, nz, ny, nx]
-    or None.  precision: 'fp64', 'fp32' or 'fp16s'.  stream: a torch.cuda.Stream,
+    or None.  precision: 'fp64', 'fp32' or 'fp16s'.  lattice: 'd3q19' (stress as a
+    forcing term) or 'd3q15' (symmetric stress in the equilibrium, antisymmetric
+    stress as a forcing term; fp64 and fp32, forward only).  stream: a torch.cuda.Stream,
     a raw hipStream_t as int, or None for the default stream.  The device tensors
     this class allocates (state, adjoint and record buffers) are created and
     zero-filled on torch's current stream, so pass that stream (or None while
     torch uses the default stream) to keep them ordered with the library's work.
     """
 
-    def __init__(self, params: dict, phi, q5, u0=None, precision: str = "fp64", stream=None):
+    def __init__(self, params: dict, phi, q5, u0=None, precision: str = "fp64", stream=None,
+                 lattice: str = "d3q19"):
         phi = _c64(phi)
         q5 = _c64(q5)
         if q5.shape != (5,) + phi.shape:
@@ -71,8 +75,10 @@ class Sim:
             raise ValueError("u0 shape mismatch")
         self.shape = phi.shape
         self.precision = precision
+        self.lattice = lattice
+        self.n_populations = _lib.N_POPULATIONS[lattice]
         self.params = dict(params)
-        self._lp = make_params(params, phi.shape, precision)
+        self._lp = make_params(params, phi.shape, precision, lattice)
         self._stream = stream
         h = ctypes.c_void_p()
         check(lib().lb_init(ctypes.byref(self._lp), _dptr(phi), _dptr(q5), _dptr(u0),
@@ -109,9 +115,9 @@ class Sim:
         check(lib().lb_sync(self._h))
 
     def set_params(self, **changes):
-        """Change model parameters (not the box or precision); kept only if the library accepts them."""
+        """Change model parameters (not the box, precision or lattice); kept only if the library accepts them."""
         new = dict(self.params, **changes)
-        lp = make_params(new, self.shape, self.precision)
+        lp = make_params(new, self.shape, self.precision, self.lattice)
         check(lib().lb_set_params(self._h, ctypes.byref(lp)))
         self.params, self._lp = new, lp
 
@@ -133,7 +139,7 @@ class Sim:
         return phi, q5
 
     def populations(self) -> np.ndarray:
-        g = np.empty((19,) + self.shape)
+        g = np.empty((self.n_populations,) + self.shape)
         check(lib().lb_populations(self._h, _dptr(g)))
         return g
 
@@ -141,6 +147,9 @@ class Sim:
         g = None if g is None else _c64(g)
         phi = None if phi is None else _c64(phi)
         q5 = None if q5 is None else _c64(q5)
+        for name, a, lead in (("g", g, (self.n_populations,)), ("phi", phi, ()), ("q5", q5, (5,))):
+            if a is not None and a.shape != lead + self.shape:
+                raise ValueError(f"{name} shape {a.shape}, expected {lead + self.shape}")
         check(lib().lb_set_fields(self._h, _dptr(g), _dptr(phi), _dptr(q5)))
 
     def totals(self) -> dict:

@@ -1,11 +1,12 @@
 /* A plain C consumer of the library: only include/lb_chiral.h and the shared
  * library, no Python and no HIP headers.  Runs on the GPU:
  *   1. a uniform body force f on a fluid without order parameters (Q = 0,
- *      phi = 0) in float64: the total momentum (u with F/2) is N f (t + 1/2)
- *      exactly after t steps;
+ *      phi = 0) in float64, on both lattices: the total momentum (u with F/2)
+ *      is N f (t + 1/2) exactly after t steps;
  *   2. a small chiral droplet in float64 and float32: mass and sum(phi) are
  *      conserved over 50 steps, the step counter advances;
- *   3. error paths: invalid parameters, negative step counts, NULL contexts.
+ *   3. error paths: invalid parameters, unknown or unsupported lattices,
+ *      negative step counts, NULL contexts, shape or lattice changes.
  * Prints "C ABI OK" and exits 0 when every check holds. */
 #include <math.h>
 #include <stdio.h>
@@ -53,9 +54,10 @@ static lb_params base_params(int nx, int ny, int nz, int prec) {
   return p;
 }
 
-static void body_force_case(void) {
+static void body_force_case(int lattice) {
   const int nx = 9, ny = 7, nz = 6, N = nx * ny * nz;
   lb_params p = base_params(nx, ny, nz, LB_FP64);
+  p.lattice = lattice;
   p.zeta = 0.0;
   p.body_force[0] = 1e-6;
   p.body_force[2] = -3e-7;
@@ -141,18 +143,28 @@ static void error_paths(void) {
   p = base_params(4, 4, 4, 7);
   CHECK(lb_init(&p, phi, q5, NULL, NULL, &c) == LB_EINVAL, "unknown precision accepted");
   p = base_params(4, 4, 4, LB_FP32);
+  p.lattice = 3;
+  CHECK(lb_init(&p, phi, q5, NULL, NULL, &c) == LB_EINVAL, "unknown lattice accepted");
+  p = base_params(4, 4, 4, LB_FP16S);
+  p.lattice = LB_D3Q15;
+  CHECK(lb_init(&p, phi, q5, NULL, NULL, &c) == LB_EINVAL, "float16 storage on D3Q15 accepted");
+  p = base_params(4, 4, 4, LB_FP32);
   CHECK(lb_init(&p, phi, q5, NULL, NULL, &c) == LB_OK && c, "lb_init: %s", lb_last_error());
   CHECK(lb_step(c, -1) == LB_EINVAL, "negative step count accepted");
   CHECK(lb_step(NULL, 1) == LB_EINVAL, "NULL context accepted");
   lb_params q = p;
   q.nx = 5;
   CHECK(lb_set_params(c, &q) == LB_EINVAL, "shape change accepted");
+  q = p;
+  q.lattice = LB_D3Q15;
+  CHECK(lb_set_params(c, &q) == LB_EINVAL, "lattice change accepted");
   lb_destroy(c);
   lb_destroy(NULL);
 }
 
 int main(void) {
-  body_force_case();
+  body_force_case(LB_D3Q19);
+  body_force_case(LB_D3Q15);
   droplet_case(LB_FP64, 1e-12);
   droplet_case(LB_FP32, 1e-6);
   error_paths();

@@ -1,0 +1,194 @@
+"""GPU parity of the paper's own LB scheme (Sec. 3; D3Q15, the symmetric stress in
+the equilibrium of Eqs. (9), (11), the antisymmetric stress as the forcing term of
+Eq. (10)) against the FP64 oracle of that scheme, through the C ABI.
+
+Tolerances are those of the D3Q19 parity tests: 1e-12 relative per field for
+FP64; FP32 is an accuracy statement against FP64 from measured error growth.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import core, d3q15
+from paper_2011_00287_amd import inputs
+from paper_2011_00287_amd._lib import LB_EINVAL, LbError
+from paper_2011_00287_amd.sim import Sim
+
+from helpers import field_errors, rel_err, t64
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _p(**kw):
+    return dict(inputs.BASE_PARAMS, **kw)
+
+
+def _run(p, g, q5, phi, n):
+    g, q5, phi = d3q15.run(t64(g), t64(q5), t64(phi), p, n)
+    return g.numpy(), q5.numpy(), phi.numpy()
+
+
+def _observe(p, g, q5, phi):
+    rho, u = d3q15.observe(t64(g), t64(q5), t64(phi), p)
+    return rho.numpy(), u.numpy()
+
+
+def _compare(sim, p, g, q5, phi, tol=TOL64):
+    rho_o, u_o = _observe(p, g, q5, phi)
+    errs = field_errors(sim.moments(), (rho_o, u_o, phi, q5), p["rho0"])
+    errs["g"] = rel_err(sim.populations(), g)
+    for name, (l2, mx) in errs.items():
+        assert l2 <= tol and mx <= tol, (name, l2, mx)
+
+
+def _g15(nx, ny, nz, seed):
+    g, phi, q5 = inputs.random_fields(nx, ny, nz, seed=seed, g_amp=2e-3, q_amp=0.2)
+    return np.ascontiguousarray(g[:15]), phi, q5
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4), (5, 3, 4), (7, 6, 5), (17, 9, 3), (33, 17, 9), (40, 20, 19)])
+def test_fp64_random_state_parity(shape):
+    nx, ny, nz = shape
+    p = _p(q0=2 * math.pi / 7, zeta=0.01, body_force=(1e-5, -2e-5, 3e-5))
+    g, phi, q5 = _g15(nx, ny, nz, nx * 100 + ny * 10 + nz)
+    with Sim(p, phi, q5, precision="fp64", lattice="d3q15") as s:
+        s.set_fields(g=g)
+        _compare(s, p, g, q5, phi)
+        s.step(3)
+        _compare(s, p, *_run(p, g, q5, phi, 3))
+
+
+def test_fp64_droplet16_100_steps():
+    """The 16^3 droplet from rest (f = w rho0), 100 steps: <= 1e-12 per field."""
+    p = inputs.params_for("droplet16")
+    phi, q5 = inputs.workload_fields("droplet16")
+    g = np.zeros((15,) + phi.shape)
+    with Sim(p, phi, q5, precision="fp64", lattice="d3q15") as s:
+        s.step(100)
+        _compare(s, p, *_run(p, g, q5, phi, 100))
+
+
+def test_init_with_velocity_is_stress_free_equilibrium():
+    p = _p()
+    u0 = inputs.ic_shear_wave(8, 1e-3, nx=4, ny=5)
+    phi = np.zeros(u0.shape[1:])
+    q5 = np.zeros((5,) + u0.shape[1:])
+    geq = d3q15.init_populations(t64(u0), p).numpy()
+    with Sim(p, phi, q5, u0=u0, lattice="d3q15") as s:
+        l2, mx = rel_err(s.populations(), geq)
+        assert l2 < 1e-15 and mx < 1e-15
+
+
+def test_totals_match_oracle():
+    """mass, momentum and kinetic energy with this scheme's velocity; F_h and sum phi
+    do not depend on the lattice."""
+    p = _p(q0=0.8, zeta=0.01)
+    g, phi, q5 = _g15(6, 7, 5, 5)
+    with Sim(p, phi, q5, lattice="d3q15") as s:
+        s.set_fields(g=g)
+        t = s.totals()
+    rho, u = _observe(p, g, q5, phi)
+    mass = phi.size * p["rho0"] + g.sum()
+    assert abs(t["mass"] - mass) <= 1e-12 * mass
+    for a in range(3):
+        assert abs(t["momentum"][a] - (rho * u[a]).sum()) <= 1e-13 * np.abs(g).sum()
+    ke = (0.5 * rho * (u * u).sum(0)).sum()
+    assert abs(t["kinetic_energy"] - ke) <= 1e-11 * ke
+    fe = float(core.free_energy(t64(phi), core.q_full(t64(q5)), p))
+    assert abs(t["free_energy"] - fe) <= 1e-12 * abs(fe)
+
+
+@pytest.mark.parametrize("lb_tile,or_tile,tz", [(0, 0, "1"), (1, 1, "3"), (2, 2, "8"), (3, 3, "5"), (4, 4, "16"),
+                                                (0, 3, "default")])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_site_kernels_match_fused_kernels(monkeypatch, lb_tile, or_tile, tz, prec):
+    """Site-parallel and fused kernels of this scheme compute the same step for every
+    tile variant and slab depth (ragged tiles and slabs included)."""
+    p = _p(q0=2 * math.pi / 9, zeta=0.01)
+    g, phi, q5 = _g15(34, 18, 11, 77)
+    if tz == "default":
+        monkeypatch.delenv("LBC_TZ_LB", raising=False)
+        monkeypatch.delenv("LBC_TZ_ORDER", raising=False)
+    else:
+        monkeypatch.setenv("LBC_TZ_LB", tz)
+        monkeypatch.setenv("LBC_TZ_ORDER", tz)
+    monkeypatch.setenv("LBC_LB_TILE", str(lb_tile))
+    monkeypatch.setenv("LBC_OR_TILE", str(or_tile))
+    tol = 1e-13 if prec == "fp64" else 2e-5
+    with Sim(p, phi, q5, precision=prec, lattice="d3q15") as fused:
+        monkeypatch.setenv("LBC_SITE_KERNELS", "1")
+        with Sim(p, phi, q5, precision=prec, lattice="d3q15") as site:
+            for s in (fused, site):
+                s.set_fields(g=g)
+                s.step(4)
+            for a, b in zip(fused.moments(), site.moments()):
+                l2, mx = rel_err(a, b)
+                assert l2 < tol and mx < tol
+            l2, mx = rel_err(fused.populations(), site.populations())
+            assert l2 < tol and mx < tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_conservation(prec):
+    p = inputs.params_for("droplet16")
+    phi, q5 = inputs.workload_fields("droplet16")
+    with Sim(p, phi, q5, precision=prec, lattice="d3q15") as s:
+        t0 = s.totals()
+        s.step(200)
+        t1 = s.totals()
+    tol = {"fp64": 1e-13, "fp32": 1e-6}[prec]
+    assert abs(t1["mass"] - t0["mass"]) <= tol * t0["mass"]
+    assert abs(t1["phi_total"] - t0["phi_total"]) <= tol * t0["phi_total"]
+    for a in range(3):
+        assert abs(t1["momentum"][a] - t0["momentum"][a]) <= tol * t0["mass"]
+
+
+def test_fp32_accuracy_droplet16():
+    """FP32 against FP64 of the same scheme after 100 steps of the 16^3 droplet."""
+    p = inputs.params_for("droplet16")
+    phi, q5 = inputs.workload_fields("droplet16")
+    with Sim(p, phi, q5, precision="fp64", lattice="d3q15") as a, \
+            Sim(p, phi, q5, precision="fp32", lattice="d3q15") as b:
+        a.step(100)
+        b.step(100)
+        ea = field_errors(b.moments(), a.moments(), p["rho0"])
+    for name, (l2, mx) in ea.items():
+        assert l2 <= 2e-4, (name, l2, mx)
+
+
+def test_bitwise_determinism_and_resume():
+    p = inputs.params_for("droplet16")
+    phi, q5 = inputs.workload_fields("droplet16")
+    with Sim(p, phi, q5, precision="fp32", lattice="d3q15") as a, \
+            Sim(p, phi, q5, precision="fp32", lattice="d3q15") as b:
+        a.step(20)
+        ck = a.get_state()
+        a.step(15)
+        b.step(35)
+        ra = a.moments()
+        for x, y in zip(ra, b.moments()):
+            assert np.array_equal(x, y)
+        b.set_state(ck)
+        b.step(15)
+        for x, y in zip(ra, b.moments()):
+            assert np.array_equal(x, y)
+
+
+def test_rejected_combinations():
+    """float16 population storage and the adjoint are D3Q19-only: refused with LB_EINVAL."""
+    p = _p()
+    phi, q5 = inputs.droplet_fields(6, 6, 6, 2.0, 0.5)
+    with pytest.raises(LbError) as e:
+        Sim(p, phi, q5, precision="fp16s", lattice="d3q15")
+    assert e.value.status == LB_EINVAL
+    with Sim(p, phi, q5, lattice="d3q15") as s:
+        assert s.adjoint_buffer().numel() == 0 and s.record_buffer().numel() == 0
+        with pytest.raises(LbError) as e:
+            s.step_record(s.get_state(), s.get_state(), torch.empty(8, dtype=torch.uint8, device="cuda"))
+        assert e.value.status == LB_EINVAL
+        s.step(2)
+        assert s.totals()["step"] == 2
