@@ -34,7 +34,17 @@ ALGO_VALUES = {
     "k_order": (0, 6),      # writes Q, phi
     "k_lb_fused": (1, 6),   # populations + reads of Q, phi
     "k_order_fused": (0, 6),
+    # the paper's predictor-corrector (per launch: its own field reads + writes;
+    # X*, Y, v and mu are traffic the stage split adds)
+    "k_pc_v": (0, 9),        # phi, Q -> v
+    "k_pc_mu": (0, 10),      # phi, Q, v -> mu
+    "k_pc_predict": (0, 16),  # Q, phi, u, mu -> X*
+    "k_pc_correct": (0, 22),  # X*, u, mu, X -> Q, phi
+    "k_pc_mu_z": (0, 7),       # phi, Q -> mu (v stays on chip)
+    "k_pc_stage_z (predict)": (0, 16),
+    "k_pc_stage_z (correct)": (0, 22),
 }
+PC4_M = 0.05  # mobility inside the explicit fourth-order Cahn-Hilliard stability bound
 NQ = {"d3q19": 19, "d3q15": 15}
 GS_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 2}
 FS_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 4}
@@ -68,10 +78,12 @@ def step_bytes(prec: str, lattice: str = "d3q19") -> int:
     return 2 * NQ[lattice] * GS_BYTES[prec] + 12 * FS_BYTES[prec]
 
 
-def time_precision(prec, p, phi, q5, steps, warmup, stream, lattice="d3q19"):
+def time_precision(prec, p, phi, q5, steps, warmup, stream, lattice="d3q19", fd_scheme="euler2"):
     import torch
     from paper_2011_00287_amd.sim import Sim
-    sim = Sim(p, phi, q5, precision=prec, stream=stream, lattice=lattice)
+    if fd_scheme == "pc4":
+        p = dict(p, M=PC4_M)
+    sim = Sim(p, phi, q5, precision=prec, stream=stream, lattice=lattice, fd_scheme=fd_scheme)
     sim.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -129,12 +141,17 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True):
     return out
 
 
-def cpu_baseline(workload: str, nsteps: int = 2, lattice: str = "d3q19"):
+def cpu_baseline(workload: str, nsteps: int = 2, lattice: str = "d3q19", fd_scheme: str = "euler2"):
     import torch
-    from oracle import core, d3q15
+    from oracle import core, d3q15, pc4
     from paper_2011_00287_amd import inputs
-    step = core.step if lattice == "d3q19" else d3q15.step
-    p = inputs.params_for(workload)
+    if fd_scheme == "pc4":
+        if lattice != "d3q19":
+            return None
+        step = pc4.step
+    else:
+        step = core.step if lattice == "d3q19" else d3q15.step
+    p = inputs.params_for(workload, **({"M": PC4_M} if fd_scheme == "pc4" else {}))
     phi, q5 = inputs.workload_fields(workload)
     phi_t, q5_t = torch.tensor(phi), torch.tensor(q5)
     g = torch.zeros((NQ[lattice],) + phi.shape, dtype=torch.float64)
@@ -145,8 +162,8 @@ def cpu_baseline(workload: str, nsteps: int = 2, lattice: str = "d3q19"):
     dt = time.perf_counter() - t0
     n = phi.size
     return {"value": n * nsteps / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"{workload} ({n} sites) FP64 oracle ({lattice.upper()}), {nsteps} timed steps after 1 "
-                      "warm-up from the initial droplet"}
+            "sample": f"{workload} ({n} sites) FP64 oracle ({lattice.upper()}, {fd_scheme}), {nsteps} timed steps "
+                      "after 1 warm-up from the initial droplet"}
 
 
 def copy_calibration(nbytes: int, reps: int):
@@ -182,6 +199,9 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16s"])
     ap.add_argument("--lattice", default="d3q19", choices=["d3q19", "d3q15"],
                     help="d3q19: stress as a body force; d3q15: the paper's scheme (forward only)")
+    ap.add_argument("--fd-scheme", default="euler2", choices=["euler2", "pc4"],
+                    help="euler2: explicit Euler, 2nd-order stencils; pc4: the paper's predictor-corrector, "
+                         f"upwind, 4th-order stencils (forward only, M = {PC4_M})")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side", action="store_true", help="skip the FP64 / FP16S side timings")
     ap.add_argument("--profile-steps", type=int, default=50)
@@ -209,18 +229,19 @@ def main():
     p = inputs.params_for(args.workload)
     phi, q5 = inputs.workload_fields(args.workload)
     n = phi.size
-    print(f"# workload {args.workload} {phi.shape} {args.precision} {args.lattice}: warmup {args.warmup}, "
-          f"steps {args.steps}", file=sys.stderr, flush=True)
+    print(f"# workload {args.workload} {phi.shape} {args.precision} {args.lattice} {args.fd_scheme}: "
+          f"warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
     if args.lattice == "d3q15" and args.precision == "fp16s":
         ap.error("float16 population storage is D3Q19-only")
 
-    sim, dt = time_precision(args.precision, p, phi, q5, args.steps, args.warmup, stream, args.lattice)
+    sim, dt = time_precision(args.precision, p, phi, q5, args.steps, args.warmup, stream, args.lattice,
+                             args.fd_scheme)
     mlups = n * args.steps / dt / 1e6
     print(f"# {args.precision}: {mlups:.1f} MLUPS ({dt / args.steps * 1e3:.4f} ms/step)", file=sys.stderr, flush=True)
 
     prof = sim.profile(args.profile_steps)
     dom = max(prof, key=prof.get)
-    gv, fv = ALGO_VALUES[dom]
+    gv, fv = ALGO_VALUES.get(dom, ALGO_VALUES.get(dom.split(" ")[0]))
     algo_bytes = (gv * 2 * NQ[args.lattice] * GS_BYTES[args.precision] + fv * FS_BYTES[args.precision]) * n
     achieved = algo_bytes / (prof[dom] * 1e-3) / 1e9
     totals = sim.totals()
@@ -229,20 +250,23 @@ def main():
 
     side = {}
     if not args.no_side:
-        cases = [(prec, "d3q19") for prec in ("fp64", "fp16s")] + [(prec, "d3q15") for prec in ("fp32", "fp64")]
-        for prec, lat in cases:
-            if (prec, lat) == (args.precision, args.lattice):
+        cases = [(prec, "d3q19", "euler2") for prec in ("fp64", "fp16s")] + \
+                [(prec, "d3q15", "euler2") for prec in ("fp32", "fp64")] + [("fp32", "d3q19", "pc4")]
+        for prec, lat, fd in cases:
+            if (prec, lat, fd) == (args.precision, args.lattice, args.fd_scheme):
                 continue
             key = prec if lat == "d3q19" else f"{lat}_{prec}"
+            if fd != "euler2":
+                key = f"{fd}_{key}"
             ns = max(20, args.steps // (4 if prec == "fp64" else 1))
-            s2, dt2 = time_precision(prec, p, phi, q5, ns, 5, stream, lat)
+            s2, dt2 = time_precision(prec, p, phi, q5, ns, 5, stream, lat, fd)
             s2.close()
             side[key] = {"mlups": n * ns / dt2 / 1e6, "ms_per_step": dt2 / ns * 1e3,
                          "step_hbm_frac": n * ns / dt2 * step_bytes(prec, lat) / (HBM_PEAK_GBS * 1e9)}
             print(f"# {key}: {side[key]['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
 
     adjoint = None
-    if args.adjoint_steps > 0 and args.lattice == "d3q19":
+    if args.adjoint_steps > 0 and args.lattice == "d3q19" and args.fd_scheme == "euler2":
         adjoint = time_adjoint(args.precision, p, phi, q5, args.adjoint_steps, args.adjoint_checkpoint, stream,
                                recorded=not args.no_adjoint_recorded)
         print(f"# adjoint/forward: {adjoint['adjoint_over_forward']:.2f} (checkpoint {args.adjoint_checkpoint})"
@@ -264,7 +288,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "box": list(phi.shape[::-1]), "droplet_radius": w["R"],
                    "q0": w["q0"], "zeta": w["zeta"], "precision": args.precision,
-                   "lattice": args.lattice.upper()},
+                   "lattice": args.lattice.upper(), "fd_scheme": args.fd_scheme,
+                   **({"M": PC4_M} if args.fd_scheme == "pc4" else {})},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, args.workload, args.precision, args.lattice), "kernel": dom,
@@ -279,7 +304,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         print("# timing the FP64 CPU oracle on a bounded sample ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(args.workload, lattice=args.lattice)
+        line["cpu_baseline"] = cpu_baseline(args.workload, lattice=args.lattice, fd_scheme=args.fd_scheme)
     print(json.dumps(line), flush=True)
 
 

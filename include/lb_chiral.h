@@ -77,6 +77,18 @@ typedef enum {
                    (Eq. (10)); float64 and float32 only, no adjoint          */
 } lb_lattice;
 
+typedef enum {
+  LB_FD_EULER2 = 0, /* explicit Euler, second-order central differences (D0, the
+                       7-point Laplacian), central advection                   */
+  LB_FD_PC4 = 1     /* the paper's integrator of Eqs. (1)-(2) (Sec. 3): Heun
+                       predictor-corrector at the time-t velocity, first-order
+                       upwind advection (donor-cell flux for phi), fourth-order
+                       stencils in mu, H, grad u and the Laplacian of mu; the
+                       LB stress and force keep the second-order stencils.
+                       Stable where M*16*(f'' + 16 k_phi) < 2 (e.g. M = 0.05 with
+                       the droplet parameters); no adjoint                     */
+} lb_fd_scheme;
+
 /* Model parameters (Eqs. (1)-(5), (7)).  K is the single elastic constant
  * K_Q of Eq. (5); Gamma is the rotational mobility multiplying H in the
  * Beris-Edwards update; xi the flow-alignment parameter; zeta the activity
@@ -90,6 +102,7 @@ typedef struct {
   double Gamma, xi, zeta;
   double body_force[3]; /* uniform external force density, added to F */
   int32_t lattice;      /* lb_lattice; 0 (a zero-initialised struct) = LB_D3Q19 */
+  int32_t fd_scheme;    /* lb_fd_scheme; 0 = LB_FD_EULER2 */
 } lb_params;
 
 /* Global sums, accumulated in float64 on the device.  mass = N*rho0 + sum g;

@@ -13,6 +13,8 @@ PRECISIONS = {"fp64": LB_FP64, "fp32": LB_FP32, "fp16s": LB_FP16S}
 LB_D3Q19, LB_D3Q15 = 0, 1
 LATTICES = {"d3q19": LB_D3Q19, "d3q15": LB_D3Q15}
 N_POPULATIONS = {"d3q19": 19, "d3q15": 15}
+LB_FD_EULER2, LB_FD_PC4 = 0, 1
+FD_SCHEMES = {"euler2": LB_FD_EULER2, "pc4": LB_FD_PC4}
 LB_MAX_KERNELS = 8
 
 
@@ -26,6 +28,7 @@ class LbParams(ctypes.Structure):
         ("K", ctypes.c_double), ("q0", ctypes.c_double), ("W", ctypes.c_double),
         ("Gamma", ctypes.c_double), ("xi", ctypes.c_double), ("zeta", ctypes.c_double),
         ("body_force", ctypes.c_double * 3), ("lattice", ctypes.c_int32),
+        ("fd_scheme", ctypes.c_int32),
     ]
 
 

@@ -18,6 +18,7 @@
 #include "lb_chiral.h"
 #include "kernels_adjoint.hpp"
 #include "kernels_fused.hpp"
+#include "kernels_pc.hpp"
 #include "kernels_reduce.hpp"
 
 namespace {
@@ -73,6 +74,8 @@ struct TileCfg {
 };
 constexpr TileCfg kLbTiles[] = {{32, 8}, {32, 16}, {64, 4}, {16, 16}, {16, 8}};
 constexpr TileCfg kOrTiles[] = {{32, 8}, {64, 4}, {32, 16}, {64, 8}, {64, 16}};
+// tiles of the z-marching predictor-corrector stage kernel (LBC_PC_TILE)
+constexpr TileCfg kPcTiles[] = {{32, 8}, {32, 16}, {16, 16}, {64, 8}};
 
 // Deepest z-slab of at most tz_max planes (halved down to tz_min) that still
 // gives per_cu workgroups per CU for a grid of ntx x nty tiles.  Small boxes
@@ -122,6 +125,7 @@ void validate(const lb_params& p) {
   if (p.lattice != LB_D3Q19 && p.lattice != LB_D3Q15) fail(LB_EINVAL, "unknown lattice");
   if (p.lattice == LB_D3Q15 && p.prec == LB_FP16S)
     fail(LB_EINVAL, "float16 population storage is scaled for the D3Q19 weights");
+  if (p.fd_scheme != LB_FD_EULER2 && p.fd_scheme != LB_FD_PC4) fail(LB_EINVAL, "unknown fd_scheme");
   if (!finite_params(p)) fail(LB_EINVAL, "non-finite parameter");
   if (!(p.tau > 0.5)) fail(LB_EINVAL, "tau must be > 0.5");
   if (!(p.rho0 > 0.0)) fail(LB_EINVAL, "rho0 must be > 0");
@@ -208,6 +212,13 @@ struct BackendT final : Backend {
   double* apart = nullptr;   // per-block (zeta, q0) adjoint partials, kept across reverse steps
   bool apart_live = false;   // apart holds sums not yet fetched by the caller
   bool site_path = false;  // three site-parallel kernels instead of the fused pair
+  // predictor-corrector integrator of the order parameters: X* (Q then phi, in
+  // FS) and the anchoring vector v [3][N]
+  bool pc4 = false;
+  FS* pcs = nullptr;
+  R* pcv = nullptr;
+  int pc_tile = 0, tz_pc = 0, pc_ntx = 1, pc_nty = 1, pc_blocks = 1;          // stage kernel
+  int pm_tile = 0, tz_pm = 0, pm_ntx = 1, pm_nty = 1, pm_blocks = 1;          // mu kernel
   int tz_lb = 8, tz_or = 8;
   int lb_tile = 0, or_tile = 0;
   int lb_ntx, lb_nty, lb_blocks, or_ntx, or_nty, or_blocks;
@@ -223,6 +234,15 @@ struct BackendT final : Backend {
     nblk = unsigned((N + TPB - 1) / TPB);
     set_params(p);
     site_path = env_int("LBC_SITE_KERNELS", 0) != 0;
+    pc4 = p.fd_scheme == LB_FD_PC4;
+    pc_tile = env_int("LBC_PC_TILE", 0);
+    if (pc_tile < 0 || pc_tile >= int(sizeof(kPcTiles) / sizeof(kPcTiles[0]))) pc_tile = 0;
+    tz_pc = std::max(0, env_int("LBC_TZ_PC", 0));
+    // mu kernel: 64 x 8 in float; in double that frame needs 150 KB of LDS, so 32 x 8
+    const int pm_default = sizeof(R) == 4 ? 3 : 0;
+    pm_tile = env_int("LBC_PCMU_TILE", pm_default);
+    if (pm_tile < 0 || pm_tile >= int(sizeof(kPcTiles) / sizeof(kPcTiles[0]))) pm_tile = pm_default;
+    tz_pm = std::max(0, env_int("LBC_TZ_PCMU", 0));
     using D = DefaultTile<R, GS>;
     tz_lb = std::max(0, env_int("LBC_TZ_LB", 0));
     tz_or = std::max(0, env_int("LBC_TZ_ORDER", 0));
@@ -241,11 +261,20 @@ struct BackendT final : Backend {
     or_nty = (p.ny + ot.ty - 1) / ot.ty;
     if (tz_or == 0) tz_or = auto_slab(or_ntx, or_nty, p.nz, 16, 1, 2);
     or_blocks = or_ntx * or_nty * ((p.nz + tz_or - 1) / tz_or);
+    pc_ntx = (p.nx + kPcTiles[pc_tile].tx - 1) / kPcTiles[pc_tile].tx;
+    pc_nty = (p.ny + kPcTiles[pc_tile].ty - 1) / kPcTiles[pc_tile].ty;
+    if (tz_pc == 0) tz_pc = auto_slab(pc_ntx, pc_nty, p.nz, 16, 1, 2);
+    pc_blocks = pc_ntx * pc_nty * ((p.nz + tz_pc - 1) / tz_pc);
+    pm_ntx = (p.nx + kPcTiles[pm_tile].tx - 1) / kPcTiles[pm_tile].tx;
+    pm_nty = (p.ny + kPcTiles[pm_tile].ty - 1) / kPcTiles[pm_tile].ty;
+    if (tz_pm == 0) tz_pm = auto_slab(pm_ntx, pm_nty, p.nz, 16, 1, 2);
+    pm_blocks = pm_ntx * pm_nty * ((p.nz + tz_pm - 1) / tz_pm);
     ao_ntx = (p.nx + kAoTX - 1) / kAoTX;
     ao_nty = (p.ny + kAoTY - 1) / kAoTY;
     ao_tz = auto_slab(ao_ntx, ao_nty, p.nz, 16, 1, 2);
     ao_blocks = ao_ntx * ao_nty * ((p.nz + ao_tz - 1) / ao_tz);
     size_t need = 2 * (NQ * N * sizeof(GS) + 6 * N * sizeof(FS)) + 4 * N * sizeof(R);
+    if (pc4) need += 6 * N * sizeof(FS) + (site_path ? 3 * N * sizeof(R) : 0);
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need > free_b)
       fail(LB_ENOMEM, "state needs " + std::to_string(need) + " bytes, " + std::to_string(free_b) + " free");
@@ -260,6 +289,10 @@ struct BackendT final : Backend {
       partial = dalloc<double>(size_t(nblk) * 16);
       sums = dalloc<double>(16);
       if (site_path) ensure_thermo();
+      if (pc4) {
+        pcs = dalloc<FS>(6 * N);
+        if (site_path) pcv = dalloc<R>(3 * N);
+      }
     } catch (...) {
       release();
       throw;
@@ -295,6 +328,10 @@ struct BackendT final : Backend {
     dfree(u);
     dfree(partial);
     dfree(sums);
+    dfree(pcs);
+    dfree(pcv);
+    pcs = nullptr;
+    pcv = nullptr;
     mu = H = sig = u = nullptr;
     partial = sums = nullptr;
     R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar};
@@ -388,15 +425,84 @@ struct BackendT final : Backend {
   }
 
   // --- the step -----------------------------------------------------------
-  int nkernels() const { return site_path ? 3 : 2; }
+  // launches of one step: the LB part (two site kernels or the fused stress /
+  // collide kernel), then the order-parameter update (one kernel, or the six
+  // launches of the predictor-corrector)
+  int n_lb() const { return site_path ? 2 : 1; }
+  int n_pc() const { return site_path ? 6 : 4; }
+  int nkernels() const { return n_lb() + (pc4 ? n_pc() : 1); }
   const char* kernel_name(int i) const override {
     static const char* site_names[3] = {"k_thermo", "k_collide", "k_order"};
     static const char* fused_names[2] = {"k_lb_fused", "k_order_fused"};
+    static const char* pc_names[6] = {"k_pc_v", "k_pc_mu", "k_pc_predict", "k_pc_v (X*)", "k_pc_mu (X*)",
+                                      "k_pc_correct"};
+    static const char* pcz_names[4] = {"k_pc_mu_z", "k_pc_stage_z (predict)", "k_pc_mu_z (X*)",
+                                       "k_pc_stage_z (correct)"};
     if (i < 0 || i >= nkernels()) return nullptr;
+    if (i >= n_lb() && pc4) return (site_path ? pc_names : pcz_names)[i - n_lb()];
     return site_path ? site_names[i] : fused_names[i];
+  }
+  void launch_pc(int k) {
+    const int nx = cur ^ 1;
+    FS* qs = pcs;
+    FS* phs = pcs + 5 * N;
+    if (!site_path) {
+      switch (k) {
+        case 0: launch_pc_mu(Ph[cur], Q[cur]); break;
+        case 1: launch_pc_stage<true>(Ph[cur], Q[cur], nullptr, nullptr, phs, qs); break;
+        case 2: launch_pc_mu(phs, qs); break;
+        default:
+          launch_pc_stage<false>(phs, qs, Ph[cur], Q[cur], Ph[nx], Q[nx]);
+          cur = nx;
+          break;
+      }
+      return;
+    }
+    switch (k) {
+      case 0: lbc::k_pc_v<R, FS><<<nblk, TPB, 0, stream>>>(box, Ph[cur], Q[cur], pcv); break;
+      case 1: lbc::k_pc_mu<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], pcv, mu); break;
+      case 2: lbc::k_pc_predict<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], u, mu, phs, qs); break;
+      case 3: lbc::k_pc_v<R, FS><<<nblk, TPB, 0, stream>>>(box, phs, qs, pcv); break;
+      case 4: lbc::k_pc_mu<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phs, qs, pcv, mu); break;
+      default:
+        lbc::k_pc_correct<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phs, qs, u, mu, Ph[cur], Q[cur], Ph[nx], Q[nx]);
+        cur = nx;
+        break;
+    }
+  }
+  void launch_pc_mu(const FS* phi_i, const FS* q_i) {
+    switch (pm_tile) {
+      case 0: launch_pc_mu_tile<32, 8, 2>(phi_i, q_i); break;
+      case 1: launch_pc_mu_tile<32, 16, 2>(phi_i, q_i); break;
+      case 2: launch_pc_mu_tile<16, 16, 2>(phi_i, q_i); break;
+      default: launch_pc_mu_tile<64, 8, 2>(phi_i, q_i); break;
+    }
+  }
+  template <int TX, int TY, int MINW>
+  void launch_pc_mu_tile(const FS* phi_i, const FS* q_i) {
+    lbc::k_pc_mu_z<R, FS, TX, TY, MINW><<<pm_blocks, TX * TY, 0, stream>>>(box, P, tz_pm, pm_ntx, pm_nty, phi_i,
+                                                                           q_i, mu);
+  }
+  template <bool PRED>
+  void launch_pc_stage(const FS* phi_i, const FS* q_i, const FS* phi_x, const FS* q_x, FS* phi_o, FS* q_o) {
+    switch (pc_tile) {
+      case 0: launch_pc_tile<32, 8, 2, PRED>(phi_i, q_i, phi_x, q_x, phi_o, q_o); break;
+      case 1: launch_pc_tile<32, 16, 2, PRED>(phi_i, q_i, phi_x, q_x, phi_o, q_o); break;
+      case 2: launch_pc_tile<16, 16, 2, PRED>(phi_i, q_i, phi_x, q_x, phi_o, q_o); break;
+      default: launch_pc_tile<64, 8, 2, PRED>(phi_i, q_i, phi_x, q_x, phi_o, q_o); break;
+    }
+  }
+  template <int TX, int TY, int MINW, bool PRED>
+  void launch_pc_tile(const FS* phi_i, const FS* q_i, const FS* phi_x, const FS* q_x, FS* phi_o, FS* q_o) {
+    lbc::k_pc_stage_z<R, FS, TX, TY, MINW, PRED><<<pc_blocks, TX * TY, 0, stream>>>(
+        box, P, tz_pc, pc_ntx, pc_nty, phi_i, q_i, u, mu, phi_x, q_x, phi_o, q_o);
   }
   void launch(int k) {
     const int nx = cur ^ 1;
+    if (pc4 && k >= n_lb()) {
+      launch_pc(k - n_lb());
+      return;
+    }
     if (site_path) {
       switch (k) {
         case 0:
@@ -594,10 +700,12 @@ struct BackendT final : Backend {
   // --- adjoint ---------------------------------------------------------------
   // adjoint buffer: g_bar [19][N], q_bar [5][N], phi_bar [N] in R (D3Q19 only)
   static constexpr bool kAdjoint = !L::kStressInEq;
+  bool has_adjoint() const { return kAdjoint && !pc4; }
   void need_adjoint() const {
-    if (!kAdjoint) fail(LB_EINVAL, "the adjoint is implemented for the D3Q19 scheme");
+    if (!has_adjoint())
+      fail(LB_EINVAL, "the adjoint is implemented for the D3Q19 lattice with the Euler integrator");
   }
-  size_t adjoint_bytes() const override { return kAdjoint ? 25 * N * sizeof(R) : 0; }
+  size_t adjoint_bytes() const override { return has_adjoint() ? 25 * N * sizeof(R) : 0; }
   void ensure_adjoint() {
     if (aF) return;
     try {
@@ -623,7 +731,7 @@ struct BackendT final : Backend {
     }
   }
   // record buffer: u [3][N] and F [3][N] of the step that leaves the state
-  size_t record_bytes() const override { return kAdjoint ? 6 * N * sizeof(R) : 0; }
+  size_t record_bytes() const override { return has_adjoint() ? 6 * N * sizeof(R) : 0; }
   struct StateView {
     const GS* B;
     const FS* q;
@@ -749,7 +857,8 @@ void need_ctx(const lb_ctx* c) {
 
 void need_adjoint_ctx(const lb_ctx* c) {
   need_ctx(c);
-  if (c->p.lattice != LB_D3Q19) fail(LB_EINVAL, "the adjoint is implemented for the D3Q19 scheme");
+  if (c->p.lattice != LB_D3Q19 || c->p.fd_scheme != LB_FD_EULER2)
+    fail(LB_EINVAL, "the adjoint is implemented for the D3Q19 lattice with the Euler integrator");
 }
 
 std::unique_ptr<Backend> make_backend(const lb_params& p, hipStream_t s) {
@@ -799,8 +908,8 @@ lb_status lb_set_params(lb_ctx* c, const lb_params* p) {
     if (!p) fail(LB_EINVAL, "null params");
     validate(*p);
     if (p->nx != c->p.nx || p->ny != c->p.ny || p->nz != c->p.nz || p->prec != c->p.prec ||
-        p->lattice != c->p.lattice)
-      fail(LB_EINVAL, "box size, precision and lattice cannot change");
+        p->lattice != c->p.lattice || p->fd_scheme != c->p.fd_scheme)
+      fail(LB_EINVAL, "box size, precision, lattice and integrator cannot change");
     c->p = *p;
     c->be->set_params(*p);
   });

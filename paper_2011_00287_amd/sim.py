@@ -18,13 +18,15 @@ _PARAM_KEYS = ("tau", "rho0", "a", "phi0", "phi_cr", "k_phi", "M", "A0", "chi0",
                "Gamma", "xi", "zeta")
 
 
-def make_params(p: dict, shape, precision: str = "fp64", lattice: str = "d3q19") -> LbParams:
+def make_params(p: dict, shape, precision: str = "fp64", lattice: str = "d3q19",
+                fd_scheme: str = "euler2") -> LbParams:
     """LbParams from a parameter dict and a field shape (nz, ny, nx)."""
     nz, ny, nx = shape
     lp = LbParams()
     lp.nx, lp.ny, lp.nz = int(nx), int(ny), int(nz)
     lp.prec = _lib.PRECISIONS[precision]
     lp.lattice = _lib.LATTICES[lattice]
+    lp.fd_scheme = _lib.FD_SCHEMES[fd_scheme]
     for k in _PARAM_KEYS:
         setattr(lp, k, float(p[k]))
     bf = p.get("body_force", (0.0, 0.0, 0.0))
@@ -57,7 +59,9 @@ class Sim:
     phi: [nz, ny, nx]; q5: [5, nz, ny, nx] (xx, xy, xz, yy, yz); u0: [3, nz, ny, nx]
     or None.  precision: 'fp64', 'fp32' or 'fp16s'.  lattice: 'd3q19' (stress as a
     forcing term) or 'd3q15' (symmetric stress in the equilibrium, antisymmetric
-    stress as a forcing term; fp64 and fp32, forward only).  stream: a torch.cuda.Stream,
+    stress as a forcing term; fp64 and fp32, forward only).  fd_scheme: 'euler2'
+    (explicit Euler, second-order stencils) or 'pc4' (the paper's predictor-corrector
+    with upwind advection and fourth-order stencils; forward only).  stream: a torch.cuda.Stream,
     a raw hipStream_t as int, or None for the default stream.  The device tensors
     this class allocates (state, adjoint and record buffers) are created and
     zero-filled on torch's current stream, so pass that stream (or None while
@@ -65,7 +69,7 @@ class Sim:
     """
 
     def __init__(self, params: dict, phi, q5, u0=None, precision: str = "fp64", stream=None,
-                 lattice: str = "d3q19"):
+                 lattice: str = "d3q19", fd_scheme: str = "euler2"):
         phi = _c64(phi)
         q5 = _c64(q5)
         if q5.shape != (5,) + phi.shape:
@@ -76,9 +80,10 @@ class Sim:
         self.shape = phi.shape
         self.precision = precision
         self.lattice = lattice
+        self.fd_scheme = fd_scheme
         self.n_populations = _lib.N_POPULATIONS[lattice]
         self.params = dict(params)
-        self._lp = make_params(params, phi.shape, precision, lattice)
+        self._lp = make_params(params, phi.shape, precision, lattice, fd_scheme)
         self._stream = stream
         h = ctypes.c_void_p()
         check(lib().lb_init(ctypes.byref(self._lp), _dptr(phi), _dptr(q5), _dptr(u0),
@@ -115,9 +120,10 @@ class Sim:
         check(lib().lb_sync(self._h))
 
     def set_params(self, **changes):
-        """Change model parameters (not the box, precision or lattice); kept only if the library accepts them."""
+        """Change model parameters (not the box, precision, lattice or integrator); kept only if
+        the library accepts them."""
         new = dict(self.params, **changes)
-        lp = make_params(new, self.shape, self.precision, self.lattice)
+        lp = make_params(new, self.shape, self.precision, self.lattice, self.fd_scheme)
         check(lib().lb_set_params(self._h, ctypes.byref(lp)))
         self.params, self._lp = new, lp
 

@@ -5,8 +5,9 @@
  *      is N f (t + 1/2) exactly after t steps;
  *   2. a small chiral droplet in float64 and float32: mass and sum(phi) are
  *      conserved over 50 steps, the step counter advances;
- *   3. error paths: invalid parameters, unknown or unsupported lattices,
- *      negative step counts, NULL contexts, shape or lattice changes.
+ *   3. error paths: invalid parameters, unknown or unsupported lattices and
+ *      integrators, negative step counts, NULL contexts, shape, lattice or
+ *      integrator changes.
  * Prints "C ABI OK" and exits 0 when every check holds. */
 #include <math.h>
 #include <stdio.h>
@@ -149,6 +150,9 @@ static void error_paths(void) {
   p.lattice = LB_D3Q15;
   CHECK(lb_init(&p, phi, q5, NULL, NULL, &c) == LB_EINVAL, "float16 storage on D3Q15 accepted");
   p = base_params(4, 4, 4, LB_FP32);
+  p.fd_scheme = 2;
+  CHECK(lb_init(&p, phi, q5, NULL, NULL, &c) == LB_EINVAL, "unknown integrator accepted");
+  p = base_params(4, 4, 4, LB_FP32);
   CHECK(lb_init(&p, phi, q5, NULL, NULL, &c) == LB_OK && c, "lb_init: %s", lb_last_error());
   CHECK(lb_step(c, -1) == LB_EINVAL, "negative step count accepted");
   CHECK(lb_step(NULL, 1) == LB_EINVAL, "NULL context accepted");
@@ -158,6 +162,9 @@ static void error_paths(void) {
   q = p;
   q.lattice = LB_D3Q15;
   CHECK(lb_set_params(c, &q) == LB_EINVAL, "lattice change accepted");
+  q = p;
+  q.fd_scheme = LB_FD_PC4;
+  CHECK(lb_set_params(c, &q) == LB_EINVAL, "integrator change accepted");
   lb_destroy(c);
   lb_destroy(NULL);
 }

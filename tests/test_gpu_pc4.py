@@ -1,0 +1,169 @@
+"""GPU parity of the paper's integrator of the order parameters (Sec. 3: Heun
+predictor-corrector, first-order upwind advection, fourth-order stencils)
+against the FP64 oracle, through the C ABI.
+
+Tolerances are those of the Euler-path parity tests: 1e-12 relative per field
+for FP64; FP32 is an accuracy statement against FP64.  The droplet runs use
+M = 0.05, inside the explicit fourth-order Cahn-Hilliard stability bound.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import core, d3q15, pc4
+from paper_2011_00287_amd import inputs
+from paper_2011_00287_amd._lib import LB_EINVAL, LbError
+from paper_2011_00287_amd.sim import Sim
+
+from helpers import field_errors, oracle_observe, rel_err, t64
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _p(**kw):
+    return dict(inputs.BASE_PARAMS, **dict(dict(M=0.05), **kw))
+
+
+def _run(p, g, q5, phi, n):
+    g, q5, phi = pc4.run(t64(g), t64(q5), t64(phi), p, n)
+    return g.numpy(), q5.numpy(), phi.numpy()
+
+
+def _compare(sim, p, g, q5, phi, tol=TOL64):
+    rho_o, u_o = oracle_observe(p, g, q5, phi)
+    errs = field_errors(sim.moments(), (rho_o, u_o, phi, q5), p["rho0"])
+    errs["g"] = rel_err(sim.populations(), g)
+    for name, (l2, mx) in errs.items():
+        assert l2 <= tol and mx <= tol, (name, l2, mx)
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4), (5, 3, 4), (7, 6, 5), (17, 9, 3), (33, 17, 9), (40, 20, 19)])
+def test_fp64_random_state_parity(shape):
+    nx, ny, nz = shape
+    p = _p(q0=2 * math.pi / 7, zeta=0.01, body_force=(1e-5, -2e-5, 3e-5))
+    g, phi, q5 = inputs.random_fields(nx, ny, nz, seed=nx * 100 + ny * 10 + nz, g_amp=2e-3, q_amp=0.2)
+    with Sim(p, phi, q5, precision="fp64", fd_scheme="pc4") as s:
+        s.set_fields(g=g)
+        s.step(3)
+        _compare(s, p, *_run(p, g, q5, phi, 3))
+
+
+def test_fp64_droplet16_100_steps():
+    p = inputs.params_for("droplet16", M=0.05)
+    phi, q5 = inputs.workload_fields("droplet16")
+    g = np.zeros((19,) + phi.shape)
+    with Sim(p, phi, q5, precision="fp64", fd_scheme="pc4") as s:
+        s.step(100)
+        _compare(s, p, *_run(p, g, q5, phi, 100))
+
+
+def _step15_pc4(g, q5, phi, p):
+    """The paper's LB scheme (D3Q15) followed by the paper's order-parameter integrator."""
+    Q = core.q_full(q5)
+    _, _, S, F = d3q15.thermo(phi, Q, p)
+    rho, u = d3q15.moments(g, F, p)
+    g1 = d3q15.stream(d3q15.collide(g, u, rho, S, F, p))
+    Q1, phi1 = pc4.update_pc(Q, phi, u, p)
+    return g1, core.q5_of(Q1), phi1
+
+
+def test_fp64_d3q15_with_pc4():
+    p = _p(q0=2 * math.pi / 7, zeta=0.01)
+    g, phi, q5 = inputs.random_fields(9, 7, 6, seed=15, g_amp=2e-3, q_amp=0.2)
+    g = np.ascontiguousarray(g[:15])
+    with Sim(p, phi, q5, precision="fp64", lattice="d3q15", fd_scheme="pc4") as s:
+        s.set_fields(g=g)
+        s.step(3)
+        go, qo, po = t64(g), t64(q5), t64(phi)
+        for _ in range(3):
+            go, qo, po = _step15_pc4(go, qo, po, p)
+        rho, u = d3q15.observe(go, qo, po, p)
+        errs = field_errors(s.moments(), (rho.numpy(), u.numpy(), po.numpy(), qo.numpy()), p["rho0"])
+        errs["g"] = rel_err(s.populations(), go.numpy())
+    for name, (l2, mx) in errs.items():
+        assert l2 <= TOL64 and mx <= TOL64, (name, l2, mx)
+
+
+@pytest.mark.parametrize("pc_tile,tz", [(0, "1"), (1, "3"), (2, "5"), (3, "16"), (0, "default")])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_site_kernels_match_z_marching(monkeypatch, pc_tile, tz, prec):
+    """Site-parallel and z-marching (LDS-tiled) stage kernels compute the same step for
+    every tile and slab depth (ragged tiles and slabs included)."""
+    p = _p(q0=2 * math.pi / 9, zeta=0.01)
+    g, phi, q5 = inputs.random_fields(34, 18, 11, seed=77, g_amp=2e-3, q_amp=0.2)
+    tol = 1e-13 if prec == "fp64" else 2e-5
+    monkeypatch.setenv("LBC_PC_TILE", str(pc_tile))
+    if tz == "default":
+        monkeypatch.delenv("LBC_TZ_PC", raising=False)
+    else:
+        monkeypatch.setenv("LBC_TZ_PC", tz)
+    with Sim(p, phi, q5, precision=prec, fd_scheme="pc4") as fused:
+        monkeypatch.setenv("LBC_SITE_KERNELS", "1")
+        with Sim(p, phi, q5, precision=prec, fd_scheme="pc4") as site:
+            for s in (fused, site):
+                s.set_fields(g=g)
+                s.step(4)
+            for a, b in zip(fused.moments(), site.moments()):
+                l2, mx = rel_err(a, b)
+                assert l2 < tol and mx < tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+def test_conservation(prec):
+    p = inputs.params_for("droplet16", M=0.05)
+    phi, q5 = inputs.workload_fields("droplet16")
+    with Sim(p, phi, q5, precision=prec, fd_scheme="pc4") as s:
+        t0 = s.totals()
+        s.step(200)
+        t1 = s.totals()
+    tol = {"fp64": 1e-13, "fp32": 1e-6, "fp16s": 1e-3}[prec]
+    assert abs(t1["mass"] - t0["mass"]) <= tol * t0["mass"]
+    assert abs(t1["phi_total"] - t0["phi_total"]) <= tol * t0["phi_total"]
+    for a in range(3):
+        assert abs(t1["momentum"][a] - t0["momentum"][a]) <= tol * t0["mass"]
+
+
+def test_fp32_accuracy_droplet16():
+    p = inputs.params_for("droplet16", M=0.05)
+    phi, q5 = inputs.workload_fields("droplet16")
+    with Sim(p, phi, q5, precision="fp64", fd_scheme="pc4") as a, \
+            Sim(p, phi, q5, precision="fp32", fd_scheme="pc4") as b:
+        a.step(100)
+        b.step(100)
+        ea = field_errors(b.moments(), a.moments(), p["rho0"])
+    for name, (l2, mx) in ea.items():
+        assert l2 <= 2e-4, (name, l2, mx)
+
+
+def test_bitwise_determinism_and_resume():
+    p = inputs.params_for("droplet16", M=0.05)
+    phi, q5 = inputs.workload_fields("droplet16")
+    with Sim(p, phi, q5, precision="fp32", fd_scheme="pc4") as a, \
+            Sim(p, phi, q5, precision="fp32", fd_scheme="pc4") as b:
+        a.step(20)
+        ck = a.get_state()
+        a.step(15)
+        b.step(35)
+        ra = a.moments()
+        for x, y in zip(ra, b.moments()):
+            assert np.array_equal(x, y)
+        b.set_state(ck)
+        b.step(15)
+        for x, y in zip(ra, b.moments()):
+            assert np.array_equal(x, y)
+
+
+def test_adjoint_is_refused():
+    p = _p()
+    phi, q5 = inputs.droplet_fields(6, 6, 6, 2.0, 0.5)
+    with Sim(p, phi, q5, fd_scheme="pc4") as s:
+        assert s.adjoint_buffer().numel() == 0 and s.record_buffer().numel() == 0
+        with pytest.raises(LbError) as e:
+            s.step_record(s.get_state(), s.get_state(), torch.empty(8, dtype=torch.uint8, device="cuda"))
+        assert e.value.status == LB_EINVAL
+        names = [k for k in s.profile(2)]
+        assert names[-1] == "k_pc_stage_z (correct)" and "k_pc_stage_z (predict)" in names
