@@ -50,13 +50,17 @@ GS_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 2}
 FS_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 4}
 
 
+# sources the 3D step kernels (and their launch configuration) are built from
+STEP_SOURCES = ("physics.hpp", "storage.hpp", "kernels_fused.hpp", "kernels_pc.hpp", "kernels_site.hpp",
+                "kernels_reduce.hpp", "kernels_adjoint.hpp", "adjoint.hpp", "lb_api.hip")
+
+
 def kernel_source_hash() -> str:
-    """Hash of the HIP sources; traffic counters are valid only for the source they were taken on."""
-    import glob
+    """Hash of the step's HIP sources; traffic counters are valid only for the source they were taken on."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2011_00287_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
+    for f in STEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2011_00287_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
