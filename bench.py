@@ -194,6 +194,82 @@ def copy_calibration(nbytes: int, reps: int):
         print(json.dumps(line), flush=True)
 
 
+# 2D active nematic (D2Q9): per-site compulsory values of each kernel
+ALGO_VALUES_2D = {"k2_lb": 20,     # 9 populations read + 9 written, Q read
+                  "k2_order": 4}   # Q read + written (its read of u is traffic the split adds)
+STEP_VALUES_2D = 22                # populations 9 + 9, Q 2 + 2
+
+
+def time_2d(workload, prec, steps, warmup):
+    """(Nematic2D, seconds for `steps` steps) on the 2D workload."""
+    import torch
+    from paper_2011_00287_amd import inputs
+    from paper_2011_00287_amd.sim2d import Nematic2D
+    p = inputs.nematic2d_params(workload)
+    q2 = inputs.nematic2d_workload_fields(workload)
+    sim = Nematic2D(p, q2, precision=prec)
+    sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    return sim, time.perf_counter() - t0
+
+
+def cpu_baseline_2d(workload: str, nsteps: int = 3):
+    import torch
+    from oracle import nematic2d
+    from paper_2011_00287_amd import inputs
+    p = inputs.nematic2d_params(workload)
+    q2 = torch.tensor(inputs.nematic2d_workload_fields(workload))
+    g = torch.zeros((9,) + tuple(q2.shape[1:]), dtype=torch.float64)
+    g, q2 = nematic2d.step(g, q2, p)
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        g, q2 = nematic2d.step(g, q2, p)
+    dt = time.perf_counter() - t0
+    n = q2[0].numel()
+    return {"value": n * nsteps / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"{workload} ({n} sites) FP64 oracle, {nsteps} timed steps after 1 warm-up"}
+
+
+def bench_2d(args):
+    """The 2D bulk active nematic as the timed line."""
+    from paper_2011_00287_amd import inputs
+    w = inputs.NEMATIC2D_WORKLOADS[args.workload]
+    prec = args.precision
+    if prec == "fp16s":
+        raise SystemExit("the 2D model runs in fp64 or fp32")
+    sim, dt = time_2d(args.workload, prec, args.steps, args.warmup)
+    n = sim.n_sites
+    mlups = n * args.steps / dt / 1e6
+    prof = sim.profile(args.profile_steps)
+    sim.close()
+    dom = max(prof, key=prof.get)
+    vb = GS_BYTES[prec]
+    algo = ALGO_VALUES_2D[dom] * vb * n
+    achieved = algo / (prof[dom] * 1e-3) / 1e9
+    print(f"# {args.workload} {prec}: {mlups:.1f} MLUPS, kernels {prof}", file=sys.stderr, flush=True)
+    line = {
+        "metric": "2D active-nematic step MLUPS (D2Q9 + Q tensor)", "value": mlups, "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32"}[prec], "data": "synthetic",
+        "config": {"workload": args.workload, "box": [w["n"], w["n"]], "zeta": w["zeta"], "precision": prec,
+                   "lattice": "D2Q9"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom, "kernel_ms": prof[dom],
+                     "algorithmic_bytes_per_launch": algo},
+        "step_roofline": {"bytes_per_site": STEP_VALUES_2D * vb,
+                          "frac": mlups * 1e6 * STEP_VALUES_2D * vb / (HBM_PEAK_GBS * 1e9)},
+        "kernel_ms": prof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_2d(args.workload)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +303,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration << 20, max(1, args.steps))
+        return
+    if args.workload in inputs.NEMATIC2D_WORKLOADS:
+        bench_2d(args)
         return
     stream = torch.cuda.current_stream()
     w = inputs.WORKLOADS[args.workload]
@@ -268,6 +347,12 @@ def main():
             side[key] = {"mlups": n * ns / dt2 / 1e6, "ms_per_step": dt2 / ns * 1e3,
                          "step_hbm_frac": n * ns / dt2 * step_bytes(prec, lat) / (HBM_PEAK_GBS * 1e9)}
             print(f"# {key}: {side[key]['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
+        s2, dt2 = time_2d("nematic512", "fp32", 2000, 50)  # the 2D workload of Fig. 3 (512^2)
+        n2d = s2.n_sites
+        s2.close()
+        side["nematic512_fp32"] = {"mlups": n2d * 2000 / dt2 / 1e6, "ms_per_step": dt2 / 2000 * 1e3,
+                                   "step_hbm_frac": n2d * 2000 / dt2 * STEP_VALUES_2D * 4 / (HBM_PEAK_GBS * 1e9)}
+        print(f"# nematic512_fp32: {side['nematic512_fp32']['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
 
     adjoint = None
     if args.adjoint_steps > 0 and args.lattice == "d3q19" and args.fd_scheme == "euler2":

@@ -1,4 +1,5 @@
-"""ctypes declarations of the C ABI in include/lb_chiral.h (marshalling only)."""
+"""ctypes declarations of the C ABI in include/lb_chiral.h and include/lb_nematic2d.h
+(marshalling only)."""
 from __future__ import annotations
 
 import ctypes
@@ -73,6 +74,38 @@ SIGNATURES = {
     "lb_last_error": (ctypes.c_char_p, []),
 }
 
+
+class Lb2dParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("prec", ctypes.c_int32),
+        ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
+        ("A0", ctypes.c_double), ("chi", ctypes.c_double), ("K", ctypes.c_double),
+        ("Gamma", ctypes.c_double), ("xi", ctypes.c_double), ("zeta", ctypes.c_double),
+        ("body_force", ctypes.c_double * 2),
+    ]
+
+
+class Lb2dTotals(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_double), ("momentum", ctypes.c_double * 2), ("free_energy", ctypes.c_double),
+        ("kinetic_energy", ctypes.c_double), ("step", ctypes.c_int64),
+    ]
+
+
+SIGNATURES_2D = {
+    "lb2d_init": (ctypes.c_int, [ctypes.POINTER(Lb2dParams), _D, _D, _P, ctypes.POINTER(_P)]),
+    "lb2d_step": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "lb2d_sync": (ctypes.c_int, [_P]),
+    "lb2d_moments": (ctypes.c_int, [_P, _D, _D, _D]),
+    "lb2d_populations": (ctypes.c_int, [_P, _D]),
+    "lb2d_set_fields": (ctypes.c_int, [_P, _D, _D]),
+    "lb2d_free_energy": (ctypes.c_int, [_P, ctypes.POINTER(Lb2dTotals)]),
+    "lb2d_profile_step": (ctypes.c_int, [_P, ctypes.c_int32, _D, ctypes.POINTER(ctypes.c_int32)]),
+    "lb2d_kernel_name": (ctypes.c_char_p, [_P, ctypes.c_int32]),
+    "lb2d_destroy": (None, [_P]),
+    "lb2d_last_error": (ctypes.c_char_p, []),
+}
+
 _lib = None
 
 
@@ -84,7 +117,7 @@ def lib() -> ctypes.CDLL:
             raise RuntimeError(f"HIP library not built: {LIB_PATH} missing "
                                "(run python -m paper_2011_00287_amd.build)")
         L = ctypes.CDLL(LIB_PATH)
-        for name, (res, args) in SIGNATURES.items():
+        for name, (res, args) in list(SIGNATURES.items()) + list(SIGNATURES_2D.items()):
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
@@ -95,4 +128,10 @@ def lib() -> ctypes.CDLL:
 def check(status: int) -> None:
     if status != LB_OK:
         msg = lib().lb_last_error()
+        raise LbError(status, msg.decode() if msg else "")
+
+
+def check2(status: int) -> None:
+    if status != LB_OK:
+        msg = lib().lb2d_last_error()
         raise LbError(status, msg.decode() if msg else "")

@@ -1,7 +1,8 @@
 """Build the HIP library for gfx950: ``python -m paper_2011_00287_amd.build``.
 
-Compiles csrc/lb_api.hip (which includes every kernel header) into
-lib/liblbchiral.so with hipcc.  Packed FP32 instructions are disabled.
+Compiles csrc/lb_api.hip (the 3D coupled step; it includes every 3D kernel
+header) and csrc/nematic2d.hip (the 2D active nematic) into lib/liblbchiral.so
+with hipcc.  Packed FP32 instructions are disabled.
 """
 from __future__ import annotations
 
@@ -12,7 +13,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = os.path.join(PKG, "csrc", "lb_api.hip")
+SRCS = [os.path.join(PKG, "csrc", "lb_api.hip"), os.path.join(PKG, "csrc", "nematic2d.hip")]
 OUT = os.path.join(PKG, "lib", "liblbchiral.so")
 
 HIPCC_FLAGS = [
@@ -32,7 +33,7 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
     tmp = OUT + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I" + os.path.join(ROOT, "include"), "-o", tmp, SRC]
+    cmd = [hipcc(), *HIPCC_FLAGS, "-I" + os.path.join(ROOT, "include"), "-o", tmp, *SRCS]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

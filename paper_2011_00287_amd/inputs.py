@@ -135,3 +135,41 @@ def ic_shear_wave(n_z: int, U0: float, nx: int = 3, ny: int = 3):
     u = np.zeros((3, n_z, ny, nx))
     u[0] = U0 * np.sin(2 * np.pi * z / n_z)[:, None, None]
     return u
+
+
+# ----------------------------------------------------------------- 2D nematic
+# Bulk active nematic on D2Q9 (the regimes of Fig. 4; the paper gives no 2D
+# parameters, so these stand in): chi = 4 puts the bulk in the nematic phase
+# with S_eq = sqrt(2 (chi/3 - 1)/chi) = 0.408.
+NEMATIC2D_PARAMS = dict(tau=2.5, rho0=1.0, A0=0.1, chi=4.0, K=0.04, Gamma=0.3, xi=0.7, zeta=0.0)
+
+# Director along x with +-0.05 rad of seeded noise, S0 = S_eq.  The regimes of
+# Fig. 4 on these parameters: quiescent below the finite-box threshold
+# (zeta = 0.0005 on 64^2), a stationary spontaneous flow (zeta = 0.002 on
+# 128^2), active turbulence with +-1/2 defects (zeta >= 0.01).
+NEMATIC2D_WORKLOADS = {
+    "nematic64": dict(n=64, zeta=0.005, S0=0.408, noise=0.05, steps=200),      # FP64 parity
+    "quiescent64": dict(n=64, zeta=0.0005, S0=0.408, noise=0.05, steps=10000),
+    "flow128": dict(n=128, zeta=0.002, S0=0.408, noise=0.05, steps=10000),
+    "chaos128": dict(n=128, zeta=0.02, S0=0.408, noise=0.05, steps=10000),
+    "nematic512": dict(n=512, zeta=0.02, S0=0.408, noise=0.05, steps=2000),    # benchmark (Fig. 3 2D size)
+}
+
+
+def nematic2d_params(workload: str, **overrides) -> dict:
+    p = dict(NEMATIC2D_PARAMS)
+    p["zeta"] = NEMATIC2D_WORKLOADS[workload]["zeta"]
+    p.update(overrides)
+    return p
+
+
+def nematic_fields(nx: int, ny: int, S0: float, noise: float, seed: int = 0) -> np.ndarray:
+    """q2 [2, ny, nx] of a director along x with uniform angle noise in
+    [-noise, noise] radians: Q = S0 (n n - I/2)."""
+    th = np.random.default_rng(seed).uniform(-noise, noise, (ny, nx))
+    return np.stack([0.5 * S0 * np.cos(2 * th), 0.5 * S0 * np.sin(2 * th)])
+
+
+def nematic2d_workload_fields(workload: str, seed: int = 0) -> np.ndarray:
+    w = NEMATIC2D_WORKLOADS[workload]
+    return nematic_fields(w["n"], w["n"], w["S0"], w["noise"], seed)

@@ -1,6 +1,6 @@
 """CPU checks of the C ABI: the built library loads and exports every function
-declared in include/lb_chiral.h, and the Python binding declares the same set.
-No compute call is made (there may be no GPU)."""
+declared in include/lb_chiral.h and include/lb_nematic2d.h, and the Python
+binding declares the same set.  No compute call is made (there may be no GPU)."""
 import ctypes
 import os
 import re
@@ -9,12 +9,13 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "lb_chiral.h")
+HEADER_2D = os.path.join(ROOT, "include", "lb_nematic2d.h")
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(header=HEADER, prefix="lb_"):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"\b(lb_[a-z_0-9]+)\s*\(", text)
+    names = re.findall(r"\b(" + prefix + r"[a-z_0-9]+)\s*\(", text)
     return sorted(set(names))
 
 
@@ -29,13 +30,48 @@ def test_library_exports_every_declared_symbol():
     if not os.path.exists(_lib.LIB_PATH):
         pytest.fail("library not built: run python -m paper_2011_00287_amd.build")
     L = ctypes.CDLL(_lib.LIB_PATH)
-    for n in declared_functions():
+    for n in declared_functions() + declared_functions(HEADER_2D, "lb2d_"):
         assert hasattr(L, n), n
 
 
 def test_binding_matches_header():
     from paper_2011_00287_amd import _lib
     assert sorted(_lib.SIGNATURES) == declared_functions()
+    assert sorted(_lib.SIGNATURES_2D) == declared_functions(HEADER_2D, "lb2d_")
+
+
+def _struct_fields(header, name):
+    text = open(header).read()
+    body = re.search(r"typedef struct \{([^}]*)\} " + name + ";", text).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        for n in decl.split(None, 1)[1].split(","):
+            fields.append(re.sub(r"\[.*\]", "", n).strip())
+    return fields
+
+
+def test_2d_struct_layouts():
+    from paper_2011_00287_amd import _lib
+    assert _struct_fields(HEADER_2D, "lb2d_params") == [f[0] for f in _lib.Lb2dParams._fields_]
+    assert _struct_fields(HEADER_2D, "lb2d_totals") == [f[0] for f in _lib.Lb2dTotals._fields_]
+
+
+def test_2d_invalid_params_rejected_on_the_host():
+    import numpy as np
+    from paper_2011_00287_amd import _lib, sim2d
+    p = dict(tau=2.5, rho0=1.0, A0=0.1, chi=4.0, K=0.04, Gamma=0.3, xi=0.7, zeta=0.0)
+    for bad, q2 in ((dict(p, tau=0.5), np.zeros((2, 4, 4))), (p, np.zeros((2, 2, 4))),
+                    (dict(p, K=float("inf")), np.zeros((2, 4, 4)))):
+        with pytest.raises(_lib.LbError) as e:
+            sim2d.Nematic2D(bad, q2)
+        assert e.value.status == _lib.LB_EINVAL
+    with pytest.raises(_lib.LbError) as e:
+        sim2d.Nematic2D(p, np.zeros((2, 4, 4)), precision="fp16s")
+    assert e.value.status == _lib.LB_EINVAL
 
 
 def test_param_struct_layout():
