@@ -19,6 +19,7 @@
 //                   (the site-local ones already summed with the Q, phi
 //                   adjoints of k_adj_order), zeta / q0 block partials
 //   k_adj_gather  : stencil transposes of the gradient data -> Q_bar(t), phi_bar(t)
+//   (k_adj_sg_fused does k_adj_stress and k_adj_gather in one z-marching pass)
 // H_bar = Gamma Q_bar(t+1) is formed where it is used.
 #pragma once
 #include "adjoint.hpp"
@@ -358,6 +359,53 @@ __device__ __forceinline__ void store_gb(const GradBar<R>& Gb, R* __restrict__ o
   for (int k = 0; k < 5; ++k) out[(GB_LAPQ + k) * N + s] = Gb.lapq[k];
 }
 
+// Gradient-data adjoint of one site: the reverse of its stress (through H), of
+// H as used by the Q update (H_bar = Gamma Q_bar(t+1)) and of mu, including
+// the anchoring vector v = Q D0 phi whose divergence enters mu.  G: the
+// site's forward gradient data (G.divv unused); Fn[g][d][a], mbn[g][d]: F_bar
+// and mu_bar at x + e_g (d = 0) and x - e_g (d = 1); mb0, aq: mu_bar and
+// Q_bar(t+1) at the site.  Gb gets the gradient-data adjoints (without the
+// order kernel's site-local Q and phi adjoints), Pb the parameter adjoints.
+template <class R>
+__device__ __forceinline__ void adj_stress_site(const Params<R>& P, const Grad<R>& G, const R Fn[3][2][3],
+                                                const R mbn[3][2], R mb0, const R aq[5], GradBar<R>& Gb,
+                                                ParBar<R>& Pb) {
+  // sigma_bar_ab = -D0_b F_bar_a;  v_bar_a = -D0_a divv_bar with divv_bar = -2 W mu_bar
+  R sb[9], vb[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sb[3 * a + c] = -R(0.5) * (Fn[c][0][a] - Fn[c][1][a]);
+    vb[c] = P.W * (mbn[c][0] - mbn[c][1]);
+  }
+  R hbs[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) hbs[k] = P.Gamma * aq[k];
+  Gb.zero();
+  Pb = ParBar<R>{R(0), R(0), R(0)};
+  sigma_site_bwd(P, G, sb, hbs, Gb, Pb);
+  mu_site_bwd(P, G.phi, G.q, mb0, Gb.phi, Gb.lapphi, Gb.divv, Gb.q);
+  // anchoring divergence: v_a = Q_ab D0_b phi  ->  Q_bar_ab += v_bar_a D0_b phi,
+  // (D0_b phi)_bar += Q_ab v_bar_a
+  R Qb[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Qb[a][c] = vb[a] * G.dphi[c];
+  full_to_stored(Qb, Gb.q);
+  const R xx = G.q[0], xy = G.q[1], xz = G.q[2], yy = G.q[3], yz = G.q[4], zz = -xx - yy;
+  Gb.dphi[0] += xx * vb[0] + xy * vb[1] + xz * vb[2];
+  Gb.dphi[1] += xy * vb[0] + yy * vb[1] + yz * vb[2];
+  Gb.dphi[2] += xz * vb[0] + yz * vb[1] + zz * vb[2];
+}
+
+// the (zeta, q0) adjoint contributions of one site
+template <class R>
+__device__ __forceinline__ void par_adjoints(const Params<R>& P, const ParBar<R>& Pb, double v[2]) {
+  v[0] += double(Pb.zeta);
+  v[1] += 2.0 * double(P.K) * double(Pb.kq) + 8.0 * double(P.K) * double(P.q0) * double(Pb.kq2);
+}
+
 // Reverse of the stress (through H), of H as used by the Q update and of mu.
 // qbp, phibp: the site-local Q and phi adjoints from k_adj_order, added to
 // the gradient data's own.  partial: one float64 pair (zeta, q0) per block,
@@ -426,43 +474,15 @@ k_adj_stress(Box b, Params<R> P, const FS* __restrict__ phi, const FS* __restric
     G.lapphi = lap - R(6) * G.phi;
 #pragma unroll
     for (int k = 0; k < 5; ++k) G.lapq[k] -= R(6) * G.q[k];
-    G.divv = R(0);  // mu's anchoring divergence is reversed below through v_bar
-    // sigma_bar_ab = -D0_b F_bar_a;  v_bar_a = -D0_a divv_bar with divv_bar = -2 W mu_bar
-    R sb[9], vb[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) sb[3 * a + c] = -R(0.5) * (Fn[c][0][a] - Fn[c][1][a]);
-      vb[c] = P.W * (mbn[c][0] - mbn[c][1]);
-    }
-    R hbs[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) hbs[k] = P.Gamma * aq[k];
+    G.divv = R(0);  // mu's anchoring divergence is reversed through v_bar
     GradBar<R> Gb;
-    Gb.zero();
-    ParBar<R> Pb{R(0), R(0), R(0)};
-    sigma_site_bwd(P, G, sb, hbs, Gb, Pb);
-    mu_site_bwd(P, G.phi, G.q, mb0, Gb.phi, Gb.lapphi, Gb.divv, Gb.q);
-    // anchoring divergence: v_a = Q_ab D0_b phi  ->  Q_bar_ab += v_bar_a D0_b phi,
-    // (D0_b phi)_bar += Q_ab v_bar_a
-    {
-      R Qb[3][3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) Qb[a][c] = vb[a] * G.dphi[c];
-      full_to_stored(Qb, Gb.q);
-      const R xx = G.q[0], xy = G.q[1], xz = G.q[2], yy = G.q[3], yz = G.q[4], zz = -xx - yy;
-      Gb.dphi[0] += xx * vb[0] + xy * vb[1] + xz * vb[2];
-      Gb.dphi[1] += xy * vb[0] + yy * vb[1] + yz * vb[2];
-      Gb.dphi[2] += xz * vb[0] + yz * vb[1] + zz * vb[2];
-    }
+    ParBar<R> Pb;
+    adj_stress_site(P, G, Fn, mbn, mb0, aq, Gb, Pb);
     Gb.phi += pbp;
 #pragma unroll
     for (int k = 0; k < 5; ++k) Gb.q[k] += qp[k];
     store_gb(Gb, gbar, N, s);
-    v[0] = double(Pb.zeta);
-    v[1] = 2.0 * double(P.K) * double(Pb.kq) + 8.0 * double(P.K) * double(P.q0) * double(Pb.kq2);
+    par_adjoints(P, Pb, v);
   }
   block_reduce_store<2>(v, partial + size_t(blockIdx.x) * 2, accumulate != 0);
 }
@@ -524,6 +544,241 @@ k_adj_gather(Box b, const R* __restrict__ gbar, R* __restrict__ adj_phi, R* __re
   adj_phi[s] = pb;
 #pragma unroll
   for (int k = 0; k < 5; ++k) adj_q[k * N + s] = qb[k];
+}
+
+// ---------------------------------------------------------------------------
+// k_adj_sg_fused: k_adj_stress and k_adj_gather in one z-marching pass, so the
+// 30 gradient-data adjoints never leave the chip.  One workgroup marches a
+// TX x TY tile through a slab of planes; at plane p it
+//   * takes phi, Q, mu_bar, F_bar of planes p-1, p, p+1 from an LDS ring of
+//     three planes on the tile with a halo of 2;
+//   * forms the gradient-data adjoint (adj_stress_site) at the owned sites and
+//     at the cross-shaped ring of 1 around the tile, and puts the 18 values
+//     the in-plane transposes read in LDS;
+//   * applies the in-plane transposes (x, y) at the owned sites, and the z
+//     transposes from the owned column's values at p-1 and p+1 held in
+//     registers, so the adjoint of plane p-1 is complete one step later.
+// The (zeta, q0) partials count owned sites only.
+// ---------------------------------------------------------------------------
+template <class R, class FS, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(1, 2)))
+k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__ phi,
+               const FS* __restrict__ q, const R* __restrict__ Fb, const R* __restrict__ adj_q,
+               const R* __restrict__ mub, const R* __restrict__ qbp, const R* __restrict__ phibp,
+               R* __restrict__ adj_phi, R* __restrict__ adj_qo, double* __restrict__ partial, int accumulate) {
+  constexpr int NT = TX * TY;
+  constexpr int IX = TX + 4, IY = TY + 4, NI = IX * IY;  // input frame (halo 2)
+  constexpr int GX = TX + 2, GY = TY + 2, NG = GX * GY;  // gradient-adjoint frame (ring 1)
+  constexpr int NR = 2 * (TX + TY);                      // ring slots (no corners)
+  constexpr int NF = 10;                                 // phi, q[5], mu_bar, F_bar[3]
+  constexpr int KI = (NI + NT - 1) / NT;
+  constexpr int NGB = 18;  // lapphi, lapq[5], dphi_x, dphi_y, dq_x[5], dq_y[5]
+  static_assert(NR <= NT, "one ring slot per thread");
+  __shared__ R sIn[3][NF][NI];
+  __shared__ R sGB[NGB][NG];
+  __shared__ int sGX[IX], sGY[IY];
+
+  const int l = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = l % ntx, ty = (l / ntx) % nty, sl = l / (ntx * nty);
+  const int x0 = tx * TX, y0 = ty * TY, z0 = sl * TZ;
+  const int z1 = min(z0 + TZ, b.nz);
+  const int tid = threadIdx.x;
+  const int lx = tid % TX, ly = tid / TX;
+  const bool active = (x0 + lx < b.nx) && (y0 + ly < b.ny);
+  const size_t N = b.N;
+  const int plane = b.nx * b.ny;
+
+  for (int k = tid; k < IX; k += NT) sGX[k] = pmod(x0 - 2 + k, b.nx);
+  for (int k = tid; k < IY; k += NT) sGY[k] = pmod(y0 - 2 + k, b.ny);
+  __syncthreads();
+
+  // input-frame slots this thread loads (padding repeats the frame origin)
+  int icol[KI];
+#pragma unroll
+  for (int j = 0; j < KI; ++j) {
+    const int k = tid + j * NT;
+    icol[j] = k < NI ? sGY[k / IX] * b.nx + sGX[k % IX] : sGY[0] * b.nx + sGX[0];
+  }
+  // plane w of the inputs into ring slot `slot` (the loads of one frame slot are
+  // stored before the next slot's are issued, which keeps few registers live)
+  auto fill_plane = [&](int w, int slot) {
+    const size_t base = size_t(pmod(w, b.nz)) * plane;
+#pragma unroll
+    for (int j = 0; j < KI; ++j) {
+      const int k = tid + j * NT;
+      const size_t g = base + icol[j];
+      R v[NF];
+      v[0] = R(phi[g]);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) v[1 + c] = R(q[c * N + g]);
+      v[6] = mub[g];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) v[7 + a] = Fb[a * N + g];
+      if (k < NI) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) sIn[slot][f][k] = v[f];
+      }
+    }
+  };
+
+  // gradient-adjoint slots: the owned site, and (tid < NR) one ring slot
+  const int ogx = lx + 1, ogy = ly + 1;
+  int rgx = 0, rgy = 0;
+  const bool has_ring = tid < NR;
+  if (has_ring) {
+    if (tid < 2 * TX) {
+      rgx = 1 + tid % TX;
+      rgy = tid < TX ? 0 : GY - 1;
+    } else {
+      const int t = tid - 2 * TX;
+      rgy = 1 + t % TY;
+      rgx = t < TY ? 0 : GX - 1;
+    }
+  }
+  const int ocol = sGY[ogy + 1] * b.nx + sGX[ogx + 1];
+  const int rcol = sGY[rgy + 1] * b.nx + sGX[rgx + 1];
+  // the gradient-data adjoint at a slot of plane p (input slots rm, r0, rp = planes p-1, p, p+1)
+  auto slot_adjoint = [&](int gx, int gy, int rm, int r0, int rp, const R aq[5], GradBar<R>& Gb, ParBar<R>& Pb) {
+    const int f = (gy + 1) * IX + (gx + 1);
+    const int nb[3][2] = {{f + 1, f - 1}, {f + IX, f - IX}, {f, f}};
+    auto at = [&](int fld, int g, int d) {
+      return g < 2 ? sIn[r0][fld][nb[g][d]] : sIn[d == 0 ? rp : rm][fld][f];
+    };
+    Grad<R> G;
+    G.phi = sIn[r0][0][f];
+    R lap = R(0);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      G.q[k] = sIn[r0][1 + k][f];
+      G.lapq[k] = R(0);
+    }
+    R Fn[3][2][3], mbn[3][2];
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      const R pp = at(0, g, 0), pm = at(0, g, 1);
+      G.dphi[g] = R(0.5) * (pp - pm);
+      lap += pp + pm;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const R a = at(1 + k, g, 0), c = at(1 + k, g, 1);
+        G.dq[g][k] = R(0.5) * (a - c);
+        G.lapq[k] += a + c;
+      }
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        mbn[g][d] = at(6, g, d);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Fn[g][d][a] = at(7 + a, g, d);
+      }
+    }
+    G.lapphi = lap - R(6) * G.phi;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) G.lapq[k] -= R(6) * G.q[k];
+    G.divv = R(0);
+    adj_stress_site(P, G, Fn, mbn, sIn[r0][6][f], aq, Gb, Pb);
+  };
+  auto put_gb = [&](int gx, int gy, const GradBar<R>& Gb) {
+    const int s = gy * GX + gx;
+    sGB[0][s] = Gb.lapphi;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) sGB[1 + k][s] = Gb.lapq[k];
+    sGB[6][s] = Gb.dphi[0];
+    sGB[7][s] = Gb.dphi[1];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      sGB[8 + k][s] = Gb.dq[0][k];
+      sGB[13 + k][s] = Gb.dq[1][k];
+    }
+  };
+  auto load_site = [&](int w, int col, R aq[5], R qp[5], R& pp, bool own) {
+    const size_t k = size_t(pmod(w, b.nz)) * plane + col;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) aq[c] = adj_q[c * N + k];
+    if (own) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) qp[c] = qbp[c * N + k];
+      pp = phibp[k];
+    }
+  };
+
+  // planes z0-2 .. z0 into the ring, the site inputs of plane z0-1 into registers
+  int rm = 0, r0 = 1, rp = 2;  // ring slots of planes p-1, p, p+1
+  fill_plane(z0 - 2, rm);
+  fill_plane(z0 - 1, r0);
+  fill_plane(z0, rp);
+  R aq_o[5], qp_o[5], pp_o = R(0), aq_r[5] = {R(0), R(0), R(0), R(0), R(0)}, dummy5[5];
+  R dummy = R(0);
+  load_site(z0 - 1, ocol, aq_o, qp_o, pp_o, true);
+  if (has_ring) load_site(z0 - 1, rcol, aq_r, dummy5, dummy, false);
+
+  // owned column: z-transpose values of the previous plane and the running adjoint
+  R zp_lapphi = R(0), zp_dphi = R(0), zp_lapq[5], zp_dq[5];
+  R acc_p = R(0), acc_q[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) zp_lapq[k] = zp_dq[k] = acc_q[k] = R(0);
+  double v[2] = {0.0, 0.0};
+  const int ogs = ogy * GX + ogx;
+
+  for (int p = z0 - 1; p <= z1; ++p) {
+    const bool more = p < z1;
+    __syncthreads();  // plane p+1 in place; the previous plane's reads of sGB are done
+    GradBar<R> Gb;
+    ParBar<R> Pb;
+    slot_adjoint(ogx, ogy, rm, r0, rp, aq_o, Gb, Pb);
+    const bool own_plane = p >= z0 && p < z1;
+    if (own_plane && active) par_adjoints(P, Pb, v);
+    Gb.phi += pp_o;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Gb.q[k] += qp_o[k];
+    put_gb(ogx, ogy, Gb);
+    if (has_ring) {
+      GradBar<R> Gr;
+      ParBar<R> Pr;
+      slot_adjoint(rgx, rgy, rm, r0, rp, aq_r, Gr, Pr);
+      put_gb(rgx, rgy, Gr);
+    }
+    __syncthreads();  // the gradient adjoints of plane p are in place
+    const size_t site = size_t(pmod(p - 1, b.nz)) * plane + ocol;
+    // plane p-1 is complete with the z+ neighbour's terms (this plane)
+    if (p - 1 >= z0 && active) {
+      adj_phi[site] = acc_p + (Gb.lapphi - R(0.5) * Gb.dphi[2]);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) adj_qo[k * N + site] = acc_q[k] + (Gb.lapq[k] - R(0.5) * Gb.dq[2][k]);
+    }
+    if (own_plane) {
+      // own terms, in-plane transposes, and the z- neighbour's terms (previous plane)
+      const int sx[2] = {ogs + 1, ogs - 1}, sy[2] = {ogs + GX, ogs - GX};
+      acc_p = (Gb.phi - R(6) * Gb.lapphi) + (zp_lapphi + R(0.5) * zp_dphi);
+      acc_p += (sGB[0][sx[0]] + sGB[0][sx[1]]) - R(0.5) * (sGB[6][sx[0]] - sGB[6][sx[1]]);
+      acc_p += (sGB[0][sy[0]] + sGB[0][sy[1]]) - R(0.5) * (sGB[7][sy[0]] - sGB[7][sy[1]]);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        R a = (Gb.q[k] - R(6) * Gb.lapq[k]) + (zp_lapq[k] + R(0.5) * zp_dq[k]);
+        a += (sGB[1 + k][sx[0]] + sGB[1 + k][sx[1]]) - R(0.5) * (sGB[8 + k][sx[0]] - sGB[8 + k][sx[1]]);
+        a += (sGB[1 + k][sy[0]] + sGB[1 + k][sy[1]]) - R(0.5) * (sGB[13 + k][sy[0]] - sGB[13 + k][sy[1]]);
+        acc_q[k] = a;
+      }
+    }
+    zp_lapphi = Gb.lapphi;
+    zp_dphi = Gb.dphi[2];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      zp_lapq[k] = Gb.lapq[k];
+      zp_dq[k] = Gb.dq[2][k];
+    }
+    if (more) {
+      // plane p-1 is read by no one any more (all passed the barrier above):
+      // plane p+2 takes its slot; the site inputs of plane p+1
+      fill_plane(p + 2, rm);
+      load_site(p + 1, ocol, aq_o, qp_o, pp_o, true);
+      if (has_ring) load_site(p + 1, rcol, aq_r, dummy5, dummy, false);
+    }
+    const int t = rm;
+    rm = r0;
+    r0 = rp;
+    rp = t;
+  }
+  block_reduce_store<2>(v, partial + size_t(blockIdx.x) * 2, accumulate != 0);
 }
 
 // out = in + 1 for the step counter of a recorded state (one thread, vector memory).

@@ -13,8 +13,9 @@ namespace lbc {
 template <int NV>
 __device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* __restrict__ out,
                                                    bool accumulate = false) {
-  __shared__ double red[NV][4];
+  __shared__ double red[NV][16];  // one slot per wave, blocks of up to 1024 threads
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (int(blockDim.x) + 63) >> 6;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
 #pragma unroll
@@ -27,7 +28,8 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* __re
   __syncthreads();
   if (threadIdx.x < NV) {
     const int k = threadIdx.x;
-    const double bs = ((red[k][0] + red[k][1]) + red[k][2]) + red[k][3];
+    double bs = red[k][0];
+    for (int w = 1; w < nw; ++w) bs += red[k][w];  // fixed order: bitwise reproducible
     out[k] = accumulate ? out[k] + bs : bs;
   }
 }

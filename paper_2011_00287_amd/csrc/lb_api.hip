@@ -210,6 +210,7 @@ struct BackendT final : Backend {
   R* aFb = nullptr;
   R* agbar = nullptr;
   double* apart = nullptr;   // per-block (zeta, q0) adjoint partials, kept across reverse steps
+  size_t apart_n = 0;        // doubles in apart
   bool apart_live = false;   // apart holds sums not yet fetched by the caller
   bool site_path = false;  // three site-parallel kernels instead of the fused pair
   // predictor-corrector integrator of the order parameters: X* (Q then phi, in
@@ -224,6 +225,9 @@ struct BackendT final : Backend {
   int lb_ntx, lb_nty, lb_blocks, or_ntx, or_nty, or_blocks;
   static constexpr int kAoTX = 32, kAoTY = 8;  // tile of the z-marching adjoint order kernel
   int ao_ntx, ao_nty, ao_tz, ao_blocks;
+  // tile of the fused stress + gather adjoint (double: 16 x 8, whose LDS frame is half as large)
+  static constexpr int kAsTX = sizeof(R) == 4 ? 32 : 16, kAsTY = 8;
+  int as_ntx, as_nty, as_tz, as_blocks;
 
   BackendT(const lb_params& p, hipStream_t s) : stream(s) {
     box.nx = p.nx;
@@ -273,6 +277,11 @@ struct BackendT final : Backend {
     ao_nty = (p.ny + kAoTY - 1) / kAoTY;
     ao_tz = auto_slab(ao_ntx, ao_nty, p.nz, 16, 1, 2);
     ao_blocks = ao_ntx * ao_nty * ((p.nz + ao_tz - 1) / ao_tz);
+    as_ntx = (p.nx + kAsTX - 1) / kAsTX;
+    as_nty = (p.ny + kAsTY - 1) / kAsTY;
+    as_tz = std::max(0, env_int("LBC_TZ_ADJ", 0));
+    if (as_tz == 0) as_tz = auto_slab(as_ntx, as_nty, p.nz, 16, 1, 1);
+    as_blocks = as_ntx * as_nty * ((p.nz + as_tz - 1) / as_tz);
     size_t need = 2 * (NQ * N * sizeof(GS) + 6 * N * sizeof(FS)) + 4 * N * sizeof(R);
     if (pc4) need += 6 * N * sizeof(FS) + (site_path ? 3 * N * sizeof(R) : 0);
     size_t free_b = 0, total_b = 0;
@@ -716,8 +725,12 @@ struct BackendT final : Backend {
       aqbp = dalloc<R>(5 * N);
       aphibp = dalloc<R>(N);
       aFb = dalloc<R>(3 * N);
-      agbar = dalloc<R>(size_t(lbc::NGB) * N);
-      apart = dalloc<double>(size_t(nblk) * 2);
+      if (site_path) agbar = dalloc<R>(size_t(lbc::NGB) * N);  // the fused kernel keeps it on chip
+      // one (zeta, q0) pair per block of whichever reverse kernel writes them
+      const size_t npart = size_t(std::max<int>(int(nblk), as_blocks)) * 2;
+      apart = dalloc<double>(npart);
+      apart_n = npart;
+      HIPCHECK(hipMemsetAsync(apart, 0, npart * sizeof(double), stream));
       apart_live = false;
     } catch (...) {
       R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar};
@@ -794,14 +807,22 @@ struct BackendT final : Backend {
     else
       lbc::k_adj_order_fused<R, FS, kAoTX, kAoTY><<<ao_blocks, kAoTX * kAoTY, 0, stream>>>(
           box, P, ao_tz, ao_ntx, ao_nty, v.phi, v.q, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp);
+    const int npart_blocks = site_path ? int(nblk) : as_blocks;
+    if (size_t(npart_blocks) * 2 > apart_n) fail(LB_EDEVICE, "adjoint partial buffer smaller than the grid");
     lbc::k_adj_collide<R, GS><<<nblk, TPB, 0, stream>>>(box, P, v.B, FF, aWb, aubp, gi, go, aFb);
-    lbc::k_adj_stress<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, aFb, qi, amub, aqbp, aphibp, agbar, apart,
-                                                        apart_live ? 1 : 0);
+    if (site_path) {
+      lbc::k_adj_stress<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, aFb, qi, amub, aqbp, aphibp, agbar,
+                                                          apart, apart_live ? 1 : 0);
+      lbc::k_adj_gather<R><<<nblk, TPB, 0, stream>>>(box, agbar, po, qo);
+    } else {
+      lbc::k_adj_sg_fused<R, FS, kAsTX, kAsTY><<<as_blocks, kAsTX * kAsTY, 0, stream>>>(
+          box, P, as_tz, as_ntx, as_nty, v.phi, v.q, aFb, qi, amub, aqbp, aphibp, po, qo, apart,
+          apart_live ? 1 : 0);
+    }
     apart_live = true;
-    lbc::k_adj_gather<R><<<nblk, TPB, 0, stream>>>(box, agbar, po, qo);
     check_launch();
     if (!zeta_bar && !q0_bar) return;  // the parameter sums stay on the device
-    lbc::k_final_sum<<<1, TPB, 0, stream>>>(apart, int(nblk), 2, sums);
+    lbc::k_final_sum<<<1, TPB, 0, stream>>>(apart, npart_blocks, 2, sums);
     check_launch();
     apart_live = false;
     double pv[2] = {0.0, 0.0};

@@ -223,13 +223,19 @@ def test_recorded_rollout_equals_checkpointed():
     assert np.array_equal(g1, g2)
 
 
+@pytest.mark.parametrize("tz", ["1", "3", "default"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
-def test_adjoint_site_and_tiled_kernels_agree(monkeypatch, prec, tol):
-    """The site-parallel and the z-marching tiled reverse kernels give the same
-    reverse step (ragged tiles and slabs: a 34 x 18 x 11 box)."""
+def test_adjoint_site_and_tiled_kernels_agree(monkeypatch, prec, tol, tz):
+    """The site-parallel and the z-marching tiled reverse kernels (the order kernel
+    and the fused stress + gather kernel) give the same reverse step, for several
+    slab depths (ragged tiles and slabs: a 34 x 18 x 11 box)."""
     p = _p(q0=2 * math.pi / 9, zeta=0.01)
     g, phi, q5 = inputs.random_fields(34, 18, 11, seed=21, g_amp=2e-3, q_amp=0.2)
     seed_vals = np.random.default_rng(4).normal(size=25 * phi.size)
+    if tz == "default":
+        monkeypatch.delenv("LBC_TZ_ADJ", raising=False)
+    else:
+        monkeypatch.setenv("LBC_TZ_ADJ", tz)
     outs = []
     for site in ("0", "1"):
         monkeypatch.setenv("LBC_SITE_KERNELS", site)
