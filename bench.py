@@ -99,12 +99,18 @@ def time_precision(prec, p, phi, q5, steps, warmup, stream, lattice="d3q19", fd_
 
 
 def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True):
-    """(reverse pass incl. segment replay) / (plain forward) over the same steps,
-    with states kept every `checkpoint` steps; with `recorded`, also the mode that
-    keeps every state and step record in the forward pass (reverse pass without
-    replay, steps x (state + record) bytes of device memory)."""
+    """(reverse pass incl. any segment replay) / (plain forward) over the same steps.
+
+    Modes (lean records hold Q, phi, drho, u, F per step; full-state records hold
+    whole states plus u, F), as the autograd function runs them:
+      checkpointed: states kept every `checkpoint` steps, each segment replayed with
+                    recording steps into state buffers, then reversed;
+      recorded:     the lean record of every step kept in the forward pass, no replay;
+    and for comparison the other record kind in each mode (`alternatives`).
+    """
     import torch
-    from paper_2011_00287_amd.autograd import backward_recorded, backward_segments, run_recorded, run_segments
+    from paper_2011_00287_amd.autograd import (backward_lean, backward_recorded, backward_segments,
+                                               backward_segments_lean, run_lean, run_recorded, run_segments)
     from paper_2011_00287_amd.sim import Sim
     sim = Sim(p, phi, q5, precision=prec, stream=stream)
     s0 = sim.get_state()
@@ -120,27 +126,40 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True):
         return out, time.perf_counter() - t0
 
     _, t_fwd = timed(lambda: sim.step(steps))
-    sim.set_state(s0)
     zc0 = float(sim.centre()[0][2])
-    ckpts, t_fwd_ck = timed(lambda: run_segments(sim, steps, checkpoint))
-    adj = sim.adjoint_buffer()
-    sim.seed_centre(zc0, adj)
-    _, t_bwd = timed(lambda: backward_segments(sim, ckpts, steps, checkpoint, adj))
-    del ckpts
+
+    def run_mode(fwd, bwd):
+        sim.set_state(s0)
+        hist, t_f = timed(fwd)
+        adj = sim.adjoint_buffer()
+        sim.seed_centre(zc0, adj)
+        _, t_b = timed(lambda: bwd(hist, adj))
+        return hist, t_f, t_b
+
+    ck, t_fwd_ck, t_bwd = run_mode(lambda: run_segments(sim, steps, checkpoint),
+                                   lambda h, a: backward_segments(sim, h, steps, checkpoint, a))
+    del ck
     out = {"steps": steps, "checkpoint": checkpoint, "precision": prec, "forward_ms": t_fwd * 1e3,
            "forward_with_checkpoints_ms": t_fwd_ck * 1e3, "backward_ms": t_bwd * 1e3,
            "adjoint_over_forward": t_bwd / t_fwd, "total_over_forward": (t_fwd_ck + t_bwd) / t_fwd}
     if recorded:
-        sim.set_state(s0)
-        (states, recs), t_fwd_rec = timed(lambda: run_recorded(sim, steps))
-        adj = sim.adjoint_buffer()
-        sim.seed_centre(zc0, adj)
-        _, t_bwd_rec = timed(lambda: backward_recorded(sim, states, recs, adj))
-        nbytes = sum(t.numel() * t.element_size() for t in states + recs)
-        del states, recs
+        recs, t_fwd_rec, t_bwd_rec = run_mode(lambda: run_lean(sim, steps), lambda h, a: backward_lean(sim, h, a))
+        nbytes = sum(t.numel() * t.element_size() for t in recs)
+        del recs
         out["recorded"] = {"forward_recording_ms": t_fwd_rec * 1e3, "backward_ms": t_bwd_rec * 1e3,
                            "adjoint_over_forward": t_bwd_rec / t_fwd,
-                           "total_over_forward": (t_fwd_rec + t_bwd_rec) / t_fwd, "device_bytes": nbytes}
+                           "total_over_forward": (t_fwd_rec + t_bwd_rec) / t_fwd, "device_bytes": nbytes,
+                           "bytes_per_site_step": nbytes / (steps * phi.size)}
+        ck, _, t_bwd_lck = run_mode(lambda: run_segments(sim, steps, checkpoint),
+                                    lambda h, a: backward_segments_lean(sim, h, steps, checkpoint, a))
+        del ck
+        hist, _, t_bwd_rfull = run_mode(lambda: run_recorded(sim, steps),
+                                        lambda h, a: backward_recorded(sim, *h, a))
+        nfull = sum(t.numel() * t.element_size() for t in hist[0] + hist[1])
+        del hist
+        out["alternatives"] = {"checkpointed_lean_replay_adjoint_over_forward": t_bwd_lck / t_fwd,
+                               "recorded_full_state_adjoint_over_forward": t_bwd_rfull / t_fwd,
+                               "recorded_full_state_bytes_per_site_step": nfull / (steps * phi.size)}
     sim.close()
     return out
 
@@ -359,7 +378,10 @@ def main():
         adjoint = time_adjoint(args.precision, p, phi, q5, args.adjoint_steps, args.adjoint_checkpoint, stream,
                                recorded=not args.no_adjoint_recorded)
         print(f"# adjoint/forward: {adjoint['adjoint_over_forward']:.2f} (checkpoint {args.adjoint_checkpoint})"
-              + (f", {adjoint['recorded']['adjoint_over_forward']:.2f} (every step recorded)"
+              + (f", {adjoint['recorded']['adjoint_over_forward']:.2f} (every step recorded, "
+                 f"{adjoint['recorded']['bytes_per_site_step']:.0f} B/site/step); lean replay "
+                 f"{adjoint['alternatives']['checkpointed_lean_replay_adjoint_over_forward']:.2f}, full-state "
+                 f"records {adjoint['alternatives']['recorded_full_state_adjoint_over_forward']:.2f}"
                  if "recorded" in adjoint else ""), file=sys.stderr, flush=True)
 
     line = {

@@ -182,8 +182,9 @@ lb_status lb_set_state(lb_ctx* c, const void* dev_src, size_t bytes);
  * as g_bar [19][N] (adjoint of the post-stream population deviations),
  * q_bar [5][N] (adjoint of the 5 stored Q components) and phi_bar [N].
  * The caller owns it (e.g. a torch tensor on the context's device).
- * The adjoint is implemented for LB_D3Q19: with LB_D3Q15, lb_adjoint_bytes
- * and lb_record_bytes return 0 and the calls below return LB_EINVAL.
+ * The adjoint is implemented for LB_D3Q19 with LB_FD_EULER2: otherwise
+ * lb_adjoint_bytes, lb_record_bytes and lb_lean_record_bytes return 0 and the
+ * calls below return LB_EINVAL.
  * ------------------------------------------------------------------------- */
 size_t lb_adjoint_bytes(const lb_ctx* c);
 
@@ -214,6 +215,26 @@ lb_status lb_step_record(lb_ctx* c, const void* dev_state_in, void* dev_state_ou
 lb_status lb_adjoint_step(lb_ctx* c, const void* dev_state_t, size_t state_bytes, const void* dev_rec_t,
                           size_t rec_bytes, const void* dev_adj_in, void* dev_adj_out, size_t adj_bytes,
                           double* zeta_bar, double* q0_bar);
+
+/* Size of a lean step record: Q [5][N] and phi [N] of time t in the storage
+ * type, then drho [N] (the sum of the population deviations), u [3][N] and
+ * F [3][N] of the step from t, in the arithmetic type; each part starts on a
+ * 256-byte boundary (about 52 B per site in float32).  The populations enter
+ * the collision only through drho and u, so a lean record holds everything
+ * the reverse of its step reads: a reverse sweep over lean records needs no
+ * state buffers and no replay. */
+size_t lb_lean_record_bytes(const lb_ctx* c);
+
+/* Record the context's current time t into dev_rec_out (lean format) and
+ * advance the context's own state by one step, as lb_step(c, 1) does.
+ * Errors: LB_ESTATE on a size mismatch, LB_EINVAL (incl. a scheme without
+ * adjoint), LB_EDEVICE. */
+lb_status lb_step_record_lean(lb_ctx* c, void* dev_rec_out, size_t rec_bytes);
+
+/* One reverse step of the step recorded in dev_rec_t (lean format); the
+ * adjoint buffers and the parameter sums behave as in lb_adjoint_step. */
+lb_status lb_adjoint_step_lean(lb_ctx* c, const void* dev_rec_t, size_t rec_bytes, const void* dev_adj_in,
+                               void* dev_adj_out, size_t adj_bytes, double* zeta_bar, double* q0_bar);
 
 /* Seed of the droplet-displacement loss L = (z_c - z_ref)^2 with z_c the
  * phi-weighted linear centre along z of the current state (the loss of a

@@ -66,6 +66,9 @@ SIGNATURES = {
     "lb_step_record": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_size_t, ctypes.c_size_t]),
     "lb_adjoint_step": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P, _P, ctypes.c_size_t,
                                         _D, _D]),
+    "lb_lean_record_bytes": (ctypes.c_size_t, [_P]),
+    "lb_step_record_lean": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
+    "lb_adjoint_step_lean": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P, _P, ctypes.c_size_t, _D, _D]),
     "lb_adjoint_seed_centre": (ctypes.c_int, [_P, ctypes.c_double, _P, ctypes.c_size_t, _D]),
     "lb_profile_step": (ctypes.c_int, [_P, ctypes.c_int32, _D, ctypes.POINTER(ctypes.c_int32)]),
     "lb_kernel_name": (ctypes.c_char_p, [_P, ctypes.c_int32]),

@@ -3,13 +3,16 @@
 displacement_loss(zeta, q0, q5, ...) runs `steps` coupled steps of the droplet
 on the GPU and returns L = (z_c(T) - z_c(0))^2, the squared displacement along
 z of the phi-weighted droplet centre.  Its backward runs the hand-written
-adjoint of the step (lb_adjoint_step) in reverse, recomputing each segment of
-`checkpoint` steps from a stored state so that only about steps/checkpoint +
-checkpoint states are ever held in device memory.  Gradients: dL/dzeta,
-dL/dq0 (float64 device sums) and dL/dq5 (the initial Q field, 5 stored
-components); phi(0) and the initial populations are held fixed.  With
-checkpoint = 0 every state and step record of the forward pass is kept
-instead, and the reverse pass runs no replay.
+adjoint of the step in reverse.  With checkpoint = k the forward pass keeps a
+state every k steps and the reverse pass replays each segment with recording
+steps (state buffers and u, F records) before reversing it; with checkpoint = 0
+the forward pass keeps the lean record of every step (Q, phi of each time and
+drho, u, F of its step: all the reverse of a step reads, about 52 B per site
+in float32) and the reverse pass replays nothing.  Gradients: dL/dzeta, dL/dq0
+(float64 device sums) and dL/dq5 (the initial Q field, 5 stored components);
+phi(0) and the initial populations are held fixed.  run_recorded /
+backward_recorded keep whole states instead of lean records, and
+backward_segments_lean replays segments into lean records.
 """
 from __future__ import annotations
 
@@ -90,6 +93,54 @@ def backward_segments(sim: Sim, ckpts, steps: int, checkpoint: int, adj):
     return zb, qb
 
 
+def run_lean(sim: Sim, steps: int):
+    """Advance `steps` steps keeping the lean record of every step (no replay in the
+    reverse pass; device memory grows as steps x lean-record bytes)."""
+    recs = []
+    for _ in range(steps):
+        recs.append(sim.lean_record_buffer())
+        sim.step_record_lean(recs[-1])
+    return recs
+
+
+def backward_lean(sim: Sim, recs, adj):
+    """Reverse pass over run_lean's records; adj as in backward_segments.
+    Returns (zeta_bar, q0_bar)."""
+    zb = qb = 0.0
+    other = torch.empty_like(adj)
+    cur, nxt = adj, other
+    for j in reversed(range(len(recs))):
+        zb, qb = sim.adjoint_step_lean(recs[j], cur, nxt, zeta_bar=zb, q0_bar=qb, fetch=j == 0)
+        cur, nxt = nxt, cur
+    if cur is not adj:
+        adj.copy_(cur)
+    return zb, qb
+
+
+def backward_segments_lean(sim: Sim, ckpts, steps: int, checkpoint: int, adj):
+    """Reverse pass over checkpointed segments: each segment is replayed from its
+    checkpoint into lean records (the context's own state advances through it),
+    then reversed.  adj as in backward_segments; returns (zeta_bar, q0_bar)."""
+    zb = qb = 0.0
+    recs = [None] * checkpoint
+    other = torch.empty_like(adj)
+    cur, nxt = adj, other
+    for s in reversed(range(len(ckpts))):
+        n = min(checkpoint, steps - s * checkpoint)
+        sim.set_state(ckpts[s])
+        for j in range(n):
+            if recs[j] is None:
+                recs[j] = sim.lean_record_buffer()
+            sim.step_record_lean(recs[j])
+        for j in reversed(range(n)):
+            last = s == 0 and j == 0
+            zb, qb = sim.adjoint_step_lean(recs[j], cur, nxt, zeta_bar=zb, q0_bar=qb, fetch=last)
+            cur, nxt = nxt, cur
+    if cur is not adj:
+        adj.copy_(cur)
+    return zb, qb
+
+
 class _DropletRollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, zeta, q0, q5, params, phi, steps, checkpoint, precision):
@@ -98,7 +149,7 @@ class _DropletRollout(torch.autograd.Function):
         sim = Sim(p, np.asarray(phi, dtype=np.float64), q5_np, precision=precision,
                   stream=torch.cuda.current_stream())
         zc0 = float(sim.centre()[0][2])
-        ckpts = run_recorded(sim, steps) if checkpoint == 0 else run_segments(sim, steps, checkpoint)
+        ckpts = run_lean(sim, steps) if checkpoint == 0 else run_segments(sim, steps, checkpoint)
         zcT = float(sim.centre()[0][2])
         ctx.sim, ctx.ckpts, ctx.zc0 = sim, ckpts, zc0
         ctx.steps, ctx.checkpoint = steps, checkpoint
@@ -111,7 +162,7 @@ class _DropletRollout(torch.autograd.Function):
         adj = sim.adjoint_buffer()
         sim.seed_centre(ctx.zc0, adj)
         if ctx.checkpoint == 0:
-            zb, qb = backward_recorded(sim, *ctx.ckpts, adj)
+            zb, qb = backward_lean(sim, ctx.ckpts, adj)
         else:
             zb, qb = backward_segments(sim, ctx.ckpts, ctx.steps, ctx.checkpoint, adj)
         _, qbar, _ = sim.adjoint_parts(adj)
@@ -131,6 +182,6 @@ def displacement_loss(zeta, q0, q5, *, params: dict, phi, steps: int, checkpoint
     zeta, q0: 0-dim tensors; q5: [5, nz, ny, nx] tensor (CPU or CUDA); phi: numpy
     [nz, ny, nx]; params: the model parameter dict (its zeta / q0 are replaced).
     checkpoint: states kept every `checkpoint` steps and segments replayed in the
-    reverse pass; 0 keeps every state and step record instead (no replay).
+    reverse pass; 0 keeps the lean record of every step instead (no replay).
     """
     return _DropletRollout.apply(zeta, q0, q5, params, phi, steps, checkpoint, precision)

@@ -495,24 +495,17 @@ __host__ __device__ __forceinline__ void corotation_site_bwd(R xi, const R q[5],
   full_to_stored(Qb, qb);
 }
 
-// Reverse of collide_site: given the adjoint of the post-collision
-// populations gsb[19] and of the velocity output ub[3], overwrite g[] with the
-// adjoint of the pre-collision populations and accumulate Fb[3].
+// Reverse of collide_site from the moments of the pre-collision populations:
+// drho = sum g, u = (j + F/2)/rho (rho = rho0 + drho), the force F, the
+// adjoint of the post-collision populations gsb[19] and of the velocity
+// output ub_in[3]; writes the adjoint of the pre-collision populations gb[19]
+// and accumulates Fb[3].  The populations enter the collision only through
+// drho and j, so their moments are all the reverse needs.
 template <class R>
-__host__ __device__ __forceinline__ void collide_site_bwd(const Params<R>& P, const R g[19], const R F[3],
-                                                          const R gsb[19], const R ub_in[3], R gb[19], R Fb[3]) {
-  R drho = R(0);
-  for (int i = 0; i < 19; ++i) drho += g[i];
-  R j[3] = {R(0), R(0), R(0)};
-  for (int i = 0; i < 19; ++i) {
-    j[0] += R(CX(i)) * g[i];
-    j[1] += R(CY(i)) * g[i];
-    j[2] += R(CZ(i)) * g[i];
-  }
+__host__ __device__ __forceinline__ void collide_site_bwd_m(const Params<R>& P, R drho, const R u[3], const R F[3],
+                                                            const R gsb[19], const R ub_in[3], R gb[19], R Fb[3]) {
   const R rho = P.rho0 + drho;
   const R inv = R(1) / rho;
-  R u[3];
-  for (int a = 0; a < 3; ++a) u[a] = (j[a] + R(0.5) * F[a]) * inv;
   const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   const R om = P.omega, om1 = R(1) - P.omega;
   // g*_i = om1 g_i + w_i [om (A + 3 rho cu_i + 4.5 rho cu_i^2) + guo (Bs + 3 cF_i + 9 cu_i cF_i)]
@@ -553,6 +546,24 @@ __host__ __device__ __forceinline__ void collide_site_bwd(const Params<R>& P, co
   }
   drhob += rhob;
   for (int i = 0; i < 19; ++i) gb[i] += drhob + R(CX(i)) * jb[0] + R(CY(i)) * jb[1] + R(CZ(i)) * jb[2];
+}
+
+// Reverse of collide_site from the pre-collision populations g[19].
+template <class R>
+__host__ __device__ __forceinline__ void collide_site_bwd(const Params<R>& P, const R g[19], const R F[3],
+                                                          const R gsb[19], const R ub_in[3], R gb[19], R Fb[3]) {
+  R drho = R(0);
+  for (int i = 0; i < 19; ++i) drho += g[i];
+  R j[3] = {R(0), R(0), R(0)};
+  for (int i = 0; i < 19; ++i) {
+    j[0] += R(CX(i)) * g[i];
+    j[1] += R(CY(i)) * g[i];
+    j[2] += R(CZ(i)) * g[i];
+  }
+  const R inv = R(1) / (P.rho0 + drho);
+  R u[3];
+  for (int a = 0; a < 3; ++a) u[a] = (j[a] + R(0.5) * F[a]) * inv;
+  collide_site_bwd_m(P, drho, u, F, gsb, ub_in, gb, Fb);
 }
 
 }  // namespace lbc

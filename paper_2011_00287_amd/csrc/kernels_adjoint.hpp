@@ -27,11 +27,12 @@
 
 namespace lbc {
 
-// Forward force F = div(sigma) + body force and u = (j + F/2)/rho at time t.
+// Forward force F = div(sigma) + body force, u = (j + F/2)/rho and (when
+// drho_out is not null) drho = sum g at time t.
 template <class R, class GS>
 __global__ void __launch_bounds__(256) k_fwd_force(Box b, Params<R> P, const GS* __restrict__ B,
                                                    const R* __restrict__ sig, R* __restrict__ F_out,
-                                                   R* __restrict__ u_out) {
+                                                   R* __restrict__ u_out, R* __restrict__ drho_out) {
   const int s = site_xcd();
   if (s >= b.N) return;
   int x, y, z;
@@ -54,6 +55,7 @@ __global__ void __launch_bounds__(256) k_fwd_force(Box b, Params<R> P, const GS*
     F_out[a * N + s] = F[a];
     u_out[a * N + s] = (j[a] + R(0.5) * F[a]) / rho;
   }
+  if (drho_out) drho_out[s] = sum;
 }
 
 // Reverse of the Q and phi updates at one site.
@@ -332,6 +334,48 @@ __global__ void __launch_bounds__(256) k_adj_collide(Box b, Params<R> P, const G
   for (int a = 0; a < 3; ++a) Fs[a] = F[a * N + s];
   R gb[19], Fb[3] = {R(0), R(0), R(0)};
   collide_site_bwd(P, g, Fs, gsb, ub, gb, Fb);
+#pragma unroll
+  for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(gb[i], g_out + i * N + s);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) Fb_out[a * N + s] = Fb[a];
+}
+
+// Reverse of the collision and the pull stream from a lean record: the
+// pre-collision populations enter only through drho = sum g and u, which the
+// record holds, so they are not read.
+template <class R>
+__global__ void __launch_bounds__(256) k_adj_collide_lean(Box b, Params<R> P, const R* __restrict__ drho,
+                                                          const R* __restrict__ u, const R* __restrict__ F,
+                                                          const R* __restrict__ Wb, const R* __restrict__ ubp,
+                                                          const R* __restrict__ adj_g, R* __restrict__ g_out,
+                                                          R* __restrict__ Fb_out) {
+  const int s = site_xcd();
+  if (s >= b.N) return;
+  int x, y, z;
+  coords(b, s, x, y, z);
+  const size_t N = b.N;
+  const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  R ub[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ub[a] = ubp[a * N + s];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int sp = sidx(b, x + off[c][0], y + off[c][1], z + off[c][2]);
+    const int sm = sidx(b, x - off[c][0], y - off[c][1], z - off[c][2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ub[a] -= R(0.5) * (Wb[(a * 3 + c) * N + sp] - Wb[(a * 3 + c) * N + sm]);
+  }
+  R gsb[19], Fs[3], us[3];
+#pragma unroll
+  for (int i = 0; i < 19; ++i)
+    gsb[i] = __builtin_nontemporal_load(adj_g + i * N + sidx(b, x + CX(i), y + CY(i), z + CZ(i)));
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Fs[a] = F[a * N + s];
+    us[a] = u[a * N + s];
+  }
+  R gb[19], Fb[3] = {R(0), R(0), R(0)};
+  collide_site_bwd_m(P, drho[s], us, Fs, gsb, ub, gb, Fb);
 #pragma unroll
   for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(gb[i], g_out + i * N + s);
 #pragma unroll

@@ -6,7 +6,8 @@
 //               D3Q15 the symmetric stress enters the equilibrium (Eq. (9))
 //               and the force is that of the antisymmetric stress;
 //               writes the post-collision populations, u and mu (and the
-//               force F when a recording step asks for it).
+//               force F and the density deviation when a recording step asks
+//               for them).
 // k_order_fused: molecular field H (Eq. (5)), Beris-Edwards update of Q
 //               (Eq. (2)) and Cahn-Hilliard update of phi (Eq. (1)).
 //
@@ -41,7 +42,7 @@ template <class R, class GS, class FS, class L, int TX, int TY, int MINW>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(MINW)))
 k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ Bin, GS* __restrict__ Bout,
            const FS* __restrict__ phi, const FS* __restrict__ q, R* __restrict__ u_out, R* __restrict__ mu_out,
-           R* __restrict__ F_out) {
+           R* __restrict__ F_out, R* __restrict__ drho_out) {
   constexpr int NT = TX * TY;
   constexpr int AX = TX + 4, AY = TY + 4, NA = AX * AY;  // phi / Q slots (halo 2)
   constexpr int SX = TX + 2, SY = TY + 2, NS = SX * SY;  // stress slots (halo 1)
@@ -280,11 +281,11 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
       R F[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) F[a] = (fin_m1[a] + R(0.5) * (saz[a] - saz_m2[a])) + P.bf[a];
-      R u[3];
+      R u[3], drho = R(0);
       if constexpr (L::kStressInEq)
         collide_site_eq(P, g, F, ssym_m1, u);
       else
-        collide_site(P, g, F, u);
+        drho = collide_site(P, g, F, u);
       const uint32_t sg = uint32_t(zc) * plane_gs + own_g, sr = uint32_t(zc) * plane_r + own_r;
 #pragma unroll
       for (int i = 0; i < L::Q; ++i) GPolO<GS>::template st<R>(Bout + size_t(i) * N, sg, i, g[i]);
@@ -294,6 +295,7 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
 #pragma unroll
         for (int a = 0; a < 3; ++a) sto(F_out + size_t(a) * N, sr, F[a]);
       }
+      if (drho_out) sto(drho_out, sr, drho);  // lean recording step: the density deviation
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {

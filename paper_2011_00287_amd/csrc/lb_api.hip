@@ -178,6 +178,10 @@ struct Backend {
   virtual void step_record(const void* state_in, void* state_out, void* rec_out) = 0;
   virtual void adjoint_step(const void* state, const void* rec, const void* adj_in, void* adj_out,
                             double* zeta_bar, double* q0_bar) = 0;
+  virtual size_t lean_record_bytes() const = 0;
+  virtual void step_record_lean(void* rec_out) = 0;
+  virtual void adjoint_step_lean(const void* rec, const void* adj_in, void* adj_out, double* zeta_bar,
+                                 double* q0_bar) = 0;
   virtual double seed_centre(double z_ref, void* adj) = 0;
 };
 
@@ -545,8 +549,9 @@ struct BackendT final : Backend {
     FS* q_o;
     R* u;
     R* F;
+    R* drho;
   };
-  Io cur_io() { return Io{B[cur], B[cur ^ 1], Ph[cur], Q[cur], Ph[cur ^ 1], Q[cur ^ 1], u, nullptr}; }
+  Io cur_io() { return Io{B[cur], B[cur ^ 1], Ph[cur], Q[cur], Ph[cur ^ 1], Q[cur ^ 1], u, nullptr, nullptr}; }
   void launch_lb_tile(const Io& io) {
     switch (lb_tile) {
       case 0: launch_lb<32, 8, 2>(io); break;
@@ -561,7 +566,7 @@ struct BackendT final : Backend {
   template <int TX, int TY, int MINW>
   void launch_lb(const Io& io) {
     lbc::k_lb_fused<R, GS, FS, L, TX, TY, MINW><<<lb_blocks, TX * TY, 0, stream>>>(
-        box, P, tz_lb, lb_ntx, lb_nty, io.Bi, io.Bo, io.phi_i, io.q_i, io.u, mu, io.F);
+        box, P, tz_lb, lb_ntx, lb_nty, io.Bi, io.Bo, io.phi_i, io.q_i, io.u, mu, io.F, io.drho);
   }
   void launch_or_tile(const Io& io) {
     switch (or_tile) {
@@ -770,53 +775,85 @@ struct BackendT final : Backend {
     if (site_path) {
       ensure_thermo();
       lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, vi.phi, vi.q, mu, H, sig);
-      lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, vi.B, sig, rF, ru);
+      lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, vi.B, sig, rF, ru, nullptr);
       lbc::k_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, vi.B, Bo, sig, ru);
       lbc::k_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, vi.phi, vi.q, ru, H, mu, po, qo);
     } else {
-      fused_step(Io{vi.B, Bo, vi.phi, vi.q, po, qo, ru, rF});
+      fused_step(Io{vi.B, Bo, vi.phi, vi.q, po, qo, ru, rF, nullptr});
     }
     lbc::k_step_count<<<1, 64, 0, stream>>>(vi.step, reinterpret_cast<int64_t*>(co + off_step()));
     check_launch();
   }
-  void adjoint_step(const void* state, const void* rec, const void* adj_in, void* adj_out, double* zeta_bar,
-                    double* q0_bar) override {
+  // lean step record: Q [5][N], phi [N] (storage type) of time t, then drho,
+  // u [3][N], F [3][N] of that step (arithmetic type), each 256-byte aligned
+  size_t lr_phi() const { return align256(5 * N * sizeof(FS)); }
+  size_t lr_drho() const { return lr_phi() + align256(N * sizeof(FS)); }
+  size_t lr_u() const { return lr_drho() + align256(N * sizeof(R)); }
+  size_t lr_F() const { return lr_u() + align256(3 * N * sizeof(R)); }
+  size_t lean_record_bytes() const override { return has_adjoint() ? lr_F() + align256(3 * N * sizeof(R)) : 0; }
+  // Record time t into a lean record and advance the context's state by one step.
+  void step_record_lean(void* rec_out) override {
+    need_adjoint();
+    char* c = static_cast<char*>(rec_out);
+    R* rd = reinterpret_cast<R*>(c + lr_drho());
+    R* ru = reinterpret_cast<R*>(c + lr_u());
+    R* rF = reinterpret_cast<R*>(c + lr_F());
+    HIPCHECK(hipMemcpyAsync(c, Q[cur], 5 * N * sizeof(FS), hipMemcpyDeviceToDevice, stream));
+    HIPCHECK(hipMemcpyAsync(c + lr_phi(), Ph[cur], N * sizeof(FS), hipMemcpyDeviceToDevice, stream));
+    const int nx = cur ^ 1;
+    if (site_path) {
+      ensure_thermo();
+      lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], mu, H, sig);
+      lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, B[cur], sig, rF, ru, rd);
+      lbc::k_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, B[cur], B[nx], sig, ru);
+      lbc::k_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], ru, H, mu, Ph[nx], Q[nx]);
+    } else {
+      fused_step(Io{B[cur], B[nx], Ph[cur], Q[cur], Ph[nx], Q[nx], ru, rF, rd});
+    }
+    cur = nx;
+    check_launch();
+  }
+  void adjoint_step_lean(const void* rec, const void* adj_in, void* adj_out, double* zeta_bar,
+                         double* q0_bar) override {
     need_adjoint();
     ensure_adjoint();
-    const StateView v = view(state);
+    const char* c = static_cast<const char*>(rec);
+    const FS* rq = reinterpret_cast<const FS*>(c);
+    const FS* rphi = reinterpret_cast<const FS*>(c + lr_phi());
+    const R* rd = reinterpret_cast<const R*>(c + lr_drho());
+    const R* ru = reinterpret_cast<const R*>(c + lr_u());
+    const R* rF = reinterpret_cast<const R*>(c + lr_F());
+    reverse_kernels(rphi, rq, ru, rF, nullptr, rd, adj_in, adj_out, zeta_bar, q0_bar);
+  }
+  // the reverse kernels of one step; the collision adjoint reads the
+  // populations B, or (B == nullptr) the recorded density deviation drho
+  void reverse_kernels(const FS* phi_t, const FS* q_t, const R* uu, const R* FF, const GS* Bt, const R* drho,
+                       const void* adj_in, void* adj_out, double* zeta_bar, double* q0_bar) {
     const R* gi = static_cast<const R*>(adj_in);
     const R* qi = gi + 19 * N;
     const R* pi = gi + 24 * N;
     R* go = static_cast<R*>(adj_out);
     R* qo = go + 19 * N;
     R* po = go + 24 * N;
-    const R* uu;
-    const R* FF;
-    if (rec) {
-      uu = static_cast<const R*>(rec);
-      FF = uu + 3 * N;
-    } else {  // recompute u and F of time t
-      ensure_thermo();
-      lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, mu, H, sig);
-      lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, v.B, sig, aF, u);
-      uu = u;
-      FF = aF;
-    }
     if (site_path)
-      lbc::k_adj_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp);
+      lbc::k_adj_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phi_t, q_t, uu, pi, qi, amub, aWb, aubp, aqbp,
+                                                         aphibp);
     else
       lbc::k_adj_order_fused<R, FS, kAoTX, kAoTY><<<ao_blocks, kAoTX * kAoTY, 0, stream>>>(
-          box, P, ao_tz, ao_ntx, ao_nty, v.phi, v.q, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp);
+          box, P, ao_tz, ao_ntx, ao_nty, phi_t, q_t, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp);
     const int npart_blocks = site_path ? int(nblk) : as_blocks;
     if (size_t(npart_blocks) * 2 > apart_n) fail(LB_EDEVICE, "adjoint partial buffer smaller than the grid");
-    lbc::k_adj_collide<R, GS><<<nblk, TPB, 0, stream>>>(box, P, v.B, FF, aWb, aubp, gi, go, aFb);
+    if (Bt)
+      lbc::k_adj_collide<R, GS><<<nblk, TPB, 0, stream>>>(box, P, Bt, FF, aWb, aubp, gi, go, aFb);
+    else
+      lbc::k_adj_collide_lean<R><<<nblk, TPB, 0, stream>>>(box, P, drho, uu, FF, aWb, aubp, gi, go, aFb);
     if (site_path) {
-      lbc::k_adj_stress<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, aFb, qi, amub, aqbp, aphibp, agbar,
+      lbc::k_adj_stress<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phi_t, q_t, aFb, qi, amub, aqbp, aphibp, agbar,
                                                           apart, apart_live ? 1 : 0);
       lbc::k_adj_gather<R><<<nblk, TPB, 0, stream>>>(box, agbar, po, qo);
     } else {
       lbc::k_adj_sg_fused<R, FS, kAsTX, kAsTY><<<as_blocks, kAsTX * kAsTY, 0, stream>>>(
-          box, P, as_tz, as_ntx, as_nty, v.phi, v.q, aFb, qi, amub, aqbp, aphibp, po, qo, apart,
+          box, P, as_tz, as_ntx, as_nty, phi_t, q_t, aFb, qi, amub, aqbp, aphibp, po, qo, apart,
           apart_live ? 1 : 0);
     }
     apart_live = true;
@@ -830,6 +867,25 @@ struct BackendT final : Backend {
     HIPCHECK(hipStreamSynchronize(stream));
     if (zeta_bar) *zeta_bar += pv[0];
     if (q0_bar) *q0_bar += pv[1];
+  }
+  void adjoint_step(const void* state, const void* rec, const void* adj_in, void* adj_out, double* zeta_bar,
+                    double* q0_bar) override {
+    need_adjoint();
+    ensure_adjoint();
+    const StateView v = view(state);
+    const R* uu;
+    const R* FF;
+    if (rec) {
+      uu = static_cast<const R*>(rec);
+      FF = uu + 3 * N;
+    } else {  // recompute u and F of time t
+      ensure_thermo();
+      lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, mu, H, sig);
+      lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, v.B, sig, aF, u, nullptr);
+      uu = u;
+      FF = aF;
+    }
+    reverse_kernels(v.phi, v.q, uu, FF, v.B, nullptr, adj_in, adj_out, zeta_bar, q0_bar);
   }
   double seed_centre(double z_ref, void* adj) override {
     need_adjoint();
@@ -1044,6 +1100,33 @@ lb_status lb_adjoint_step(lb_ctx* c, const void* dev_state_t, size_t state_bytes
     if (dev_rec_t && rec_bytes != c->be->record_bytes()) fail(LB_ESTATE, "record buffer size mismatch");
     if (adj_bytes != c->be->adjoint_bytes()) fail(LB_ESTATE, "adjoint buffer size mismatch");
     c->be->adjoint_step(dev_state_t, dev_rec_t, dev_adj_in, dev_adj_out, zeta_bar, q0_bar);
+  });
+}
+
+size_t lb_lean_record_bytes(const lb_ctx* c) {
+  if (!c || !c->be) return 0;
+  return c->be->lean_record_bytes();
+}
+
+lb_status lb_step_record_lean(lb_ctx* c, void* dev_rec_out, size_t rec_bytes) {
+  return guarded([&] {
+    need_adjoint_ctx(c);
+    if (!dev_rec_out) fail(LB_EINVAL, "null buffer");
+    if (rec_bytes != c->be->lean_record_bytes()) fail(LB_ESTATE, "lean record buffer size mismatch");
+    c->be->step_record_lean(dev_rec_out);
+    c->step += 1;
+  });
+}
+
+lb_status lb_adjoint_step_lean(lb_ctx* c, const void* dev_rec_t, size_t rec_bytes, const void* dev_adj_in,
+                               void* dev_adj_out, size_t adj_bytes, double* zeta_bar, double* q0_bar) {
+  return guarded([&] {
+    need_adjoint_ctx(c);
+    if (!dev_rec_t || !dev_adj_in || !dev_adj_out) fail(LB_EINVAL, "null buffer");
+    if (dev_adj_in == dev_adj_out) fail(LB_EINVAL, "adj_in and adj_out must differ");
+    if (rec_bytes != c->be->lean_record_bytes()) fail(LB_ESTATE, "lean record buffer size mismatch");
+    if (adj_bytes != c->be->adjoint_bytes()) fail(LB_ESTATE, "adjoint buffer size mismatch");
+    c->be->adjoint_step_lean(dev_rec_t, dev_adj_in, dev_adj_out, zeta_bar, q0_bar);
   });
 }
 

@@ -301,7 +301,8 @@ __host__ __device__ __forceinline__ void corotation_site(R xi, const R q[5], con
 }
 
 // BGK collision with Guo forcing on the 19 deviations g (in place).
-// rho = rho0 + sum g, u = (sum c g + F/2)/rho; returns u.  With cu = c_i.u,
+// rho = rho0 + sum g, u = (sum c g + F/2)/rho; writes u and returns
+// drho = sum g of the pre-collision populations.  With cu = c_i.u,
 // cF = c_i.F, the equilibrium and source of population i are
 //   g_eq_i = w (A + 3 rho cu + 4.5 rho cu^2),  A = (rho - rho0) - 1.5 rho u.u
 //   src_i  = guo w (-3 u.F + 3 cF + 9 cu cF)
@@ -309,7 +310,7 @@ __host__ __device__ __forceinline__ void corotation_site(R xi, const R q[5], con
 // sign of the odd part.  The weight w and the relaxation factors are folded
 // into per-class constants, so a pair costs a few fused multiply-adds.
 template <class R>
-__host__ __device__ __forceinline__ void collide_site(const Params<R>& P, R g[19], const R F[3], R u[3]) {
+__host__ __device__ __forceinline__ R collide_site(const Params<R>& P, R g[19], const R F[3], R u[3]) {
   R drho = g[0];
 #pragma unroll
   for (int i = 1; i < 19; ++i) drho += g[i];
@@ -352,6 +353,7 @@ __host__ __device__ __forceinline__ void collide_site(const Params<R>& P, R g[19
     g[i] = (om1 * gi + even) + odd;
     g[i + 1] = (om1 * gj + even) - odd;
   }
+  return drho;
 }
 
 // BGK collision of the paper's scheme on the 15 D3Q15 deviations g (in place).

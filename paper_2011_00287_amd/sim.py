@@ -245,6 +245,27 @@ class Sim:
                                     ctypes.byref(zb) if fetch else None, ctypes.byref(qb) if fetch else None))
         return zb.value, qb.value
 
+    def lean_record_buffer(self):
+        """uint8 device tensor for one lean step record (Q, phi of time t; drho, u, F of its step)."""
+        import torch
+        return torch.empty(int(lib().lb_lean_record_bytes(self._h)), dtype=torch.uint8, device="cuda")
+
+    def step_record_lean(self, rec):
+        """Record the current time into rec (lean format) and advance the state by one step."""
+        check(lib().lb_step_record_lean(self._h, ctypes.c_void_p(rec.data_ptr()), rec.numel() * rec.element_size()))
+
+    def adjoint_step_lean(self, rec, adj_in, adj_out, zeta_bar: float = 0.0, q0_bar: float = 0.0,
+                          fetch: bool = True):
+        """adj_out <- adjoint at t from adj_in (adjoint at t+1), given the lean record of the
+        step from t; parameter sums as in adjoint_step."""
+        zb = ctypes.c_double(zeta_bar)
+        qb = ctypes.c_double(q0_bar)
+        check(lib().lb_adjoint_step_lean(self._h, ctypes.c_void_p(rec.data_ptr()), rec.numel() * rec.element_size(),
+                                         ctypes.c_void_p(adj_in.data_ptr()), ctypes.c_void_p(adj_out.data_ptr()),
+                                         adj_in.numel() * adj_in.element_size(),
+                                         ctypes.byref(zb) if fetch else None, ctypes.byref(qb) if fetch else None))
+        return zb.value, qb.value
+
     # ----------------------------------------------------------------- profiling
     def profile(self, nsteps: int):
         """{kernel name: average ms per launch} over nsteps steps (state advances)."""

@@ -251,3 +251,80 @@ def test_adjoint_site_and_tiled_kernels_agree(monkeypatch, prec, tol, tz):
     l2, mx = rel_err(a, b)
     assert l2 < tol and mx < tol, (l2, mx)
     assert abs(za - zb_) <= tol * abs(za) and abs(qa - qb_) <= tol * abs(qa)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
+def test_lean_reverse_step_equals_full_state_step(prec, tol):
+    """The reverse of a step from its lean record (Q, phi, drho, u, F) equals the reverse
+    from the full state and its u, F record (the populations enter only through drho, u)."""
+    p = _p(q0=2 * math.pi / 7, zeta=0.01)
+    g, phi, q5 = inputs.random_fields(9, 8, 6, seed=41, g_amp=2e-3, q_amp=0.2)
+    seed_vals = np.random.default_rng(6).normal(size=25 * phi.size)
+    with Sim(p, phi, q5, precision=prec) as sim:
+        sim.set_fields(g=g)
+        state = sim.get_state()
+        adj = sim.adjoint_buffer()
+        adj.copy_(torch.tensor(seed_vals, dtype=adj.dtype))
+        rec = sim.record_buffer()
+        nxt = torch.empty_like(state)
+        sim.step_record(state, nxt, rec)
+        out_full = sim.adjoint_buffer()
+        zf, qf = sim.adjoint_step(state, adj, out_full, rec=rec)
+        sim.set_state(state)
+        lean = sim.lean_record_buffer()
+        assert lean.numel() < state.numel() + rec.numel() * rec.element_size()
+        sim.step_record_lean(lean)
+        assert sim.totals()["step"] == 1
+        # the lean recording step advanced the context exactly as an ordinary step
+        sim2_ref = sim.moments()
+        sim.set_state(nxt)
+        for a, b in zip(sim2_ref, sim.moments()):
+            assert np.array_equal(a, b)
+        out_lean = sim.adjoint_buffer()
+        zl, ql = sim.adjoint_step_lean(lean, adj, out_lean)
+    a, b = out_lean.double().cpu().numpy(), out_full.double().cpu().numpy()
+    l2, mx = rel_err(a, b)
+    assert l2 < tol and mx < tol, (l2, mx)
+    assert abs(zl - zf) <= tol * abs(zf) and abs(ql - qf) <= tol * abs(qf)
+
+
+def test_lean_rollouts_equal_full_state_rollout():
+    """run_lean + backward_lean and the lean checkpointed replay give the gradient of the
+    full-state checkpointed rollout (FP64)."""
+    from paper_2011_00287_amd.autograd import backward_lean, backward_segments_lean, run_lean
+    p = _p(q0=2 * math.pi / 8, zeta=0.02)
+    phi, q5 = inputs.droplet_fields(10, 9, 12, 3.0, p["q0"], seed=5)
+    steps, ck = 11, 4
+    res = []
+    for mode in ("full", "lean", "lean_ckpt"):
+        with Sim(p, phi, q5, precision="fp64") as sim:
+            zc0 = sim.centre()[0][2]
+            if mode == "lean":
+                recs = run_lean(sim, steps)
+            else:
+                ckpts = run_segments(sim, steps, ck)
+            adj = sim.adjoint_buffer()
+            L = sim.seed_centre(zc0, adj)
+            if mode == "full":
+                zb, qb = backward_segments(sim, ckpts, steps, ck, adj)
+            elif mode == "lean":
+                zb, qb = backward_lean(sim, recs, adj)
+            else:
+                zb, qb = backward_segments_lean(sim, ckpts, steps, ck, adj)
+            res.append((L, zb, qb, adj.double().cpu().numpy()))
+    (L0, z0, q0_, a0) = res[0]
+    for L, zb, qb, a in res[1:]:
+        assert abs(L - L0) <= 1e-14 * abs(L0)
+        assert abs(zb - z0) <= 1e-12 * abs(z0) and abs(qb - q0_) <= 1e-12 * abs(q0_)
+        l2, mx = rel_err(a, a0)
+        assert l2 < 1e-12 and mx < 1e-12, (l2, mx)
+
+
+def test_lean_records_refused_without_adjoint():
+    from paper_2011_00287_amd._lib import LB_EINVAL, LbError
+    phi, q5 = inputs.droplet_fields(6, 6, 6, 2.0, 0.5)
+    with Sim(_p(), phi, q5, lattice="d3q15") as sim:
+        assert sim.lean_record_buffer().numel() == 0
+        with pytest.raises(LbError) as e:
+            sim.step_record_lean(torch.empty(8, dtype=torch.uint8, device="cuda"))
+        assert e.value.status == LB_EINVAL
