@@ -1,8 +1,8 @@
 // Global float64 reductions: conservation totals, the discrete free energy
 // F_h of Eq. (5), and the phi-weighted droplet centre.
 //
-// Each launch writes one partial vector per 256-thread block (wave64 shuffles,
-// then a fixed-order pass over the 4 waves); k_final_sum adds the block
+// Each launch writes one partial vector per block (wave64 shuffles, then a
+// fixed-order pass over the block's waves); k_final_sum adds the block
 // partials in a fixed order, so results are bitwise reproducible.
 #pragma once
 #include "kernels_site.hpp"
