@@ -110,7 +110,8 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True):
     """
     import torch
     from paper_2011_00287_amd.autograd import (backward_lean, backward_recorded, backward_segments,
-                                               backward_segments_lean, run_lean, run_recorded, run_segments)
+                                               backward_segments_lean, backward_segments_overlapped, run_lean,
+                                               run_recorded, run_segments)
     from paper_2011_00287_amd.sim import Sim
     sim = Sim(p, phi, q5, precision=prec, stream=stream)
     s0 = sim.get_state()
@@ -142,6 +143,17 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True):
     out = {"steps": steps, "checkpoint": checkpoint, "precision": prec, "forward_ms": t_fwd * 1e3,
            "forward_with_checkpoints_ms": t_fwd_ck * 1e3, "backward_ms": t_bwd * 1e3,
            "adjoint_over_forward": t_bwd / t_fwd, "total_over_forward": (t_fwd_ck + t_bwd) / t_fwd}
+    # the same sweep with the replay of segment s-1 on a second context and stream
+    # while segment s is reversed (the replay context exists before the timed region)
+    replay_stream = torch.cuda.Stream()
+    rep = Sim(p, phi, q5, precision=prec, stream=replay_stream)
+    ck, _, t_bwd_ov = run_mode(lambda: run_segments(sim, steps, checkpoint),
+                               lambda h, a: backward_segments_overlapped(sim, rep, h, steps, checkpoint, a,
+                                                                         replay_stream))
+    del ck
+    rep.close()
+    out["overlapped"] = {"backward_ms": t_bwd_ov * 1e3, "adjoint_over_forward": t_bwd_ov / t_fwd,
+                         "total_over_forward": (t_fwd_ck + t_bwd_ov) / t_fwd}
     if recorded:
         recs, t_fwd_rec, t_bwd_rec = run_mode(lambda: run_lean(sim, steps), lambda h, a: backward_lean(sim, h, a))
         nbytes = sum(t.numel() * t.element_size() for t in recs)
@@ -377,7 +389,8 @@ def main():
     if args.adjoint_steps > 0 and args.lattice == "d3q19" and args.fd_scheme == "euler2":
         adjoint = time_adjoint(args.precision, p, phi, q5, args.adjoint_steps, args.adjoint_checkpoint, stream,
                                recorded=not args.no_adjoint_recorded)
-        print(f"# adjoint/forward: {adjoint['adjoint_over_forward']:.2f} (checkpoint {args.adjoint_checkpoint})"
+        print(f"# adjoint/forward: {adjoint['adjoint_over_forward']:.2f} (checkpoint {args.adjoint_checkpoint}; "
+              f"{adjoint['overlapped']['adjoint_over_forward']:.2f} with the replay overlapped)"
               + (f", {adjoint['recorded']['adjoint_over_forward']:.2f} (every step recorded, "
                  f"{adjoint['recorded']['bytes_per_site_step']:.0f} B/site/step); lean replay "
                  f"{adjoint['alternatives']['checkpointed_lean_replay_adjoint_over_forward']:.2f}, full-state "

@@ -93,6 +93,56 @@ def backward_segments(sim: Sim, ckpts, steps: int, checkpoint: int, adj):
     return zb, qb
 
 
+def backward_segments_overlapped(sim: Sim, replay: Sim, ckpts, steps: int, checkpoint: int, adj,
+                                 replay_stream):
+    """backward_segments with the replay of segment s-1 running on a second context
+    (`replay`, same parameters, created on `replay_stream`) while segment s is
+    reversed on `sim`'s stream.  A recording step touches only the state buffers
+    and records it is given, so the two contexts share nothing but those buffers,
+    which are double-buffered per segment; events order each reverse after its
+    segment's replay and each replay after the reverse that last used its buffers.
+    `sim` must run on torch's current stream.  The result equals backward_segments
+    bit for bit.  Returns (zeta_bar, q0_bar)."""
+    main_stream = torch.cuda.current_stream()
+    nseg = len(ckpts)
+    bufs = []
+    for _ in range(min(2, nseg)):
+        bufs.append(([None] + [torch.empty_like(ckpts[0]) for _ in range(checkpoint)],
+                     [sim.record_buffer() for _ in range(checkpoint)]))
+    replayed = [torch.cuda.Event() for _ in range(nseg)]
+    reversed_ = [torch.cuda.Event() for _ in range(nseg)]
+
+    def replay_segment(s):
+        states, recs = bufs[s % 2]
+        with torch.cuda.stream(replay_stream):
+            if s + 2 < nseg:  # this buffer set was last used by the reverse of segment s + 2
+                replay_stream.wait_event(reversed_[s + 2])
+            n = min(checkpoint, steps - s * checkpoint)
+            states[0] = ckpts[s]
+            for j in range(n):
+                replay.step_record(states[j], states[j + 1], recs[j])
+            replayed[s].record(replay_stream)
+
+    zb = qb = 0.0
+    other = torch.empty_like(adj)
+    cur, nxt = adj, other
+    replay_segment(nseg - 1)
+    for s in reversed(range(nseg)):
+        if s > 0:
+            replay_segment(s - 1)
+        main_stream.wait_event(replayed[s])
+        states, recs = bufs[s % 2]
+        n = min(checkpoint, steps - s * checkpoint)
+        for j in reversed(range(n)):
+            last = s == 0 and j == 0
+            zb, qb = sim.adjoint_step(states[j], cur, nxt, rec=recs[j], zeta_bar=zb, q0_bar=qb, fetch=last)
+            cur, nxt = nxt, cur
+        reversed_[s].record(main_stream)
+    if cur is not adj:
+        adj.copy_(cur)
+    return zb, qb
+
+
 def run_lean(sim: Sim, steps: int):
     """Advance `steps` steps keeping the lean record of every step (no replay in the
     reverse pass; device memory grows as steps x lean-record bytes)."""

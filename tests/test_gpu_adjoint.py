@@ -328,3 +328,30 @@ def test_lean_records_refused_without_adjoint():
         with pytest.raises(LbError) as e:
             sim.step_record_lean(torch.empty(8, dtype=torch.uint8, device="cuda"))
         assert e.value.status == LB_EINVAL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_overlapped_replay_equals_sequential(prec):
+    """Replaying segment s-1 on a second context and stream while segment s is reversed
+    gives the sequential checkpointed sweep bit for bit."""
+    from paper_2011_00287_amd.autograd import backward_segments_overlapped
+    p = _p(q0=2 * math.pi / 8, zeta=0.02)
+    phi, q5 = inputs.droplet_fields(12, 10, 14, 3.5, p["q0"], seed=7)
+    steps, ck = 13, 4
+    res = []
+    replay_stream = torch.cuda.Stream()
+    for mode in ("sequential", "overlapped"):
+        with Sim(p, phi, q5, precision=prec, stream=torch.cuda.current_stream()) as sim:
+            zc0 = sim.centre()[0][2]
+            ckpts = run_segments(sim, steps, ck)
+            adj = sim.adjoint_buffer()
+            sim.seed_centre(zc0, adj)
+            if mode == "sequential":
+                zb, qb = backward_segments(sim, ckpts, steps, ck, adj)
+            else:
+                with Sim(p, phi, q5, precision=prec, stream=replay_stream) as rep:
+                    zb, qb = backward_segments_overlapped(sim, rep, ckpts, steps, ck, adj, replay_stream)
+            torch.cuda.synchronize()
+            res.append((zb, qb, adj.cpu().numpy().copy()))
+    assert res[0][0] == res[1][0] and res[0][1] == res[1][1]
+    assert np.array_equal(res[0][2], res[1][2])
