@@ -188,13 +188,14 @@ lb_status lb_set_state(lb_ctx* c, const void* dev_src, size_t bytes);
  * ------------------------------------------------------------------------- */
 size_t lb_adjoint_bytes(const lb_ctx* c);
 
-/* Size of a step record: u [3][N] and F [3][N] (the velocity with F/2 and the
- * force of Eq. (3)) of one time t, in the context's arithmetic type. */
+/* Size of a step record: u [3][N], F [3][N] and drho [N] (the velocity with
+ * F/2, the force of Eq. (3) and rho - rho0 = sum g) of one time t, in the
+ * context's arithmetic type. */
 size_t lb_record_bytes(const lb_ctx* c);
 
 /* One forward step from the state buffer dev_state_in (time t, lb_get_state
- * format) into dev_state_out (time t+1, a different buffer), writing u and F
- * of time t into dev_rec_out.  The context's own state is not touched.  This is
+ * format) into dev_state_out (time t+1, a different buffer), writing u, F and
+ * drho of time t into dev_rec_out.  The context's own state is not touched.  This is
  * the replay of a checkpoint segment before its reverse steps. */
 lb_status lb_step_record(lb_ctx* c, const void* dev_state_in, void* dev_state_out, void* dev_rec_out,
                          size_t state_bytes, size_t rec_bytes);
@@ -202,8 +203,9 @@ lb_status lb_step_record(lb_ctx* c, const void* dev_state_in, void* dev_state_ou
 /* One reverse step: dev_adj_out <- (d step / d state_t)^T dev_adj_in, the
  * vector-Jacobian product of one coupled step at the forward state dev_state_t
  * with the context's current parameters.  dev_rec_t is that step's record
- * from lb_step_record (NULL: u and F are recomputed).  adj_in and adj_out
- * must differ.
+ * from lb_step_record (NULL: u and F are recomputed and the collision's
+ * reverse reads the populations of dev_state_t; with a record it reads drho
+ * and u from it).  adj_in and adj_out must differ.
  * The step's contributions to dL/dzeta and dL/dq0 are summed in float64 on
  * the device and kept there across calls.  When zeta_bar or q0_bar is
  * non-NULL, every contribution kept since the last such call (this one's

@@ -593,15 +593,23 @@ k_adj_gather(Box b, const R* __restrict__ gbar, R* __restrict__ adj_phi, R* __re
 // ---------------------------------------------------------------------------
 // k_adj_sg_fused: k_adj_stress and k_adj_gather in one z-marching pass, so the
 // 30 gradient-data adjoints never leave the chip.  One workgroup marches a
-// TX x TY tile through a slab of planes; at plane p it
+// TX x TY tile through a slab of planes, one site per thread; at plane p it
 //   * takes phi, Q, mu_bar, F_bar of planes p-1, p, p+1 from an LDS ring of
-//     three planes on the tile with a halo of 2;
-//   * forms the gradient-data adjoint (adj_stress_site) at the owned sites and
-//     at the cross-shaped ring of 1 around the tile, and puts the 18 values
-//     the in-plane transposes read in LDS;
-//   * applies the in-plane transposes (x, y) at the owned sites, and the z
-//     transposes from the owned column's values at p-1 and p+1 held in
-//     registers, so the adjoint of plane p-1 is complete one step later.
+//     three planes on the tile with a halo of 1;
+//   * forms the gradient-data adjoint (adj_stress_site) at its own site and
+//     puts the 18 values the in-plane transposes read in LDS;
+//   * applies the in-plane transposes from the neighbours inside the tile,
+//     and the z transposes from the own column's values at p-1 and p+1 held
+//     in registers, so the adjoint of plane p-1 is complete one step later
+//     except for the terms of neighbours in other tiles;
+//   * an edge site of an owned plane writes the term it owes the neighbour
+//     across the tile face to the face buffers (hx, hy), which k_adj_face_x
+//     and k_adj_face_y then add.  Every wave does one stress adjoint per
+//     plane: no site's adjoint is recomputed by a second tile.
+// Face buffers: hx[f][side][k][z][y] for the face between x tiles k and k+1
+// (mod ntx), hy[f][side][k][z][x] for y tiles; side 0 is the term sent in the
+// + direction, side 1 the term sent in the - direction; f = phi, q[5].  They
+// are written only when the box has more than one tile along that axis.
 // The (zeta, q0) partials count owned sites only.
 // ---------------------------------------------------------------------------
 template <class R, class FS, int TX, int TY>
@@ -609,31 +617,30 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(1, 
 k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__ phi,
                const FS* __restrict__ q, const R* __restrict__ Fb, const R* __restrict__ adj_q,
                const R* __restrict__ mub, const R* __restrict__ qbp, const R* __restrict__ phibp,
-               R* __restrict__ adj_phi, R* __restrict__ adj_qo, double* __restrict__ partial, int accumulate) {
+               R* __restrict__ adj_phi, R* __restrict__ adj_qo, R* __restrict__ hx, R* __restrict__ hy,
+               double* __restrict__ partial, int accumulate) {
   constexpr int NT = TX * TY;
-  constexpr int IX = TX + 4, IY = TY + 4, NI = IX * IY;  // input frame (halo 2)
-  constexpr int GX = TX + 2, GY = TY + 2, NG = GX * GY;  // gradient-adjoint frame (ring 1)
-  constexpr int NR = 2 * (TX + TY);                      // ring slots (no corners)
+  constexpr int IX = TX + 2, IY = TY + 2, NI = IX * IY;  // input frame (halo 1)
   constexpr int NF = 10;                                 // phi, q[5], mu_bar, F_bar[3]
   constexpr int KI = (NI + NT - 1) / NT;
   constexpr int NGB = 18;  // lapphi, lapq[5], dphi_x, dphi_y, dq_x[5], dq_y[5]
-  static_assert(NR <= NT, "one ring slot per thread");
   __shared__ R sIn[3][NF][NI];
-  __shared__ R sGB[NGB][NG];
+  __shared__ R sGB[NGB][NT];
   __shared__ int sGX[IX], sGY[IY];
 
   const int l = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = l % ntx, ty = (l / ntx) % nty, sl = l / (ntx * nty);
   const int x0 = tx * TX, y0 = ty * TY, z0 = sl * TZ;
   const int z1 = min(z0 + TZ, b.nz);
+  const int w = min(TX, b.nx - x0), h = min(TY, b.ny - y0);  // the tile's extent in the box
   const int tid = threadIdx.x;
   const int lx = tid % TX, ly = tid / TX;
-  const bool active = (x0 + lx < b.nx) && (y0 + ly < b.ny);
+  const bool active = lx < w && ly < h;
   const size_t N = b.N;
   const int plane = b.nx * b.ny;
 
-  for (int k = tid; k < IX; k += NT) sGX[k] = pmod(x0 - 2 + k, b.nx);
-  for (int k = tid; k < IY; k += NT) sGY[k] = pmod(y0 - 2 + k, b.ny);
+  for (int k = tid; k < IX; k += NT) sGX[k] = pmod(x0 - 1 + k, b.nx);
+  for (int k = tid; k < IY; k += NT) sGY[k] = pmod(y0 - 1 + k, b.ny);
   __syncthreads();
 
   // input-frame slots this thread loads (padding repeats the frame origin)
@@ -645,8 +652,8 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
   }
   // plane w of the inputs into ring slot `slot` (the loads of one frame slot are
   // stored before the next slot's are issued, which keeps few registers live)
-  auto fill_plane = [&](int w, int slot) {
-    const size_t base = size_t(pmod(w, b.nz)) * plane;
+  auto fill_plane = [&](int wp, int slot) {
+    const size_t base = size_t(pmod(wp, b.nz)) * plane;
 #pragma unroll
     for (int j = 0; j < KI; ++j) {
       const int k = tid + j * NT;
@@ -665,25 +672,25 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
     }
   };
 
-  // gradient-adjoint slots: the owned site, and (tid < NR) one ring slot
-  const int ogx = lx + 1, ogy = ly + 1;
-  int rgx = 0, rgy = 0;
-  const bool has_ring = tid < NR;
-  if (has_ring) {
-    if (tid < 2 * TX) {
-      rgx = 1 + tid % TX;
-      rgy = tid < TX ? 0 : GY - 1;
-    } else {
-      const int t = tid - 2 * TX;
-      rgy = 1 + t % TY;
-      rgx = t < TY ? 0 : GX - 1;
-    }
-  }
-  const int ocol = sGY[ogy + 1] * b.nx + sGX[ogx + 1];
-  const int rcol = sGY[rgy + 1] * b.nx + sGX[rgx + 1];
-  // the gradient-data adjoint at a slot of plane p (input slots rm, r0, rp = planes p-1, p, p+1)
-  auto slot_adjoint = [&](int gx, int gy, int rm, int r0, int rp, const R aq[5], GradBar<R>& Gb, ParBar<R>& Pb) {
-    const int f = (gy + 1) * IX + (gx + 1);
+  // in-plane neighbours inside the tile (a lone tile along an axis wraps
+  // periodically inside itself); -1 where the neighbour is in another tile
+  const int nxp = ntx == 1 ? (lx + 1) % w : (lx + 1 < w ? lx + 1 : -1);
+  const int nxm = ntx == 1 ? (lx + w - 1) % w : (lx > 0 ? lx - 1 : -1);
+  const int nyp = nty == 1 ? (ly + 1) % h : (ly + 1 < h ? ly + 1 : -1);
+  const int nym = nty == 1 ? (ly + h - 1) % h : (ly > 0 ? ly - 1 : -1);
+  const int sxp = nxp < 0 ? tid : ly * TX + nxp, sxm = nxm < 0 ? tid : ly * TX + nxm;
+  const int syp = nyp < 0 ? tid : nyp * TX + lx, sym = nym < 0 ? tid : nym * TX + lx;
+  // the tile faces this site sends across (owned planes only)
+  const bool send_xp = active && ntx > 1 && lx == w - 1, send_xm = active && ntx > 1 && lx == 0;
+  const bool send_yp = active && nty > 1 && ly == h - 1, send_ym = active && nty > 1 && ly == 0;
+  const size_t fxs = size_t(ntx) * b.nz * b.ny, fys = size_t(nty) * b.nz * b.nx;  // one field-side block
+  const int kxm = (tx + ntx - 1) % ntx, kym = (ty + nty - 1) % nty;
+
+  const int f0 = (ly + 1) * IX + (lx + 1);
+  const int col = sGY[ly + 1] * b.nx + sGX[lx + 1];
+  // the gradient-data adjoint of the own site at plane p (input slots rm, r0, rp = planes p-1, p, p+1)
+  auto site_adjoint = [&](int rm, int r0, int rp, const R aq[5], GradBar<R>& Gb, ParBar<R>& Pb) {
+    const int f = f0;
     const int nb[3][2] = {{f + 1, f - 1}, {f + IX, f - IX}, {f, f}};
     auto at = [&](int fld, int g, int d) {
       return g < 2 ? sIn[r0][fld][nb[g][d]] : sIn[d == 0 ? rp : rm][fld][f];
@@ -721,28 +728,19 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
     G.divv = R(0);
     adj_stress_site(P, G, Fn, mbn, sIn[r0][6][f], aq, Gb, Pb);
   };
-  auto put_gb = [&](int gx, int gy, const GradBar<R>& Gb) {
-    const int s = gy * GX + gx;
-    sGB[0][s] = Gb.lapphi;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) sGB[1 + k][s] = Gb.lapq[k];
-    sGB[6][s] = Gb.dphi[0];
-    sGB[7][s] = Gb.dphi[1];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      sGB[8 + k][s] = Gb.dq[0][k];
-      sGB[13 + k][s] = Gb.dq[1][k];
-    }
-  };
-  auto load_site = [&](int w, int col, R aq[5], R qp[5], R& pp, bool own) {
-    const size_t k = size_t(pmod(w, b.nz)) * plane + col;
+  auto load_site = [&](int wp, R aq[5], R qp[5], R& pp) {
+    const size_t k = size_t(pmod(wp, b.nz)) * plane + col;
 #pragma unroll
     for (int c = 0; c < 5; ++c) aq[c] = adj_q[c * N + k];
-    if (own) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) qp[c] = qbp[c * N + k];
-      pp = phibp[k];
-    }
+    for (int c = 0; c < 5; ++c) qp[c] = qbp[c * N + k];
+    pp = phibp[k];
+  };
+  // the term a site sends across a face: lap + (sgn/2) d, for phi and q[5]
+  auto send = [&](R* __restrict__ buf, size_t fs, size_t off, R sgn, const GradBar<R>& Gb, int g) {
+    buf[off] = Gb.lapphi + sgn * R(0.5) * Gb.dphi[g];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) buf[size_t(2 * (1 + k)) * fs + off] = Gb.lapq[k] + sgn * R(0.5) * Gb.dq[g][k];
   };
 
   // planes z0-2 .. z0 into the ring, the site inputs of plane z0-1 into registers
@@ -750,39 +748,47 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
   fill_plane(z0 - 2, rm);
   fill_plane(z0 - 1, r0);
   fill_plane(z0, rp);
-  R aq_o[5], qp_o[5], pp_o = R(0), aq_r[5] = {R(0), R(0), R(0), R(0), R(0)}, dummy5[5];
-  R dummy = R(0);
-  load_site(z0 - 1, ocol, aq_o, qp_o, pp_o, true);
-  if (has_ring) load_site(z0 - 1, rcol, aq_r, dummy5, dummy, false);
+  R aq_o[5], qp_o[5], pp_o = R(0);
+  load_site(z0 - 1, aq_o, qp_o, pp_o);
 
-  // owned column: z-transpose values of the previous plane and the running adjoint
+  // own column: z-transpose values of the previous plane and the running adjoint
   R zp_lapphi = R(0), zp_dphi = R(0), zp_lapq[5], zp_dq[5];
   R acc_p = R(0), acc_q[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) zp_lapq[k] = zp_dq[k] = acc_q[k] = R(0);
   double v[2] = {0.0, 0.0};
-  const int ogs = ogy * GX + ogx;
 
   for (int p = z0 - 1; p <= z1; ++p) {
     const bool more = p < z1;
     __syncthreads();  // plane p+1 in place; the previous plane's reads of sGB are done
     GradBar<R> Gb;
     ParBar<R> Pb;
-    slot_adjoint(ogx, ogy, rm, r0, rp, aq_o, Gb, Pb);
+    site_adjoint(rm, r0, rp, aq_o, Gb, Pb);
     const bool own_plane = p >= z0 && p < z1;
     if (own_plane && active) par_adjoints(P, Pb, v);
     Gb.phi += pp_o;
 #pragma unroll
     for (int k = 0; k < 5; ++k) Gb.q[k] += qp_o[k];
-    put_gb(ogx, ogy, Gb);
-    if (has_ring) {
-      GradBar<R> Gr;
-      ParBar<R> Pr;
-      slot_adjoint(rgx, rgy, rm, r0, rp, aq_r, Gr, Pr);
-      put_gb(rgx, rgy, Gr);
+    sGB[0][tid] = Gb.lapphi;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) sGB[1 + k][tid] = Gb.lapq[k];
+    sGB[6][tid] = Gb.dphi[0];
+    sGB[7][tid] = Gb.dphi[1];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      sGB[8 + k][tid] = Gb.dq[0][k];
+      sGB[13 + k][tid] = Gb.dq[1][k];
+    }
+    if (own_plane) {
+      const int pz = pmod(p, b.nz);
+      const int gy = sGY[ly + 1], gx = sGX[lx + 1];
+      if (send_xp) send(hx, fxs, (size_t(tx) * b.nz + pz) * b.ny + gy, R(1), Gb, 0);
+      if (send_xm) send(hx + fxs, fxs, (size_t(kxm) * b.nz + pz) * b.ny + gy, R(-1), Gb, 0);
+      if (send_yp) send(hy, fys, (size_t(ty) * b.nz + pz) * b.nx + gx, R(1), Gb, 1);
+      if (send_ym) send(hy + fys, fys, (size_t(kym) * b.nz + pz) * b.nx + gx, R(-1), Gb, 1);
     }
     __syncthreads();  // the gradient adjoints of plane p are in place
-    const size_t site = size_t(pmod(p - 1, b.nz)) * plane + ocol;
+    const size_t site = size_t(pmod(p - 1, b.nz)) * plane + col;
     // plane p-1 is complete with the z+ neighbour's terms (this plane)
     if (p - 1 >= z0 && active) {
       adj_phi[site] = acc_p + (Gb.lapphi - R(0.5) * Gb.dphi[2]);
@@ -790,16 +796,20 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
       for (int k = 0; k < 5; ++k) adj_qo[k * N + site] = acc_q[k] + (Gb.lapq[k] - R(0.5) * Gb.dq[2][k]);
     }
     if (own_plane) {
-      // own terms, in-plane transposes, and the z- neighbour's terms (previous plane)
-      const int sx[2] = {ogs + 1, ogs - 1}, sy[2] = {ogs + GX, ogs - GX};
+      // own terms, the z- neighbour's terms (previous plane), and the in-plane
+      // transposes of the neighbours in this tile: lap - d/2 from the + side,
+      // lap + d/2 from the - side
+      auto nbr = [&](int fl, int fd, int s, bool in, R sgn) {
+        return in ? sGB[fl][s] + sgn * R(0.5) * sGB[fd][s] : R(0);
+      };
       acc_p = (Gb.phi - R(6) * Gb.lapphi) + (zp_lapphi + R(0.5) * zp_dphi);
-      acc_p += (sGB[0][sx[0]] + sGB[0][sx[1]]) - R(0.5) * (sGB[6][sx[0]] - sGB[6][sx[1]]);
-      acc_p += (sGB[0][sy[0]] + sGB[0][sy[1]]) - R(0.5) * (sGB[7][sy[0]] - sGB[7][sy[1]]);
+      acc_p += nbr(0, 6, sxp, nxp >= 0, R(-1)) + nbr(0, 6, sxm, nxm >= 0, R(1));
+      acc_p += nbr(0, 7, syp, nyp >= 0, R(-1)) + nbr(0, 7, sym, nym >= 0, R(1));
 #pragma unroll
       for (int k = 0; k < 5; ++k) {
         R a = (Gb.q[k] - R(6) * Gb.lapq[k]) + (zp_lapq[k] + R(0.5) * zp_dq[k]);
-        a += (sGB[1 + k][sx[0]] + sGB[1 + k][sx[1]]) - R(0.5) * (sGB[8 + k][sx[0]] - sGB[8 + k][sx[1]]);
-        a += (sGB[1 + k][sy[0]] + sGB[1 + k][sy[1]]) - R(0.5) * (sGB[13 + k][sy[0]] - sGB[13 + k][sy[1]]);
+        a += nbr(1 + k, 8 + k, sxp, nxp >= 0, R(-1)) + nbr(1 + k, 8 + k, sxm, nxm >= 0, R(1));
+        a += nbr(1 + k, 13 + k, syp, nyp >= 0, R(-1)) + nbr(1 + k, 13 + k, sym, nym >= 0, R(1));
         acc_q[k] = a;
       }
     }
@@ -814,8 +824,7 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
       // plane p-1 is read by no one any more (all passed the barrier above):
       // plane p+2 takes its slot; the site inputs of plane p+1
       fill_plane(p + 2, rm);
-      load_site(p + 1, ocol, aq_o, qp_o, pp_o, true);
-      if (has_ring) load_site(p + 1, rcol, aq_r, dummy5, dummy, false);
+      load_site(p + 1, aq_o, qp_o, pp_o);
     }
     const int t = rm;
     rm = r0;
@@ -823,6 +832,49 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
     rp = t;
   }
   block_reduce_store<2>(v, partial + size_t(blockIdx.x) * 2, accumulate != 0);
+}
+
+// The face terms of k_adj_sg_fused along x: one thread per (field, x tile j,
+// z, y) adds to the first column of tile j the term sent in the + direction
+// across face j-1, and to its last column the term sent in the - direction
+// across face j (one thread does both when the tile is one column wide).
+// Fields 0..5: phi, q[5].
+template <class R>
+__global__ void __launch_bounds__(256) k_adj_face_x(Box b, int TX, int ntx, const R* __restrict__ hx,
+                                                    R* __restrict__ adj_phi, R* __restrict__ adj_q) {
+  const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t nzy = size_t(b.nz) * b.ny, fs = size_t(ntx) * nzy;
+  if (t >= 6 * fs) return;
+  const int f = int(t / fs);
+  const size_t r = t % fs;
+  const int j = int(r / nzy);
+  const size_t zy = r % nzy;
+  const int xa = j * TX, xb = min(xa + TX, b.nx) - 1;
+  R* out = (f == 0 ? adj_phi : adj_q + size_t(f - 1) * b.N) + zy * b.nx;  // row (z, y)
+  const R* hs = hx + size_t(2 * f) * fs;
+  out[xa] += hs[size_t((j + ntx - 1) % ntx) * nzy + zy];
+  out[xb] += hs[fs + size_t(j) * nzy + zy];
+}
+
+// The face terms along y: one thread per (field, y tile i, z, x), as
+// k_adj_face_x with rows for columns.  Launched after k_adj_face_x, so a
+// corner site takes its x terms first.
+template <class R>
+__global__ void __launch_bounds__(256) k_adj_face_y(Box b, int TY, int nty, const R* __restrict__ hy,
+                                                    R* __restrict__ adj_phi, R* __restrict__ adj_q) {
+  const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t nzx = size_t(b.nz) * b.nx, fs = size_t(nty) * nzx;
+  if (t >= 6 * fs) return;
+  const int f = int(t / fs);
+  const size_t r = t % fs;
+  const int i = int(r / nzx);
+  const size_t zx = r % nzx;
+  const int z = int(zx / b.nx), x = int(zx % b.nx);
+  const int ya = i * TY, yb = min(ya + TY, b.ny) - 1;
+  R* out = (f == 0 ? adj_phi : adj_q + size_t(f - 1) * b.N) + size_t(z) * b.ny * b.nx + x;
+  const R* hs = hy + size_t(2 * f) * fs;
+  out[size_t(ya) * b.nx] += hs[size_t((i + nty - 1) % nty) * nzx + zx];
+  out[size_t(yb) * b.nx] += hs[fs + size_t(i) * nzx + zx];
 }
 
 // out = in + 1 for the step counter of a recorded state (one thread, vector memory).

@@ -213,6 +213,8 @@ struct BackendT final : Backend {
   R* aphibp = nullptr;
   R* aFb = nullptr;
   R* agbar = nullptr;
+  R* ahx = nullptr;  // face terms of the fused stress + gather adjoint along x (more than one x tile)
+  R* ahy = nullptr;  // the same along y
   double* apart = nullptr;   // per-block (zeta, q0) adjoint partials, kept across reverse steps
   size_t apart_n = 0;        // doubles in apart
   bool apart_live = false;   // apart holds sums not yet fetched by the caller
@@ -347,7 +349,7 @@ struct BackendT final : Backend {
     pcv = nullptr;
     mu = H = sig = u = nullptr;
     partial = sums = nullptr;
-    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar};
+    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy};
     for (R** a : adj) {
       dfree(*a);
       *a = nullptr;
@@ -731,6 +733,8 @@ struct BackendT final : Backend {
       aphibp = dalloc<R>(N);
       aFb = dalloc<R>(3 * N);
       if (site_path) agbar = dalloc<R>(size_t(lbc::NGB) * N);  // the fused kernel keeps it on chip
+      if (!site_path && as_ntx > 1) ahx = dalloc<R>(12 * size_t(as_ntx) * box.nz * box.ny);
+      if (!site_path && as_nty > 1) ahy = dalloc<R>(12 * size_t(as_nty) * box.nz * box.nx);
       // one (zeta, q0) pair per block of whichever reverse kernel writes them
       const size_t npart = size_t(std::max<int>(int(nblk), as_blocks)) * 2;
       apart = dalloc<double>(npart);
@@ -738,7 +742,7 @@ struct BackendT final : Backend {
       HIPCHECK(hipMemsetAsync(apart, 0, npart * sizeof(double), stream));
       apart_live = false;
     } catch (...) {
-      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar};
+      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy};
       for (R** a : adj) {
         dfree(*a);
         *a = nullptr;
@@ -749,7 +753,8 @@ struct BackendT final : Backend {
     }
   }
   // record buffer: u [3][N] and F [3][N] of the step that leaves the state
-  size_t record_bytes() const override { return has_adjoint() ? 6 * N * sizeof(R) : 0; }
+  // step record: u [3][N], F [3][N] and drho [N] of the step that leaves the state
+  size_t record_bytes() const override { return has_adjoint() ? 7 * N * sizeof(R) : 0; }
   struct StateView {
     const GS* B;
     const FS* q;
@@ -761,8 +766,8 @@ struct BackendT final : Backend {
     return StateView{reinterpret_cast<const GS*>(c), reinterpret_cast<const FS*>(c + off_q()),
                      reinterpret_cast<const FS*>(c + off_phi()), reinterpret_cast<const int64_t*>(c + off_step())};
   }
-  // One forward step from a state buffer into another, recording u and F of
-  // the input time (the replay of a checkpoint segment for the adjoint).
+  // One forward step from a state buffer into another, recording u, F and
+  // drho of the input time (the replay of a checkpoint segment for the adjoint).
   void step_record(const void* state_in, void* state_out, void* rec_out) override {
     need_adjoint();
     const StateView vi = view(state_in);
@@ -772,14 +777,15 @@ struct BackendT final : Backend {
     FS* po = reinterpret_cast<FS*>(co + off_phi());
     R* ru = static_cast<R*>(rec_out);
     R* rF = ru + 3 * N;
+    R* rd = ru + 6 * N;
     if (site_path) {
       ensure_thermo();
       lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, vi.phi, vi.q, mu, H, sig);
-      lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, vi.B, sig, rF, ru, nullptr);
+      lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, vi.B, sig, rF, ru, rd);
       lbc::k_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, vi.B, Bo, sig, ru);
       lbc::k_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, vi.phi, vi.q, ru, H, mu, po, qo);
     } else {
-      fused_step(Io{vi.B, Bo, vi.phi, vi.q, po, qo, ru, rF, nullptr});
+      fused_step(Io{vi.B, Bo, vi.phi, vi.q, po, qo, ru, rF, rd});
     }
     lbc::k_step_count<<<1, 64, 0, stream>>>(vi.step, reinterpret_cast<int64_t*>(co + off_step()));
     check_launch();
@@ -853,8 +859,16 @@ struct BackendT final : Backend {
       lbc::k_adj_gather<R><<<nblk, TPB, 0, stream>>>(box, agbar, po, qo);
     } else {
       lbc::k_adj_sg_fused<R, FS, kAsTX, kAsTY><<<as_blocks, kAsTX * kAsTY, 0, stream>>>(
-          box, P, as_tz, as_ntx, as_nty, phi_t, q_t, aFb, qi, amub, aqbp, aphibp, po, qo, apart,
+          box, P, as_tz, as_ntx, as_nty, phi_t, q_t, aFb, qi, amub, aqbp, aphibp, po, qo, ahx, ahy, apart,
           apart_live ? 1 : 0);
+      if (as_ntx > 1) {
+        const size_t n = 6 * size_t(as_ntx) * box.nz * box.ny;  // one thread per field
+        lbc::k_adj_face_x<R><<<unsigned((n + TPB - 1) / TPB), TPB, 0, stream>>>(box, kAsTX, as_ntx, ahx, po, qo);
+      }
+      if (as_nty > 1) {
+        const size_t n = 6 * size_t(as_nty) * box.nz * box.nx;  // one thread per field
+        lbc::k_adj_face_y<R><<<unsigned((n + TPB - 1) / TPB), TPB, 0, stream>>>(box, kAsTY, as_nty, ahy, po, qo);
+      }
     }
     apart_live = true;
     check_launch();
@@ -873,19 +887,16 @@ struct BackendT final : Backend {
     need_adjoint();
     ensure_adjoint();
     const StateView v = view(state);
-    const R* uu;
-    const R* FF;
-    if (rec) {
-      uu = static_cast<const R*>(rec);
-      FF = uu + 3 * N;
-    } else {  // recompute u and F of time t
-      ensure_thermo();
-      lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, mu, H, sig);
-      lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, v.B, sig, aF, u, nullptr);
-      uu = u;
-      FF = aF;
+    if (rec) {  // the collision adjoint reads the recorded drho and u, not the populations
+      const R* uu = static_cast<const R*>(rec);
+      reverse_kernels(v.phi, v.q, uu, uu + 3 * N, nullptr, uu + 6 * N, adj_in, adj_out, zeta_bar, q0_bar);
+      return;
     }
-    reverse_kernels(v.phi, v.q, uu, FF, v.B, nullptr, adj_in, adj_out, zeta_bar, q0_bar);
+    // recompute u and F of time t
+    ensure_thermo();
+    lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, mu, H, sig);
+    lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, v.B, sig, aF, u, nullptr);
+    reverse_kernels(v.phi, v.q, u, aF, v.B, nullptr, adj_in, adj_out, zeta_bar, q0_bar);
   }
   double seed_centre(double z_ref, void* adj) override {
     need_adjoint();

@@ -204,9 +204,10 @@ def test_parameter_sums_kept_on_device_between_fetches():
 
 
 def test_recorded_rollout_equals_checkpointed():
-    """checkpoint = 0 keeps every state and step record instead of replaying
-    segments; the reverse pass sees the same states and records, so the
-    gradients agree to float64 rounding (only the device-sum order differs)."""
+    """checkpoint = 0 keeps the lean record of every step instead of replaying
+    segments.  The reverse collision then takes u and rho - rho0 from the
+    forward kernel's record rather than recomputing them from the populations,
+    so the gradients agree to float64 rounding, not bit for bit."""
     p = _p(q0=2 * math.pi / 8, zeta=0.02)
     phi, q5 = inputs.droplet_fields(8, 8, 10, 2.5, p["q0"], seed=3)
     grads = []
@@ -219,18 +220,23 @@ def test_recorded_rollout_equals_checkpointed():
         grads.append((float(L.detach()), float(zeta.grad), float(q0.grad), q5t.grad.numpy()))
     (L1, z1, c1, g1), (L2, z2, c2, g2) = grads
     assert L1 == L2
-    assert abs(z1 - z2) <= 1e-13 * abs(z1) and abs(c1 - c2) <= 1e-13 * abs(c1)
-    assert np.array_equal(g1, g2)
+    assert abs(z1 - z2) <= 1e-12 * abs(z1) and abs(c1 - c2) <= 1e-12 * abs(c1)
+    l2, mx = rel_err(g2, g1)
+    assert l2 < 1e-12 and mx < 1e-12, (l2, mx)
 
 
+@pytest.mark.parametrize("shape", [(34, 18, 11), (33, 9, 5), (12, 6, 7)])
 @pytest.mark.parametrize("tz", ["1", "3", "default"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
-def test_adjoint_site_and_tiled_kernels_agree(monkeypatch, prec, tol, tz):
+def test_adjoint_site_and_tiled_kernels_agree(monkeypatch, prec, tol, tz, shape):
     """The site-parallel and the z-marching tiled reverse kernels (the order kernel
-    and the fused stress + gather kernel) give the same reverse step, for several
-    slab depths (ragged tiles and slabs: a 34 x 18 x 11 box)."""
+    and the fused stress + gather kernel with its tile-face terms) give the same
+    reverse step, for several slab depths.  Boxes: ragged tiles and slabs
+    (34 x 18 x 11); edge tiles one column and one row wide, whose sites send
+    across both faces of an axis (33 x 9 x 5); one tile smaller than the tile
+    shape, which wraps periodically inside itself (12 x 6 x 7)."""
     p = _p(q0=2 * math.pi / 9, zeta=0.01)
-    g, phi, q5 = inputs.random_fields(34, 18, 11, seed=21, g_amp=2e-3, q_amp=0.2)
+    g, phi, q5 = inputs.random_fields(*shape, seed=21, g_amp=2e-3, q_amp=0.2)
     seed_vals = np.random.default_rng(4).normal(size=25 * phi.size)
     if tz == "default":
         monkeypatch.delenv("LBC_TZ_ADJ", raising=False)
@@ -256,7 +262,7 @@ def test_adjoint_site_and_tiled_kernels_agree(monkeypatch, prec, tol, tz):
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
 def test_lean_reverse_step_equals_full_state_step(prec, tol):
     """The reverse of a step from its lean record (Q, phi, drho, u, F) equals the reverse
-    from the full state and its u, F record (the populations enter only through drho, u)."""
+    from the full state and its u, F, drho record (the populations enter only through drho, u)."""
     p = _p(q0=2 * math.pi / 7, zeta=0.01)
     g, phi, q5 = inputs.random_fields(9, 8, 6, seed=41, g_amp=2e-3, q_amp=0.2)
     seed_vals = np.random.default_rng(6).normal(size=25 * phi.size)
