@@ -609,7 +609,11 @@ k_adj_gather(Box b, const R* __restrict__ gbar, R* __restrict__ adj_phi, R* __re
 // Face buffers: hx[f][side][k][z][y] for the face between x tiles k and k+1
 // (mod ntx), hy[f][side][k][z][x] for y tiles; side 0 is the term sent in the
 // + direction, side 1 the term sent in the - direction; f = phi, q[5].  They
-// are written only when the box has more than one tile along that axis.
+// are written only when the box has more than one tile along that axis.  hx
+// has two more sides: the adjoint of the first (2) and last (3) column of
+// tile k without its face terms.  Those columns are left out of adj_phi and
+// adj_qo here, and k_adj_face_x writes them whole (a plain store instead of
+// a read-modify-write of every cache line that holds a tile edge).
 // The (zeta, q0) partials count owned sites only.
 // ---------------------------------------------------------------------------
 template <class R, class FS, int TX, int TY>
@@ -684,6 +688,7 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
   const bool send_xp = active && ntx > 1 && lx == w - 1, send_xm = active && ntx > 1 && lx == 0;
   const bool send_yp = active && nty > 1 && ly == h - 1, send_ym = active && nty > 1 && ly == 0;
   const size_t fxs = size_t(ntx) * b.nz * b.ny, fys = size_t(nty) * b.nz * b.nx;  // one field-side block
+  const bool xedge = active && ntx > 1 && (lx == 0 || lx == w - 1);  // adjoint goes to hx side 2 / 3
   const int kxm = (tx + ntx - 1) % ntx, kym = (ty + nty - 1) % nty;
 
   const int f0 = (ly + 1) * IX + (lx + 1);
@@ -737,10 +742,11 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
     pp = phibp[k];
   };
   // the term a site sends across a face: lap + (sgn/2) d, for phi and q[5]
-  auto send = [&](R* __restrict__ buf, size_t fs, size_t off, R sgn, const GradBar<R>& Gb, int g) {
+  // (fields fstride apart)
+  auto send = [&](R* __restrict__ buf, size_t fstride, size_t off, R sgn, const GradBar<R>& Gb, int g) {
     buf[off] = Gb.lapphi + sgn * R(0.5) * Gb.dphi[g];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) buf[size_t(2 * (1 + k)) * fs + off] = Gb.lapq[k] + sgn * R(0.5) * Gb.dq[g][k];
+    for (int k = 0; k < 5; ++k) buf[size_t(1 + k) * fstride + off] = Gb.lapq[k] + sgn * R(0.5) * Gb.dq[g][k];
   };
 
   // planes z0-2 .. z0 into the ring, the site inputs of plane z0-1 into registers
@@ -782,18 +788,27 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
     if (own_plane) {
       const int pz = pmod(p, b.nz);
       const int gy = sGY[ly + 1], gx = sGX[lx + 1];
-      if (send_xp) send(hx, fxs, (size_t(tx) * b.nz + pz) * b.ny + gy, R(1), Gb, 0);
-      if (send_xm) send(hx + fxs, fxs, (size_t(kxm) * b.nz + pz) * b.ny + gy, R(-1), Gb, 0);
-      if (send_yp) send(hy, fys, (size_t(ty) * b.nz + pz) * b.nx + gx, R(1), Gb, 1);
-      if (send_ym) send(hy + fys, fys, (size_t(kym) * b.nz + pz) * b.nx + gx, R(-1), Gb, 1);
+      if (send_xp) send(hx, 4 * fxs, (size_t(tx) * b.nz + pz) * b.ny + gy, R(1), Gb, 0);
+      if (send_xm) send(hx + fxs, 4 * fxs, (size_t(kxm) * b.nz + pz) * b.ny + gy, R(-1), Gb, 0);
+      if (send_yp) send(hy, 2 * fys, (size_t(ty) * b.nz + pz) * b.nx + gx, R(1), Gb, 1);
+      if (send_ym) send(hy + fys, 2 * fys, (size_t(kym) * b.nz + pz) * b.nx + gx, R(-1), Gb, 1);
     }
     __syncthreads();  // the gradient adjoints of plane p are in place
     const size_t site = size_t(pmod(p - 1, b.nz)) * plane + col;
     // plane p-1 is complete with the z+ neighbour's terms (this plane)
     if (p - 1 >= z0 && active) {
-      adj_phi[site] = acc_p + (Gb.lapphi - R(0.5) * Gb.dphi[2]);
+      R* op = adj_phi;
+      R* oq = adj_qo;
+      size_t off = site, qs = N;
+      if (xedge) {  // a tile-edge column: its adjoint without the face terms goes to hx
+        op = hx + (lx == 0 ? 2 : 3) * fxs;
+        oq = op + 4 * fxs;
+        qs = 4 * fxs;
+        off = (size_t(tx) * b.nz + pmod(p - 1, b.nz)) * b.ny + sGY[ly + 1];
+      }
+      op[off] = acc_p + (Gb.lapphi - R(0.5) * Gb.dphi[2]);
 #pragma unroll
-      for (int k = 0; k < 5; ++k) adj_qo[k * N + site] = acc_q[k] + (Gb.lapq[k] - R(0.5) * Gb.dq[2][k]);
+      for (int k = 0; k < 5; ++k) oq[k * qs + off] = acc_q[k] + (Gb.lapq[k] - R(0.5) * Gb.dq[2][k]);
     }
     if (own_plane) {
       // own terms, the z- neighbour's terms (previous plane), and the in-plane
@@ -835,10 +850,10 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
 }
 
 // The face terms of k_adj_sg_fused along x: one thread per (field, x tile j,
-// z, y) adds to the first column of tile j the term sent in the + direction
-// across face j-1, and to its last column the term sent in the - direction
-// across face j (one thread does both when the tile is one column wide).
-// Fields 0..5: phi, q[5].
+// z, y) writes the first column of tile j (its adjoint without face terms,
+// plus the term sent in the + direction across face j-1) and the last column
+// (the same, with the term sent in the - direction across face j); one thread
+// writes both terms when the tile is one column wide.  Fields 0..5: phi, q[5].
 template <class R>
 __global__ void __launch_bounds__(256) k_adj_face_x(Box b, int TX, int ntx, const R* __restrict__ hx,
                                                     R* __restrict__ adj_phi, R* __restrict__ adj_q) {
@@ -851,9 +866,12 @@ __global__ void __launch_bounds__(256) k_adj_face_x(Box b, int TX, int ntx, cons
   const size_t zy = r % nzy;
   const int xa = j * TX, xb = min(xa + TX, b.nx) - 1;
   R* out = (f == 0 ? adj_phi : adj_q + size_t(f - 1) * b.N) + zy * b.nx;  // row (z, y)
-  const R* hs = hx + size_t(2 * f) * fs;
-  out[xa] += hs[size_t((j + ntx - 1) % ntx) * nzy + zy];
-  out[xb] += hs[fs + size_t(j) * nzy + zy];
+  const R* hs = hx + size_t(4 * f) * fs;
+  const size_t own = size_t(j) * nzy + zy;
+  R va = hs[2 * fs + own] + hs[size_t((j + ntx - 1) % ntx) * nzy + zy];
+  if (xb == xa) va += hs[fs + own];
+  out[xa] = va;
+  if (xb != xa) out[xb] = hs[3 * fs + own] + hs[fs + own];
 }
 
 // The face terms along y: one thread per (field, y tile i, z, x), as
@@ -873,7 +891,7 @@ __global__ void __launch_bounds__(256) k_adj_face_y(Box b, int TY, int nty, cons
   const int ya = i * TY, yb = min(ya + TY, b.ny) - 1;
   R* out = (f == 0 ? adj_phi : adj_q + size_t(f - 1) * b.N) + size_t(z) * b.ny * b.nx + x;
   const R* hs = hy + size_t(2 * f) * fs;
-  out[size_t(ya) * b.nx] += hs[size_t((i + nty - 1) % nty) * nzx + zx];
+  out[size_t(ya) * b.nx] += hs[size_t((i + nty - 1) % nty) * nzx + zx];  // after k_adj_face_x
   out[size_t(yb) * b.nx] += hs[fs + size_t(i) * nzx + zx];
 }
 

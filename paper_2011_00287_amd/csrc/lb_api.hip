@@ -213,7 +213,7 @@ struct BackendT final : Backend {
   R* aphibp = nullptr;
   R* aFb = nullptr;
   R* agbar = nullptr;
-  R* ahx = nullptr;  // face terms of the fused stress + gather adjoint along x (more than one x tile)
+  R* ahx = nullptr;  // face terms and edge-column adjoints of the fused stress + gather adjoint (x tiles > 1)
   R* ahy = nullptr;  // the same along y
   double* apart = nullptr;   // per-block (zeta, q0) adjoint partials, kept across reverse steps
   size_t apart_n = 0;        // doubles in apart
@@ -733,7 +733,7 @@ struct BackendT final : Backend {
       aphibp = dalloc<R>(N);
       aFb = dalloc<R>(3 * N);
       if (site_path) agbar = dalloc<R>(size_t(lbc::NGB) * N);  // the fused kernel keeps it on chip
-      if (!site_path && as_ntx > 1) ahx = dalloc<R>(12 * size_t(as_ntx) * box.nz * box.ny);
+      if (!site_path && as_ntx > 1) ahx = dalloc<R>(24 * size_t(as_ntx) * box.nz * box.ny);
       if (!site_path && as_nty > 1) ahy = dalloc<R>(12 * size_t(as_nty) * box.nz * box.nx);
       // one (zeta, q0) pair per block of whichever reverse kernel writes them
       const size_t npart = size_t(std::max<int>(int(nblk), as_blocks)) * 2;
