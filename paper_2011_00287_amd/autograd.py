@@ -5,7 +5,7 @@ on the GPU and returns L = (z_c(T) - z_c(0))^2, the squared displacement along
 z of the phi-weighted droplet centre.  Its backward runs the hand-written
 adjoint of the step in reverse.  With checkpoint = k the forward pass keeps a
 state every k steps and the reverse pass replays each segment with recording
-steps (state buffers and u, F records) before reversing it; with checkpoint = 0
+steps (state buffers and u, F, drho records) before reversing it; with checkpoint = 0
 the forward pass keeps the lean record of every step (Q, phi of each time and
 drho, u, F of its step: all the reverse of a step reads, about 52 B per site
 in float32) and the reverse pass replays nothing.  Gradients: dL/dzeta, dL/dq0
@@ -67,7 +67,7 @@ def backward_segments(sim: Sim, ckpts, steps: int, checkpoint: int, adj):
 
     adj holds the adjoint of the final state on entry and the adjoint of the
     initial state on return.  Each segment is replayed from its checkpoint with
-    recording steps (state buffers and u, F records), then reversed step by
+    recording steps (state buffers and u, F, drho records), then reversed step by
     step.  Returns (zeta_bar, q0_bar)."""
     zb = qb = 0.0
     states = [None] * (checkpoint + 1)
