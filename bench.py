@@ -98,7 +98,7 @@ def time_precision(prec, p, phi, q5, steps, warmup, stream, lattice="d3q19", fd_
     return sim, dt
 
 
-def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True):
+def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True, lattice="d3q19", alternatives=True):
     """(reverse pass incl. any segment replay) / (plain forward) over the same steps.
 
     Modes (lean records hold Q, phi, drho, u, F per step; full-state records hold
@@ -113,7 +113,7 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True):
                                                backward_segments_lean, backward_segments_overlapped, run_lean,
                                                run_recorded, run_segments)
     from paper_2011_00287_amd.sim import Sim
-    sim = Sim(p, phi, q5, precision=prec, stream=stream)
+    sim = Sim(p, phi, q5, precision=prec, stream=stream, lattice=lattice)
     s0 = sim.get_state()
     sim.step(3)
     sim.set_state(s0)
@@ -140,13 +140,22 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True):
     ck, t_fwd_ck, t_bwd = run_mode(lambda: run_segments(sim, steps, checkpoint),
                                    lambda h, a: backward_segments(sim, h, steps, checkpoint, a))
     del ck
-    out = {"steps": steps, "checkpoint": checkpoint, "precision": prec, "forward_ms": t_fwd * 1e3,
-           "forward_with_checkpoints_ms": t_fwd_ck * 1e3, "backward_ms": t_bwd * 1e3,
+    out = {"steps": steps, "checkpoint": checkpoint, "precision": prec, "lattice": lattice.upper(),
+           "forward_ms": t_fwd * 1e3, "forward_with_checkpoints_ms": t_fwd_ck * 1e3, "backward_ms": t_bwd * 1e3,
            "adjoint_over_forward": t_bwd / t_fwd, "total_over_forward": (t_fwd_ck + t_bwd) / t_fwd}
+    if not alternatives:
+        if recorded:
+            recs, t_fwd_rec, t_bwd_rec = run_mode(lambda: run_lean(sim, steps),
+                                                  lambda h, a: backward_lean(sim, h, a))
+            del recs
+            out["recorded"] = {"adjoint_over_forward": t_bwd_rec / t_fwd,
+                               "total_over_forward": (t_fwd_rec + t_bwd_rec) / t_fwd}
+        sim.close()
+        return out
     # the same sweep with the replay of segment s-1 on a second context and stream
     # while segment s is reversed (the replay context exists before the timed region)
     replay_stream = torch.cuda.Stream()
-    rep = Sim(p, phi, q5, precision=prec, stream=replay_stream)
+    rep = Sim(p, phi, q5, precision=prec, stream=replay_stream, lattice=lattice)
     ck, _, t_bwd_ov = run_mode(lambda: run_segments(sim, steps, checkpoint),
                                lambda h, a: backward_segments_overlapped(sim, rep, h, steps, checkpoint, a,
                                                                          replay_stream))
@@ -309,7 +318,7 @@ def main():
     ap.add_argument("--workload", default="droplet128")
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16s"])
     ap.add_argument("--lattice", default="d3q19", choices=["d3q19", "d3q15"],
-                    help="d3q19: stress as a body force; d3q15: the paper's scheme (forward only)")
+                    help="d3q19: stress as a body force; d3q15: the paper's scheme")
     ap.add_argument("--fd-scheme", default="euler2", choices=["euler2", "pc4"],
                     help="euler2: explicit Euler, 2nd-order stencils; pc4: the paper's predictor-corrector, "
                          f"upwind, 4th-order stencils (forward only, M = {PC4_M})")
@@ -378,6 +387,16 @@ def main():
             side[key] = {"mlups": n * ns / dt2 / 1e6, "ms_per_step": dt2 / ns * 1e3,
                          "step_hbm_frac": n * ns / dt2 * step_bytes(prec, lat) / (HBM_PEAK_GBS * 1e9)}
             print(f"# {key}: {side[key]['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
+        if args.adjoint_steps > 0 and args.lattice == "d3q19" and args.fd_scheme == "euler2":
+            # the adjoint of the paper's own LB scheme, checkpointed and recorded modes
+            a15 = time_adjoint("fp32", p, phi, q5, args.adjoint_steps, args.adjoint_checkpoint, stream,
+                               lattice="d3q15", alternatives=False)
+            side["d3q15_fp32_adjoint"] = {"adjoint_over_forward": a15["adjoint_over_forward"],
+                                          "recorded_adjoint_over_forward": a15["recorded"]["adjoint_over_forward"],
+                                          "checkpoint": args.adjoint_checkpoint, "steps": args.adjoint_steps}
+            print(f"# d3q15_fp32 adjoint/forward: {a15['adjoint_over_forward']:.2f} (checkpoint "
+                  f"{args.adjoint_checkpoint}), {a15['recorded']['adjoint_over_forward']:.2f} (every step recorded)",
+                  file=sys.stderr, flush=True)
         s2, dt2 = time_2d("nematic512", "fp32", 2000, 50)  # the 2D workload of Fig. 3 (512^2)
         n2d = s2.n_sites
         s2.close()
@@ -386,9 +405,9 @@ def main():
         print(f"# nematic512_fp32: {side['nematic512_fp32']['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
 
     adjoint = None
-    if args.adjoint_steps > 0 and args.lattice == "d3q19" and args.fd_scheme == "euler2":
+    if args.adjoint_steps > 0 and args.fd_scheme == "euler2":
         adjoint = time_adjoint(args.precision, p, phi, q5, args.adjoint_steps, args.adjoint_checkpoint, stream,
-                               recorded=not args.no_adjoint_recorded)
+                               recorded=not args.no_adjoint_recorded, lattice=args.lattice)
         print(f"# adjoint/forward: {adjoint['adjoint_over_forward']:.2f} (checkpoint {args.adjoint_checkpoint}; "
               f"{adjoint['overlapped']['adjoint_over_forward']:.2f} with the replay overlapped)"
               + (f", {adjoint['recorded']['adjoint_over_forward']:.2f} (every step recorded, "

@@ -179,10 +179,15 @@ lb_status lb_set_state(lb_ctx* c, const void* dev_src, size_t bytes);
  *
  * The adjoint of a state is a device buffer of lb_adjoint_bytes() bytes in the
  * context's arithmetic type (double for LB_FP64, float otherwise), laid out
- * as g_bar [19][N] (adjoint of the post-stream population deviations),
- * q_bar [5][N] (adjoint of the 5 stored Q components) and phi_bar [N].
- * The caller owns it (e.g. a torch tensor on the context's device).
- * The adjoint is implemented for LB_D3Q19 with LB_FD_EULER2: otherwise
+ * as g_bar [Q][N] (adjoint of the post-stream population deviations; Q = 19
+ * for LB_D3Q19, 15 for LB_D3Q15), q_bar [5][N] (adjoint of the 5 stored Q
+ * components) and phi_bar [N].  The caller owns it (e.g. a torch tensor on
+ * the context's device).  On LB_D3Q15 the reverse of the collision also
+ * carries the adjoint of the symmetric stress in the equilibrium (Eq. (9))
+ * into the stress; the force is the divergence of the antisymmetric part only
+ * (Eq. (10)).
+ * The adjoint is implemented for LB_FD_EULER2: with LB_FD_PC4 (and for
+ * LB_D3Q15 when the library runs its site-parallel test kernels)
  * lb_adjoint_bytes, lb_record_bytes and lb_lean_record_bytes return 0 and the
  * calls below return LB_EINVAL.
  * ------------------------------------------------------------------------- */

@@ -566,4 +566,93 @@ __host__ __device__ __forceinline__ void collide_site_bwd(const Params<R>& P, co
   collide_site_bwd_m(P, drho, u, F, gsb, ub_in, gb, Fb);
 }
 
+// Reverse of collide_site_eq (the paper's D3Q15 scheme with the symmetric
+// stress S in the equilibrium) from the moments drho and u:
+//   g*_i = om1 g_i + w_i [om (drho - 1.5 trT + 3 rho cu_i + 4.5 c.T.c) + guo (-3 uF + 3 cF_i + 9 cu_i cF_i)],
+//   T = rho u u - S.
+// The collision is linear in S with constant coefficients, so its adjoint
+// Sb[6] (xx, xy, xz, yy, yz, zz, stored components) needs no forward value of
+// S.  gsb, ub_in: adjoints of the post-collision populations and of the
+// velocity output; gb gets the pre-collision adjoints, Fb and Sb accumulate.
+template <class R>
+__host__ __device__ __forceinline__ void collide_eq_site_bwd_m(const Params<R>& P, R drho, const R u[3],
+                                                               const R F[3], const R gsb[15], const R ub_in[3],
+                                                               R gb[15], R Fb[3], R Sb[6]) {
+  using L = D3Q15;
+  const R rho = P.rho0 + drho;
+  const R inv = R(1) / rho;
+  const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const R om = P.omega, om1 = R(1) - P.omega;
+  // with c.T.c = rho cu^2 - c.S.c and trT = rho uu - trS:
+  // g*_i = om1 g_i + w_i [om (drho - 1.5 rho uu + 1.5 trS + 3 rho cu + 4.5 rho cu^2 - 4.5 c.S.c) + guo (...)]
+  R Ab = R(0), Bsb = R(0), rhob = R(0);
+  R ub[3] = {ub_in[0], ub_in[1], ub_in[2]};
+  for (int i = 0; i < 15; ++i) {
+    const R cx = R(L::cx(i)), cy = R(L::cy(i)), cz = R(L::cz(i));
+    const R cu = cx * u[0] + cy * u[1] + cz * u[2];
+    const R cF = cx * F[0] + cy * F[1] + cz * F[2];
+    const R e = L::w<R>(i) * gsb[i];
+    gb[i] = om1 * gsb[i];
+    Ab += om * e;
+    Bsb += P.guo * e;
+    rhob += om * e * (R(3) * cu + R(4.5) * cu * cu);
+    const R cub = e * (om * (R(3) * rho + R(9) * rho * cu) + P.guo * R(9) * cF);
+    const R cFb = e * P.guo * (R(3) + R(9) * cu);
+    ub[0] += cub * cx;
+    ub[1] += cub * cy;
+    ub[2] += cub * cz;
+    Fb[0] += cFb * cx;
+    Fb[1] += cFb * cy;
+    Fb[2] += cFb * cz;
+    // -4.5 om c.S.c, with c.S.c = cx^2 Sxx + cy^2 Syy + cz^2 Szz + 2 (cx cy Sxy + cx cz Sxz + cy cz Syz)
+    const R es = R(-4.5) * om * e;
+    Sb[0] += es * cx * cx;
+    Sb[1] += R(2) * es * cx * cy;
+    Sb[2] += R(2) * es * cx * cz;
+    Sb[3] += es * cy * cy;
+    Sb[4] += R(2) * es * cy * cz;
+    Sb[5] += es * cz * cz;
+  }
+  // +1.5 om trS, summed over i through Ab = om sum w_i gsb_i
+  Sb[0] += R(1.5) * Ab;
+  Sb[3] += R(1.5) * Ab;
+  Sb[5] += R(1.5) * Ab;
+  R drhob = Ab;
+  rhob += R(-1.5) * uu * Ab;
+  const R uub = R(-1.5) * rho * Ab;
+  const R uFb = R(-3) * Bsb;
+  for (int a = 0; a < 3; ++a) {
+    ub[a] += R(2) * u[a] * uub + F[a] * uFb;
+    Fb[a] += u[a] * uFb;
+  }
+  // u = (j + F/2) / rho
+  R jb[3];
+  for (int a = 0; a < 3; ++a) {
+    jb[a] = ub[a] * inv;
+    Fb[a] += R(0.5) * ub[a] * inv;
+    rhob -= ub[a] * u[a] * inv;
+  }
+  drhob += rhob;
+  for (int i = 0; i < 15; ++i) gb[i] += drhob + R(L::cx(i)) * jb[0] + R(L::cy(i)) * jb[1] + R(L::cz(i)) * jb[2];
+}
+
+// Reverse of collide_site_eq from the pre-collision populations g[15].
+template <class R>
+__host__ __device__ __forceinline__ void collide_eq_site_bwd(const Params<R>& P, const R g[15], const R F[3],
+                                                             const R gsb[15], const R ub_in[3], R gb[15], R Fb[3],
+                                                             R Sb[6]) {
+  using L = D3Q15;
+  R drho = R(0), j[3] = {R(0), R(0), R(0)};
+  for (int i = 0; i < 15; ++i) {
+    drho += g[i];
+    j[0] += R(L::cx(i)) * g[i];
+    j[1] += R(L::cy(i)) * g[i];
+    j[2] += R(L::cz(i)) * g[i];
+  }
+  const R inv = R(1) / (P.rho0 + drho);
+  R u[3];
+  for (int a = 0; a < 3; ++a) u[a] = (j[a] + R(0.5) * F[a]) * inv;
+  collide_eq_site_bwd_m(P, drho, u, F, gsb, ub_in, gb, Fb, Sb);
+}
+
 }  // namespace lbc

@@ -27,9 +27,10 @@
 
 namespace lbc {
 
-// Forward force F = div(sigma) + body force, u = (j + F/2)/rho and (when
-// drho_out is not null) drho = sum g at time t.
-template <class R, class GS>
+// Forward force F = div(sigma) + body force (div of the antisymmetric part
+// on the D3Q15 scheme), u = (j + F/2)/rho and (when drho_out is not null)
+// drho = sum g at time t.
+template <class R, class GS, class L>
 __global__ void __launch_bounds__(256) k_fwd_force(Box b, Params<R> P, const GS* __restrict__ B,
                                                    const R* __restrict__ sig, R* __restrict__ F_out,
                                                    R* __restrict__ u_out, R* __restrict__ drho_out) {
@@ -39,15 +40,15 @@ __global__ void __launch_bounds__(256) k_fwd_force(Box b, Params<R> P, const GS*
   coords(b, s, x, y, z);
   const size_t N = b.N;
   R F[3];
-  force_at<D3Q19>(b, P, sig, x, y, z, F);
+  force_at<L>(b, P, sig, x, y, z, F);
   R sum = R(0), j[3] = {R(0), R(0), R(0)};
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    const R gi = GPol<GS>::template ld<R>(B, i * N + sidx(b, x - CX(i), y - CY(i), z - CZ(i)), i);
+  for (int i = 0; i < L::Q; ++i) {
+    const R gi = GPol<GS>::template ld<R>(B, i * N + sidx(b, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i);
     sum += gi;
-    j[0] += R(CX(i)) * gi;
-    j[1] += R(CY(i)) * gi;
-    j[2] += R(CZ(i)) * gi;
+    j[0] += R(L::cx(i)) * gi;
+    j[1] += R(L::cy(i)) * gi;
+    j[2] += R(L::cz(i)) * gi;
   }
   const R rho = P.rho0 + sum;
 #pragma unroll
@@ -295,20 +296,12 @@ k_adj_order_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __rest
   }
 }
 
-// Reverse of the collision and the pull stream at one site.
-template <class R, class GS>
-__global__ void __launch_bounds__(256) k_adj_collide(Box b, Params<R> P, const GS* __restrict__ B,
-                                                     const R* __restrict__ F, const R* __restrict__ Wb,
-                                                     const R* __restrict__ ubp, const R* __restrict__ adj_g,
-                                                     R* __restrict__ g_out, R* __restrict__ Fb_out) {
-  const int s = site_xcd();
-  if (s >= b.N) return;
-  int x, y, z;
-  coords(b, s, x, y, z);
+// u_bar = u_bar partial - sum_b D0_b W_bar_ab  (W_ab = D0_b u_a) at site (x, y, z)
+template <class R>
+__device__ __forceinline__ void ubar_at(const Box& b, const R* __restrict__ Wb, const R* __restrict__ ubp, int s,
+                                        int x, int y, int z, R ub[3]) {
   const size_t N = b.N;
   const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
-  // u_bar = partial - sum_b D0_b W_bar_ab   (W_ab = D0_b u_a)
-  R ub[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) ub[a] = ubp[a * N + s];
 #pragma unroll
@@ -318,66 +311,103 @@ __global__ void __launch_bounds__(256) k_adj_collide(Box b, Params<R> P, const G
 #pragma unroll
     for (int a = 0; a < 3; ++a) ub[a] -= R(0.5) * (Wb[(a * 3 + c) * N + sp] - Wb[(a * 3 + c) * N + sm]);
   }
-  R g[19], gsb[19], Fs[3];
+}
+
+// The collision reverse of one site on lattice L from its moments; on the
+// D3Q15 scheme it also writes the adjoint of the symmetric stress (Sb_out,
+// 6 stored components), which enters that collision.
+template <class R, class L>
+__device__ __forceinline__ void collide_bwd_site_l(const Params<R>& P, R drho, const R u[3], const R F[3],
+                                                   const R gsb[L::Q], const R ub[3], R gb[L::Q], R Fb[3],
+                                                   R* __restrict__ Sb_out, size_t N, int s) {
+  if constexpr (L::kStressInEq) {
+    R Sb[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    collide_eq_site_bwd_m(P, drho, u, F, gsb, ub, gb, Fb, Sb);
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
+    for (int k = 0; k < 6; ++k) Sb_out[k * N + s] = Sb[k];
+  } else {
+    collide_site_bwd_m(P, drho, u, F, gsb, ub, gb, Fb);
+  }
+}
+
+// Reverse of the collision and the pull stream at one site (the moments are
+// formed from the pulled populations B).
+template <class R, class GS, class L>
+__global__ void __launch_bounds__(256) k_adj_collide(Box b, Params<R> P, const GS* __restrict__ B,
+                                                     const R* __restrict__ F, const R* __restrict__ Wb,
+                                                     const R* __restrict__ ubp, const R* __restrict__ adj_g,
+                                                     R* __restrict__ g_out, R* __restrict__ Fb_out,
+                                                     R* __restrict__ Sb_out) {
+  const int s = site_xcd();
+  if (s >= b.N) return;
+  int x, y, z;
+  coords(b, s, x, y, z);
+  const size_t N = b.N;
+  R ub[3];
+  ubar_at(b, Wb, ubp, s, x, y, z, ub);
+  R g[L::Q], gsb[L::Q], Fs[3];
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
     // pulled populations and pushed adjoints are read once: streaming loads
     // (32/64-bit storage; half storage keeps ordinary loads)
-    const int sp = sidx(b, x - CX(i), y - CY(i), z - CZ(i));
+    const int sp = sidx(b, x - L::cx(i), y - L::cy(i), z - L::cz(i));
     if constexpr (sizeof(GS) >= 4)
       g[i] = R(__builtin_nontemporal_load(B + i * N + sp));
     else
       g[i] = GPol<GS>::template ld<R>(B, i * N + sp, i);
-    gsb[i] = __builtin_nontemporal_load(adj_g + i * N + sidx(b, x + CX(i), y + CY(i), z + CZ(i)));
+    gsb[i] = __builtin_nontemporal_load(adj_g + i * N + sidx(b, x + L::cx(i), y + L::cy(i), z + L::cz(i)));
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) Fs[a] = F[a * N + s];
-  R gb[19], Fb[3] = {R(0), R(0), R(0)};
-  collide_site_bwd(P, g, Fs, gsb, ub, gb, Fb);
+  R drho = R(0), j[3] = {R(0), R(0), R(0)};
 #pragma unroll
-  for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(gb[i], g_out + i * N + s);
+  for (int i = 0; i < L::Q; ++i) {
+    drho += g[i];
+    j[0] += R(L::cx(i)) * g[i];
+    j[1] += R(L::cy(i)) * g[i];
+    j[2] += R(L::cz(i)) * g[i];
+  }
+  const R inv = R(1) / (P.rho0 + drho);
+  R us[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) us[a] = (j[a] + R(0.5) * Fs[a]) * inv;
+  R gb[L::Q], Fb[3] = {R(0), R(0), R(0)};
+  collide_bwd_site_l<R, L>(P, drho, us, Fs, gsb, ub, gb, Fb, Sb_out, N, s);
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) __builtin_nontemporal_store(gb[i], g_out + i * N + s);
 #pragma unroll
   for (int a = 0; a < 3; ++a) Fb_out[a * N + s] = Fb[a];
 }
 
-// Reverse of the collision and the pull stream from a lean record: the
+// Reverse of the collision and the pull stream from a record: the
 // pre-collision populations enter only through drho = sum g and u, which the
 // record holds, so they are not read.
-template <class R>
+template <class R, class L>
 __global__ void __launch_bounds__(256) k_adj_collide_lean(Box b, Params<R> P, const R* __restrict__ drho,
                                                           const R* __restrict__ u, const R* __restrict__ F,
                                                           const R* __restrict__ Wb, const R* __restrict__ ubp,
                                                           const R* __restrict__ adj_g, R* __restrict__ g_out,
-                                                          R* __restrict__ Fb_out) {
+                                                          R* __restrict__ Fb_out, R* __restrict__ Sb_out) {
   const int s = site_xcd();
   if (s >= b.N) return;
   int x, y, z;
   coords(b, s, x, y, z);
   const size_t N = b.N;
-  const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
   R ub[3];
+  ubar_at(b, Wb, ubp, s, x, y, z, ub);
+  R gsb[L::Q], Fs[3], us[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) ub[a] = ubp[a * N + s];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const int sp = sidx(b, x + off[c][0], y + off[c][1], z + off[c][2]);
-    const int sm = sidx(b, x - off[c][0], y - off[c][1], z - off[c][2]);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) ub[a] -= R(0.5) * (Wb[(a * 3 + c) * N + sp] - Wb[(a * 3 + c) * N + sm]);
-  }
-  R gsb[19], Fs[3], us[3];
-#pragma unroll
-  for (int i = 0; i < 19; ++i)
-    gsb[i] = __builtin_nontemporal_load(adj_g + i * N + sidx(b, x + CX(i), y + CY(i), z + CZ(i)));
+  for (int i = 0; i < L::Q; ++i)
+    gsb[i] = __builtin_nontemporal_load(adj_g + i * N + sidx(b, x + L::cx(i), y + L::cy(i), z + L::cz(i)));
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     Fs[a] = F[a * N + s];
     us[a] = u[a * N + s];
   }
-  R gb[19], Fb[3] = {R(0), R(0), R(0)};
-  collide_site_bwd_m(P, drho[s], us, Fs, gsb, ub, gb, Fb);
+  R gb[L::Q], Fb[3] = {R(0), R(0), R(0)};
+  collide_bwd_site_l<R, L>(P, drho[s], us, Fs, gsb, ub, gb, Fb, Sb_out, N, s);
 #pragma unroll
-  for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(gb[i], g_out + i * N + s);
+  for (int i = 0; i < L::Q; ++i) __builtin_nontemporal_store(gb[i], g_out + i * N + s);
 #pragma unroll
   for (int a = 0; a < 3; ++a) Fb_out[a * N + s] = Fb[a];
 }
@@ -408,12 +438,16 @@ __device__ __forceinline__ void store_gb(const GradBar<R>& Gb, R* __restrict__ o
 // the anchoring vector v = Q D0 phi whose divergence enters mu.  G: the
 // site's forward gradient data (G.divv unused); Fn[g][d][a], mbn[g][d]: F_bar
 // and mu_bar at x + e_g (d = 0) and x - e_g (d = 1); mb0, aq: mu_bar and
-// Q_bar(t+1) at the site.  Gb gets the gradient-data adjoints (without the
-// order kernel's site-local Q and phi adjoints), Pb the parameter adjoints.
-template <class R>
+// Q_bar(t+1) at the site.  On the D3Q15 scheme (SYM) the force is the
+// divergence of the antisymmetric part A = (sigma - sigma^T)/2 only, and the
+// symmetric part S enters the site's own collision, whose adjoint Ssb (6
+// stored components) is added here.  Gb gets the gradient-data adjoints
+// (without the order kernel's site-local Q and phi adjoints), Pb the
+// parameter adjoints.
+template <class R, bool SYM = false>
 __device__ __forceinline__ void adj_stress_site(const Params<R>& P, const Grad<R>& G, const R Fn[3][2][3],
                                                 const R mbn[3][2], R mb0, const R aq[5], GradBar<R>& Gb,
-                                                ParBar<R>& Pb) {
+                                                ParBar<R>& Pb, const R* Ssb = nullptr) {
   // sigma_bar_ab = -D0_b F_bar_a;  v_bar_a = -D0_a divv_bar with divv_bar = -2 W mu_bar
   R sb[9], vb[3];
 #pragma unroll
@@ -421,6 +455,25 @@ __device__ __forceinline__ void adj_stress_site(const Params<R>& P, const Grad<R
 #pragma unroll
     for (int a = 0; a < 3; ++a) sb[3 * a + c] = -R(0.5) * (Fn[c][0][a] - Fn[c][1][a]);
     vb[c] = P.W * (mbn[c][0] - mbn[c][1]);
+  }
+  if constexpr (SYM) {
+    // A_ac = (sigma_ac - sigma_ca)/2, S_ac = (sigma_ac + sigma_ca)/2 (S stored xx, xy, xz, yy, yz, zz)
+    R t[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) t[3 * a + c] = R(0.5) * (sb[3 * a + c] - sb[3 * c + a]);
+    t[0] += Ssb[0];
+    t[4] += Ssb[3];
+    t[8] += Ssb[5];
+    t[1] += R(0.5) * Ssb[1];
+    t[3] += R(0.5) * Ssb[1];
+    t[2] += R(0.5) * Ssb[2];
+    t[6] += R(0.5) * Ssb[2];
+    t[5] += R(0.5) * Ssb[4];
+    t[7] += R(0.5) * Ssb[4];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) sb[k] = t[k];
   }
   R hbs[5];
 #pragma unroll
@@ -616,13 +669,13 @@ k_adj_gather(Box b, const R* __restrict__ gbar, R* __restrict__ adj_phi, R* __re
 // a read-modify-write of every cache line that holds a tile edge).
 // The (zeta, q0) partials count owned sites only.
 // ---------------------------------------------------------------------------
-template <class R, class FS, int TX, int TY>
+template <class R, class FS, int TX, int TY, bool SYM = false>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(1, 2)))
 k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__ phi,
                const FS* __restrict__ q, const R* __restrict__ Fb, const R* __restrict__ adj_q,
                const R* __restrict__ mub, const R* __restrict__ qbp, const R* __restrict__ phibp,
-               R* __restrict__ adj_phi, R* __restrict__ adj_qo, R* __restrict__ hx, R* __restrict__ hy,
-               double* __restrict__ partial, int accumulate) {
+               const R* __restrict__ Sbar, R* __restrict__ adj_phi, R* __restrict__ adj_qo, R* __restrict__ hx,
+               R* __restrict__ hy, double* __restrict__ partial, int accumulate) {
   constexpr int NT = TX * TY;
   constexpr int IX = TX + 2, IY = TY + 2, NI = IX * IY;  // input frame (halo 1)
   constexpr int NF = 10;                                 // phi, q[5], mu_bar, F_bar[3]
@@ -694,7 +747,7 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
   const int f0 = (ly + 1) * IX + (lx + 1);
   const int col = sGY[ly + 1] * b.nx + sGX[lx + 1];
   // the gradient-data adjoint of the own site at plane p (input slots rm, r0, rp = planes p-1, p, p+1)
-  auto site_adjoint = [&](int rm, int r0, int rp, const R aq[5], GradBar<R>& Gb, ParBar<R>& Pb) {
+  auto site_adjoint = [&](int rm, int r0, int rp, const R aq[5], const R ssb[6], GradBar<R>& Gb, ParBar<R>& Pb) {
     const int f = f0;
     const int nb[3][2] = {{f + 1, f - 1}, {f + IX, f - IX}, {f, f}};
     auto at = [&](int fld, int g, int d) {
@@ -731,15 +784,19 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
 #pragma unroll
     for (int k = 0; k < 5; ++k) G.lapq[k] -= R(6) * G.q[k];
     G.divv = R(0);
-    adj_stress_site(P, G, Fn, mbn, sIn[r0][6][f], aq, Gb, Pb);
+    adj_stress_site<R, SYM>(P, G, Fn, mbn, sIn[r0][6][f], aq, Gb, Pb, ssb);
   };
-  auto load_site = [&](int wp, R aq[5], R qp[5], R& pp) {
+  auto load_site = [&](int wp, R aq[5], R qp[5], R& pp, R ssb[6]) {
     const size_t k = size_t(pmod(wp, b.nz)) * plane + col;
 #pragma unroll
     for (int c = 0; c < 5; ++c) aq[c] = adj_q[c * N + k];
 #pragma unroll
     for (int c = 0; c < 5; ++c) qp[c] = qbp[c * N + k];
     pp = phibp[k];
+    if constexpr (SYM) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) ssb[c] = Sbar[c * N + k];
+    }
   };
   // the term a site sends across a face: lap + (sgn/2) d, for phi and q[5]
   // (fields fstride apart)
@@ -754,8 +811,8 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
   fill_plane(z0 - 2, rm);
   fill_plane(z0 - 1, r0);
   fill_plane(z0, rp);
-  R aq_o[5], qp_o[5], pp_o = R(0);
-  load_site(z0 - 1, aq_o, qp_o, pp_o);
+  R aq_o[5], qp_o[5], pp_o = R(0), ss_o[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+  load_site(z0 - 1, aq_o, qp_o, pp_o, ss_o);
 
   // own column: z-transpose values of the previous plane and the running adjoint
   R zp_lapphi = R(0), zp_dphi = R(0), zp_lapq[5], zp_dq[5];
@@ -769,7 +826,7 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
     __syncthreads();  // plane p+1 in place; the previous plane's reads of sGB are done
     GradBar<R> Gb;
     ParBar<R> Pb;
-    site_adjoint(rm, r0, rp, aq_o, Gb, Pb);
+    site_adjoint(rm, r0, rp, aq_o, ss_o, Gb, Pb);
     const bool own_plane = p >= z0 && p < z1;
     if (own_plane && active) par_adjoints(P, Pb, v);
     Gb.phi += pp_o;
@@ -839,7 +896,7 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
       // plane p-1 is read by no one any more (all passed the barrier above):
       // plane p+2 takes its slot; the site inputs of plane p+1
       fill_plane(p + 2, rm);
-      load_site(p + 1, aq_o, qp_o, pp_o);
+      load_site(p + 1, aq_o, qp_o, pp_o, ss_o);
     }
     const int t = rm;
     rm = r0;
@@ -903,15 +960,14 @@ __global__ void k_step_count(const int64_t* __restrict__ in, int64_t* __restrict
 // Seed of the displacement loss L = (z_c - z_ref)^2, z_c = sum phi z / sum phi:
 // dL/dphi(x) = 2 (z_c - z_ref)(z - z_c) / sum phi; zero for g and Q.
 template <class R>
-__global__ void __launch_bounds__(256) k_seed_centre(Box b, double zc, double zref, double phitot,
+__global__ void __launch_bounds__(256) k_seed_centre(Box b, int nq, double zc, double zref, double phitot,
                                                      R* __restrict__ adj) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= b.N) return;
   const size_t N = b.N;
   const int z = s / (b.nx * b.ny);
-#pragma unroll
-  for (int i = 0; i < 24; ++i) adj[i * N + s] = R(0);
-  adj[24 * N + s] = R(2.0 * (zc - zref) * (double(z) - zc) / phitot);
+  for (int i = 0; i < nq + 5; ++i) adj[i * N + s] = R(0);
+  adj[(nq + 5) * N + s] = R(2.0 * (zc - zref) * (double(z) - zc) / phitot);
 }
 
 }  // namespace lbc

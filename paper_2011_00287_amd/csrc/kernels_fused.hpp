@@ -283,7 +283,7 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
       for (int a = 0; a < 3; ++a) F[a] = (fin_m1[a] + R(0.5) * (saz[a] - saz_m2[a])) + P.bf[a];
       R u[3], drho = R(0);
       if constexpr (L::kStressInEq)
-        collide_site_eq(P, g, F, ssym_m1, u);
+        drho = collide_site_eq(P, g, F, ssym_m1, u);
       else
         drho = collide_site(P, g, F, u);
       const uint32_t sg = uint32_t(zc) * plane_gs + own_g, sr = uint32_t(zc) * plane_r + own_r;

@@ -215,6 +215,7 @@ struct BackendT final : Backend {
   R* agbar = nullptr;
   R* ahx = nullptr;  // face terms and edge-column adjoints of the fused stress + gather adjoint (x tiles > 1)
   R* ahy = nullptr;  // the same along y
+  R* aSb = nullptr;  // D3Q15: adjoint of the symmetric stress S_ab in the collision, [6][N]
   double* apart = nullptr;   // per-block (zeta, q0) adjoint partials, kept across reverse steps
   size_t apart_n = 0;        // doubles in apart
   bool apart_live = false;   // apart holds sums not yet fetched by the caller
@@ -349,7 +350,7 @@ struct BackendT final : Backend {
     pcv = nullptr;
     mu = H = sig = u = nullptr;
     partial = sums = nullptr;
-    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy};
+    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb};
     for (R** a : adj) {
       dfree(*a);
       *a = nullptr;
@@ -714,14 +715,14 @@ struct BackendT final : Backend {
   }
 
   // --- adjoint ---------------------------------------------------------------
-  // adjoint buffer: g_bar [19][N], q_bar [5][N], phi_bar [N] in R (D3Q19 only)
-  static constexpr bool kAdjoint = !L::kStressInEq;
-  bool has_adjoint() const { return kAdjoint && !pc4; }
+  // adjoint buffer: g_bar [NQ][N], q_bar [5][N], phi_bar [N] in R.  The
+  // D3Q15 scheme's reverse exists for the fused kernels only.
+  bool has_adjoint() const { return !pc4 && !(L::kStressInEq && site_path); }
   void need_adjoint() const {
     if (!has_adjoint())
-      fail(LB_EINVAL, "the adjoint is implemented for the D3Q19 lattice with the Euler integrator");
+      fail(LB_EINVAL, "the adjoint is implemented for the Euler integrator (D3Q15: fused kernels only)");
   }
-  size_t adjoint_bytes() const override { return has_adjoint() ? 25 * N * sizeof(R) : 0; }
+  size_t adjoint_bytes() const override { return has_adjoint() ? (NQ + 6) * N * sizeof(R) : 0; }
   void ensure_adjoint() {
     if (aF) return;
     try {
@@ -733,6 +734,7 @@ struct BackendT final : Backend {
       aphibp = dalloc<R>(N);
       aFb = dalloc<R>(3 * N);
       if (site_path) agbar = dalloc<R>(size_t(lbc::NGB) * N);  // the fused kernel keeps it on chip
+      if (L::kStressInEq) aSb = dalloc<R>(6 * N);  // adjoint of the symmetric stress in the collision
       if (!site_path && as_ntx > 1) ahx = dalloc<R>(24 * size_t(as_ntx) * box.nz * box.ny);
       if (!site_path && as_nty > 1) ahy = dalloc<R>(12 * size_t(as_nty) * box.nz * box.nx);
       // one (zeta, q0) pair per block of whichever reverse kernel writes them
@@ -742,7 +744,7 @@ struct BackendT final : Backend {
       HIPCHECK(hipMemsetAsync(apart, 0, npart * sizeof(double), stream));
       apart_live = false;
     } catch (...) {
-      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy};
+      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb};
       for (R** a : adj) {
         dfree(*a);
         *a = nullptr;
@@ -781,7 +783,7 @@ struct BackendT final : Backend {
     if (site_path) {
       ensure_thermo();
       lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, vi.phi, vi.q, mu, H, sig);
-      lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, vi.B, sig, rF, ru, rd);
+      lbc::k_fwd_force<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, vi.B, sig, rF, ru, rd);
       lbc::k_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, vi.B, Bo, sig, ru);
       lbc::k_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, vi.phi, vi.q, ru, H, mu, po, qo);
     } else {
@@ -810,7 +812,7 @@ struct BackendT final : Backend {
     if (site_path) {
       ensure_thermo();
       lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], mu, H, sig);
-      lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, B[cur], sig, rF, ru, rd);
+      lbc::k_fwd_force<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, B[cur], sig, rF, ru, rd);
       lbc::k_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, B[cur], B[nx], sig, ru);
       lbc::k_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], ru, H, mu, Ph[nx], Q[nx]);
     } else {
@@ -836,11 +838,11 @@ struct BackendT final : Backend {
   void reverse_kernels(const FS* phi_t, const FS* q_t, const R* uu, const R* FF, const GS* Bt, const R* drho,
                        const void* adj_in, void* adj_out, double* zeta_bar, double* q0_bar) {
     const R* gi = static_cast<const R*>(adj_in);
-    const R* qi = gi + 19 * N;
-    const R* pi = gi + 24 * N;
+    const R* qi = gi + NQ * N;
+    const R* pi = gi + (NQ + 5) * N;
     R* go = static_cast<R*>(adj_out);
-    R* qo = go + 19 * N;
-    R* po = go + 24 * N;
+    R* qo = go + NQ * N;
+    R* po = go + (NQ + 5) * N;
     if (site_path)
       lbc::k_adj_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phi_t, q_t, uu, pi, qi, amub, aWb, aubp, aqbp,
                                                          aphibp);
@@ -850,16 +852,16 @@ struct BackendT final : Backend {
     const int npart_blocks = site_path ? int(nblk) : as_blocks;
     if (size_t(npart_blocks) * 2 > apart_n) fail(LB_EDEVICE, "adjoint partial buffer smaller than the grid");
     if (Bt)
-      lbc::k_adj_collide<R, GS><<<nblk, TPB, 0, stream>>>(box, P, Bt, FF, aWb, aubp, gi, go, aFb);
+      lbc::k_adj_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, Bt, FF, aWb, aubp, gi, go, aFb, aSb);
     else
-      lbc::k_adj_collide_lean<R><<<nblk, TPB, 0, stream>>>(box, P, drho, uu, FF, aWb, aubp, gi, go, aFb);
+      lbc::k_adj_collide_lean<R, L><<<nblk, TPB, 0, stream>>>(box, P, drho, uu, FF, aWb, aubp, gi, go, aFb, aSb);
     if (site_path) {
       lbc::k_adj_stress<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phi_t, q_t, aFb, qi, amub, aqbp, aphibp, agbar,
                                                           apart, apart_live ? 1 : 0);
       lbc::k_adj_gather<R><<<nblk, TPB, 0, stream>>>(box, agbar, po, qo);
     } else {
-      lbc::k_adj_sg_fused<R, FS, kAsTX, kAsTY><<<as_blocks, kAsTX * kAsTY, 0, stream>>>(
-          box, P, as_tz, as_ntx, as_nty, phi_t, q_t, aFb, qi, amub, aqbp, aphibp, po, qo, ahx, ahy, apart,
+      lbc::k_adj_sg_fused<R, FS, kAsTX, kAsTY, L::kStressInEq><<<as_blocks, kAsTX * kAsTY, 0, stream>>>(
+          box, P, as_tz, as_ntx, as_nty, phi_t, q_t, aFb, qi, amub, aqbp, aphibp, aSb, po, qo, ahx, ahy, apart,
           apart_live ? 1 : 0);
       if (as_ntx > 1) {
         const size_t n = 6 * size_t(as_ntx) * box.nz * box.ny;  // one thread per field
@@ -895,7 +897,7 @@ struct BackendT final : Backend {
     // recompute u and F of time t
     ensure_thermo();
     lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, v.phi, v.q, mu, H, sig);
-    lbc::k_fwd_force<R, GS><<<nblk, TPB, 0, stream>>>(box, P, v.B, sig, aF, u, nullptr);
+    lbc::k_fwd_force<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, v.B, sig, aF, u, nullptr);
     reverse_kernels(v.phi, v.q, u, aF, v.B, nullptr, adj_in, adj_out, zeta_bar, q0_bar);
   }
   double seed_centre(double z_ref, void* adj) override {
@@ -903,7 +905,7 @@ struct BackendT final : Backend {
     double v[lbc::NCEN];
     centre(v);
     const double zc = v[2] / v[3];
-    lbc::k_seed_centre<R><<<nblk, TPB, 0, stream>>>(box, zc, z_ref, v[3], static_cast<R*>(adj));
+    lbc::k_seed_centre<R><<<nblk, TPB, 0, stream>>>(box, NQ, zc, z_ref, v[3], static_cast<R*>(adj));
     check_launch();
     HIPCHECK(hipStreamSynchronize(stream));
     return (zc - z_ref) * (zc - z_ref);
@@ -945,8 +947,8 @@ void need_ctx(const lb_ctx* c) {
 
 void need_adjoint_ctx(const lb_ctx* c) {
   need_ctx(c);
-  if (c->p.lattice != LB_D3Q19 || c->p.fd_scheme != LB_FD_EULER2)
-    fail(LB_EINVAL, "the adjoint is implemented for the D3Q19 lattice with the Euler integrator");
+  if (c->p.fd_scheme != LB_FD_EULER2) fail(LB_EINVAL, "the adjoint is implemented for the Euler integrator");
+  if (c->be->adjoint_bytes() == 0) fail(LB_EINVAL, "no adjoint for this context (D3Q15: fused kernels only)");
 }
 
 std::unique_ptr<Backend> make_backend(const lb_params& p, hipStream_t s) {

@@ -363,8 +363,8 @@ __host__ __device__ __forceinline__ R collide_site(const Params<R>& P, R g[19], 
 // the Guo source guo w (-3 u.F + 3 cF + 9 cu cF) with u = (sum c g + F/2)/rho.
 // Opposite pairs (i, i+1) share the even part, as in collide_site.
 template <class R>
-__host__ __device__ __forceinline__ void collide_site_eq(const Params<R>& P, R g[15], const R F[3], const R S[6],
-                                                         R u[3]) {
+__host__ __device__ __forceinline__ R collide_site_eq(const Params<R>& P, R g[15], const R F[3], const R S[6],
+                                                      R u[3]) {
   using L = D3Q15;
   R drho = g[0];
 #pragma unroll
@@ -403,6 +403,7 @@ __host__ __device__ __forceinline__ void collide_site_eq(const Params<R>& P, R g
     g[i] = (om1 * gi + even) + odd;
     g[i + 1] = (om1 * gj + even) - odd;
   }
+  return drho;
 }
 
 }  // namespace lbc

@@ -194,17 +194,17 @@ class Sim:
         return torch.float64 if self.precision == "fp64" else torch.float32
 
     def adjoint_buffer(self):
-        """Zeroed device tensor holding (g_bar [19][N], q_bar [5][N], phi_bar [N])."""
+        """Zeroed device tensor holding (g_bar [Q][N], q_bar [5][N], phi_bar [N]); Q = 19 or 15."""
         import torch
         nb = int(lib().lb_adjoint_bytes(self._h))
         esz = 8 if self.precision == "fp64" else 4
         return torch.zeros(nb // esz, dtype=self.compute_dtype, device="cuda")
 
     def adjoint_parts(self, adj):
-        """Views (g_bar [19,nz,ny,nx], q_bar [5,...], phi_bar [...]) of an adjoint buffer."""
-        n = self.n_sites
-        return (adj[:19 * n].view((19,) + self.shape), adj[19 * n:24 * n].view((5,) + self.shape),
-                adj[24 * n:].view(self.shape))
+        """Views (g_bar [Q,nz,ny,nx], q_bar [5,...], phi_bar [...]) of an adjoint buffer (Q populations)."""
+        n, nq = self.n_sites, self.n_populations
+        return (adj[:nq * n].view((nq,) + self.shape), adj[nq * n:(nq + 5) * n].view((5,) + self.shape),
+                adj[(nq + 5) * n:].view(self.shape))
 
     def seed_centre(self, z_ref: float, adj) -> float:
         """adj <- dL/d(state) of L = (z_c - z_ref)^2 at the current state; returns L."""

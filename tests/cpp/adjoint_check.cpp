@@ -196,11 +196,41 @@ static void check_collide() {
   report("collide wrt g, F", fd, ad);
 }
 
+// the paper's D3Q15 collision with the symmetric stress in the equilibrium
+static void check_collide_eq() {
+  Params<R> P = params();
+  R g[15], F[3], S[6], vg[15], vu[3], dg[15], dF[3], dS[6];
+  for (int i = 0; i < 15; ++i) { g[i] = U(-2e-2, 2e-2); vg[i] = U(-1, 1); dg[i] = U(-1, 1); }
+  for (int a = 0; a < 3; ++a) { F[a] = U(-1e-2, 1e-2); vu[a] = U(-1, 1); dF[a] = U(-1, 1); }
+  for (int k = 0; k < 6; ++k) { S[k] = U(-1e-2, 1e-2); dS[k] = U(-1, 1); }
+  const double h = 1e-6;
+  auto f = [&](double s) {
+    R gg[15], FF[3], SS[6], u[3];
+    for (int i = 0; i < 15; ++i) gg[i] = g[i] + s * dg[i];
+    for (int a = 0; a < 3; ++a) FF[a] = F[a] + s * dF[a];
+    for (int k = 0; k < 6; ++k) SS[k] = S[k] + s * dS[k];
+    collide_site_eq(P, gg, FF, SS, u);
+    double r = 0;
+    for (int i = 0; i < 15; ++i) r += vg[i] * gg[i];
+    for (int a = 0; a < 3; ++a) r += vu[a] * u[a];
+    return r;
+  };
+  const double fd = (f(h) - f(-h)) / (2 * h);
+  R gb[15], Fb[3] = {0, 0, 0}, Sb[6] = {0, 0, 0, 0, 0, 0};
+  collide_eq_site_bwd(P, g, F, vg, vu, gb, Fb, Sb);
+  double ad = 0;
+  for (int i = 0; i < 15; ++i) ad += gb[i] * dg[i];
+  for (int a = 0; a < 3; ++a) ad += Fb[a] * dF[a];
+  for (int k = 0; k < 6; ++k) ad += Sb[k] * dS[k];
+  report("D3Q15 collide wrt g, F, S", fd, ad);
+}
+
 int main() {
   for (int t = 0; t < 4; ++t) check_sigma(t);
   for (int t = 0; t < 3; ++t) check_mu();
   for (int t = 0; t < 3; ++t) check_corotation();
   for (int t = 0; t < 3; ++t) check_collide();
+  for (int t = 0; t < 3; ++t) check_collide_eq();
   std::printf("%s\n", failures ? "FAILED" : "ALL OK");
   return failures ? 1 : 0;
 }

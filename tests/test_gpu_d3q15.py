@@ -178,13 +178,15 @@ def test_bitwise_determinism_and_resume():
             assert np.array_equal(x, y)
 
 
-def test_rejected_combinations():
-    """float16 population storage and the adjoint are D3Q19-only: refused with LB_EINVAL."""
+def test_rejected_combinations(monkeypatch):
+    """float16 population storage is D3Q19-only, and the D3Q15 adjoint runs on the
+    fused kernels only: both are refused with LB_EINVAL (the forward still runs)."""
     p = _p()
     phi, q5 = inputs.droplet_fields(6, 6, 6, 2.0, 0.5)
     with pytest.raises(LbError) as e:
         Sim(p, phi, q5, precision="fp16s", lattice="d3q15")
     assert e.value.status == LB_EINVAL
+    monkeypatch.setenv("LBC_SITE_KERNELS", "1")
     with Sim(p, phi, q5, lattice="d3q15") as s:
         assert s.adjoint_buffer().numel() == 0 and s.record_buffer().numel() == 0
         with pytest.raises(LbError) as e:
