@@ -216,6 +216,8 @@ struct BackendT final : Backend {
   R* ahx = nullptr;  // face terms and edge-column adjoints of the fused stress + gather adjoint (x tiles > 1)
   R* ahy = nullptr;  // the same along y
   R* aSb = nullptr;  // D3Q15: adjoint of the symmetric stress S_ab in the collision, [6][N]
+  R* ahxw = nullptr;  // the order adjoint's W_bar_ax of tile-edge columns (x tiles > 1)
+  R* ahyw = nullptr;  // its W_bar_ay of tile-edge rows (y tiles > 1)
   double* apart = nullptr;   // per-block (zeta, q0) adjoint partials, kept across reverse steps
   size_t apart_n = 0;        // doubles in apart
   bool apart_live = false;   // apart holds sums not yet fetched by the caller
@@ -350,7 +352,7 @@ struct BackendT final : Backend {
     pcv = nullptr;
     mu = H = sig = u = nullptr;
     partial = sums = nullptr;
-    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb};
+    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &ahxw, &ahyw};
     for (R** a : adj) {
       dfree(*a);
       *a = nullptr;
@@ -736,6 +738,8 @@ struct BackendT final : Backend {
       if (site_path) agbar = dalloc<R>(size_t(lbc::NGB) * N);  // the fused kernel keeps it on chip
       if (L::kStressInEq) aSb = dalloc<R>(6 * N);  // adjoint of the symmetric stress in the collision
       if (!site_path && as_ntx > 1) ahx = dalloc<R>(24 * size_t(as_ntx) * box.nz * box.ny);
+      if (!site_path && ao_ntx > 1) ahxw = dalloc<R>(6 * size_t(ao_ntx) * box.nz * box.ny);
+      if (!site_path && ao_nty > 1) ahyw = dalloc<R>(6 * size_t(ao_nty) * box.nz * box.nx);
       if (!site_path && as_nty > 1) ahy = dalloc<R>(12 * size_t(as_nty) * box.nz * box.nx);
       // one (zeta, q0) pair per block of whichever reverse kernel writes them
       const size_t npart = size_t(std::max<int>(int(nblk), as_blocks)) * 2;
@@ -744,7 +748,7 @@ struct BackendT final : Backend {
       HIPCHECK(hipMemsetAsync(apart, 0, npart * sizeof(double), stream));
       apart_live = false;
     } catch (...) {
-      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb};
+      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &ahxw, &ahyw};
       for (R** a : adj) {
         dfree(*a);
         *a = nullptr;
@@ -843,18 +847,21 @@ struct BackendT final : Backend {
     R* go = static_cast<R*>(adj_out);
     R* qo = go + NQ * N;
     R* po = go + (NQ + 5) * N;
+    // site path: W_bar [9][N] and the local u_bar part; fused: W_bar_az [3][N] (in aWb) and
+    // u_bar with the in-plane transposes (in aubp), plus the tile-face terms
+    lbc::UbarIn<R> ubin{aWb, aubp, ahxw, ahyw, kAoTX, kAoTY, ao_ntx, ao_nty, site_path ? 0 : 1};
     if (site_path)
       lbc::k_adj_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phi_t, q_t, uu, pi, qi, amub, aWb, aubp, aqbp,
                                                          aphibp);
     else
       lbc::k_adj_order_fused<R, FS, kAoTX, kAoTY><<<ao_blocks, kAoTX * kAoTY, 0, stream>>>(
-          box, P, ao_tz, ao_ntx, ao_nty, phi_t, q_t, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp);
+          box, P, ao_tz, ao_ntx, ao_nty, phi_t, q_t, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp, ahxw, ahyw);
     const int npart_blocks = site_path ? int(nblk) : as_blocks;
     if (size_t(npart_blocks) * 2 > apart_n) fail(LB_EDEVICE, "adjoint partial buffer smaller than the grid");
     if (Bt)
-      lbc::k_adj_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, Bt, FF, aWb, aubp, gi, go, aFb, aSb);
+      lbc::k_adj_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, Bt, FF, ubin, gi, go, aFb, aSb);
     else
-      lbc::k_adj_collide_lean<R, L><<<nblk, TPB, 0, stream>>>(box, P, drho, uu, FF, aWb, aubp, gi, go, aFb, aSb);
+      lbc::k_adj_collide_lean<R, L><<<nblk, TPB, 0, stream>>>(box, P, drho, uu, FF, ubin, gi, go, aFb, aSb);
     if (site_path) {
       lbc::k_adj_stress<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phi_t, q_t, aFb, qi, amub, aqbp, aphibp, agbar,
                                                           apart, apart_live ? 1 : 0);
