@@ -8,6 +8,15 @@ benchmark times (default tiles and slab depths).
   is exact.  Tolerance: FP32 rounding of the step, 2e-6 absolute on g, Q, phi.
 * 64^3 droplet, FP64: 30 steps against the oracle on the whole box, 1e-12.
 * 256^3 droplet, FP32, 100 steps: mass and sum(phi) conserved (float64 sums).
+* 128^3 droplet with the paper's D3Q15 scheme, FP32: one step at sampled sites
+  against the D3Q15 oracle on 13^3 patches (its step reaches 4 sites, as
+  above), and one reverse step at sampled sites against the autograd of that
+  oracle on 17^3 patches.
+* 128^3 droplet with the paper's FD integrator (pc4, M = 0.05), FP32: one step
+  at sampled sites against the pc4 oracle on 33^3 patches.  The two stages of
+  Heun's method each apply fourth-order stencils of radius up to 6 (L4 of mu,
+  with D4 . (Q D4 phi) inside mu), so a step reaches 12 sites; the patch centre
+  was checked to be exact from radius 12 on.
 * 256^3 droplet, FP32: one step at sampled sites against 13^3 oracle patches,
   and one reverse step (through the recorded path the benchmark times) at
   sampled sites against the oracle's autograd on 17^3 patches.  The adjoint
@@ -19,7 +28,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import core
+from oracle import core, d3q15, pc4
 from paper_2011_00287_amd import inputs
 from paper_2011_00287_amd.sim import Sim
 
@@ -149,6 +158,82 @@ def test_fp32_256_adjoint_sampled_sites_vs_oracle():
         go, qo, po = core.step(gt, qt, pt, p)
         tot = (go * torch.tensor(seed[:19])).sum() + (qo * torch.tensor(seed[19:24])).sum() + \
             (po * torch.tensor(seed[24])).sum()
+        tot.backward()
+        orc = np.concatenate([gt.grad[:, R, R, R].numpy(), qt.grad[:, R, R, R].numpy(), [pt.grad[R, R, R].item()]])
+        err = float(np.abs(orc - gv).max() / np.abs(orc).max())
+        worst = max(worst, err)
+    print("worst relative reverse-step error", worst)
+    assert worst <= 1e-4, worst
+
+
+def _variant_sampled_sites(workload, lattice, fd_scheme, mod, nq, r, p_extra):
+    p = inputs.params_for(workload, **p_extra)
+    phi, q5 = inputs.workload_fields(workload)
+    n = phi.shape[0]
+    with Sim(p, phi, q5, precision="fp32", lattice=lattice, fd_scheme=fd_scheme) as s:
+        s.step(1)
+        g1 = s.populations()
+        _, _, phi1, q1 = s.moments()
+    g0 = torch.zeros((nq, 2 * r + 1, 2 * r + 1, 2 * r + 1), dtype=torch.float64)
+    worst = {"g": 0.0, "Q": 0.0, "phi": 0.0}
+    for (z, y, x) in _sites(n, inputs.WORKLOADS[workload]["R"]):
+        go, qo, po = mod.step(g0, torch.tensor(_patch(q5, z, y, x, r)), torch.tensor(_patch(phi, z, y, x, r)), p)
+        worst["g"] = max(worst["g"], float(np.abs(go[:, r, r, r].numpy() - g1[:, z, y, x]).max()))
+        worst["Q"] = max(worst["Q"], float(np.abs(qo[:, r, r, r].numpy() - q1[:, z, y, x]).max()))
+        worst["phi"] = max(worst["phi"], float(abs(po[r, r, r].item() - phi1[z, y, x])))
+    print(worst)
+    assert all(v <= 2e-6 for v in worst.values()), worst
+
+
+def test_fp32_128_d3q15_sampled_sites_vs_oracle():
+    _variant_sampled_sites("droplet128", "d3q15", "euler2", d3q15, 15, 6, {})
+
+
+def test_fp32_128_pc4_sampled_sites_vs_oracle():
+    _variant_sampled_sites("droplet128", "d3q19", "pc4", pc4, 19, 16, {"M": 0.05})
+
+
+def test_fp32_128_d3q15_adjoint_sampled_sites_vs_oracle():
+    """One reverse step of the D3Q15 scheme (the recorded path) at sampled sites."""
+    p = inputs.params_for("droplet128")
+    phi, q5 = inputs.workload_fields("droplet128")
+    n = phi.shape[0]
+    nf = 15 + 6
+    sites = _sites(n, inputs.WORKLOADS["droplet128"]["R"])[:6]
+    with Sim(p, phi, q5, precision="fp32", lattice="d3q15") as sim:
+        state = sim.get_state()
+        rec = sim.record_buffer()
+        nxt = torch.empty_like(state)
+        sim.step_record(state, nxt, rec)
+        del nxt
+        adj = sim.adjoint_buffer()
+        a5 = adj.view(nf, n, n, n)
+        zz = torch.arange(n, device="cuda", dtype=torch.float64).view(n, 1, 1)
+        yy = zz.view(1, n, 1)
+        xx = zz.view(1, 1, n)
+        for c in range(nf):  # the same closed form as _seed_field, built on the device
+            a5[c] = (torch.sin(0.37 * xx + 0.91 * yy + 1.3 * zz + 0.7 * c) * torch.cos(0.23 * xx - 0.5 * zz + c)).float()
+        out = sim.adjoint_buffer()
+        sim.adjoint_step(state, adj, out, rec=rec)
+        o5 = out.view(nf, n, n, n)
+        gpu = [o5[:, z, y, x].double().cpu().numpy() for (z, y, x) in sites]
+    R, r = 8, 4
+    m = 2 * R + 1
+    worst = 0.0
+    for (z, y, x), gv in zip(sites, gpu):
+        iz = (np.arange(z - R, z + R + 1)) % n
+        iy = (np.arange(y - R, y + R + 1)) % n
+        ix = (np.arange(x - R, x + R + 1)) % n
+        seed = _seed_field(iz[:, None, None], iy[None, :, None], ix[None, None, :], np.arange(nf))
+        mask = np.zeros((m, m, m))
+        mask[R - r:R + r + 1, R - r:R + r + 1, R - r:R + r + 1] = 1.0
+        seed = seed * mask
+        gt = torch.zeros((15, m, m, m), dtype=torch.float64, requires_grad=True)
+        qt = torch.tensor(_patch(q5, z, y, x, R), requires_grad=True)
+        pt = torch.tensor(_patch(phi, z, y, x, R), requires_grad=True)
+        go, qo, po = d3q15.step(gt, qt, pt, p)
+        tot = (go * torch.tensor(seed[:15])).sum() + (qo * torch.tensor(seed[15:20])).sum() + \
+            (po * torch.tensor(seed[20])).sum()
         tot.backward()
         orc = np.concatenate([gt.grad[:, R, R, R].numpy(), qt.grad[:, R, R, R].numpy(), [pt.grad[R, R, R].item()]])
         err = float(np.abs(orc - gv).max() / np.abs(orc).max())
