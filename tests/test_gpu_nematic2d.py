@@ -67,6 +67,29 @@ def test_fp64_nematic64_200_steps():
         _compare(s, p, go.numpy(), qo.numpy())
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("fp32", 1e-5)])
+def test_nematic512_full_box_vs_oracle(prec, tol):
+    """The 512^2 workload of the benchmark (zeta = 0.02), in its launch configuration:
+    10 steps from a random state with flow, every site against the FP64 oracle
+    (FP64: 1e-12 relative per field; FP32: float32 rounding of 10 steps)."""
+    p = inputs.nematic2d_params("nematic512")
+    q2 = inputs.nematic2d_workload_fields("nematic512")
+    rng = np.random.default_rng(512)
+    g = 1e-3 * rng.standard_normal((9,) + q2.shape[1:])
+    with Nematic2D(p, q2, precision=prec) as s:
+        s.set_fields(g=g)
+        s.step(10)
+        go, qo = n2.run(t64(g), t64(q2), p, 10)
+        if prec == "fp64":
+            _compare(s, p, go.numpy(), qo.numpy())
+        else:
+            _, u_o = n2.observe(go, qo, p)
+            _, u, q = s.moments()
+            for name, a, b in (("g", s.populations(), go.numpy()), ("u", u, u_o.numpy()), ("Q", q, qo.numpy())):
+                l2, mx = rel_err(a, b)
+                assert l2 <= tol and mx <= tol, (name, l2, mx)
+
+
 def test_init_with_velocity_and_totals():
     p = _p(zeta=0.01)
     ny, nx = 12, 10
