@@ -59,7 +59,7 @@ class Sim:
     phi: [nz, ny, nx]; q5: [5, nz, ny, nx] (xx, xy, xz, yy, yz); u0: [3, nz, ny, nx]
     or None.  precision: 'fp64', 'fp32' or 'fp16s'.  lattice: 'd3q19' (stress as a
     forcing term) or 'd3q15' (symmetric stress in the equilibrium, antisymmetric
-    stress as a forcing term; fp64 and fp32, forward only).  fd_scheme: 'euler2'
+    stress as a forcing term; fp64 and fp32).  fd_scheme: 'euler2'
     (explicit Euler, second-order stencils) or 'pc4' (the paper's predictor-corrector
     with upwind advection and fourth-order stencils; forward only).  stream: a torch.cuda.Stream,
     a raw hipStream_t as int, or None for the default stream.  The device tensors
