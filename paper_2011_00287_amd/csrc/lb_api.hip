@@ -97,7 +97,8 @@ int auto_slab(int ntx, int nty, int nz, int tz_max, int tz_min, int per_cu) {
 // register and LDS footprint leaves one or two small workgroups per CU); the
 // slab is the deepest that still gives a workgroup per CU.  Order kernel
 // 64 x 8 with the deepest slab of at most 16 planes that gives two
-// workgroups per CU.  LBC_TZ_LB / LBC_TZ_ORDER fix a depth instead.
+// workgroups per CU.  LBC_TZ_LB / LBC_TZ_ORDER fix a depth instead, and
+// LBC_TZ_ADJ / LBC_TZ_AO that of the fused stress + gather and order adjoints.
 template <class R, class GS>
 struct DefaultTile {
   static constexpr int lb = 0, order = 3, tz_lb_max = 16;
@@ -284,7 +285,8 @@ struct BackendT final : Backend {
     pm_blocks = pm_ntx * pm_nty * ((p.nz + tz_pm - 1) / tz_pm);
     ao_ntx = (p.nx + kAoTX - 1) / kAoTX;
     ao_nty = (p.ny + kAoTY - 1) / kAoTY;
-    ao_tz = auto_slab(ao_ntx, ao_nty, p.nz, 16, 1, 2);
+    ao_tz = std::max(0, env_int("LBC_TZ_AO", 0));
+    if (ao_tz == 0) ao_tz = auto_slab(ao_ntx, ao_nty, p.nz, 16, 1, 2);
     ao_blocks = ao_ntx * ao_nty * ((p.nz + ao_tz - 1) / ao_tz);
     as_ntx = (p.nx + kAsTX - 1) / kAsTX;
     as_nty = (p.ny + kAsTY - 1) / kAsTY;
