@@ -354,8 +354,6 @@ def main():
     n = phi.size
     print(f"# workload {args.workload} {phi.shape} {args.precision} {args.lattice} {args.fd_scheme}: "
           f"warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
-    if args.lattice == "d3q15" and args.precision == "fp16s":
-        ap.error("float16 population storage is D3Q19-only")
 
     sim, dt = time_precision(args.precision, p, phi, q5, args.steps, args.warmup, stream, args.lattice,
                              args.fd_scheme)
@@ -374,7 +372,7 @@ def main():
     side = {}
     if not args.no_side:
         cases = [(prec, "d3q19", "euler2") for prec in ("fp64", "fp16s")] + \
-                [(prec, "d3q15", "euler2") for prec in ("fp32", "fp64")] + [("fp32", "d3q19", "pc4")]
+                [(prec, "d3q15", "euler2") for prec in ("fp32", "fp64", "fp16s")] + [("fp32", "d3q19", "pc4")]
         for prec, lat, fd in cases:
             if (prec, lat, fd) == (args.precision, args.lattice, args.fd_scheme):
                 continue

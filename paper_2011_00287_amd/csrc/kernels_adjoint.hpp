@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(256) k_fwd_force(Box b, Params<R> P, const GS*
   R sum = R(0), j[3] = {R(0), R(0), R(0)};
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
-    const R gi = GPol<GS>::template ld<R>(B, i * N + sidx(b, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i);
+    const R gi = GPol<GS, L>::template ld<R>(B, i * N + sidx(b, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i);
     sum += gi;
     j[0] += R(L::cx(i)) * gi;
     j[1] += R(L::cy(i)) * gi;
@@ -460,7 +460,7 @@ __global__ void __launch_bounds__(256) k_adj_collide(Box b, Params<R> P, const G
     if constexpr (sizeof(GS) >= 4)
       g[i] = R(__builtin_nontemporal_load(B + i * N + sp));
     else
-      g[i] = GPol<GS>::template ld<R>(B, i * N + sp, i);
+      g[i] = GPol<GS, L>::template ld<R>(B, i * N + sp, i);
     gsb[i] = __builtin_nontemporal_load(adj_g + i * N + sidx(b, x + L::cx(i), y + L::cy(i), z + L::cz(i)));
   }
 #pragma unroll

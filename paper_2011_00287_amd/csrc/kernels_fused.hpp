@@ -137,7 +137,7 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
       const uint32_t zb[3] = {uint32_t(zc_m) * plane_gs, uint32_t(zc_0) * plane_gs, uint32_t(zc_p) * plane_gs};
 #pragma unroll
       for (int i = 0; i < L::Q; ++i)
-        g[i] = GPolO<GS>::template ld<R>(Bin + size_t(i) * N, zb[1 - L::cz(i)] + colb[1 - L::cy(i)][1 - L::cx(i)], i);
+        g[i] = GPolO<GS, L>::template ld<R>(Bin + size_t(i) * N, zb[1 - L::cz(i)] + colb[1 - L::cy(i)][1 - L::cx(i)], i);
     }
     const bool refill = p < z1;
     R nphi[KR], nq[KR][5];
@@ -288,7 +288,7 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
         drho = collide_site(P, g, F, u);
       const uint32_t sg = uint32_t(zc) * plane_gs + own_g, sr = uint32_t(zc) * plane_r + own_r;
 #pragma unroll
-      for (int i = 0; i < L::Q; ++i) GPolO<GS>::template st<R>(Bout + size_t(i) * N, sg, i, g[i]);
+      for (int i = 0; i < L::Q; ++i) GPolO<GS, L>::template st<R>(Bout + size_t(i) * N, sg, i, g[i]);
 #pragma unroll
       for (int a = 0; a < 3; ++a) sto(u_out + size_t(a) * N, sr, u[a]);
       if (F_out) {  // recording step (adjoint replay): keep the force of this plane

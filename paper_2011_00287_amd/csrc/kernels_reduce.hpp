@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(256) k_totals(Box b, Params<double> P, const G
     double sum = 0.0, j[3] = {0.0, 0.0, 0.0};
     for (int i = 0; i < L::Q; ++i) {
       const double gi =
-          double(GPol<GS>::template ld<R>(B, i * N + sidx(b, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i));
+          double(GPol<GS, L>::template ld<R>(B, i * N + sidx(b, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i));
       sum += gi;
       j[0] += L::cx(i) * gi;
       j[1] += L::cy(i) * gi;

@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(256) k_collide(Box b, Params<R> P, const GS* _
   R g[L::Q];
 #pragma unroll
   for (int i = 0; i < L::Q; ++i)
-    g[i] = GPol<GS>::template ld<R>(Bin, i * N + sidx(b, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i);
+    g[i] = GPol<GS, L>::template ld<R>(Bin, i * N + sidx(b, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i);
   R u[3];
   if constexpr (L::kStressInEq) {
     const R S[6] = {sig[s], R(0.5) * (sig[N + s] + sig[3 * N + s]), R(0.5) * (sig[2 * N + s] + sig[6 * N + s]),
@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(256) k_collide(Box b, Params<R> P, const GS* _
     collide_site(P, g, F, u);
   }
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) GPol<GS>::template st<R>(Bout, i * N + s, i, g[i]);
+  for (int i = 0; i < L::Q; ++i) GPol<GS, L>::template st<R>(Bout, i * N + s, i, g[i]);
 #pragma unroll
   for (int a = 0; a < 3; ++a) u_out[a * N + s] = u[a];
 }
@@ -209,7 +209,7 @@ __global__ void k_pull(Box b, const GS* __restrict__ B, R* __restrict__ g) {
   const size_t N = b.N;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i)
-    g[i * N + s] = GPol<GS>::template ld<R>(B, i * N + sidx(b, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i);
+    g[i * N + s] = GPol<GS, L>::template ld<R>(B, i * N + sidx(b, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i);
 }
 
 // B_i(x) = g_i(x + c_i): the inverse of the pull, from float64 deviations.
@@ -222,7 +222,7 @@ __global__ void k_push(Box b, const double* __restrict__ g, GS* __restrict__ B) 
   const size_t N = b.N;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i)
-    GPol<GS>::template st<double>(B, i * N + s, i, g[i * N + sidx(b, x + L::cx(i), y + L::cy(i), z + L::cz(i))]);
+    GPol<GS, L>::template st<double>(B, i * N + s, i, g[i * N + sidx(b, x + L::cx(i), y + L::cy(i), z + L::cz(i))]);
 }
 
 // Second-order equilibrium deviations of (rho0, u0) in float64 (Eq. (11) with
@@ -257,7 +257,7 @@ __global__ void k_moments(Box b, Params<R> P, const GS* __restrict__ B, const R*
   R sum = R(0), j[3] = {R(0), R(0), R(0)};
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
-    const R gi = GPol<GS>::template ld<R>(B, i * N + sidx(b, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i);
+    const R gi = GPol<GS, L>::template ld<R>(B, i * N + sidx(b, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i);
     sum += gi;
     j[0] += R(L::cx(i)) * gi;
     j[1] += R(L::cy(i)) * gi;

@@ -124,8 +124,6 @@ void validate(const lb_params& p) {
   if (p.nx < 3 || p.ny < 3 || p.nz < 3) fail(LB_EINVAL, "box sides must be >= 3");
   if (p.prec < LB_FP64 || p.prec > LB_FP16S) fail(LB_EINVAL, "unknown precision");
   if (p.lattice != LB_D3Q19 && p.lattice != LB_D3Q15) fail(LB_EINVAL, "unknown lattice");
-  if (p.lattice == LB_D3Q15 && p.prec == LB_FP16S)
-    fail(LB_EINVAL, "float16 population storage is scaled for the D3Q19 weights");
   if (p.fd_scheme != LB_FD_EULER2 && p.fd_scheme != LB_FD_PC4) fail(LB_EINVAL, "unknown fd_scheme");
   if (!finite_params(p)) fail(LB_EINVAL, "non-finite parameter");
   if (!(p.tau > 0.5)) fail(LB_EINVAL, "tau must be > 0.5");
@@ -969,6 +967,7 @@ std::unique_ptr<Backend> make_backend(const lb_params& p, hipStream_t s) {
       if (p.lattice == LB_D3Q15) return std::unique_ptr<Backend>(new BackendT<float, float, float, lbc::D3Q15>(p, s));
       return std::unique_ptr<Backend>(new BackendT<float, float, float, lbc::D3Q19>(p, s));
     default:
+      if (p.lattice == LB_D3Q15) return std::unique_ptr<Backend>(new BackendT<float, __half, float, lbc::D3Q15>(p, s));
       return std::unique_ptr<Backend>(new BackendT<float, __half, float, lbc::D3Q19>(p, s));
   }
 }

@@ -20,9 +20,10 @@ __device__ __forceinline__ void sto(T* __restrict__ base, uint32_t byteoff, T v)
 }
 
 // Population storage.  float64 / float32 store the deviation g_i itself;
-// float16 stores g_i * 64 / w_i, which keeps the typical O(1e-4 .. 1e-1)
-// values of g_i / w_i inside the normal range of the format.
-template <class GS>
+// float16 stores g_i * 64 / w_i (w_i the weights of lattice L), which keeps
+// the typical O(1e-4 .. 1e-1) values of g_i / w_i inside the normal range of
+// the format.
+template <class GS, class L = D3Q19>
 struct GPol {
   template <class R>
   __device__ __forceinline__ static R ld(const GS* p, size_t k, int) { return R(p[k]); }
@@ -43,7 +44,7 @@ __device__ __forceinline__ void sto_nt(T* __restrict__ base, uint32_t byteoff, T
   __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byteoff));
 }
 
-template <class GS>
+template <class GS, class L = D3Q19>
 struct GPolO {
   // element of the population array starting at base, by byte offset (streaming)
   template <class R>
@@ -51,28 +52,28 @@ struct GPolO {
   template <class R>
   __device__ __forceinline__ static void st(GS* base, uint32_t off, int, R v) { sto_nt(base, off, GS(v)); }
 };
-template <>
-struct GPolO<__half> {
+template <class L>
+struct GPolO<__half, L> {
   // ordinary (cached) access: 16-bit streaming accesses measured much slower
   template <class R>
   __device__ __forceinline__ static R ld(const __half* base, uint32_t off, int i) {
-    return R(__half2float(ldo(base, off))) * (WQ<R>(i) * R(1.0 / 64.0));
+    return R(__half2float(ldo(base, off))) * (L::template w<R>(i) * R(1.0 / 64.0));
   }
   template <class R>
   __device__ __forceinline__ static void st(__half* base, uint32_t off, int i, R v) {
-    sto(base, off, __float2half(float(v * (R(64) / WQ<R>(i)))));
+    sto(base, off, __float2half(float(v * (R(64) / L::template w<R>(i)))));
   }
 };
 
-template <>
-struct GPol<__half> {
+template <class L>
+struct GPol<__half, L> {
   template <class R>
   __device__ __forceinline__ static R ld(const __half* p, size_t k, int i) {
-    return R(__half2float(p[k])) * (WQ<R>(i) * R(1.0 / 64.0));
+    return R(__half2float(p[k])) * (L::template w<R>(i) * R(1.0 / 64.0));
   }
   template <class R>
   __device__ __forceinline__ static void st(__half* p, size_t k, int i, R v) {
-    p[k] = __float2half(float(v * (R(64) / WQ<R>(i))));
+    p[k] = __float2half(float(v * (R(64) / L::template w<R>(i))));
   }
 };
 

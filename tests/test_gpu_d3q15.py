@@ -178,14 +178,11 @@ def test_bitwise_determinism_and_resume():
             assert np.array_equal(x, y)
 
 
-def test_rejected_combinations(monkeypatch):
-    """float16 population storage is D3Q19-only, and the D3Q15 adjoint runs on the
-    fused kernels only: both are refused with LB_EINVAL (the forward still runs)."""
+def test_site_kernel_adjoint_refused(monkeypatch):
+    """The D3Q15 adjoint runs on the fused kernels only: with the site-parallel test
+    kernels it is refused with LB_EINVAL (the forward still runs)."""
     p = _p()
     phi, q5 = inputs.droplet_fields(6, 6, 6, 2.0, 0.5)
-    with pytest.raises(LbError) as e:
-        Sim(p, phi, q5, precision="fp16s", lattice="d3q15")
-    assert e.value.status == LB_EINVAL
     monkeypatch.setenv("LBC_SITE_KERNELS", "1")
     with Sim(p, phi, q5, lattice="d3q15") as s:
         assert s.adjoint_buffer().numel() == 0 and s.record_buffer().numel() == 0
@@ -194,3 +191,41 @@ def test_rejected_combinations(monkeypatch):
         assert e.value.status == LB_EINVAL
         s.step(2)
         assert s.totals()["step"] == 2
+
+
+def test_fp16s_conservation_and_resume():
+    """float16 population storage on the D3Q15 scheme (g_i * 64 / w_i with the D3Q15
+    weights): mass, momentum and sum(phi) over 200 steps as for D3Q19 FP16S, and a
+    bitwise resume from a saved state."""
+    p = inputs.params_for("droplet16")
+    phi, q5 = inputs.workload_fields("droplet16")
+    with Sim(p, phi, q5, precision="fp16s", lattice="d3q15") as s, \
+            Sim(p, phi, q5, precision="fp16s", lattice="d3q15") as b:
+        t0 = s.totals()
+        s.step(20)
+        ck = s.get_state()
+        s.step(180)
+        t1 = s.totals()
+        b.set_state(ck)
+        b.step(180)
+        for x, y in zip(s.moments(), b.moments()):
+            assert np.array_equal(x, y)
+    assert abs(t1["mass"] - t0["mass"]) <= 1e-3 * t0["mass"]
+    assert abs(t1["phi_total"] - t0["phi_total"]) <= 1e-3 * t0["phi_total"]
+    for a in range(3):
+        assert abs(t1["momentum"][a] - t0["momentum"][a]) <= 1e-3 * t0["mass"]
+
+
+def test_fp16s_accuracy_droplet16():
+    """Stated accuracy of float16 population storage on the D3Q15 scheme against its
+    FP64 path after 100 steps of the 16^3 droplet (the D3Q19 FP16S bound, 5e-2)."""
+    p = inputs.params_for("droplet16")
+    phi, q5 = inputs.workload_fields("droplet16")
+    with Sim(p, phi, q5, precision="fp64", lattice="d3q15") as a, \
+            Sim(p, phi, q5, precision="fp16s", lattice="d3q15") as b:
+        a.step(100)
+        b.step(100)
+        ea = field_errors(b.moments(), a.moments(), p["rho0"])
+    print(ea)
+    for name, (l2, mx) in ea.items():
+        assert l2 <= 5e-2, (name, l2, mx)
