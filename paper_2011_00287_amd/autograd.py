@@ -193,11 +193,11 @@ def backward_segments_lean(sim: Sim, ckpts, steps: int, checkpoint: int, adj):
 
 class _DropletRollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, zeta, q0, q5, params, phi, steps, checkpoint, precision, lattice):
+    def forward(ctx, zeta, q0, q5, params, phi, steps, checkpoint, precision, lattice, fd_scheme):
         p = dict(params, zeta=float(zeta), q0=float(q0))
         q5_np = q5.detach().to("cpu", torch.float64).numpy()
         sim = Sim(p, np.asarray(phi, dtype=np.float64), q5_np, precision=precision, lattice=lattice,
-                  stream=torch.cuda.current_stream())
+                  fd_scheme=fd_scheme, stream=torch.cuda.current_stream())
         zc0 = float(sim.centre()[0][2])
         ckpts = run_lean(sim, steps) if checkpoint == 0 else run_segments(sim, steps, checkpoint)
         zcT = float(sim.centre()[0][2])
@@ -222,17 +222,18 @@ class _DropletRollout(torch.autograd.Function):
         sim.close()
         ctx.sim = ctx.ckpts = None
         return (torch.tensor(g * zb, dtype=torch.float64), torch.tensor(g * qb, dtype=torch.float64), q5_grad,
-                None, None, None, None, None, None)
+                None, None, None, None, None, None, None)
 
 
 def displacement_loss(zeta, q0, q5, *, params: dict, phi, steps: int, checkpoint: int = 20,
-                      precision: str = "fp32", lattice: str = "d3q19"):
+                      precision: str = "fp32", lattice: str = "d3q19", fd_scheme: str = "euler2"):
     """Squared z-displacement of the droplet centre after `steps` steps (differentiable).
 
     zeta, q0: 0-dim tensors; q5: [5, nz, ny, nx] tensor (CPU or CUDA); phi: numpy
     [nz, ny, nx]; params: the model parameter dict (its zeta / q0 are replaced).
     checkpoint: states kept every `checkpoint` steps and segments replayed in the
     reverse pass; 0 keeps the lean record of every step instead (no replay).
-    lattice: 'd3q19' or the paper's 'd3q15' scheme.
+    lattice: 'd3q19' or the paper's 'd3q15' scheme; fd_scheme: 'euler2' or the paper's
+    predictor-corrector 'pc4'.
     """
-    return _DropletRollout.apply(zeta, q0, q5, params, phi, steps, checkpoint, precision, lattice)
+    return _DropletRollout.apply(zeta, q0, q5, params, phi, steps, checkpoint, precision, lattice, fd_scheme)

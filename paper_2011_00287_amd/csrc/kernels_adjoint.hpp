@@ -359,9 +359,10 @@ k_adj_order_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __rest
 // Where the velocity adjoint u_bar comes from.  Site path (fused == 0): the
 // order kernel's local part u (ubp [3][N]) and W_bar (W [9][N]), and
 //   u_bar_a = ubp_a - sum_c D0_c W_bar_ac.
-// Fused path: k_adj_order_fused's u (u_bar with the in-plane transposes from
-// inside its TX x TY tiles) and W = W_bar_az [3][N]; the z transpose and the
-// tile-face terms (hx, hy: the edge sites' W_bar_ax, W_bar_ay) are added here.
+// Fused path (fused == 1): k_adj_order_fused's u (u_bar with the in-plane
+// transposes from inside its TX x TY tiles) and W = W_bar_az [3][N]; the z
+// transpose and the tile-face terms (hx, hy: the edge sites' W_bar_ax,
+// W_bar_ay) are added here.  fused == 2: u is the whole u_bar (the pc4 reverse).
 template <class R>
 struct UbarIn {
   const R* W;
@@ -377,6 +378,7 @@ __device__ __forceinline__ void ubar_at(const Box& b, const UbarIn<R>& in, int s
   const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
 #pragma unroll
   for (int a = 0; a < 3; ++a) ub[a] = in.u[a * N + s];
+  if (in.fused == 2) return;
   if (!in.fused) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {

@@ -1,0 +1,267 @@
+// Reverse of the paper's finite-difference integrator of the order parameters
+// (Sec. 3: Heun predictor-corrector, first-order upwind advection, fourth-order
+// stencils; the forward is kernels_pc.hpp).
+//
+// Forward, with u the LB velocity of time t in both stages:
+//   X* = X + R(X),   X(t+1) = ((X + X*) + R(X*))/2,
+//   R_Q   = -upwind(u, Q) + S(D4 u, Q) + Gamma H4(Q, phi),
+//   R_phi = -div_donor(u, phi) + M L4 mu4(phi, Q),
+//   mu4   = mu_site(phi, L4 phi, D4 . v, Q),  v = Q D4 phi.
+// Reverse, given X_bar(t+1):
+//   X*_bar = X_bar(t+1)/2 + R'(X*)^T V2,          V2 = X_bar(t+1)/2,
+//   X_bar  = X_bar(t+1)/2 + X*_bar + R'(X)^T X*_bar,
+//   u_bar  = the u parts of both products.
+// One product R'(X)^T V takes three site-parallel passes:
+//   k_pcb_local: the local reverses at each site (H4 through local_thermo_bwd
+//     with H_bar = Gamma V_Q, the co-rotation, mu4 with mu_bar = M L4 V_phi, the
+//     site's own upwind terms) -> the adjoints of the site's stencil data
+//     (D4 phi, D4 Q, L4 Q, L4 phi, D4 . v, W = D4 u) and its local adjoints;
+//   k_pcb_v: v_bar = -D4 (D4.v)_bar (D4^T = -D4), then the adjoints of Q and D4 phi
+//     through v = Q D4 phi;
+//   k_pcb_gather: the transposed stencils (D4^T = -D4, L4^T = L4) of those
+//     adjoints, and the neighbour terms of the upwind and donor-cell operators.
+// The upwind and donor-cell terms are max(w, 0) a + min(w, 0) b of a velocity
+// w; at w = 0 their w-derivative is taken as a + b (both one-sided parts), the
+// convention of the clamp form the oracle writes them in.
+#pragma once
+#include "adjoint.hpp"
+#include "kernels_pc.hpp"
+#include "kernels_reduce.hpp"
+
+namespace lbc {
+
+// fields of the per-site scratch of one product (arithmetic type, [NPB][N])
+constexpr int PB_DPHI = 0;     // adjoint of D4 phi (3)
+constexpr int PB_DQ = 3;       // adjoint of D4_g Q_k at 3 + 5 g + k (15)
+constexpr int PB_LAPQ = 18;    // adjoint of L4 Q (5)
+constexpr int PB_LAPPHI = 23;  // adjoint of L4 phi in mu4
+constexpr int PB_DIVV = 24;    // adjoint of D4 . v in mu4
+constexpr int PB_W = 25;       // adjoint of W_ag = D4_g u_a at 25 + 3 a + g (9)
+constexpr int PB_Q = 34;       // local adjoint of Q (5)
+constexpr int PB_PHI = 39;     // local adjoint of phi
+constexpr int PB_U = 40;       // local adjoint of u (upwind) (3)
+constexpr int NPB = 43;
+
+// The local reverses of R at each site for the adjoint V = vs (vq, vphi) of R.
+// partial: one float64 (zeta, q0) pair per block, overwritten (accumulate = 0)
+// or added to (accumulate = 1); R depends on q0 through H4 and not on zeta.
+template <class R, class FS>
+__global__ void __launch_bounds__(256) k_pcb_local(Box b, Params<R> P, const FS* __restrict__ phi,
+                                                   const FS* __restrict__ q, const R* __restrict__ u,
+                                                   const R* __restrict__ vq, const R* __restrict__ vphi, R vs,
+                                                   R* __restrict__ pb, double* __restrict__ partial,
+                                                   int accumulate) {
+  const int s = site_xcd();
+  double v2[2] = {0.0, 0.0};
+  if (s < b.N) {
+    int x, y, z;
+    coords(b, s, x, y, z);
+    const size_t N = b.N;
+    int n[3][4];
+    star2(b, x, y, z, n);
+    Grad<R> G;
+    G.phi = R(phi[s]);
+    G.lapphi = R(0);
+    G.divv = R(0);
+    R qm1[3][5], qp1[3][5], W[3][3], uc[3];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      G.q[k] = R(q[k * N + s]);
+      G.lapq[k] = R(-7.5) * G.q[k];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) uc[a] = u[a * N + s];
+    R lapv = R(-7.5) * vphi[s];
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      G.dphi[g] = d4c(R(phi[n[g][0]]), R(phi[n[g][1]]), R(phi[n[g][2]]), R(phi[n[g][3]]));
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const FS* qk = q + size_t(k) * N;
+        const R m2 = R(qk[n[g][0]]), m1 = R(qk[n[g][1]]), p1 = R(qk[n[g][2]]), p2 = R(qk[n[g][3]]);
+        G.dq[g][k] = d4c(m2, m1, p1, p2);
+        G.lapq[k] += l4c(m2, m1, p1, p2);
+        qm1[g][k] = m1;
+        qp1[g][k] = p1;
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const R* ua = u + size_t(a) * N;
+        W[a][g] = d4c(ua[n[g][0]], ua[n[g][1]], ua[n[g][2]], ua[n[g][3]]);
+      }
+      lapv += l4c(vphi[n[g][0]], vphi[n[g][1]], vphi[n[g][2]], vphi[n[g][3]]);
+    }
+    R VQ[5], hb[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      VQ[k] = vs * vq[k * N + s];
+      hb[k] = P.Gamma * VQ[k];
+    }
+    const R mub = P.M * vs * lapv;  // (M L4)^T V_phi = M L4 V_phi
+    // H4 through local_thermo
+    Local<R> Lc;
+    local_thermo(P, G, Lc);
+    GradBar<R> Gb;
+    Gb.zero();
+    ParBar<R> Pb{R(0), R(0), R(0)};
+    local_thermo_bwd(P, G, Lc, hb, R(0), R(0), R(0), R(0), R(0), Gb, Pb);
+    // co-rotation S(W, Q)
+    R qb[5], Wb[3][3] = {{R(0), R(0), R(0)}, {R(0), R(0), R(0)}, {R(0), R(0), R(0)}};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) qb[k] = Gb.q[k];
+    corotation_site_bwd(P.xi, G.q, W, VQ, qb, Wb);
+    // mu4 (its own adjoints of L4 phi and D4 . v go to the next passes)
+    R phb = Gb.phi, lapphib = R(0), divvb = R(0);
+    mu_site_bwd(P, G.phi, G.q, mub, phb, lapphib, divvb, qb);
+    // the site's own upwind terms: R_Q gets -sum_g max(u_g,0)(Q - Q(x-e_g)) + min(u_g,0)(Q(x+e_g) - Q)
+    R ub[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      const R ug = uc[g], up = ug > R(0) ? ug : R(0), um = ug < R(0) ? ug : R(0);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const R a = -VQ[k];
+        const R back = G.q[k] - qm1[g][k], fwd = qp1[g][k] - G.q[k];
+        qb[k] += a * (up - um);
+        ub[g] += a * ((ug >= R(0) ? back : R(0)) + (ug <= R(0) ? fwd : R(0)));
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < 3; ++g) pb[(PB_DPHI + g) * N + s] = Gb.dphi[g];
+#pragma unroll
+    for (int g = 0; g < 3; ++g)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) pb[(PB_DQ + 5 * g + k) * N + s] = Gb.dq[g][k];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) pb[(PB_LAPQ + k) * N + s] = Gb.lapq[k];
+    pb[PB_LAPPHI * N + s] = lapphib;
+    pb[PB_DIVV * N + s] = divvb;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int g = 0; g < 3; ++g) pb[(PB_W + 3 * a + g) * N + s] = Wb[a][g];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) pb[(PB_Q + k) * N + s] = qb[k];
+    pb[PB_PHI * N + s] = phb;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) pb[(PB_U + a) * N + s] = ub[a];
+    par_adjoints(P, Pb, v2);
+  }
+  block_reduce_store<2>(v2, partial + size_t(blockIdx.x) * 2, accumulate != 0);
+}
+
+// v = Q D4 phi: v_bar = D4^T (D4 . v)_bar = -D4 (D4 . v)_bar, then
+// Q_bar_ab += v_bar_a D4_b phi and (D4 phi)_bar_b += Q_ab v_bar_a at the site.
+template <class R, class FS>
+__global__ void __launch_bounds__(256) k_pcb_v(Box b, const FS* __restrict__ phi, const FS* __restrict__ q,
+                                               R* __restrict__ pb) {
+  const int s = site_xcd();
+  if (s >= b.N) return;
+  int x, y, z;
+  coords(b, s, x, y, z);
+  const size_t N = b.N;
+  int n[3][4];
+  star2(b, x, y, z, n);
+  const R* dv = pb + size_t(PB_DIVV) * N;
+  R vb[3], dp[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    vb[a] = -d4c(dv[n[a][0]], dv[n[a][1]], dv[n[a][2]], dv[n[a][3]]);
+    dp[a] = d4c(R(phi[n[a][0]]), R(phi[n[a][1]]), R(phi[n[a][2]]), R(phi[n[a][3]]));
+  }
+  const R xx = R(q[s]), xy = R(q[N + s]), xz = R(q[2 * N + s]), yy = R(q[3 * N + s]), yz = R(q[4 * N + s]);
+  const R zz = -xx - yy;
+  const R Qm[3][3] = {{xx, xy, xz}, {xy, yy, yz}, {xz, yz, zz}};
+  R Qb[3][3], qb[5] = {R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Qb[a][c] = vb[a] * dp[c];
+    pb[(PB_DPHI + a) * N + s] += Qm[a][0] * vb[0] + Qm[a][1] * vb[1] + Qm[a][2] * vb[2];
+  }
+  full_to_stored(Qb, qb);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) pb[(PB_Q + k) * N + s] += qb[k];
+}
+
+// The transposed stencils and neighbour terms of one product, combined with
+// the Heun weights: out = c1 X_bar(t+1) + c2 Xs + R'^T V at each site, and
+// u_bar (ub_out) written (accumulate = 0) or added to (accumulate = 1).
+// phi, u: the stage's phi and the velocity; V = vs (vq, vphi).
+template <class R, class FS>
+__global__ void __launch_bounds__(256) k_pcb_gather(Box b, const FS* __restrict__ phi, const R* __restrict__ u,
+                                                    const R* __restrict__ vq, const R* __restrict__ vphi, R vs,
+                                                    const R* __restrict__ pb, const R* __restrict__ xq1,
+                                                    const R* __restrict__ xp1, R c1, const R* __restrict__ xsq,
+                                                    const R* __restrict__ xsp, R c2, R* __restrict__ q_out,
+                                                    R* __restrict__ phi_out, R* __restrict__ ub_out,
+                                                    int accumulate) {
+  const int s = site_xcd();
+  if (s >= b.N) return;
+  int x, y, z;
+  coords(b, s, x, y, z);
+  const size_t N = b.N;
+  int n[3][4];
+  star2(b, x, y, z, n);
+  auto l4t = [&](const R* f) {  // L4^T = L4
+    R r = R(-7.5) * f[s];
+#pragma unroll
+    for (int g = 0; g < 3; ++g) r += l4c(f[n[g][0]], f[n[g][1]], f[n[g][2]], f[n[g][3]]);
+    return r;
+  };
+  auto d4t = [&](const R* f, int g) { return -d4c(f[n[g][0]], f[n[g][1]], f[n[g][2]], f[n[g][3]]); };
+  R qo[5], po, ub[3];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    R r = pb[(PB_Q + k) * N + s] + l4t(pb + size_t(PB_LAPQ + k) * N);
+#pragma unroll
+    for (int g = 0; g < 3; ++g) r += d4t(pb + size_t(PB_DQ + 5 * g + k) * N, g);
+    qo[k] = r;
+  }
+  {
+    R r = pb[PB_PHI * N + s] + l4t(pb + size_t(PB_LAPPHI) * N);
+#pragma unroll
+    for (int g = 0; g < 3; ++g) r += d4t(pb + size_t(PB_DPHI + g) * N, g);
+    po = r;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    R r = pb[(PB_U + a) * N + s];
+#pragma unroll
+    for (int g = 0; g < 3; ++g) r += d4t(pb + size_t(PB_W + 3 * a + g) * N, g);
+    ub[a] = r;
+  }
+  const R ph = R(phi[s]), vp0 = vs * vphi[s];
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    const int m1 = n[g][1], p1 = n[g][2];
+    const R* ug = u + size_t(g) * N;
+    // upwind terms of the neighbours: x = y + e_g reads Q(y) backward, x = y - e_g forward
+    const R upx = ug[p1] > R(0) ? ug[p1] : R(0), umx = ug[m1] < R(0) ? ug[m1] : R(0);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) qo[k] += (vs * vq[k * N + p1]) * upx - (vs * vq[k * N + m1]) * umx;
+    // donor-cell faces y + e_g/2 and y - e_g/2; the flux's adjoint is V_phi(right) - V_phi(left)
+    const R fp = R(0.5) * (ug[s] + ug[p1]), fm = R(0.5) * (ug[m1] + ug[s]);
+    const R cp = vs * vphi[p1] - vp0, cm = vp0 - vs * vphi[m1];
+    const R php = R(phi[p1]), phm = R(phi[m1]);
+    po += cp * (fp > R(0) ? fp : R(0)) + cm * (fm < R(0) ? fm : R(0));
+    const R dfp = (fp >= R(0) ? ph : R(0)) + (fp <= R(0) ? php : R(0));
+    const R dfm = (fm >= R(0) ? phm : R(0)) + (fm <= R(0) ? ph : R(0));
+    ub[g] += R(0.5) * (cp * dfp + cm * dfm);
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    R r = c1 * xq1[k * N + s] + qo[k];
+    if (xsq) r += c2 * xsq[k * N + s];
+    q_out[k * N + s] = r;
+  }
+  {
+    R r = c1 * xp1[s] + po;
+    if (xsp) r += c2 * xsp[s];
+    phi_out[s] = r;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ub_out[a * N + s] = accumulate ? ub_out[a * N + s] + ub[a] : ub[a];
+}
+
+}  // namespace lbc

@@ -19,6 +19,7 @@
 #include "kernels_adjoint.hpp"
 #include "kernels_fused.hpp"
 #include "kernels_pc.hpp"
+#include "kernels_pc_adjoint.hpp"
 #include "kernels_reduce.hpp"
 
 namespace {
@@ -217,6 +218,10 @@ struct BackendT final : Backend {
   R* aSb = nullptr;  // D3Q15: adjoint of the symmetric stress S_ab in the collision, [6][N]
   R* ahxw = nullptr;  // the order adjoint's W_bar_ax of tile-edge columns (x tiles > 1)
   R* ahyw = nullptr;  // its W_bar_ay of tile-edge rows (y tiles > 1)
+  R* apb = nullptr;    // pc4 reverse: per-site adjoints of one product's stencil data [NPB][N]
+  R* axs = nullptr;    // pc4 reverse: X*_bar [6][N]
+  R* aupc = nullptr;   // pc4 reverse: u_bar [3][N]
+  R* azero = nullptr;  // pc4 reverse: zeros [6][N]
   double* apart = nullptr;   // per-block (zeta, q0) adjoint partials, kept across reverse steps
   size_t apart_n = 0;        // doubles in apart
   bool apart_live = false;   // apart holds sums not yet fetched by the caller
@@ -352,7 +357,7 @@ struct BackendT final : Backend {
     pcv = nullptr;
     mu = H = sig = u = nullptr;
     partial = sums = nullptr;
-    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &ahxw, &ahyw};
+    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &ahxw, &ahyw, &apb, &axs, &aupc, &azero};
     for (R** a : adj) {
       dfree(*a);
       *a = nullptr;
@@ -501,19 +506,23 @@ struct BackendT final : Backend {
     lbc::k_pc_mu_z<R, FS, TX, TY, MINW><<<pm_blocks, TX * TY, 0, stream>>>(box, P, tz_pm, pm_ntx, pm_nty, phi_i,
                                                                            q_i, mu);
   }
+  // one Heun stage on explicit buffers with the velocity uu (the context's u by default)
   template <bool PRED>
-  void launch_pc_stage(const FS* phi_i, const FS* q_i, const FS* phi_x, const FS* q_x, FS* phi_o, FS* q_o) {
+  void launch_pc_stage(const FS* phi_i, const FS* q_i, const FS* phi_x, const FS* q_x, FS* phi_o, FS* q_o,
+                       const R* uu = nullptr) {
+    if (!uu) uu = u;
     switch (pc_tile) {
-      case 0: launch_pc_tile<32, 8, 2, PRED>(phi_i, q_i, phi_x, q_x, phi_o, q_o); break;
-      case 1: launch_pc_tile<32, 16, 2, PRED>(phi_i, q_i, phi_x, q_x, phi_o, q_o); break;
-      case 2: launch_pc_tile<16, 16, 2, PRED>(phi_i, q_i, phi_x, q_x, phi_o, q_o); break;
-      default: launch_pc_tile<64, 8, 2, PRED>(phi_i, q_i, phi_x, q_x, phi_o, q_o); break;
+      case 0: launch_pc_tile<32, 8, 2, PRED>(phi_i, q_i, phi_x, q_x, phi_o, q_o, uu); break;
+      case 1: launch_pc_tile<32, 16, 2, PRED>(phi_i, q_i, phi_x, q_x, phi_o, q_o, uu); break;
+      case 2: launch_pc_tile<16, 16, 2, PRED>(phi_i, q_i, phi_x, q_x, phi_o, q_o, uu); break;
+      default: launch_pc_tile<64, 8, 2, PRED>(phi_i, q_i, phi_x, q_x, phi_o, q_o, uu); break;
     }
   }
   template <int TX, int TY, int MINW, bool PRED>
-  void launch_pc_tile(const FS* phi_i, const FS* q_i, const FS* phi_x, const FS* q_x, FS* phi_o, FS* q_o) {
+  void launch_pc_tile(const FS* phi_i, const FS* q_i, const FS* phi_x, const FS* q_x, FS* phi_o, FS* q_o,
+                      const R* uu) {
     lbc::k_pc_stage_z<R, FS, TX, TY, MINW, PRED><<<pc_blocks, TX * TY, 0, stream>>>(
-        box, P, tz_pc, pc_ntx, pc_nty, phi_i, q_i, u, mu, phi_x, q_x, phi_o, q_o);
+        box, P, tz_pc, pc_ntx, pc_nty, phi_i, q_i, uu, mu, phi_x, q_x, phi_o, q_o);
   }
   void launch(int k) {
     const int nx = cur ^ 1;
@@ -590,9 +599,21 @@ struct BackendT final : Backend {
         box, P, tz_or, or_ntx, or_nty, io.phi_i, io.q_i, io.u, mu, io.phi_o, io.q_o);
   }
   // the fused pair on explicit buffers
+  // the whole Heun update of one step on the buffers of io (z-marching kernels)
+  void pc_update(const Io& io) {
+    FS* qs = pcs;
+    FS* phs = pcs + 5 * N;
+    launch_pc_mu(io.phi_i, io.q_i);
+    launch_pc_stage<true>(io.phi_i, io.q_i, nullptr, nullptr, phs, qs, io.u);
+    launch_pc_mu(phs, qs);
+    launch_pc_stage<false>(phs, qs, io.phi_i, io.q_i, io.phi_o, io.q_o, io.u);
+  }
   void fused_step(const Io& io) {
     launch_lb_tile(io);
-    launch_or_tile(io);
+    if (pc4)
+      pc_update(io);
+    else
+      launch_or_tile(io);
   }
   void step(int n) override {
     const int nk = nkernels();
@@ -718,11 +739,12 @@ struct BackendT final : Backend {
 
   // --- adjoint ---------------------------------------------------------------
   // adjoint buffer: g_bar [NQ][N], q_bar [5][N], phi_bar [N] in R.  The
-  // D3Q15 scheme's reverse exists for the fused kernels only.
-  bool has_adjoint() const { return !pc4 && !(L::kStressInEq && site_path); }
+  // reverses of the D3Q15 scheme and of the pc4 integrator exist for the
+  // fused kernels only.
+  bool has_adjoint() const { return !(site_path && (pc4 || L::kStressInEq)); }
   void need_adjoint() const {
     if (!has_adjoint())
-      fail(LB_EINVAL, "the adjoint is implemented for the Euler integrator (D3Q15: fused kernels only)");
+      fail(LB_EINVAL, "the adjoint of the D3Q15 scheme and of the pc4 integrator needs the fused kernels");
   }
   size_t adjoint_bytes() const override { return has_adjoint() ? (NQ + 6) * N * sizeof(R) : 0; }
   void ensure_adjoint() {
@@ -737,18 +759,26 @@ struct BackendT final : Backend {
       aFb = dalloc<R>(3 * N);
       if (site_path) agbar = dalloc<R>(size_t(lbc::NGB) * N);  // the fused kernel keeps it on chip
       if (L::kStressInEq) aSb = dalloc<R>(6 * N);  // adjoint of the symmetric stress in the collision
+      if (pc4) {
+        apb = dalloc<R>(size_t(lbc::NPB) * N);  // per-site scratch of one R'^T V product
+        axs = dalloc<R>(6 * N);                 // X*_bar: q [5][N], phi [N]
+        aupc = dalloc<R>(3 * N);                // u_bar of both Heun stages
+        azero = dalloc<R>(6 * N);               // zero Q_bar(t+1), mu_bar for the stress kernel
+        HIPCHECK(hipMemsetAsync(azero, 0, 6 * N * sizeof(R), stream));
+      }
       if (!site_path && as_ntx > 1) ahx = dalloc<R>(24 * size_t(as_ntx) * box.nz * box.ny);
       if (!site_path && ao_ntx > 1) ahxw = dalloc<R>(6 * size_t(ao_ntx) * box.nz * box.ny);
       if (!site_path && ao_nty > 1) ahyw = dalloc<R>(6 * size_t(ao_nty) * box.nz * box.nx);
       if (!site_path && as_nty > 1) ahy = dalloc<R>(12 * size_t(as_nty) * box.nz * box.nx);
       // one (zeta, q0) pair per block of whichever reverse kernel writes them
-      const size_t npart = size_t(std::max<int>(int(nblk), as_blocks)) * 2;
+      // pc4: the stress kernel's blocks, then those of k_pcb_local
+      const size_t npart = size_t(pc4 ? as_blocks + int(nblk) : std::max<int>(int(nblk), as_blocks)) * 2;
       apart = dalloc<double>(npart);
       apart_n = npart;
       HIPCHECK(hipMemsetAsync(apart, 0, npart * sizeof(double), stream));
       apart_live = false;
     } catch (...) {
-      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &ahxw, &ahyw};
+      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &ahxw, &ahyw, &apb, &axs, &aupc, &azero};
       for (R** a : adj) {
         dfree(*a);
         *a = nullptr;
@@ -837,6 +867,54 @@ struct BackendT final : Backend {
     const R* rF = reinterpret_cast<const R*>(c + lr_F());
     reverse_kernels(rphi, rq, ru, rF, nullptr, rd, adj_in, adj_out, zeta_bar, q0_bar);
   }
+  // the fused stress + gather adjoint and its tile-face terms; aq: Q_bar(t+1)
+  // for the Euler update's H_bar (zeros under pc4), mb: mu_bar
+  void stress_gather(const FS* phi_t, const FS* q_t, const R* aq, const R* mb, R* po, R* qo) {
+    lbc::k_adj_sg_fused<R, FS, kAsTX, kAsTY, L::kStressInEq><<<as_blocks, kAsTX * kAsTY, 0, stream>>>(
+        box, P, as_tz, as_ntx, as_nty, phi_t, q_t, aFb, aq, mb, aqbp, aphibp, aSb, po, qo, ahx, ahy, apart,
+        apart_live ? 1 : 0);
+    if (as_ntx > 1) {
+      const size_t n = 6 * size_t(as_ntx) * box.nz * box.ny;  // one thread per field
+      lbc::k_adj_face_x<R><<<unsigned((n + TPB - 1) / TPB), TPB, 0, stream>>>(box, kAsTX, as_ntx, ahx, po, qo);
+    }
+    if (as_nty > 1) {
+      const size_t n = 6 * size_t(as_nty) * box.nz * box.nx;  // one thread per field
+      lbc::k_adj_face_y<R><<<unsigned((n + TPB - 1) / TPB), TPB, 0, stream>>>(box, kAsTY, as_nty, ahy, po, qo);
+    }
+  }
+  // Reverse of a step of the pc4 integrator: the predictor is replayed from
+  // X = (phi_t, q_t) with the step's velocity uu, the two Heun products
+  // R'(X*)^T (X_bar(t+1)/2) and R'(X)^T X*_bar give the order parameters' part
+  // of X_bar(t) (in aqbp, aphibp) and u_bar (aupc); then the collision and
+  // the stress reverses (the stress kernel without the Euler update's H_bar
+  // and mu_bar, which pc4 does not use).
+  void reverse_pc4(const FS* phi_t, const FS* q_t, const R* uu, const R* FF, const GS* Bt, const R* drho,
+                   const R* gi, const R* qi, const R* pi, R* go, R* qo, R* po) {
+    FS* qs = pcs;
+    FS* phs = pcs + 5 * N;
+    launch_pc_mu(phi_t, q_t);
+    launch_pc_stage<true>(phi_t, q_t, nullptr, nullptr, phs, qs, uu);
+    double* pl = apart + size_t(as_blocks) * 2;  // k_pcb_local's block partials follow the stress kernel's
+    R* xsq = axs;
+    R* xsp = axs + 5 * N;
+    // X*_bar = X_bar(t+1)/2 + R'(X*)^T (X_bar(t+1)/2)
+    lbc::k_pcb_local<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phs, qs, uu, qi, pi, R(0.5), apb, pl,
+                                                       apart_live ? 1 : 0);
+    lbc::k_pcb_v<R, FS><<<nblk, TPB, 0, stream>>>(box, phs, qs, apb);
+    lbc::k_pcb_gather<R, FS><<<nblk, TPB, 0, stream>>>(box, phs, uu, qi, pi, R(0.5), apb, qi, pi, R(0.5), nullptr,
+                                                        nullptr, R(0), xsq, xsp, aupc, 0);
+    // X_bar = X_bar(t+1)/2 + X*_bar + R'(X)^T X*_bar
+    lbc::k_pcb_local<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phi_t, q_t, uu, xsq, xsp, R(1), apb, pl, 1);
+    lbc::k_pcb_v<R, FS><<<nblk, TPB, 0, stream>>>(box, phi_t, q_t, apb);
+    lbc::k_pcb_gather<R, FS><<<nblk, TPB, 0, stream>>>(box, phi_t, uu, xsq, xsp, R(1), apb, qi, pi, R(0.5), xsq,
+                                                        xsp, R(1), aqbp, aphibp, aupc, 1);
+    lbc::UbarIn<R> ubin{nullptr, aupc, nullptr, nullptr, 0, 0, 0, 0, 2};
+    if (Bt)
+      lbc::k_adj_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, Bt, FF, ubin, gi, go, aFb, aSb);
+    else
+      lbc::k_adj_collide_lean<R, L><<<nblk, TPB, 0, stream>>>(box, P, drho, uu, FF, ubin, gi, go, aFb, aSb);
+    stress_gather(phi_t, q_t, azero, azero + 5 * N, po, qo);
+  }
   // the reverse kernels of one step; the collision adjoint reads the
   // populations B, or (B == nullptr) the recorded density deviation drho
   void reverse_kernels(const FS* phi_t, const FS* q_t, const R* uu, const R* FF, const GS* Bt, const R* drho,
@@ -847,36 +925,30 @@ struct BackendT final : Backend {
     R* go = static_cast<R*>(adj_out);
     R* qo = go + NQ * N;
     R* po = go + (NQ + 5) * N;
-    // site path: W_bar [9][N] and the local u_bar part; fused: W_bar_az [3][N] (in aWb) and
-    // u_bar with the in-plane transposes (in aubp), plus the tile-face terms
-    lbc::UbarIn<R> ubin{aWb, aubp, ahxw, ahyw, kAoTX, kAoTY, ao_ntx, ao_nty, site_path ? 0 : 1};
-    if (site_path)
-      lbc::k_adj_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phi_t, q_t, uu, pi, qi, amub, aWb, aubp, aqbp,
-                                                         aphibp);
-    else
-      lbc::k_adj_order_fused<R, FS, kAoTX, kAoTY><<<ao_blocks, kAoTX * kAoTY, 0, stream>>>(
-          box, P, ao_tz, ao_ntx, ao_nty, phi_t, q_t, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp, ahxw, ahyw);
-    const int npart_blocks = site_path ? int(nblk) : as_blocks;
+    const int npart_blocks = site_path ? int(nblk) : (pc4 ? as_blocks + int(nblk) : as_blocks);
     if (size_t(npart_blocks) * 2 > apart_n) fail(LB_EDEVICE, "adjoint partial buffer smaller than the grid");
-    if (Bt)
-      lbc::k_adj_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, Bt, FF, ubin, gi, go, aFb, aSb);
-    else
-      lbc::k_adj_collide_lean<R, L><<<nblk, TPB, 0, stream>>>(box, P, drho, uu, FF, ubin, gi, go, aFb, aSb);
-    if (site_path) {
-      lbc::k_adj_stress<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phi_t, q_t, aFb, qi, amub, aqbp, aphibp, agbar,
-                                                          apart, apart_live ? 1 : 0);
-      lbc::k_adj_gather<R><<<nblk, TPB, 0, stream>>>(box, agbar, po, qo);
+    if (pc4) {
+      reverse_pc4(phi_t, q_t, uu, FF, Bt, drho, gi, qi, pi, go, qo, po);
     } else {
-      lbc::k_adj_sg_fused<R, FS, kAsTX, kAsTY, L::kStressInEq><<<as_blocks, kAsTX * kAsTY, 0, stream>>>(
-          box, P, as_tz, as_ntx, as_nty, phi_t, q_t, aFb, qi, amub, aqbp, aphibp, aSb, po, qo, ahx, ahy, apart,
-          apart_live ? 1 : 0);
-      if (as_ntx > 1) {
-        const size_t n = 6 * size_t(as_ntx) * box.nz * box.ny;  // one thread per field
-        lbc::k_adj_face_x<R><<<unsigned((n + TPB - 1) / TPB), TPB, 0, stream>>>(box, kAsTX, as_ntx, ahx, po, qo);
-      }
-      if (as_nty > 1) {
-        const size_t n = 6 * size_t(as_nty) * box.nz * box.nx;  // one thread per field
-        lbc::k_adj_face_y<R><<<unsigned((n + TPB - 1) / TPB), TPB, 0, stream>>>(box, kAsTY, as_nty, ahy, po, qo);
+      // site path: W_bar [9][N] and the local u_bar part; fused: W_bar_az [3][N] (in aWb) and
+      // u_bar with the in-plane transposes (in aubp), plus the tile-face terms
+      lbc::UbarIn<R> ubin{aWb, aubp, ahxw, ahyw, kAoTX, kAoTY, ao_ntx, ao_nty, site_path ? 0 : 1};
+      if (site_path)
+        lbc::k_adj_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phi_t, q_t, uu, pi, qi, amub, aWb, aubp, aqbp,
+                                                           aphibp);
+      else
+        lbc::k_adj_order_fused<R, FS, kAoTX, kAoTY><<<ao_blocks, kAoTX * kAoTY, 0, stream>>>(
+            box, P, ao_tz, ao_ntx, ao_nty, phi_t, q_t, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp, ahxw, ahyw);
+      if (Bt)
+        lbc::k_adj_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, Bt, FF, ubin, gi, go, aFb, aSb);
+      else
+        lbc::k_adj_collide_lean<R, L><<<nblk, TPB, 0, stream>>>(box, P, drho, uu, FF, ubin, gi, go, aFb, aSb);
+      if (site_path) {
+        lbc::k_adj_stress<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phi_t, q_t, aFb, qi, amub, aqbp, aphibp, agbar,
+                                                            apart, apart_live ? 1 : 0);
+        lbc::k_adj_gather<R><<<nblk, TPB, 0, stream>>>(box, agbar, po, qo);
+      } else {
+        stress_gather(phi_t, q_t, qi, amub, po, qo);
       }
     }
     apart_live = true;
@@ -954,7 +1026,6 @@ void need_ctx(const lb_ctx* c) {
 
 void need_adjoint_ctx(const lb_ctx* c) {
   need_ctx(c);
-  if (c->p.fd_scheme != LB_FD_EULER2) fail(LB_EINVAL, "the adjoint is implemented for the Euler integrator");
   if (c->be->adjoint_bytes() == 0) fail(LB_EINVAL, "no adjoint for this context (D3Q15: fused kernels only)");
 }
 

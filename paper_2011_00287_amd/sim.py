@@ -61,7 +61,7 @@ class Sim:
     forcing term) or 'd3q15' (symmetric stress in the equilibrium, antisymmetric
     stress as a forcing term; fp64 and fp32).  fd_scheme: 'euler2'
     (explicit Euler, second-order stencils) or 'pc4' (the paper's predictor-corrector
-    with upwind advection and fourth-order stencils; forward only).  stream: a torch.cuda.Stream,
+    with upwind advection and fourth-order stencils).  stream: a torch.cuda.Stream,
     a raw hipStream_t as int, or None for the default stream.  The device tensors
     this class allocates (state, adjoint and record buffers) are created and
     zero-filled on torch's current stream, so pass that stream (or None while

@@ -326,10 +326,12 @@ def test_lean_rollouts_equal_full_state_rollout():
         assert l2 < 1e-12 and mx < 1e-12, (l2, mx)
 
 
-def test_lean_records_refused_without_adjoint():
-    """A context without an adjoint (the pc4 integrator) has no lean records either."""
+def test_lean_records_refused_without_adjoint(monkeypatch):
+    """A context without an adjoint (the pc4 integrator on the site-parallel test
+    kernels) has no lean records either."""
     from paper_2011_00287_amd._lib import LB_EINVAL, LbError
     phi, q5 = inputs.droplet_fields(6, 6, 6, 2.0, 0.5)
+    monkeypatch.setenv("LBC_SITE_KERNELS", "1")
     with Sim(_p(M=0.05), phi, q5, fd_scheme="pc4") as sim:
         assert sim.lean_record_buffer().numel() == 0
         with pytest.raises(LbError) as e:

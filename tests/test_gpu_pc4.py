@@ -157,13 +157,18 @@ def test_bitwise_determinism_and_resume():
             assert np.array_equal(x, y)
 
 
-def test_adjoint_is_refused():
+def test_adjoint_on_site_kernels_is_refused(monkeypatch):
+    """The pc4 reverse runs with the fused kernels only: with the site-parallel
+    test kernels the adjoint calls are refused with LB_EINVAL."""
     p = _p()
     phi, q5 = inputs.droplet_fields(6, 6, 6, 2.0, 0.5)
+    monkeypatch.setenv("LBC_SITE_KERNELS", "1")
     with Sim(p, phi, q5, fd_scheme="pc4") as s:
         assert s.adjoint_buffer().numel() == 0 and s.record_buffer().numel() == 0
         with pytest.raises(LbError) as e:
             s.step_record(s.get_state(), s.get_state(), torch.empty(8, dtype=torch.uint8, device="cuda"))
         assert e.value.status == LB_EINVAL
+    monkeypatch.delenv("LBC_SITE_KERNELS")
+    with Sim(p, phi, q5, fd_scheme="pc4") as s:
         names = [k for k in s.profile(2)]
         assert names[-1] == "k_pc_stage_z (correct)" and "k_pc_stage_z (predict)" in names
