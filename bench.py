@@ -98,7 +98,8 @@ def time_precision(prec, p, phi, q5, steps, warmup, stream, lattice="d3q19", fd_
     return sim, dt
 
 
-def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True, lattice="d3q19", alternatives=True):
+def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True, lattice="d3q19", alternatives=True,
+                 fd_scheme="euler2"):
     """(reverse pass incl. any segment replay) / (plain forward) over the same steps.
 
     Modes (lean records hold Q, phi, drho, u, F per step; full-state records hold
@@ -113,7 +114,7 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True, lat
                                                backward_segments_lean, backward_segments_overlapped, run_lean,
                                                run_recorded, run_segments)
     from paper_2011_00287_amd.sim import Sim
-    sim = Sim(p, phi, q5, precision=prec, stream=stream, lattice=lattice)
+    sim = Sim(p, phi, q5, precision=prec, stream=stream, lattice=lattice, fd_scheme=fd_scheme)
     s0 = sim.get_state()
     sim.step(3)
     sim.set_state(s0)
@@ -141,6 +142,7 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True, lat
                                    lambda h, a: backward_segments(sim, h, steps, checkpoint, a))
     del ck
     out = {"steps": steps, "checkpoint": checkpoint, "precision": prec, "lattice": lattice.upper(),
+           "fd_scheme": fd_scheme,
            "forward_ms": t_fwd * 1e3, "forward_with_checkpoints_ms": t_fwd_ck * 1e3, "backward_ms": t_bwd * 1e3,
            "adjoint_over_forward": t_bwd / t_fwd, "total_over_forward": (t_fwd_ck + t_bwd) / t_fwd}
     if not alternatives:
@@ -155,7 +157,7 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True, lat
     # the same sweep with the replay of segment s-1 on a second context and stream
     # while segment s is reversed (the replay context exists before the timed region)
     replay_stream = torch.cuda.Stream()
-    rep = Sim(p, phi, q5, precision=prec, stream=replay_stream, lattice=lattice)
+    rep = Sim(p, phi, q5, precision=prec, stream=replay_stream, lattice=lattice, fd_scheme=fd_scheme)
     ck, _, t_bwd_ov = run_mode(lambda: run_segments(sim, steps, checkpoint),
                                lambda h, a: backward_segments_overlapped(sim, rep, h, steps, checkpoint, a,
                                                                          replay_stream))
@@ -321,7 +323,7 @@ def main():
                     help="d3q19: stress as a body force; d3q15: the paper's scheme")
     ap.add_argument("--fd-scheme", default="euler2", choices=["euler2", "pc4"],
                     help="euler2: explicit Euler, 2nd-order stencils; pc4: the paper's predictor-corrector, "
-                         f"upwind, 4th-order stencils (forward only, M = {PC4_M})")
+                         f"upwind, 4th-order stencils (M = {PC4_M})")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side", action="store_true", help="skip the FP64 / FP16S side timings")
     ap.add_argument("--profile-steps", type=int, default=50)
@@ -395,6 +397,15 @@ def main():
             print(f"# d3q15_fp32 adjoint/forward: {a15['adjoint_over_forward']:.2f} (checkpoint "
                   f"{args.adjoint_checkpoint}), {a15['recorded']['adjoint_over_forward']:.2f} (every step recorded)",
                   file=sys.stderr, flush=True)
+            # the adjoint of the paper's FD integrator (pc4, its mobility)
+            apc = time_adjoint("fp32", dict(p, M=PC4_M), phi, q5, args.adjoint_steps, args.adjoint_checkpoint,
+                               stream, alternatives=False, fd_scheme="pc4")
+            side["pc4_fp32_adjoint"] = {"adjoint_over_forward": apc["adjoint_over_forward"],
+                                        "recorded_adjoint_over_forward": apc["recorded"]["adjoint_over_forward"],
+                                        "checkpoint": args.adjoint_checkpoint, "steps": args.adjoint_steps}
+            print(f"# pc4_fp32 adjoint/forward: {apc['adjoint_over_forward']:.2f} (checkpoint "
+                  f"{args.adjoint_checkpoint}), {apc['recorded']['adjoint_over_forward']:.2f} (every step recorded)",
+                  file=sys.stderr, flush=True)
         s2, dt2 = time_2d("nematic512", "fp32", 2000, 50)  # the 2D workload of Fig. 3 (512^2)
         n2d = s2.n_sites
         s2.close()
@@ -403,9 +414,10 @@ def main():
         print(f"# nematic512_fp32: {side['nematic512_fp32']['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
 
     adjoint = None
-    if args.adjoint_steps > 0 and args.fd_scheme == "euler2":
-        adjoint = time_adjoint(args.precision, p, phi, q5, args.adjoint_steps, args.adjoint_checkpoint, stream,
-                               recorded=not args.no_adjoint_recorded, lattice=args.lattice)
+    if args.adjoint_steps > 0:
+        pa = dict(p, M=PC4_M) if args.fd_scheme == "pc4" else p
+        adjoint = time_adjoint(args.precision, pa, phi, q5, args.adjoint_steps, args.adjoint_checkpoint, stream,
+                               recorded=not args.no_adjoint_recorded, lattice=args.lattice, fd_scheme=args.fd_scheme)
         print(f"# adjoint/forward: {adjoint['adjoint_over_forward']:.2f} (checkpoint {args.adjoint_checkpoint}; "
               f"{adjoint['overlapped']['adjoint_over_forward']:.2f} with the replay overlapped)"
               + (f", {adjoint['recorded']['adjoint_over_forward']:.2f} (every step recorded, "
