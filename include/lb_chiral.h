@@ -74,7 +74,7 @@ typedef enum {
   LB_D3Q15 = 1  /* the paper's scheme (Sec. 3): D3Q15 (Fig. 1), the symmetric
                    stress in the second moment of the equilibrium (Eqs. (9),
                    (11)), the antisymmetric stress as a Guo forcing term
-                   (Eq. (10)); float64 and float32 only, no adjoint          */
+                   (Eq. (10)); all three precisions, with its adjoint       */
 } lb_lattice;
 
 typedef enum {
@@ -86,7 +86,7 @@ typedef enum {
                        stencils in mu, H, grad u and the Laplacian of mu; the
                        LB stress and force keep the second-order stencils.
                        Stable where M*16*(f'' + 16 k_phi) < 2 (e.g. M = 0.05 with
-                       the droplet parameters); no adjoint                     */
+                       the droplet parameters); with its adjoint               */
 } lb_fd_scheme;
 
 /* Model parameters (Eqs. (1)-(5), (7)).  K is the single elastic constant
@@ -186,10 +186,12 @@ lb_status lb_set_state(lb_ctx* c, const void* dev_src, size_t bytes);
  * carries the adjoint of the symmetric stress in the equilibrium (Eq. (9))
  * into the stress; the force is the divergence of the antisymmetric part only
  * (Eq. (10)).
- * The adjoint is implemented for LB_FD_EULER2: with LB_FD_PC4 (and for
- * LB_D3Q15 when the library runs its site-parallel test kernels)
- * lb_adjoint_bytes, lb_record_bytes and lb_lean_record_bytes return 0 and the
- * calls below return LB_EINVAL.
+ * The adjoint covers both lattices and both integrators (on LB_FD_PC4 it is
+ * the reverse of Heun's two stages, Sec. 3).  Only when the library runs its
+ * site-parallel test kernels (LBC_SITE_KERNELS=1) is it limited to LB_D3Q19
+ * with LB_FD_EULER2: there, for the other schemes, lb_adjoint_bytes,
+ * lb_record_bytes and lb_lean_record_bytes return 0 and the calls below
+ * return LB_EINVAL.
  * ------------------------------------------------------------------------- */
 size_t lb_adjoint_bytes(const lb_ctx* c);
 
