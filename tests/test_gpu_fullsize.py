@@ -17,6 +17,11 @@ benchmark times (default tiles and slab depths).
   Heun's method each apply fourth-order stencils of radius up to 6 (L4 of mu,
   with D4 . (Q D4 phi) inside mu), so a step reaches 12 sites; the patch centre
   was checked to be exact from radius 12 on.
+* 128^3 droplet with the pc4 integrator, FP32: one reverse step (the recorded
+  path) at 3 sampled sites against the autograd of the pc4 oracle on 49^3
+  patches with the seed on the central 25^3 cube (a reverse value depends on
+  the seed within 12 sites, whose forward values need 12 more; exact from
+  radius 22 on, checked on the CPU).
 * 256^3 droplet, FP32: one step at sampled sites against 13^3 oracle patches,
   and one reverse step (through the recorded path the benchmark times) at
   sampled sites against the oracle's autograd on 17^3 patches.  The adjoint
@@ -234,6 +239,53 @@ def test_fp32_128_d3q15_adjoint_sampled_sites_vs_oracle():
         go, qo, po = d3q15.step(gt, qt, pt, p)
         tot = (go * torch.tensor(seed[:15])).sum() + (qo * torch.tensor(seed[15:20])).sum() + \
             (po * torch.tensor(seed[20])).sum()
+        tot.backward()
+        orc = np.concatenate([gt.grad[:, R, R, R].numpy(), qt.grad[:, R, R, R].numpy(), [pt.grad[R, R, R].item()]])
+        err = float(np.abs(orc - gv).max() / np.abs(orc).max())
+        worst = max(worst, err)
+    print("worst relative reverse-step error", worst)
+    assert worst <= 1e-4, worst
+
+
+def test_fp32_128_pc4_adjoint_sampled_sites_vs_oracle():
+    p = inputs.params_for("droplet128", M=0.05)
+    phi, q5 = inputs.workload_fields("droplet128")
+    n = phi.shape[0]
+    sites = [_sites(n, inputs.WORKLOADS["droplet128"]["R"])[i] for i in (1, 0, 4)]
+    with Sim(p, phi, q5, precision="fp32", fd_scheme="pc4") as sim:
+        state = sim.get_state()
+        rec = sim.record_buffer()
+        nxt = torch.empty_like(state)
+        sim.step_record(state, nxt, rec)
+        del nxt
+        adj = sim.adjoint_buffer()
+        a5 = adj.view(25, n, n, n)
+        zz = torch.arange(n, device="cuda", dtype=torch.float64).view(n, 1, 1)
+        yy = zz.view(1, n, 1)
+        xx = zz.view(1, 1, n)
+        for c in range(25):  # the same closed form as _seed_field, built on the device
+            a5[c] = (torch.sin(0.37 * xx + 0.91 * yy + 1.3 * zz + 0.7 * c) * torch.cos(0.23 * xx - 0.5 * zz + c)).float()
+        out = sim.adjoint_buffer()
+        sim.adjoint_step(state, adj, out, rec=rec)
+        o5 = out.view(25, n, n, n)
+        gpu = [o5[:, z, y, x].double().cpu().numpy() for (z, y, x) in sites]
+    R, r = 24, 12
+    m = 2 * R + 1
+    worst = 0.0
+    for (z, y, x), gv in zip(sites, gpu):
+        iz = (np.arange(z - R, z + R + 1)) % n
+        iy = (np.arange(y - R, y + R + 1)) % n
+        ix = (np.arange(x - R, x + R + 1)) % n
+        seed = _seed_field(iz[:, None, None], iy[None, :, None], ix[None, None, :], np.arange(25))
+        mask = np.zeros((m, m, m))
+        mask[R - r:R + r + 1, R - r:R + r + 1, R - r:R + r + 1] = 1.0
+        seed = seed * mask
+        gt = torch.zeros((19, m, m, m), dtype=torch.float64, requires_grad=True)
+        qt = torch.tensor(_patch(q5, z, y, x, R), requires_grad=True)
+        pt = torch.tensor(_patch(phi, z, y, x, R), requires_grad=True)
+        go, qo, po = pc4.step(gt, qt, pt, p)
+        tot = (go * torch.tensor(seed[:19])).sum() + (qo * torch.tensor(seed[19:24])).sum() + \
+            (po * torch.tensor(seed[24])).sum()
         tot.backward()
         orc = np.concatenate([gt.grad[:, R, R, R].numpy(), qt.grad[:, R, R, R].numpy(), [pt.grad[R, R, R].item()]])
         err = float(np.abs(orc - gv).max() / np.abs(orc).max())
