@@ -46,11 +46,10 @@ constexpr int NPB = 43;
 // partial: one float64 (zeta, q0) pair per block, overwritten (accumulate = 0)
 // or added to (accumulate = 1); R depends on q0 through H4 and not on zeta.
 template <class R, class FS>
-__global__ void __launch_bounds__(256) k_pcb_local(Box b, Params<R> P, const FS* __restrict__ phi,
-                                                   const FS* __restrict__ q, const R* __restrict__ u,
-                                                   const R* __restrict__ vq, const R* __restrict__ vphi, R vs,
-                                                   R* __restrict__ pb, double* __restrict__ partial,
-                                                   int accumulate) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
+k_pcb_local(Box b, Params<R> P, const FS* __restrict__ phi, const FS* __restrict__ q, const R* __restrict__ u,
+            const R* __restrict__ vq, const R* __restrict__ vphi, R vs, R* __restrict__ pb,
+            double* __restrict__ partial, int accumulate) {
   const int s = site_xcd();
   double v2[2] = {0.0, 0.0};
   if (s < b.N) {
@@ -189,13 +188,11 @@ __global__ void __launch_bounds__(256) k_pcb_v(Box b, const FS* __restrict__ phi
 // u_bar (ub_out) written (accumulate = 0) or added to (accumulate = 1).
 // phi, u: the stage's phi and the velocity; V = vs (vq, vphi).
 template <class R, class FS>
-__global__ void __launch_bounds__(256) k_pcb_gather(Box b, const FS* __restrict__ phi, const R* __restrict__ u,
-                                                    const R* __restrict__ vq, const R* __restrict__ vphi, R vs,
-                                                    const R* __restrict__ pb, const R* __restrict__ xq1,
-                                                    const R* __restrict__ xp1, R c1, const R* __restrict__ xsq,
-                                                    const R* __restrict__ xsp, R c2, R* __restrict__ q_out,
-                                                    R* __restrict__ phi_out, R* __restrict__ ub_out,
-                                                    int accumulate) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2)))
+k_pcb_gather(Box b, const FS* __restrict__ phi, const R* __restrict__ u, const R* __restrict__ vq,
+             const R* __restrict__ vphi, R vs, const R* __restrict__ pb, const R* __restrict__ xq1,
+             const R* __restrict__ xp1, R c1, const R* __restrict__ xsq, const R* __restrict__ xsp, R c2,
+             R* __restrict__ q_out, R* __restrict__ phi_out, R* __restrict__ ub_out, int accumulate) {
   const int s = site_xcd();
   if (s >= b.N) return;
   int x, y, z;
@@ -210,8 +207,10 @@ __global__ void __launch_bounds__(256) k_pcb_gather(Box b, const FS* __restrict_
     return r;
   };
   auto d4t = [&](const R* f, int g) { return -d4c(f[n[g][0]], f[n[g][1]], f[n[g][2]], f[n[g][3]]); };
+  // one output field's gathers at a time (not unrolled): the loads of all
+  // fields at once would need more registers than four waves per SIMD allow
   R qo[5], po, ub[3];
-#pragma unroll
+#pragma unroll 1
   for (int k = 0; k < 5; ++k) {
     R r = pb[(PB_Q + k) * N + s] + l4t(pb + size_t(PB_LAPQ + k) * N);
 #pragma unroll
@@ -224,7 +223,7 @@ __global__ void __launch_bounds__(256) k_pcb_gather(Box b, const FS* __restrict_
     for (int g = 0; g < 3; ++g) r += d4t(pb + size_t(PB_DPHI + g) * N, g);
     po = r;
   }
-#pragma unroll
+#pragma unroll 1
   for (int a = 0; a < 3; ++a) {
     R r = pb[(PB_U + a) * N + s];
 #pragma unroll
