@@ -19,7 +19,11 @@
 //   k_pcb_v: v_bar = -D4 (D4.v)_bar (D4^T = -D4), then the adjoints of Q and D4 phi
 //     through v = Q D4 phi;
 //   k_pcb_gather: the transposed stencils (D4^T = -D4, L4^T = L4) of those
-//     adjoints, and the neighbour terms of the upwind and donor-cell operators.
+//     adjoints, and the neighbour terms of the upwind and donor-cell operators,
+//     along x and y (NAX = 2; their neighbours share the plane, so they come
+//     from L2), then k_pcb_gather_z adds the z terms marching each column
+//     through a slab with the z neighbours in register rings (reading the 23
+//     fields of the z stencils once instead of from five planes at a time).
 // The upwind and donor-cell terms are max(w, 0) a + min(w, 0) b of a velocity
 // w; at w = 0 their w-derivative is taken as a + b (both one-sided parts), the
 // convention of the clamp form the oracle writes them in.
@@ -183,11 +187,12 @@ __global__ void __launch_bounds__(256) k_pcb_v(Box b, const FS* __restrict__ phi
   for (int k = 0; k < 5; ++k) pb[(PB_Q + k) * N + s] += qb[k];
 }
 
-// The transposed stencils and neighbour terms of one product, combined with
-// the Heun weights: out = c1 X_bar(t+1) + c2 Xs + R'^T V at each site, and
-// u_bar (ub_out) written (accumulate = 0) or added to (accumulate = 1).
+// The transposed stencils and neighbour terms of one product along the first
+// NAX axes, combined with the Heun weights: out = c1 X_bar(t+1) + c2 Xs +
+// R'^T V at each site (the z terms follow in k_pcb_gather_z when NAX = 2),
+// and u_bar (ub_out) written (accumulate = 0) or added to (accumulate = 1).
 // phi, u: the stage's phi and the velocity; V = vs (vq, vphi).
-template <class R, class FS>
+template <class R, class FS, int NAX>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2)))
 k_pcb_gather(Box b, const FS* __restrict__ phi, const R* __restrict__ u, const R* __restrict__ vq,
              const R* __restrict__ vphi, R vs, const R* __restrict__ pb, const R* __restrict__ xq1,
@@ -203,7 +208,7 @@ k_pcb_gather(Box b, const FS* __restrict__ phi, const R* __restrict__ u, const R
   auto l4t = [&](const R* f) {  // L4^T = L4
     R r = R(-7.5) * f[s];
 #pragma unroll
-    for (int g = 0; g < 3; ++g) r += l4c(f[n[g][0]], f[n[g][1]], f[n[g][2]], f[n[g][3]]);
+    for (int g = 0; g < NAX; ++g) r += l4c(f[n[g][0]], f[n[g][1]], f[n[g][2]], f[n[g][3]]);
     return r;
   };
   auto d4t = [&](const R* f, int g) { return -d4c(f[n[g][0]], f[n[g][1]], f[n[g][2]], f[n[g][3]]); };
@@ -214,25 +219,25 @@ k_pcb_gather(Box b, const FS* __restrict__ phi, const R* __restrict__ u, const R
   for (int k = 0; k < 5; ++k) {
     R r = pb[(PB_Q + k) * N + s] + l4t(pb + size_t(PB_LAPQ + k) * N);
 #pragma unroll
-    for (int g = 0; g < 3; ++g) r += d4t(pb + size_t(PB_DQ + 5 * g + k) * N, g);
+    for (int g = 0; g < NAX; ++g) r += d4t(pb + size_t(PB_DQ + 5 * g + k) * N, g);
     qo[k] = r;
   }
   {
     R r = pb[PB_PHI * N + s] + l4t(pb + size_t(PB_LAPPHI) * N);
 #pragma unroll
-    for (int g = 0; g < 3; ++g) r += d4t(pb + size_t(PB_DPHI + g) * N, g);
+    for (int g = 0; g < NAX; ++g) r += d4t(pb + size_t(PB_DPHI + g) * N, g);
     po = r;
   }
 #pragma unroll 1
   for (int a = 0; a < 3; ++a) {
     R r = pb[(PB_U + a) * N + s];
 #pragma unroll
-    for (int g = 0; g < 3; ++g) r += d4t(pb + size_t(PB_W + 3 * a + g) * N, g);
+    for (int g = 0; g < NAX; ++g) r += d4t(pb + size_t(PB_W + 3 * a + g) * N, g);
     ub[a] = r;
   }
   const R ph = R(phi[s]), vp0 = vs * vphi[s];
 #pragma unroll
-  for (int g = 0; g < 3; ++g) {
+  for (int g = 0; g < NAX; ++g) {
     const int m1 = n[g][1], p1 = n[g][2];
     const R* ug = u + size_t(g) * N;
     // upwind terms of the neighbours: x = y + e_g reads Q(y) backward, x = y - e_g forward
@@ -261,6 +266,89 @@ k_pcb_gather(Box b, const FS* __restrict__ phi, const R* __restrict__ u, const R
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) ub_out[a * N + s] = accumulate ? ub_out[a * N + s] + ub[a] : ub[a];
+}
+
+// The z terms of one product (after k_pcb_gather<R, FS, 2>), added to q_out,
+// phi_out and ub_out.  One thread per (x, y) column marches the planes of a
+// slab of TZ; the 15 fields with a radius-2 z stencil (the adjoints of
+// D4_z Q, L4 Q, D4_z phi, L4 phi, W_az) sit in five-plane register rings, the
+// 8 with a radius-1 one (V, u_z, phi) in three-plane rings.
+template <class R, class FS>
+__global__ void __launch_bounds__(256) k_pcb_gather_z(Box b, int TZ, const FS* __restrict__ phi,
+                                                      const R* __restrict__ u, const R* __restrict__ vq,
+                                                      const R* __restrict__ vphi, R vs, const R* __restrict__ pb,
+                                                      R* __restrict__ q_out, R* __restrict__ phi_out,
+                                                      R* __restrict__ ub_out) {
+  const int plane = b.nx * b.ny;
+  const int ncb = (plane + 255) / 256;
+  const int col = (blockIdx.x % ncb) * 256 + threadIdx.x;
+  if (col >= plane) return;
+  const int z0 = (blockIdx.x / ncb) * TZ, z1 = min(z0 + TZ, b.nz);
+  const size_t N = b.N;
+  constexpr int N2 = 15, N1 = 8;
+  // radius-2 fields: D4_z Q adjoint (5), L4 Q adjoint (5), D4_z phi, L4 phi adjoints, W_az adjoint (3)
+  const R* f2[N2];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    f2[k] = pb + size_t(PB_DQ + 10 + k) * N;
+    f2[5 + k] = pb + size_t(PB_LAPQ + k) * N;
+  }
+  f2[10] = pb + size_t(PB_DPHI + 2) * N;
+  f2[11] = pb + size_t(PB_LAPPHI) * N;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) f2[12 + a] = pb + size_t(PB_W + 3 * a + 2) * N;
+  auto at = [&](int zz) { return size_t(pmod(zz, b.nz)) * plane + col; };
+  auto ld1 = [&](int zz, R v[N1]) {
+    const size_t k = at(zz);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) v[c] = vs * vq[c * N + k];
+    v[5] = vs * vphi[k];
+    v[6] = u[2 * N + k];
+    v[7] = R(phi[k]);
+  };
+  R r2[5][N2], r1[3][N1];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const size_t k = at(z0 - 2 + j);
+#pragma unroll
+    for (int f = 0; f < N2; ++f) r2[j][f] = f2[f][k];
+  }
+  ld1(z0 - 1, r1[0]);
+  ld1(z0, r1[1]);
+  for (int zc = z0; zc < z1; ++zc) {
+    {
+      const size_t k = at(zc + 2);
+#pragma unroll
+      for (int f = 0; f < N2; ++f) r2[4][f] = f2[f][k];
+    }
+    ld1(zc + 1, r1[2]);
+    auto d4z = [&](int f) { return -d4c(r2[0][f], r2[1][f], r2[3][f], r2[4][f]); };
+    auto l4z = [&](int f) { return l4c(r2[0][f], r2[1][f], r2[3][f], r2[4][f]); };
+    const size_t s = size_t(zc) * plane + col;
+    // upwind terms of the z neighbours; donor-cell faces z + 1/2 and z - 1/2
+    const R uzp = r1[2][6], uzm = r1[0][6], uz = r1[1][6];
+    const R upx = uzp > R(0) ? uzp : R(0), umx = uzm < R(0) ? uzm : R(0);
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+      q_out[k * N + s] += (d4z(k) + l4z(5 + k)) + (r1[2][k] * upx - r1[0][k] * umx);
+    const R fp = R(0.5) * (uz + uzp), fm = R(0.5) * (uzm + uz);
+    const R cp = r1[2][5] - r1[1][5], cm = r1[1][5] - r1[0][5];
+    const R ph = r1[1][7], php = r1[2][7], phm = r1[0][7];
+    phi_out[s] += (d4z(10) + l4z(11)) + (cp * (fp > R(0) ? fp : R(0)) + cm * (fm < R(0) ? fm : R(0)));
+    const R dfp = (fp >= R(0) ? ph : R(0)) + (fp <= R(0) ? php : R(0));
+    const R dfm = (fm >= R(0) ? phm : R(0)) + (fm <= R(0) ? ph : R(0));
+    ub_out[s] += d4z(12);
+    ub_out[N + s] += d4z(13);
+    ub_out[2 * N + s] += d4z(14) + R(0.5) * (cp * dfp + cm * dfm);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int f = 0; f < N2; ++f) r2[j][f] = r2[j + 1][f];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int f = 0; f < N1; ++f) r1[j][f] = r1[j + 1][f];
+  }
 }
 
 }  // namespace lbc

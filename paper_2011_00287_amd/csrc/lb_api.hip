@@ -222,6 +222,7 @@ struct BackendT final : Backend {
   R* axs = nullptr;    // pc4 reverse: X*_bar [6][N]
   R* aupc = nullptr;   // pc4 reverse: u_bar [3][N]
   R* azero = nullptr;  // pc4 reverse: zeros [6][N]
+  int gz_tz = 0, gz_blocks = 0;  // pc4 reverse: slab depth and grid of k_pcb_gather_z
   double* apart = nullptr;   // per-block (zeta, q0) adjoint partials, kept across reverse steps
   size_t apart_n = 0;        // doubles in apart
   bool apart_live = false;   // apart holds sums not yet fetched by the caller
@@ -765,6 +766,9 @@ struct BackendT final : Backend {
         aupc = dalloc<R>(3 * N);                // u_bar of both Heun stages
         azero = dalloc<R>(6 * N);               // zero Q_bar(t+1), mu_bar for the stress kernel
         HIPCHECK(hipMemsetAsync(azero, 0, 6 * N * sizeof(R), stream));
+        const int ncb = (box.nx * box.ny + 255) / 256;  // column blocks of a plane
+        gz_tz = auto_slab(ncb, 1, box.nz, 16, 1, 2);
+        gz_blocks = ncb * ((box.nz + gz_tz - 1) / gz_tz);
       }
       if (!site_path && as_ntx > 1) ahx = dalloc<R>(24 * size_t(as_ntx) * box.nz * box.ny);
       if (!site_path && ao_ntx > 1) ahxw = dalloc<R>(6 * size_t(ao_ntx) * box.nz * box.ny);
@@ -901,13 +905,17 @@ struct BackendT final : Backend {
     lbc::k_pcb_local<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phs, qs, uu, qi, pi, R(0.5), apb, pl,
                                                        apart_live ? 1 : 0);
     lbc::k_pcb_v<R, FS><<<nblk, TPB, 0, stream>>>(box, phs, qs, apb);
-    lbc::k_pcb_gather<R, FS><<<nblk, TPB, 0, stream>>>(box, phs, uu, qi, pi, R(0.5), apb, qi, pi, R(0.5), nullptr,
-                                                        nullptr, R(0), xsq, xsp, aupc, 0);
+    lbc::k_pcb_gather<R, FS, 2><<<nblk, TPB, 0, stream>>>(box, phs, uu, qi, pi, R(0.5), apb, qi, pi, R(0.5),
+                                                           nullptr, nullptr, R(0), xsq, xsp, aupc, 0);
+    lbc::k_pcb_gather_z<R, FS><<<gz_blocks, 256, 0, stream>>>(box, gz_tz, phs, uu, qi, pi, R(0.5), apb, xsq, xsp,
+                                                               aupc);
     // X_bar = X_bar(t+1)/2 + X*_bar + R'(X)^T X*_bar
     lbc::k_pcb_local<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phi_t, q_t, uu, xsq, xsp, R(1), apb, pl, 1);
     lbc::k_pcb_v<R, FS><<<nblk, TPB, 0, stream>>>(box, phi_t, q_t, apb);
-    lbc::k_pcb_gather<R, FS><<<nblk, TPB, 0, stream>>>(box, phi_t, uu, xsq, xsp, R(1), apb, qi, pi, R(0.5), xsq,
-                                                        xsp, R(1), aqbp, aphibp, aupc, 1);
+    lbc::k_pcb_gather<R, FS, 2><<<nblk, TPB, 0, stream>>>(box, phi_t, uu, xsq, xsp, R(1), apb, qi, pi, R(0.5), xsq,
+                                                           xsp, R(1), aqbp, aphibp, aupc, 1);
+    lbc::k_pcb_gather_z<R, FS><<<gz_blocks, 256, 0, stream>>>(box, gz_tz, phi_t, uu, xsq, xsp, R(1), apb, aqbp,
+                                                               aphibp, aupc);
     lbc::UbarIn<R> ubin{nullptr, aupc, nullptr, nullptr, 0, 0, 0, 0, 2};
     if (Bt)
       lbc::k_adj_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, Bt, FF, ubin, gi, go, aFb, aSb);
