@@ -34,20 +34,23 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* __re
   }
 }
 
-// out[k] = sum over blocks of partial[b*nv + k]; one block of 256 threads.
+// out[g*nv + k] = sum over the blocks b of chunk g (b in [g*chunk, (g+1)*chunk)
+// and below nblocks) of partial[b*nv + k]; one workgroup of 256 threads per
+// chunk g (one chunk covering every block gives the plain total).
 __global__ void __launch_bounds__(256) k_final_sum(const double* __restrict__ partial, int nblocks, int nv,
-                                                   double* __restrict__ out) {
+                                                   double* __restrict__ out, int chunk = 1 << 30) {
   __shared__ double buf[256];
+  const int b0 = blockIdx.x * chunk, b1 = min(nblocks, b0 + chunk);
   for (int k = 0; k < nv; ++k) {
     double s = 0.0;
-    for (int bI = threadIdx.x; bI < nblocks; bI += 256) s += partial[(size_t)bI * nv + k];
+    for (int bI = b0 + threadIdx.x; bI < b1; bI += 256) s += partial[(size_t)bI * nv + k];
     buf[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
       if (threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
       __syncthreads();
     }
-    if (threadIdx.x == 0) out[k] = buf[0];
+    if (threadIdx.x == 0) out[size_t(blockIdx.x) * nv + k] = buf[0];
     __syncthreads();
   }
 }

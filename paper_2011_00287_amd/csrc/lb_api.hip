@@ -204,6 +204,7 @@ struct BackendT final : Backend {
   R* u = nullptr;
   double* partial = nullptr;
   double* sums = nullptr;
+  double* mids = nullptr;  // chunk sums of the two-stage total over many blocks
   // adjoint scratch (allocated on first use)
   R* aF = nullptr;
   R* amub = nullptr;
@@ -312,6 +313,7 @@ struct BackendT final : Backend {
       u = dalloc<R>(3 * N);
       partial = dalloc<double>(size_t(nblk) * 16);
       sums = dalloc<double>(16);
+      mids = dalloc<double>(size_t(kSumChunks) * 16);
       if (site_path) ensure_thermo();
       if (pc4) {
         pcs = dalloc<FS>(6 * N);
@@ -352,12 +354,13 @@ struct BackendT final : Backend {
     dfree(u);
     dfree(partial);
     dfree(sums);
+    dfree(mids);
     dfree(pcs);
     dfree(pcv);
     pcs = nullptr;
     pcv = nullptr;
     mu = H = sig = u = nullptr;
-    partial = sums = nullptr;
+    partial = sums = mids = nullptr;
     R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &ahxw, &ahyw, &apb, &axs, &aupc, &azero};
     for (R** a : adj) {
       dfree(*a);
@@ -698,17 +701,29 @@ struct BackendT final : Backend {
     }
     dfree(g);
   }
+  // sums[k] = sum over nblocks block partials (nv values each) in a fixed
+  // order: one workgroup for few blocks, else kSumChunks chunk sums first
+  static constexpr int kSumChunks = 64;
+  void final_sum(const double* part, int nblocks, int nv) {
+    if (nblocks <= 4096) {
+      lbc::k_final_sum<<<1, TPB, 0, stream>>>(part, nblocks, nv, sums);
+      return;
+    }
+    const int chunk = (nblocks + kSumChunks - 1) / kSumChunks;
+    lbc::k_final_sum<<<kSumChunks, TPB, 0, stream>>>(part, nblocks, nv, mids, chunk);
+    lbc::k_final_sum<<<1, TPB, 0, stream>>>(mids, kSumChunks, nv, sums);
+  }
   void totals(double out[lbc::NTOT]) override {
     thermo_now();
     lbc::k_totals<R, GS, FS, L><<<nblk, TPB, 0, stream>>>(box, Pd, B[cur], Ph[cur], Q[cur], sig, partial);
-    lbc::k_final_sum<<<1, TPB, 0, stream>>>(partial, int(nblk), lbc::NTOT, sums);
+    final_sum(partial, int(nblk), lbc::NTOT);
     check_launch();
     HIPCHECK(hipMemcpyAsync(out, sums, lbc::NTOT * sizeof(double), hipMemcpyDeviceToHost, stream));
     HIPCHECK(hipStreamSynchronize(stream));
   }
   void centre(double out[lbc::NCEN]) override {
     lbc::k_centre<FS><<<nblk, TPB, 0, stream>>>(box, Ph[cur], partial);
-    lbc::k_final_sum<<<1, TPB, 0, stream>>>(partial, int(nblk), lbc::NCEN, sums);
+    final_sum(partial, int(nblk), lbc::NCEN);
     check_launch();
     HIPCHECK(hipMemcpyAsync(out, sums, lbc::NCEN * sizeof(double), hipMemcpyDeviceToHost, stream));
     HIPCHECK(hipStreamSynchronize(stream));
@@ -962,7 +977,7 @@ struct BackendT final : Backend {
     apart_live = true;
     check_launch();
     if (!zeta_bar && !q0_bar) return;  // the parameter sums stay on the device
-    lbc::k_final_sum<<<1, TPB, 0, stream>>>(apart, npart_blocks, 2, sums);
+    final_sum(apart, npart_blocks, 2);
     check_launch();
     apart_live = false;
     double pv[2] = {0.0, 0.0};
