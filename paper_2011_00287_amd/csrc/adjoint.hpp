@@ -223,27 +223,30 @@ __host__ __device__ __forceinline__ void local_thermo_bwd(const Params<R>& P, co
   invariants_bwd(G.q, q2b, tr2b, tr3b, Gb.q);
 }
 
-// Reverse of sdot(A, B) = A:B for 5-component symmetric traceless tensors.
+// The reverse of mu_site except its path through Q: accumulates the phi,
+// lapphi and divv adjoints and the adjoints of tr(Q^2) (tr2b) and tr(Q^3)
+// (tr3b), so that a caller which also reverses H reverses the invariants once.
+//   mu = a phi (phi - phi0)(2 phi - phi0) ipc2 + A0 chi_s (-tr2/6 - tr3/3 + tr2^2/4)
+//        - k_phi lapphi - 2 W divv
 template <class R>
-__host__ __device__ __forceinline__ void sdot_bwd(const R* A, const R* B, R s, R* Ab, R* Bb) {
-  Ab[0] += s * (R(2) * B[0] + B[3]);
-  Ab[1] += s * (R(2) * B[1]);
-  Ab[2] += s * (R(2) * B[2]);
-  Ab[3] += s * (B[0] + R(2) * B[3]);
-  Ab[4] += s * (R(2) * B[4]);
-  Bb[0] += s * (R(2) * A[0] + A[3]);
-  Bb[1] += s * (R(2) * A[1]);
-  Bb[2] += s * (R(2) * A[2]);
-  Bb[3] += s * (A[0] + R(2) * A[3]);
-  Bb[4] += s * (R(2) * A[4]);
+__host__ __device__ __forceinline__ void mu_site_bwd_local(const Params<R>& P, R phi, R tr2, R mub, R& phib,
+                                                           R& lapphib, R& divvb, R& tr2b, R& tr3b) {
+  phib += P.a * P.inv_phicr2 * (R(6) * phi * phi - R(6) * phi * P.phi0 + P.phi0 * P.phi0) * mub;
+  tr2b += P.A0 * P.chi_s * (-C3<R>::sixth + R(0.5) * tr2) * mub;
+  tr3b -= P.A0 * P.chi_s * C3<R>::third * mub;
+  lapphib -= P.k_phi * mub;
+  divvb -= R(2) * P.W * mub;
 }
 
-// Reverse of sigma_site: adjoint of the stress (sb[3*a+b]) and of the
-// molecular field output (hb_out[5], e.g. from the Beris-Edwards update)
-// -> gradient-data adjoint and parameter adjoints.
+// Reverse of sigma_site: adjoint of the stress (sb[3*a+b]), of the
+// molecular field output (hb_out[5], e.g. from the Beris-Edwards update) and
+// of the chemical potential mu_site at the same site (mub; its divv adjoint
+// goes to Gb.divv) -> gradient-data adjoint and parameter adjoints.  mu shares
+// tr(Q^2) and tr(Q^3) with H, so their reverse through Q runs once.
 template <class R>
 __host__ __device__ __forceinline__ void sigma_site_bwd(const Params<R>& P, const Grad<R>& G, const R sb[9],
-                                                        const R hb_out[5], GradBar<R>& Gb, ParBar<R>& Pb) {
+                                                        const R hb_out[5], GradBar<R>& Gb, ParBar<R>& Pb,
+                                                        R mub = R(0)) {
   Local<R> L;
   local_thermo(P, G, L);
   const R xx = L.xx, xy = L.xy, xz = L.xz, yy = L.yy, yz = L.yz, zz = L.zz;
@@ -251,19 +254,6 @@ __host__ __device__ __forceinline__ void sigma_site_bwd(const Params<R>& P, cons
   const R kq = R(2) * P.K * P.q0;
   const R kq2 = R(4) * P.K * P.q0 * P.q0;
   // forward intermediates
-  R D[3][3], ax[3][3];
-  for (int a = 0; a < 3; ++a)
-    for (int b = a; b < 3; ++b) {
-      D[a][b] = sdot(G.dq[a], G.dq[b]);
-      D[b][a] = D[a][b];
-    }
-  for (int a = 0; a < 3; ++a) {
-    const R dxx = G.dq[a][0], dxy = G.dq[a][1], dxz = G.dq[a][2], dyy = G.dq[a][3], dyz = G.dq[a][4];
-    const R dzz = -dxx - dyy;
-    ax[a][0] = (dxy * xz + dyy * yz + dyz * zz) - (dxz * xy + dyz * yy + dzz * yz);
-    ax[a][1] = (dxz * xx + dyz * xy + dzz * xz) - (dxx * xz + dxy * yz + dxz * zz);
-    ax[a][2] = (dxx * xy + dxy * yy + dxz * yz) - (dxy * xx + dyy * xy + dyz * xz);
-  }
   const R Qm[3][3] = {{xx, xy, xz}, {xy, yy, yz}, {xz, yz, zz}};
   const R Qd[3] = {xx * dp[0] + xy * dp[1] + xz * dp[2], xy * dp[0] + yy * dp[1] + yz * dp[2],
                    xz * dp[0] + yz * dp[1] + zz * dp[2]};
@@ -282,7 +272,8 @@ __host__ __device__ __forceinline__ void sigma_site_bwd(const Params<R>& P, cons
                   P.k_phi * dp[2] + R(2) * P.W * Qd[2]};
 
   // ---- reverse of sig_ab = -dp_a t_b - K D_ab - kq ax_ab + cA QH_ba + cB QH_ab + cH H_ab + cQ Q_ab + d_ab iso
-  R Qmb[3][3] = {}, Hmb[3][3] = {}, QHb[3][3] = {}, Db[3][3] = {}, axb[3][3] = {};
+  // (the ax term is reversed below with sb itself as the cotangent, then scaled by -kq)
+  R Qmb[3][3] = {}, Hmb[3][3] = {}, QHb[3][3] = {}, Db[3][3] = {};
   R dpb[3] = {R(0), R(0), R(0)}, tb[3] = {R(0), R(0), R(0)};
   R cQb = R(0);
   const R isob = sb[0] + sb[4] + sb[8];
@@ -292,8 +283,6 @@ __host__ __device__ __forceinline__ void sigma_site_bwd(const Params<R>& P, cons
       dpb[a] -= s * t[b];
       tb[b] -= s * dp[a];
       Db[a][b] -= P.K * s;
-      axb[a][b] -= kq * s;
-      Pb.kq -= s * ax[a][b];
       QHb[b][a] += cA * s;
       QHb[a][b] += cB * s;
       Hmb[a][b] += cH * s;
@@ -352,13 +341,16 @@ __host__ __device__ __forceinline__ void sigma_site_bwd(const Params<R>& P, cons
       Qmb[b][c] += Qdb[b] * dp[c];
       dpb[c] += Qm[b][c] * Qdb[b];
     }
-  // ax (per a), from dq[a] and Q
+  // ax (per a), from dq[a] and Q, bilinear: with sb as its cotangent the reverse
+  // gives r = d(sb:ax)/d(dq, Q); the stress takes -kq ax, so G.dq and Q get
+  // -kq r, and since ax is linear in dq, sb:ax = sum r_dq . dq (kq's adjoint)
   R qb5[5] = {R(0), R(0), R(0), R(0), R(0)};
   R xxb = R(0), xyb = R(0), xzb = R(0), yyb = R(0), yzb = R(0), zzb = R(0);
+  R sax = R(0);
   for (int a = 0; a < 3; ++a) {
     const R dxx = G.dq[a][0], dxy = G.dq[a][1], dxz = G.dq[a][2], dyy = G.dq[a][3], dyz = G.dq[a][4];
     const R dzz = -dxx - dyy;
-    const R a0b = axb[a][0], a1b = axb[a][1], a2b = axb[a][2];
+    const R a0b = sb[3 * a], a1b = sb[3 * a + 1], a2b = sb[3 * a + 2];
     R dxxb = R(0), dxyb = R(0), dxzb = R(0), dyyb = R(0), dyzb = R(0), dzzb = R(0);
     // ax0 = (dxy xz + dyy yz + dyz zz) - (dxz xy + dyz yy + dzz yz)
     dxyb += a0b * xz; xzb += a0b * dxy;
@@ -384,32 +376,44 @@ __host__ __device__ __forceinline__ void sigma_site_bwd(const Params<R>& P, cons
     // dzz = -dxx - dyy
     dxxb -= dzzb;
     dyyb -= dzzb;
-    Gb.dq[a][0] += dxxb;
-    Gb.dq[a][1] += dxyb;
-    Gb.dq[a][2] += dxzb;
-    Gb.dq[a][3] += dyyb;
-    Gb.dq[a][4] += dyzb;
+    sax += dxxb * dxx + dxyb * dxy + dxzb * dxz + dyyb * dyy + dyzb * dyz;
+    Gb.dq[a][0] -= kq * dxxb;
+    Gb.dq[a][1] -= kq * dxyb;
+    Gb.dq[a][2] -= kq * dxzb;
+    Gb.dq[a][3] -= kq * dyyb;
+    Gb.dq[a][4] -= kq * dyzb;
   }
-  // D_ab = dq[a] : dq[b] (computed once per unordered pair)
-  for (int a = 0; a < 3; ++a)
-    for (int b = a; b < 3; ++b) {
-      const R s = (a == b) ? Db[a][a] : Db[a][b] + Db[b][a];
-      sdot_bwd(G.dq[a], G.dq[b], s, Gb.dq[a], Gb.dq[b]);
+  Pb.kq -= sax;
+  // D_ab = dq[a] : dq[b] = dq[a]^T J dq[b] with J the metric of sdot, so
+  // dq_bar[a] += J sum_b (Db_ab + Db_ba) dq[b]
+  for (int a = 0; a < 3; ++a) {
+    R T[5];
+    for (int k = 0; k < 5; ++k) T[k] = R(0);
+    for (int b = 0; b < 3; ++b) {
+      const R m = Db[a][b] + Db[b][a];
+      for (int k = 0; k < 5; ++k) T[k] += m * G.dq[b][k];
     }
+    Gb.dq[a][0] += R(2) * T[0] + T[3];
+    Gb.dq[a][1] += R(2) * T[1];
+    Gb.dq[a][2] += R(2) * T[2];
+    Gb.dq[a][3] += T[0] + R(2) * T[3];
+    Gb.dq[a][4] += R(2) * T[4];
+  }
   // Q from its explicit uses (Qm and the ax/xx.. scalars) -> stored components
   xxb -= zzb;
   yyb -= zzb;
-  qb5[0] += xxb;
-  qb5[1] += xyb;
-  qb5[2] += xzb;
-  qb5[3] += yyb;
-  qb5[4] += yzb;
+  qb5[0] -= kq * xxb;
+  qb5[1] -= kq * xyb;
+  qb5[2] -= kq * xzb;
+  qb5[3] -= kq * yyb;
+  qb5[4] -= kq * yzb;
   full_to_stored(Qmb, qb5);
   for (int k = 0; k < 5; ++k) Gb.q[k] += qb5[k];
   for (int g = 0; g < 3; ++g) Gb.dphi[g] += dpb[g];
   // H -> stored components, plus the adjoint of the molecular-field output
   R hb[5] = {hb_out[0], hb_out[1], hb_out[2], hb_out[3], hb_out[4]};
   full_to_stored(Hmb, hb);
+  mu_site_bwd_local(P, G.phi, L.tr2, mub, Gb.phi, Gb.lapphi, Gb.divv, tr2b, tr3b);
   // back through local_thermo
   local_thermo_bwd(P, G, L, hb, tr2b, tr3b, qcb, dp2b, chib, Gb, Pb);
 }
@@ -420,14 +424,10 @@ __host__ __device__ __forceinline__ void mu_site_bwd(const Params<R>& P, R phi, 
                                                      R& lapphib, R& divvb, R qb[5]) {
   const R xx = q[0], xy = q[1], xz = q[2], yy = q[3], yz = q[4], zz = -xx - yy;
   const R tr2 = (xx * xx + xy * xy + xz * xz) + (xy * xy + yy * yy + yz * yz) + (xz * xz + yz * yz + zz * zz);
-  // a phi (phi - phi0)(2 phi - phi0) ipc2 -> derivative a ipc2 (6 phi^2 - 6 phi phi0 + phi0^2)
-  phib += P.a * P.inv_phicr2 * (R(6) * phi * phi - R(6) * phi * P.phi0 + P.phi0 * P.phi0) * mub;
-  const R tr2b = P.A0 * P.chi_s * (-C3<R>::sixth + R(0.5) * tr2) * mub;
-  const R tr3b = -P.A0 * P.chi_s * C3<R>::third * mub;
+  R tr2b = R(0), tr3b = R(0);
+  mu_site_bwd_local(P, phi, tr2, mub, phib, lapphib, divvb, tr2b, tr3b);
   R q2b[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
   invariants_bwd(q, q2b, tr2b, tr3b, qb);
-  lapphib += -P.k_phi * mub;
-  divvb += -R(2) * P.W * mub;
 }
 
 // Reverse of corotation_site: s5b -> qb (stored components) and Wb (3x3).

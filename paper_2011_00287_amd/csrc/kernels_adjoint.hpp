@@ -588,8 +588,7 @@ __device__ __forceinline__ void adj_stress_site(const Params<R>& P, const Grad<R
   for (int k = 0; k < 5; ++k) hbs[k] = P.Gamma * aq[k];
   Gb.zero();
   Pb = ParBar<R>{R(0), R(0), R(0)};
-  sigma_site_bwd(P, G, sb, hbs, Gb, Pb);
-  mu_site_bwd(P, G.phi, G.q, mb0, Gb.phi, Gb.lapphi, Gb.divv, Gb.q);
+  sigma_site_bwd(P, G, sb, hbs, Gb, Pb, mb0);
   // anchoring divergence: v_a = Q_ab D0_b phi  ->  Q_bar_ab += v_bar_a D0_b phi,
   // (D0_b phi)_bar += Q_ab v_bar_a
   R Qb[3][3];
@@ -795,9 +794,12 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
 
   const int l = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = l % ntx, ty = (l / ntx) % nty, sl = l / (ntx * nty);
-  const int x0 = tx * TX, y0 = ty * TY, z0 = sl * TZ;
+  // with several x tiles, tile tx starts one column early (x0 = tx TX - 1,
+  // mod nx): the edge columns of neighbouring tiles are then adjacent in
+  // memory, and so are the two columns k_adj_face_x writes per face
+  const int x0 = tx * TX - (ntx > 1 ? 1 : 0), y0 = ty * TY, z0 = sl * TZ;
   const int z1 = min(z0 + TZ, b.nz);
-  const int w = min(TX, b.nx - x0), h = min(TY, b.ny - y0);  // the tile's extent in the box
+  const int w = min(TX, b.nx - tx * TX), h = min(TY, b.ny - y0);  // the tile's extent in the box
   const int tid = threadIdx.x;
   const int lx = tid % TX, ly = tid / TX;
   const bool active = lx < w && ly < h;
@@ -1014,11 +1016,14 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
   block_reduce_store<2>(v, partial + size_t(blockIdx.x) * 2, accumulate != 0);
 }
 
-// The face terms of k_adj_sg_fused along x: one thread per (field, x tile j,
-// z, y) writes the first column of tile j (its adjoint without face terms,
-// plus the term sent in the + direction across face j-1) and the last column
-// (the same, with the term sent in the - direction across face j); one thread
-// writes both terms when the tile is one column wide.  Fields 0..5: phi, q[5].
+// The face terms of k_adj_sg_fused along x.  Tile j covers the columns
+// j TX - 1 .. j TX + w_j - 2 (mod nx), so the last column of tile j and the
+// first of tile j+1 are neighbours in memory.  One thread per (field, face j,
+// z, y) writes both: the last column of tile j (its adjoint without face terms
+// plus the term sent in the - direction across face j) and the first column
+// of tile j+1 (the same, with the term sent in the + direction).  A tile one
+// column wide (only the last tile can be) gets both of its terms from the
+// thread of the face before it.  Fields 0..5: phi, q[5].
 template <class R>
 __global__ void __launch_bounds__(256) k_adj_face_x(Box b, int TX, int ntx, const R* __restrict__ hx,
                                                     R* __restrict__ adj_phi, R* __restrict__ adj_q) {
@@ -1029,14 +1034,16 @@ __global__ void __launch_bounds__(256) k_adj_face_x(Box b, int TX, int ntx, cons
   const size_t r = t % fs;
   const int j = int(r / nzy);
   const size_t zy = r % nzy;
-  const int xa = j * TX, xb = min(xa + TX, b.nx) - 1;
+  const int jn = j + 1 < ntx ? j + 1 : 0;
+  const int wj = min(TX, b.nx - j * TX), wn = min(TX, b.nx - jn * TX);
+  const int xf = jn > 0 ? jn * TX - 1 : b.nx - 1;  // first column of tile jn; tile j's last is xf - 1
   R* out = (f == 0 ? adj_phi : adj_q + size_t(f - 1) * b.N) + zy * b.nx;  // row (z, y)
   const R* hs = hx + size_t(4 * f) * fs;
-  const size_t own = size_t(j) * nzy + zy;
-  R va = hs[2 * fs + own] + hs[size_t((j + ntx - 1) % ntx) * nzy + zy];
-  if (xb == xa) va += hs[fs + own];
-  out[xa] = va;
-  if (xb != xa) out[xb] = hs[3 * fs + own] + hs[fs + own];
+  const size_t fj = size_t(j) * nzy + zy, fn = size_t(jn) * nzy + zy;
+  R vf = hs[2 * fs + fn] + hs[fj];
+  if (wn == 1) vf += hs[fs + fn];
+  if (wj > 1) out[xf - 1] = hs[3 * fs + fj] + hs[fs + fj];
+  out[xf] = vf;
 }
 
 // The face terms along y: one thread per (field, y tile i, z, x), as

@@ -107,15 +107,17 @@ k_pcb_local(Box b, Params<R> P, const FS* __restrict__ phi, const FS* __restrict
     GradBar<R> Gb;
     Gb.zero();
     ParBar<R> Pb{R(0), R(0), R(0)};
-    local_thermo_bwd(P, G, Lc, hb, R(0), R(0), R(0), R(0), R(0), Gb, Pb);
+    // mu4 (its own adjoints of L4 phi and D4 . v go to the next passes) shares
+    // the invariants of Q with H4, whose reverse takes both
+    R lapphib = R(0), divvb = R(0), tr2b = R(0), tr3b = R(0);
+    mu_site_bwd_local(P, G.phi, Lc.tr2, mub, Gb.phi, lapphib, divvb, tr2b, tr3b);
+    local_thermo_bwd(P, G, Lc, hb, tr2b, tr3b, R(0), R(0), R(0), Gb, Pb);
     // co-rotation S(W, Q)
     R qb[5], Wb[3][3] = {{R(0), R(0), R(0)}, {R(0), R(0), R(0)}, {R(0), R(0), R(0)}};
 #pragma unroll
     for (int k = 0; k < 5; ++k) qb[k] = Gb.q[k];
     corotation_site_bwd(P.xi, G.q, W, VQ, qb, Wb);
-    // mu4 (its own adjoints of L4 phi and D4 . v go to the next passes)
-    R phb = Gb.phi, lapphib = R(0), divvb = R(0);
-    mu_site_bwd(P, G.phi, G.q, mub, phb, lapphib, divvb, qb);
+    const R phb = Gb.phi;
     // the site's own upwind terms: R_Q gets -sum_g max(u_g,0)(Q - Q(x-e_g)) + min(u_g,0)(Q(x+e_g) - Q)
     R ub[3] = {R(0), R(0), R(0)};
 #pragma unroll

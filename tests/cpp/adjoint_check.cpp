@@ -86,17 +86,18 @@ static void check_sigma(int trial) {
   Params<R> P = params();
   Grad<R> G;
   rand_grad(G);
-  double v[14], d[31], x[31];
+  double v[15], d[31], x[31];
   for (double& t : v) t = U(-1, 1);
   for (double& t : d) t = U(-1, 1);
   flat(G, x);
+  // v: cotangents of sigma (9), H (5) and mu at the site (1)
   auto f = [&](const Grad<R>& g, const Params<R>& p) {
     R sig[9], h[5];
     sigma_site(p, g, sig, h);
     double s = 0;
     for (int k = 0; k < 9; ++k) s += v[k] * sig[k];
     for (int k = 0; k < 5; ++k) s += v[9 + k] * h[k];
-    return s;
+    return s + v[14] * mu_site(p, g.phi, g.lapphi, g.divv, g.q);
   };
   const double hstep = 1e-6;
   double xp[31], xm[31];
@@ -108,13 +109,13 @@ static void check_sigma(int trial) {
   GradBar<R> Gb;
   Gb.zero();
   ParBar<R> Pb{0, 0, 0};
-  sigma_site_bwd(P, G, v, v + 9, Gb, Pb);
+  sigma_site_bwd(P, G, v, v + 9, Gb, Pb, v[14]);
   double gb[31];
   flatb(Gb, gb);
   double ad = 0;
   for (int i = 0; i < 31; ++i) ad += gb[i] * d[i];
   char name[64];
-  std::snprintf(name, sizeof name, "sigma+h wrt G #%d", trial);
+  std::snprintf(name, sizeof name, "sigma+h+mu wrt G #%d", trial);
   report(name, fd, ad);
   // parameters: zeta and q0
   Params<R> pp = P, pm = P;
