@@ -28,6 +28,9 @@ benchmark times (default tiles and slab depths).
   seed is a smooth closed-form field; a site's reverse value depends on the
   seed within 4 sites, whose forward values in turn need 4 more, so the centre
   of a 17^3 patch with the seed kept on the central 9^3 cube is exact.
+* 128^3 droplet, FP32: one reverse step over the whole box with the z-marching
+  reverse kernels (tile-face buffers on every x and y tile face, the periodic
+  wrap faces included) against the site-parallel reverse kernels, 1e-5.
 """
 import numpy as np
 import pytest
@@ -292,6 +295,36 @@ def test_fp32_128_pc4_adjoint_sampled_sites_vs_oracle():
         worst = max(worst, err)
     print("worst relative reverse-step error", worst)
     assert worst <= 1e-4, worst
+
+
+def test_fp32_128_adjoint_tiled_equals_site_kernels(monkeypatch):
+    """One reverse step over the whole 128^3 box: the z-marching reverse kernels,
+    whose tiles exchange terms across every tile face and the periodic wrap
+    faces through face buffers, against the site-parallel reverse kernels,
+    which gather every neighbour's term themselves."""
+    p = inputs.params_for("droplet128")
+    phi, q5 = inputs.workload_fields("droplet128")
+    n, nq = phi.shape[0], 19
+    outs = []
+    for site in ("0", "1"):
+        monkeypatch.setenv("LBC_SITE_KERNELS", site)
+        with Sim(p, phi, q5, precision="fp32") as sim:
+            sim.step(3)  # a state with flow
+            state = sim.get_state()
+            adj = sim.adjoint_buffer()
+            a5 = adj.view(nq + 6, n, n, n)
+            zz = torch.arange(n, device="cuda", dtype=torch.float64).view(n, 1, 1)
+            yy, xx = zz.view(1, n, 1), zz.view(1, 1, n)
+            for c in range(nq + 6):
+                a5[c] = (torch.sin(0.37 * xx + 0.91 * yy + 1.3 * zz + 0.7 * c) * torch.cos(0.23 * xx - 0.5 * zz + c)).float()
+            out = sim.adjoint_buffer()
+            zb, qb = sim.adjoint_step(state, adj, out)
+            outs.append((out.view(nq + 6, n, n, n).cpu().numpy(), zb, qb))
+    (a, za, qa), (b, zs, qs) = outs
+    for name, sl in (("g", slice(0, nq)), ("q", slice(nq, nq + 5)), ("phi", slice(nq + 5, nq + 6))):
+        l2, mx = rel_err(a[sl], b[sl])
+        assert l2 < 1e-5 and mx < 1e-5, (name, l2, mx)
+    assert abs(za - zs) <= 1e-5 * abs(zs) and abs(qa - qs) <= 1e-5 * abs(qs)
 
 
 def test_fp32_256_conservation():
