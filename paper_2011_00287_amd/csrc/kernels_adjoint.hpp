@@ -763,8 +763,8 @@ k_adj_gather(Box b, const R* __restrict__ gbar, R* __restrict__ adj_phi, R* __re
 //     in registers, so the adjoint of plane p-1 is complete one step later
 //     except for the terms of neighbours in other tiles;
 //   * an edge site of an owned plane writes the term it owes the neighbour
-//     across the tile face to the face buffers (hx, hy), which k_adj_face_x
-//     and k_adj_face_y then add.  Every wave does one stress adjoint per
+//     across the tile face to the face buffers (hx, hy), which k_adj_faces
+//     then adds.  Every wave does one stress adjoint per
 //     plane: no site's adjoint is recomputed by a second tile.
 // Face buffers: hx[f][side][k][z][y] for the face between x tiles k and k+1
 // (mod ntx), hy[f][side][k][z][x] for y tiles; side 0 is the term sent in the
@@ -772,7 +772,7 @@ k_adj_gather(Box b, const R* __restrict__ gbar, R* __restrict__ adj_phi, R* __re
 // are written only when the box has more than one tile along that axis.  hx
 // has two more sides: the adjoint of the first (2) and last (3) column of
 // tile k without its face terms.  Those columns are left out of adj_phi and
-// adj_qo here, and k_adj_face_x writes them whole (a plain store instead of
+// adj_qo here, and k_adj_faces writes them whole (a plain store instead of
 // a read-modify-write of every cache line that holds a tile edge).
 // The (zeta, q0) partials count owned sites only.
 // ---------------------------------------------------------------------------
@@ -796,7 +796,7 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
   const int tx = l % ntx, ty = (l / ntx) % nty, sl = l / (ntx * nty);
   // with several x tiles, tile tx starts one column early (x0 = tx TX - 1,
   // mod nx): the edge columns of neighbouring tiles are then adjacent in
-  // memory, and so are the two columns k_adj_face_x writes per face
+  // memory, and so are the two columns k_adj_faces writes per face
   const int x0 = tx * TX - (ntx > 1 ? 1 : 0), y0 = ty * TY, z0 = sl * TZ;
   const int z1 = min(z0 + TZ, b.nz);
   const int w = min(TX, b.nx - tx * TX), h = min(TY, b.ny - y0);  // the tile's extent in the box
@@ -1016,55 +1016,78 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
   block_reduce_store<2>(v, partial + size_t(blockIdx.x) * 2, accumulate != 0);
 }
 
-// The face terms of k_adj_sg_fused along x.  Tile j covers the columns
-// j TX - 1 .. j TX + w_j - 2 (mod nx), so the last column of tile j and the
-// first of tile j+1 are neighbours in memory.  One thread per (field, face j,
-// z, y) writes both: the last column of tile j (its adjoint without face terms
-// plus the term sent in the - direction across face j) and the first column
-// of tile j+1 (the same, with the term sent in the + direction).  A tile one
-// column wide (only the last tile can be) gets both of its terms from the
-// thread of the face before it.  Fields 0..5: phi, q[5].
+// The face terms of k_adj_sg_fused, in one launch of two thread ranges.
+// Fields f = 0..5: phi, q[5].
+// * x faces, one thread per (field, face j, z, y) when there are several x
+//   tiles.  Tile j covers the columns j TX - 1 .. j TX + w_j - 2 (mod nx), so
+//   the last column of tile j and the first of tile j+1 are neighbours in
+//   memory; the thread writes both whole: the last column of tile j (its
+//   adjoint without face terms plus the term sent in the - direction across
+//   face j) and the first column of tile j+1 (the same, with the term sent in
+//   the + direction).  A tile one column wide (only the last tile can be) gets
+//   both of its terms from the thread of the face before it.  On a row that is
+//   the first or last of its y tile, the thread adds that row's y-face terms
+//   as well, so the corner sites are complete.
+// * y faces, one thread per (field, y tile i, z, x) when there are several y
+//   tiles: the first row of tile i takes the term sent in the + direction
+//   across face i-1, its last row the term sent in the - direction across
+//   face i (read-modify-write of what k_adj_sg_fused stored), at every column
+//   except the x-edge columns, which the first range writes.
 template <class R>
-__global__ void __launch_bounds__(256) k_adj_face_x(Box b, int TX, int ntx, const R* __restrict__ hx,
-                                                    R* __restrict__ adj_phi, R* __restrict__ adj_q) {
+__global__ void __launch_bounds__(256) k_adj_faces(Box b, int TX, int ntx, int TY, int nty,
+                                                   const R* __restrict__ hx, const R* __restrict__ hy,
+                                                   R* __restrict__ adj_phi, R* __restrict__ adj_q) {
   const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const size_t nzy = size_t(b.nz) * b.ny, fs = size_t(ntx) * nzy;
-  if (t >= 6 * fs) return;
-  const int f = int(t / fs);
-  const size_t r = t % fs;
-  const int j = int(r / nzy);
-  const size_t zy = r % nzy;
-  const int jn = j + 1 < ntx ? j + 1 : 0;
-  const int wj = min(TX, b.nx - j * TX), wn = min(TX, b.nx - jn * TX);
-  const int xf = jn > 0 ? jn * TX - 1 : b.nx - 1;  // first column of tile jn; tile j's last is xf - 1
-  R* out = (f == 0 ? adj_phi : adj_q + size_t(f - 1) * b.N) + zy * b.nx;  // row (z, y)
-  const R* hs = hx + size_t(4 * f) * fs;
-  const size_t fj = size_t(j) * nzy + zy, fn = size_t(jn) * nzy + zy;
-  R vf = hs[2 * fs + fn] + hs[fj];
-  if (wn == 1) vf += hs[fs + fn];
-  if (wj > 1) out[xf - 1] = hs[3 * fs + fj] + hs[fs + fj];
-  out[xf] = vf;
-}
-
-// The face terms along y: one thread per (field, y tile i, z, x), as
-// k_adj_face_x with rows for columns.  Launched after k_adj_face_x, so a
-// corner site takes its x terms first.
-template <class R>
-__global__ void __launch_bounds__(256) k_adj_face_y(Box b, int TY, int nty, const R* __restrict__ hy,
-                                                    R* __restrict__ adj_phi, R* __restrict__ adj_q) {
-  const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const size_t nzx = size_t(b.nz) * b.nx, fs = size_t(nty) * nzx;
-  if (t >= 6 * fs) return;
-  const int f = int(t / fs);
-  const size_t r = t % fs;
+  const size_t nzy = size_t(b.nz) * b.ny, nzx = size_t(b.nz) * b.nx;
+  const size_t fxs = size_t(ntx) * nzy, fys = size_t(nty) * nzx;  // one field-side block of hx, hy
+  const size_t nxt = ntx > 1 ? 6 * fxs : 0, nyt = nty > 1 ? 6 * fys : 0;
+  if (t < nxt) {
+    const int f = int(t / fxs);
+    const size_t r = t % fxs;
+    const int j = int(r / nzy);
+    const size_t zy = r % nzy;
+    const int jn = j + 1 < ntx ? j + 1 : 0;
+    const int wj = min(TX, b.nx - j * TX), wn = min(TX, b.nx - jn * TX);
+    const int xf = jn > 0 ? jn * TX - 1 : b.nx - 1;  // first column of tile jn; tile j's last is xf - 1
+    R* out = (f == 0 ? adj_phi : adj_q + size_t(f - 1) * b.N) + zy * b.nx;  // row (z, y)
+    const R* hs = hx + size_t(4 * f) * fxs;
+    const size_t fj = size_t(j) * nzy + zy, fn = size_t(jn) * nzy + zy;
+    R vl = hs[3 * fxs + fj] + hs[fxs + fj];
+    R vf = hs[2 * fxs + fn] + hs[fj];
+    if (wn == 1) vf += hs[fxs + fn];
+    if (nty > 1) {  // the y-face terms of a first or last row of a y tile
+      const int z = int(zy / b.ny), y = int(zy % b.ny);
+      const int i = y / TY, ly = y - i * TY, h = min(TY, b.ny - i * TY);
+      const R* ys = hy + size_t(2 * f) * fys + size_t(z) * b.nx;
+      if (ly == 0) {
+        const R* s0 = ys + size_t((i + nty - 1) % nty) * nzx;
+        vl += s0[xf - 1];
+        vf += s0[xf];
+      }
+      if (ly == h - 1) {
+        const R* s1 = ys + fys + size_t(i) * nzx;
+        vl += s1[xf - 1];
+        vf += s1[xf];
+      }
+    }
+    if (wj > 1) out[xf - 1] = vl;
+    out[xf] = vf;
+    return;
+  }
+  if (t - nxt >= nyt) return;
+  const size_t u = t - nxt;
+  const int f = int(u / fys);
+  const size_t r = u % fys;
   const int i = int(r / nzx);
   const size_t zx = r % nzx;
   const int z = int(zx / b.nx), x = int(zx % b.nx);
+  // the x-edge columns (first and last of every x tile) belong to the first range
+  if (ntx > 1 && ((x + 1) % TX == 0 || (x + 2) % TX == 0 || x >= b.nx - 2)) return;
   const int ya = i * TY, yb = min(ya + TY, b.ny) - 1;
   R* out = (f == 0 ? adj_phi : adj_q + size_t(f - 1) * b.N) + size_t(z) * b.ny * b.nx + x;
-  const R* hs = hy + size_t(2 * f) * fs;
-  out[size_t(ya) * b.nx] += hs[size_t((i + nty - 1) % nty) * nzx + zx];  // after k_adj_face_x
-  out[size_t(yb) * b.nx] += hs[fs + size_t(i) * nzx + zx];
+  const R* hs = hy + size_t(2 * f) * fys;
+  out[size_t(ya) * b.nx] += hs[size_t((i + nty - 1) % nty) * nzx + zx];
+  out[size_t(yb) * b.nx] += hs[fys + size_t(i) * nzx + zx];
 }
 
 // out = in + 1 for the step counter of a recorded state (one thread, vector memory).

@@ -892,14 +892,12 @@ struct BackendT final : Backend {
     lbc::k_adj_sg_fused<R, FS, kAsTX, kAsTY, L::kStressInEq><<<as_blocks, kAsTX * kAsTY, 0, stream>>>(
         box, P, as_tz, as_ntx, as_nty, phi_t, q_t, aFb, aq, mb, aqbp, aphibp, aSb, po, qo, ahx, ahy, apart,
         apart_live ? 1 : 0);
-    if (as_ntx > 1) {
-      const size_t n = 6 * size_t(as_ntx) * box.nz * box.ny;  // one thread per field
-      lbc::k_adj_face_x<R><<<unsigned((n + TPB - 1) / TPB), TPB, 0, stream>>>(box, kAsTX, as_ntx, ahx, po, qo);
-    }
-    if (as_nty > 1) {
-      const size_t n = 6 * size_t(as_nty) * box.nz * box.nx;  // one thread per field
-      lbc::k_adj_face_y<R><<<unsigned((n + TPB - 1) / TPB), TPB, 0, stream>>>(box, kAsTY, as_nty, ahy, po, qo);
-    }
+    // one thread per field and x-face row, then one per field and y-face column
+    const size_t n = (as_ntx > 1 ? 6 * size_t(as_ntx) * box.nz * box.ny : 0) +
+                     (as_nty > 1 ? 6 * size_t(as_nty) * box.nz * box.nx : 0);
+    if (n > 0)
+      lbc::k_adj_faces<R><<<unsigned((n + TPB - 1) / TPB), TPB, 0, stream>>>(box, kAsTX, as_ntx, kAsTY, as_nty, ahx,
+                                                                             ahy, po, qo);
   }
   // Reverse of a step of the pc4 integrator: the predictor is replayed from
   // X = (phi_t, q_t) with the step's velocity uu, the two Heun products
