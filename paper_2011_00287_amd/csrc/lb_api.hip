@@ -82,11 +82,15 @@ constexpr TileCfg kPcTiles[] = {{32, 8}, {32, 16}, {16, 16}, {64, 8}};
 // gives per_cu workgroups per CU for a grid of ntx x nty tiles.  Small boxes
 // get shallow slabs: a deep slab on few tiles leaves most CUs idle while a
 // handful of workgroups march through the planes one after another.
-int auto_slab(int ntx, int nty, int nz, int tz_max, int tz_min, int per_cu) {
+int cu_count() {
   int dev = 0, ncu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
     ncu = 256;
+  return ncu;
+}
+int auto_slab(int ntx, int nty, int nz, int tz_max, int tz_min, int per_cu) {
+  const int ncu = cu_count();
   int tz = tz_max;
   while (tz > tz_min && size_t(ntx) * nty * ((nz + tz - 1) / tz) < size_t(per_cu) * ncu) tz /= 2;
   return tz;
@@ -296,7 +300,13 @@ struct BackendT final : Backend {
     as_ntx = (p.nx + kAsTX - 1) / kAsTX;
     as_nty = (p.ny + kAsTY - 1) / kAsTY;
     as_tz = std::max(0, env_int("LBC_TZ_ADJ", 0));
-    if (as_tz == 0) as_tz = auto_slab(as_ntx, as_nty, p.nz, 16, 1, 1);
+    if (as_tz == 0) {
+      // large boxes (four or more workgroups per CU at 64 planes or less): deeper
+      // slabs, since each slab marches two planes more than it owns
+      as_tz = auto_slab(as_ntx, as_nty, p.nz, 64, 16, 4);
+      if (size_t(as_ntx) * as_nty * ((p.nz + as_tz - 1) / as_tz) < 4 * size_t(cu_count()))
+        as_tz = auto_slab(as_ntx, as_nty, p.nz, 16, 1, 1);
+    }
     as_blocks = as_ntx * as_nty * ((p.nz + as_tz - 1) / as_tz);
     size_t need = 2 * (NQ * N * sizeof(GS) + 6 * N * sizeof(FS)) + 4 * N * sizeof(R);
     if (pc4) need += 6 * N * sizeof(FS) + (site_path ? 3 * N * sizeof(R) : 0);
