@@ -513,8 +513,8 @@ __host__ __device__ __forceinline__ void collide_site_bwd_m(const Params<R>& P, 
   R Ab = R(0), Bsb = R(0), rhob = R(0);
   R ub[3] = {ub_in[0], ub_in[1], ub_in[2]};
   for (int i = 0; i < 19; ++i) {
-    const R cu = R(CX(i)) * u[0] + R(CY(i)) * u[1] + R(CZ(i)) * u[2];
-    const R cF = R(CX(i)) * F[0] + R(CY(i)) * F[1] + R(CZ(i)) * F[2];
+    const R cu = cdot(CX(i), CY(i), CZ(i), u);
+    const R cF = cdot(CX(i), CY(i), CZ(i), F);
     const R e = WQ<R>(i) * gsb[i];
     gb[i] = om1 * gsb[i];
     Ab += om * e;
@@ -522,12 +522,12 @@ __host__ __device__ __forceinline__ void collide_site_bwd_m(const Params<R>& P, 
     rhob += om * e * (R(3) * cu + R(4.5) * cu * cu);
     const R cub = e * (om * (R(3) * rho + R(9) * rho * cu) + P.guo * R(9) * cF);
     const R cFb = e * P.guo * (R(3) + R(9) * cu);
-    ub[0] += cub * R(CX(i));
-    ub[1] += cub * R(CY(i));
-    ub[2] += cub * R(CZ(i));
-    Fb[0] += cFb * R(CX(i));
-    Fb[1] += cFb * R(CY(i));
-    Fb[2] += cFb * R(CZ(i));
+    cadd(CX(i), cub, ub[0]);
+    cadd(CY(i), cub, ub[1]);
+    cadd(CZ(i), cub, ub[2]);
+    cadd(CX(i), cFb, Fb[0]);
+    cadd(CY(i), cFb, Fb[1]);
+    cadd(CZ(i), cFb, Fb[2]);
   }
   R drhob = Ab;
   rhob += R(-1.5) * uu * Ab;
@@ -545,7 +545,13 @@ __host__ __device__ __forceinline__ void collide_site_bwd_m(const Params<R>& P, 
     rhob -= ub[a] * u[a] * inv;
   }
   drhob += rhob;
-  for (int i = 0; i < 19; ++i) gb[i] += drhob + R(CX(i)) * jb[0] + R(CY(i)) * jb[1] + R(CZ(i)) * jb[2];
+  for (int i = 0; i < 19; ++i) {
+    R t = drhob;
+    cadd(CX(i), jb[0], t);
+    cadd(CY(i), jb[1], t);
+    cadd(CZ(i), jb[2], t);
+    gb[i] += t;
+  }
 }
 
 // Reverse of collide_site from the pre-collision populations g[19].
@@ -556,9 +562,9 @@ __host__ __device__ __forceinline__ void collide_site_bwd(const Params<R>& P, co
   for (int i = 0; i < 19; ++i) drho += g[i];
   R j[3] = {R(0), R(0), R(0)};
   for (int i = 0; i < 19; ++i) {
-    j[0] += R(CX(i)) * g[i];
-    j[1] += R(CY(i)) * g[i];
-    j[2] += R(CZ(i)) * g[i];
+    cadd(CX(i), g[i], j[0]);
+    cadd(CY(i), g[i], j[1]);
+    cadd(CZ(i), g[i], j[2]);
   }
   const R inv = R(1) / (P.rho0 + drho);
   R u[3];
@@ -588,9 +594,9 @@ __host__ __device__ __forceinline__ void collide_eq_site_bwd_m(const Params<R>& 
   R Ab = R(0), Bsb = R(0), rhob = R(0);
   R ub[3] = {ub_in[0], ub_in[1], ub_in[2]};
   for (int i = 0; i < 15; ++i) {
-    const R cx = R(L::cx(i)), cy = R(L::cy(i)), cz = R(L::cz(i));
-    const R cu = cx * u[0] + cy * u[1] + cz * u[2];
-    const R cF = cx * F[0] + cy * F[1] + cz * F[2];
+    const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
+    const R cu = cdot(cx, cy, cz, u);
+    const R cF = cdot(cx, cy, cz, F);
     const R e = L::w<R>(i) * gsb[i];
     gb[i] = om1 * gsb[i];
     Ab += om * e;
@@ -598,20 +604,20 @@ __host__ __device__ __forceinline__ void collide_eq_site_bwd_m(const Params<R>& 
     rhob += om * e * (R(3) * cu + R(4.5) * cu * cu);
     const R cub = e * (om * (R(3) * rho + R(9) * rho * cu) + P.guo * R(9) * cF);
     const R cFb = e * P.guo * (R(3) + R(9) * cu);
-    ub[0] += cub * cx;
-    ub[1] += cub * cy;
-    ub[2] += cub * cz;
-    Fb[0] += cFb * cx;
-    Fb[1] += cFb * cy;
-    Fb[2] += cFb * cz;
+    cadd(cx, cub, ub[0]);
+    cadd(cy, cub, ub[1]);
+    cadd(cz, cub, ub[2]);
+    cadd(cx, cFb, Fb[0]);
+    cadd(cy, cFb, Fb[1]);
+    cadd(cz, cFb, Fb[2]);
     // -4.5 om c.S.c, with c.S.c = cx^2 Sxx + cy^2 Syy + cz^2 Szz + 2 (cx cy Sxy + cx cz Sxz + cy cz Syz)
-    const R es = R(-4.5) * om * e;
-    Sb[0] += es * cx * cx;
-    Sb[1] += R(2) * es * cx * cy;
-    Sb[2] += R(2) * es * cx * cz;
-    Sb[3] += es * cy * cy;
-    Sb[4] += R(2) * es * cy * cz;
-    Sb[5] += es * cz * cz;
+    const R es = R(-4.5) * om * e, es2 = R(2) * es;
+    cadd(cx * cx, es, Sb[0]);
+    cadd(cx * cy, es2, Sb[1]);
+    cadd(cx * cz, es2, Sb[2]);
+    cadd(cy * cy, es, Sb[3]);
+    cadd(cy * cz, es2, Sb[4]);
+    cadd(cz * cz, es, Sb[5]);
   }
   // +1.5 om trS, summed over i through Ab = om sum w_i gsb_i
   Sb[0] += R(1.5) * Ab;
@@ -633,7 +639,13 @@ __host__ __device__ __forceinline__ void collide_eq_site_bwd_m(const Params<R>& 
     rhob -= ub[a] * u[a] * inv;
   }
   drhob += rhob;
-  for (int i = 0; i < 15; ++i) gb[i] += drhob + R(L::cx(i)) * jb[0] + R(L::cy(i)) * jb[1] + R(L::cz(i)) * jb[2];
+  for (int i = 0; i < 15; ++i) {
+    R t = drhob;
+    cadd(L::cx(i), jb[0], t);
+    cadd(L::cy(i), jb[1], t);
+    cadd(L::cz(i), jb[2], t);
+    gb[i] += t;
+  }
 }
 
 // Reverse of collide_site_eq from the pre-collision populations g[15].
@@ -645,9 +657,9 @@ __host__ __device__ __forceinline__ void collide_eq_site_bwd(const Params<R>& P,
   R drho = R(0), j[3] = {R(0), R(0), R(0)};
   for (int i = 0; i < 15; ++i) {
     drho += g[i];
-    j[0] += R(L::cx(i)) * g[i];
-    j[1] += R(L::cy(i)) * g[i];
-    j[2] += R(L::cz(i)) * g[i];
+    cadd(L::cx(i), g[i], j[0]);
+    cadd(L::cy(i), g[i], j[1]);
+    cadd(L::cz(i), g[i], j[2]);
   }
   const R inv = R(1) / (P.rho0 + drho);
   R u[3];

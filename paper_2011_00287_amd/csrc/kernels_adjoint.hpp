@@ -46,9 +46,9 @@ __global__ void __launch_bounds__(256) k_fwd_force(Box b, Params<R> P, const GS*
   for (int i = 0; i < L::Q; ++i) {
     const R gi = GPol<GS, L>::template ld<R>(B, i * N + sidx(b, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i);
     sum += gi;
-    j[0] += R(L::cx(i)) * gi;
-    j[1] += R(L::cy(i)) * gi;
-    j[2] += R(L::cz(i)) * gi;
+    cadd(L::cx(i), gi, j[0]);
+    cadd(L::cy(i), gi, j[1]);
+    cadd(L::cz(i), gi, j[2]);
   }
   const R rho = P.rho0 + sum;
 #pragma unroll
@@ -471,9 +471,9 @@ __global__ void __launch_bounds__(256) k_adj_collide(Box b, Params<R> P, const G
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
     drho += g[i];
-    j[0] += R(L::cx(i)) * g[i];
-    j[1] += R(L::cy(i)) * g[i];
-    j[2] += R(L::cz(i)) * g[i];
+    cadd(L::cx(i), g[i], j[0]);
+    cadd(L::cy(i), g[i], j[1]);
+    cadd(L::cz(i), g[i], j[2]);
   }
   const R inv = R(1) / (P.rho0 + drho);
   R us[3];

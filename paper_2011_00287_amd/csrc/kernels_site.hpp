@@ -259,9 +259,9 @@ __global__ void k_moments(Box b, Params<R> P, const GS* __restrict__ B, const R*
   for (int i = 0; i < L::Q; ++i) {
     const R gi = GPol<GS, L>::template ld<R>(B, i * N + sidx(b, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i);
     sum += gi;
-    j[0] += R(L::cx(i)) * gi;
-    j[1] += R(L::cy(i)) * gi;
-    j[2] += R(L::cz(i)) * gi;
+    cadd(L::cx(i), gi, j[0]);
+    cadd(L::cy(i), gi, j[1]);
+    cadd(L::cz(i), gi, j[2]);
   }
   const R rho = P.rho0 + sum;
   rho_out[s] = rho;

@@ -47,6 +47,24 @@ __host__ __device__ constexpr R WQ(int i) {
   return i == 0 ? R(1) / R(3) : (i <= 6 ? R(1) / R(18) : R(1) / R(36));
 }
 
+// c . v and acc += c v for lattice-velocity components c in {-1, 0, 1} known
+// at compile time, from the nonzero components only.  Under IEEE rules the
+// compiler may not drop a product with 0 (0 * inf is NaN), so R(c) * v would
+// cost an instruction for every zero component.  For finite v the results
+// equal those of the full sums exactly.
+template <class R>
+__host__ __device__ __forceinline__ R cdot(int cx, int cy, int cz, const R v[3]) {
+  R s = R(-0.0);  // -0 + x == x for every x: the first term is exact and the add folds
+  if (cx != 0) s += cx > 0 ? v[0] : -v[0];
+  if (cy != 0) s += cy > 0 ? v[1] : -v[1];
+  if (cz != 0) s += cz > 0 ? v[2] : -v[2];
+  return s;
+}
+template <class R>
+__host__ __device__ __forceinline__ void cadd(int c, R v, R& acc) {
+  if (c != 0) acc += c > 0 ? v : -v;
+}
+
 // Velocity sets as traits.  D3Q19 (the order above) carries the whole stress as
 // a Guo body force.  D3Q15, the paper's lattice (Fig. 1), carries the symmetric
 // stress in the second moment of the equilibrium (Eqs. (9), (11)) and only the
@@ -345,8 +363,8 @@ __host__ __device__ __forceinline__ R collide_site(const Params<R>& P, R g[19], 
 #pragma unroll
   for (int i = 1; i < 19; i += 2) {
     const int k = i < 7 ? 0 : 1;
-    const R cu = R(CX(i)) * u[0] + R(CY(i)) * u[1] + R(CZ(i)) * u[2];
-    const R cF = R(CX(i)) * F[0] + R(CY(i)) * F[1] + R(CZ(i)) * F[2];
+    const R cu = cdot(CX(i), CY(i), CZ(i), u);
+    const R cF = cdot(CX(i), CY(i), CZ(i), F);
     const R even = cb[k] + cu * (ca[k] * cu + cg9[k] * cF);
     const R odd = cr[k] * cu + cg3[k] * cF;
     const R gi = g[i], gj = g[i + 1];
@@ -373,9 +391,9 @@ __host__ __device__ __forceinline__ R collide_site_eq(const Params<R>& P, R g[15
 #pragma unroll
   for (int i = 1; i < 15; i += 2) {
     const R e = g[i] - g[i + 1];
-    j[0] += R(L::cx(i)) * e;
-    j[1] += R(L::cy(i)) * e;
-    j[2] += R(L::cz(i)) * e;
+    cadd(L::cx(i), e, j[0]);
+    cadd(L::cy(i), e, j[1]);
+    cadd(L::cz(i), e, j[2]);
   }
   const R rho = P.rho0 + drho;
   const R inv = R(1) / rho;
@@ -392,10 +410,16 @@ __host__ __device__ __forceinline__ R collide_site_eq(const Params<R>& P, R g[15
 #pragma unroll
   for (int i = 1; i < 15; i += 2) {
     const int ex = L::cx(i), ey = L::cy(i), ez = L::cz(i);
-    const R cu = R(ex) * u[0] + R(ey) * u[1] + R(ez) * u[2];
-    const R cF = R(ex) * F[0] + R(ey) * F[1] + R(ez) * F[2];
-    const R cTc = R(ex * ex) * Txx + R(ey * ey) * Tyy + R(ez * ez) * Tzz +
-                  R(2) * (R(ex * ey) * Txy + R(ex * ez) * Txz + R(ey * ez) * Tyz);
+    const R cu = cdot(ex, ey, ez, u);
+    const R cF = cdot(ex, ey, ez, F);
+    R cd = R(-0.0), co = R(-0.0);  // c.T.c = sum c_a^2 T_aa + 2 sum_{a<b} c_a c_b T_ab
+    cadd(ex * ex, Txx, cd);
+    cadd(ey * ey, Tyy, cd);
+    cadd(ez * ez, Tzz, cd);
+    cadd(ex * ey, Txy, co);
+    cadd(ex * ez, Txz, co);
+    cadd(ey * ez, Tyz, co);
+    const R cTc = cd + R(2) * co;
     const R w = L::w<R>(i);
     const R even = w * (base + a45 * cTc + g9 * cu * cF);
     const R odd = w * (r3 * cu + g3 * cF);
