@@ -37,13 +37,18 @@ namespace lbc {
 //   the stress of planes p-2..p.  The global loads needed after the stress
 //   pass (the pull of plane p-1, the ring planes for p+1) are issued before
 //   it so that their latency overlaps the stress arithmetic.
+//   A recording step also passes the step counters of its input and output
+//   states (step_in, step_out; null otherwise): one thread writes
+//   *step_out = *step_in + 1, which spares a launch per recorded step.
 // ---------------------------------------------------------------------------
 template <class R, class GS, class FS, class L, int TX, int TY, int MINW>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(MINW)))
 k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ Bin, GS* __restrict__ Bout,
            const FS* __restrict__ phi, const FS* __restrict__ q, R* __restrict__ u_out, R* __restrict__ mu_out,
-           R* __restrict__ F_out, R* __restrict__ drho_out) {
+           R* __restrict__ F_out, R* __restrict__ drho_out, const int64_t* __restrict__ step_in,
+           int64_t* __restrict__ step_out) {
   constexpr int NT = TX * TY;
+  if (step_out != nullptr && blockIdx.x == 0 && threadIdx.x == 0) step_out[0] = step_in[0] + 1;
   constexpr int AX = TX + 4, AY = TY + 4, NA = AX * AY;  // phi / Q slots (halo 2)
   constexpr int SX = TX + 2, SY = TY + 2, NS = SX * SY;  // stress slots (halo 1)
   __shared__ R sPhi[5][NA];

@@ -578,6 +578,8 @@ struct BackendT final : Backend {
     R* u;
     R* F;
     R* drho;
+    const int64_t* step_in = nullptr;  // step counters of a recording step's states
+    int64_t* step_out = nullptr;
   };
   Io cur_io() { return Io{B[cur], B[cur ^ 1], Ph[cur], Q[cur], Ph[cur ^ 1], Q[cur ^ 1], u, nullptr, nullptr}; }
   void launch_lb_tile(const Io& io) {
@@ -594,7 +596,8 @@ struct BackendT final : Backend {
   template <int TX, int TY, int MINW>
   void launch_lb(const Io& io) {
     lbc::k_lb_fused<R, GS, FS, L, TX, TY, MINW><<<lb_blocks, TX * TY, 0, stream>>>(
-        box, P, tz_lb, lb_ntx, lb_nty, io.Bi, io.Bo, io.phi_i, io.q_i, io.u, mu, io.F, io.drho);
+        box, P, tz_lb, lb_ntx, lb_nty, io.Bi, io.Bo, io.phi_i, io.q_i, io.u, mu, io.F, io.drho, io.step_in,
+        io.step_out);
   }
   void launch_or_tile(const Io& io) {
     switch (or_tile) {
@@ -843,16 +846,17 @@ struct BackendT final : Backend {
     R* ru = static_cast<R*>(rec_out);
     R* rF = ru + 3 * N;
     R* rd = ru + 6 * N;
+    int64_t* step_out = reinterpret_cast<int64_t*>(co + off_step());
     if (site_path) {
       ensure_thermo();
       lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, vi.phi, vi.q, mu, H, sig);
       lbc::k_fwd_force<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, vi.B, sig, rF, ru, rd);
       lbc::k_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, vi.B, Bo, sig, ru);
       lbc::k_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, vi.phi, vi.q, ru, H, mu, po, qo);
+      lbc::k_step_count<<<1, 64, 0, stream>>>(vi.step, step_out);
     } else {
-      fused_step(Io{vi.B, Bo, vi.phi, vi.q, po, qo, ru, rF, rd});
+      fused_step(Io{vi.B, Bo, vi.phi, vi.q, po, qo, ru, rF, rd, vi.step, step_out});  // k_lb_fused counts
     }
-    lbc::k_step_count<<<1, 64, 0, stream>>>(vi.step, reinterpret_cast<int64_t*>(co + off_step()));
     check_launch();
   }
   // lean step record: Q [5][N], phi [N] (storage type) of time t, then drho,
