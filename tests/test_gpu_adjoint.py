@@ -225,7 +225,7 @@ def test_recorded_rollout_equals_checkpointed():
     assert l2 < 1e-12 and mx < 1e-12, (l2, mx)
 
 
-@pytest.mark.parametrize("shape", [(34, 18, 11), (33, 9, 5), (12, 6, 7)])
+@pytest.mark.parametrize("shape", [(34, 18, 11), (33, 9, 5), (12, 6, 7), (64, 16, 5)])
 @pytest.mark.parametrize("tz", ["1", "3", "default"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
 def test_adjoint_site_and_tiled_kernels_agree(monkeypatch, prec, tol, tz, shape):
@@ -234,7 +234,8 @@ def test_adjoint_site_and_tiled_kernels_agree(monkeypatch, prec, tol, tz, shape)
     reverse step, for several slab depths.  Boxes: ragged tiles and slabs
     (34 x 18 x 11); edge tiles one column and one row wide, whose sites send
     across both faces of an axis (33 x 9 x 5); one tile smaller than the tile
-    shape, which wraps periodically inside itself (12 x 6 x 7)."""
+    shape, which wraps periodically inside itself (12 x 6 x 7); whole tiles
+    only, on two or more x tiles and two y tiles (64 x 16 x 5)."""
     p = _p(q0=2 * math.pi / 9, zeta=0.01)
     g, phi, q5 = inputs.random_fields(*shape, seed=21, g_amp=2e-3, q_amp=0.2)
     seed_vals = np.random.default_rng(4).normal(size=25 * phi.size)
