@@ -156,11 +156,16 @@ __global__ void __launch_bounds__(TX* TY) k2_lb(Box2 b, Params2<R> P, int ntx, c
   for (int i = 0; i < 9; ++i)
     g[i] = Bin[i * N + wrap2(y - CY9(i), b.ny) * b.nx + wrap2(x - CX9(i), b.nx)];
   R drho = g[0], j[2] = {R(0), R(0)};
+  // lattice-velocity products from the nonzero components only (a product
+  // with 0 is not dropped by the compiler under IEEE rules; same results)
+  auto cadd9 = [](int c, R v, R& acc) {
+    if (c != 0) acc += c > 0 ? v : -v;
+  };
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
     drho += g[i];
-    j[0] += R(CX9(i)) * g[i];
-    j[1] += R(CY9(i)) * g[i];
+    cadd9(CX9(i), g[i], j[0]);
+    cadd9(CY9(i), g[i], j[1]);
   }
   const R rho = P.rho0 + drho;
   const R u[2] = {(j[0] + R(0.5) * F[0]) / rho, (j[1] + R(0.5) * F[1]) / rho};
@@ -168,8 +173,11 @@ __global__ void __launch_bounds__(TX* TY) k2_lb(Box2 b, Params2<R> P, int ntx, c
   const int s = y * b.nx + x;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    const R cu = R(CX9(i)) * u[0] + R(CY9(i)) * u[1];
-    const R cF = R(CX9(i)) * F[0] + R(CY9(i)) * F[1];
+    R cu = R(-0.0), cF = R(-0.0);  // -0 + x == x: the first add folds
+    cadd9(CX9(i), u[0], cu);
+    cadd9(CY9(i), u[1], cu);
+    cadd9(CX9(i), F[0], cF);
+    cadd9(CY9(i), F[1], cF);
     const R w = W9<R>(i);
     const R geq = w * (drho + rho * ((R(3) * cu + R(4.5) * cu * cu) - R(1.5) * uu));
     const R src = P.guo * w * (R(3) * (cF - uF) + R(9) * cu * cF);
