@@ -116,6 +116,10 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True, lat
     from paper_2011_00287_amd.sim import Sim
     sim = Sim(p, phi, q5, precision=prec, stream=stream, lattice=lattice, fd_scheme=fd_scheme)
     s0 = sim.get_state()
+    # the loss is the displacement of the centre from its position at time 0,
+    # so the reference is read from the initial state (a reference taken at
+    # time T would give a zero loss and an all-zero adjoint seed)
+    zc0 = float(sim.centre()[0][2])
     sim.step(3)
     sim.set_state(s0)
 
@@ -128,13 +132,17 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True, lat
         return out, time.perf_counter() - t0
 
     _, t_fwd = timed(lambda: sim.step(steps))
-    zc0 = float(sim.centre()[0][2])
+    losses = []
 
     def run_mode(fwd, bwd):
         sim.set_state(s0)
         hist, t_f = timed(fwd)
         adj = sim.adjoint_buffer()
-        sim.seed_centre(zc0, adj)
+        loss = sim.seed_centre(zc0, adj)
+        if not loss > 0.0:
+            raise RuntimeError(f"adjoint timing: displacement loss {loss!r} after {steps} steps; the reverse "
+                               "pass would run on a zero seed")
+        losses.append(loss)
         _, t_b = timed(lambda: bwd(hist, adj))
         return hist, t_f, t_b
 
@@ -144,7 +152,8 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True, lat
     out = {"steps": steps, "checkpoint": checkpoint, "precision": prec, "lattice": lattice.upper(),
            "fd_scheme": fd_scheme,
            "forward_ms": t_fwd * 1e3, "forward_with_checkpoints_ms": t_fwd_ck * 1e3, "backward_ms": t_bwd * 1e3,
-           "adjoint_over_forward": t_bwd / t_fwd, "total_over_forward": (t_fwd_ck + t_bwd) / t_fwd}
+           "adjoint_over_forward": t_bwd / t_fwd, "total_over_forward": (t_fwd_ck + t_bwd) / t_fwd,
+           "loss": losses[0]}
     if not alternatives:
         if recorded:
             recs, t_fwd_rec, t_bwd_rec = run_mode(lambda: run_lean(sim, steps),
