@@ -196,13 +196,12 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True, lat
     return out
 
 
-def cpu_baseline(workload: str, nsteps: int = 2, lattice: str = "d3q19", fd_scheme: str = "euler2"):
+def _oracle_mlups(workload, nsteps, threads, lattice="d3q19", fd_scheme="euler2"):
+    """MLUPS of the FP64 oracle on `threads` host threads: `nsteps` timed steps after one warm-up."""
     import torch
     from oracle import core, d3q15, pc4
     from paper_2011_00287_amd import inputs
     if fd_scheme == "pc4":
-        if lattice != "d3q19":
-            return None
         step = pc4.step
     else:
         step = core.step if lattice == "d3q19" else d3q15.step
@@ -210,15 +209,50 @@ def cpu_baseline(workload: str, nsteps: int = 2, lattice: str = "d3q19", fd_sche
     phi, q5 = inputs.workload_fields(workload)
     phi_t, q5_t = torch.tensor(phi), torch.tensor(q5)
     g = torch.zeros((NQ[lattice],) + phi.shape, dtype=torch.float64)
-    g, q5_t, phi_t = step(g, q5_t, phi_t, p)  # warm-up
-    t0 = time.perf_counter()
-    for _ in range(nsteps):
-        g, q5_t, phi_t = step(g, q5_t, phi_t, p)
-    dt = time.perf_counter() - t0
-    n = phi.size
-    return {"value": n * nsteps / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"{workload} ({n} sites) FP64 oracle ({lattice.upper()}, {fd_scheme}), {nsteps} timed steps "
-                      "after 1 warm-up from the initial droplet"}
+    prev = torch.get_num_threads()
+    torch.set_num_threads(threads)
+    try:
+        g, q5_t, phi_t = step(g, q5_t, phi_t, p)  # warm-up
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            g, q5_t, phi_t = step(g, q5_t, phi_t, p)
+        dt = time.perf_counter() - t0
+    finally:
+        torch.set_num_threads(prev)
+    return phi.size * nsteps / dt / 1e6, dt
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(workload: str, nsteps: int = 3, lattice: str = "d3q19", fd_scheme: str = "euler2",
+                 small: str = "droplet64", small_steps: int = 20):
+    """The FP64 oracle on the host: the timed workload on all threads (the
+    reported value), and the 64^3 droplet on all threads and on one thread."""
+    import torch
+    if fd_scheme == "pc4" and lattice != "d3q19":
+        return None
+    threads = torch.get_num_threads()
+    v, dt = _oracle_mlups(workload, nsteps, threads, lattice, fd_scheme)
+    out = {"value": v, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"{workload} FP64 oracle ({lattice.upper()}, {fd_scheme}), {nsteps} timed steps after 1 "
+                     f"warm-up from the initial droplet ({dt:.1f} s)",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    if small:
+        v_all, dt_all = _oracle_mlups(small, small_steps, threads, lattice, fd_scheme)
+        v_one, dt_one = _oracle_mlups(small, small_steps, 1, lattice, fd_scheme)
+        out[small] = {"all_threads": {"value": v_all, "threads": threads, "steps": small_steps, "seconds": dt_all},
+                      "one_thread": {"value": v_one, "threads": 1, "steps": small_steps, "seconds": dt_one}}
+    return out
 
 
 def copy_calibration(nbytes: int, reps: int):
@@ -421,6 +455,27 @@ def main():
         side["nematic512_fp32"] = {"mlups": n2d * 2000 / dt2 / 1e6, "ms_per_step": dt2 / 2000 * 1e3,
                                    "step_hbm_frac": n2d * 2000 / dt2 * STEP_VALUES_2D * 4 / (HBM_PEAK_GBS * 1e9)}
         print(f"# nematic512_fp32: {side['nematic512_fp32']['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
+        if args.workload != "droplet256":
+            # the large box: 256^3 forward rate and the 50-step adjoint with checkpoint 10
+            w5 = inputs.WORKLOADS["droplet256"]
+            p5 = inputs.params_for("droplet256")
+            phi5, q55 = inputs.workload_fields("droplet256")
+            n5 = phi5.size
+            ns = max(50, args.steps)
+            s5, dt5 = time_precision("fp32", p5, phi5, q55, ns, 5, stream)
+            s5.close()
+            side["droplet256_fp32"] = {"mlups": n5 * ns / dt5 / 1e6, "ms_per_step": dt5 / ns * 1e3, "steps": ns,
+                                       "step_hbm_frac": n5 * ns / dt5 * step_bytes("fp32") / (HBM_PEAK_GBS * 1e9)}
+            print(f"# droplet256_fp32: {side['droplet256_fp32']['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
+            if args.adjoint_steps > 0:
+                a5 = time_adjoint("fp32", p5, phi5, q55, w5["adjoint_steps"], w5["checkpoint"], stream,
+                                  recorded=False, alternatives=False)
+                side["droplet256_fp32_adjoint"] = {k: a5[k] for k in ("adjoint_over_forward", "total_over_forward",
+                                                                      "forward_ms", "backward_ms", "checkpoint",
+                                                                      "steps", "loss")}
+                print(f"# droplet256_fp32 adjoint/forward: {a5['adjoint_over_forward']:.2f} (checkpoint "
+                      f"{w5['checkpoint']}, {w5['adjoint_steps']} steps)", file=sys.stderr, flush=True)
+            del phi5, q55
 
     adjoint = None
     if args.adjoint_steps > 0:
