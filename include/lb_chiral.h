@@ -164,6 +164,30 @@ lb_status lb_free_energy(lb_ctx* c, lb_totals* out);
  * *phi_total = sum phi.  float64 device sums.  Synchronises. */
 lb_status lb_centre(lb_ctx* c, double out[6], double* phi_total);
 
+/* Allocation-free variant of lb_centre, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Computes the centre of lb_centre (same kernels, same
+ * fixed-order float64 sums) from a caller-owned device array without a
+ * context, and allocates nothing.
+ *   nx, ny, nz  periodic box, each >= 1, N = nx*ny*nz <= LB_NOALLOC_MAX_SITES
+ *               (2^25; larger boxes return LB_EINVAL before any work)
+ *   prec        LB_FP64: dev_phi is float64; LB_FP32 or LB_FP16S: float32
+ *   dev_phi     [N] concentration, [z][y][x] with x fastest (caller-owned)
+ *   dev_out     7 float64 on the device (caller-owned): linear centre (x, y, z),
+ *               circular-mean centre (x, y, z) in [0, n), sum phi
+ *   hip_stream  stream the work is enqueued on (NULL = default stream)
+ * The call only enqueues work and does not synchronise.  Its block partials
+ * live in one static device array of LB_NOALLOC_SCRATCH_BYTES per GPU, held
+ * until the process ends; every call on a GPU shares it and nothing in it
+ * needs clearing between calls.  Calls that overlap on one GPU (several
+ * streams or host threads) race on that array: order them.  dev_phi, dev_out
+ * and the stream must belong to the current device.
+ * Errors: LB_EINVAL (box, precision, null pointer), LB_EDEVICE. */
+#define LB_NOALLOC_MAX_SITES (1 << 25)
+#define LB_NOALLOC_SCRATCH_BYTES (11u << 20)
+lb_status lb_centre_noalloc(int32_t nx, int32_t ny, int32_t nz, int32_t prec, const void* dev_phi,
+                            double* dev_out, void* hip_stream);
+
 /* Size in bytes of the opaque state buffer (populations, Q, phi in storage
  * precision, plus the step counter). */
 size_t lb_state_bytes(const lb_ctx* c);

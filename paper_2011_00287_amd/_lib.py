@@ -58,6 +58,8 @@ SIGNATURES = {
     "lb_set_fields": (ctypes.c_int, [_P, _D, _D, _D]),
     "lb_free_energy": (ctypes.c_int, [_P, ctypes.POINTER(LbTotals)]),
     "lb_centre": (ctypes.c_int, [_P, _D, _D]),
+    "lb_centre_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P,
+                                         _P]),
     "lb_state_bytes": (ctypes.c_size_t, [_P]),
     "lb_get_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "lb_set_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),

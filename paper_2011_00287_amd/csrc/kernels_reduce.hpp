@@ -194,4 +194,20 @@ __global__ void __launch_bounds__(256) k_centre(Box b, const FS* __restrict__ ph
   block_reduce_store<NCEN>(v, partial + (size_t)blockIdx.x * NCEN);
 }
 
+// Centre from the summed k_centre partials (sums[0..NCEN)) on the device:
+// out[0..2] linear centre, out[3..5] circular mean per axis in [0, n),
+// out[6] sum of phi.  One thread.
+__global__ void k_centre_finish(Box b, const double* __restrict__ sums, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int n[3] = {b.nx, b.ny, b.nz};
+  for (int a = 0; a < 3; ++a) {
+    out[a] = sums[a] / sums[3];
+    const double ang = atan2(sums[4 + 2 * a], sums[5 + 2 * a]);
+    double c = ang * n[a] / (2.0 * M_PI);
+    if (c < 0) c += n[a];
+    out[3 + a] = c;
+  }
+  out[6] = sums[3];
+}
+
 }  // namespace lbc

@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -58,6 +59,20 @@ void dfree(void* p) {
 }
 
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+// sums[k] = sum over nblocks block partials (nv values each) in a fixed
+// order: one workgroup for few blocks, else kSumChunks chunk sums (into mids)
+// first.  mids holds kSumChunks * nv doubles, sums nv.
+constexpr int kSumChunks = 64;
+void final_sum_into(hipStream_t stream, const double* part, int nblocks, int nv, double* mids, double* sums) {
+  if (nblocks <= 4096) {
+    lbc::k_final_sum<<<1, TPB, 0, stream>>>(part, nblocks, nv, sums);
+    return;
+  }
+  const int chunk = (nblocks + kSumChunks - 1) / kSumChunks;
+  lbc::k_final_sum<<<kSumChunks, TPB, 0, stream>>>(part, nblocks, nv, mids, chunk);
+  lbc::k_final_sum<<<1, TPB, 0, stream>>>(mids, kSumChunks, nv, sums);
+}
 
 int env_int(const char* name, int dflt) {
   const char* v = std::getenv(name);
@@ -714,18 +729,7 @@ struct BackendT final : Backend {
     }
     dfree(g);
   }
-  // sums[k] = sum over nblocks block partials (nv values each) in a fixed
-  // order: one workgroup for few blocks, else kSumChunks chunk sums first
-  static constexpr int kSumChunks = 64;
-  void final_sum(const double* part, int nblocks, int nv) {
-    if (nblocks <= 4096) {
-      lbc::k_final_sum<<<1, TPB, 0, stream>>>(part, nblocks, nv, sums);
-      return;
-    }
-    const int chunk = (nblocks + kSumChunks - 1) / kSumChunks;
-    lbc::k_final_sum<<<kSumChunks, TPB, 0, stream>>>(part, nblocks, nv, mids, chunk);
-    lbc::k_final_sum<<<1, TPB, 0, stream>>>(mids, kSumChunks, nv, sums);
-  }
+  void final_sum(const double* part, int nblocks, int nv) { final_sum_into(stream, part, nblocks, nv, mids, sums); }
   void totals(double out[lbc::NTOT]) override {
     thermo_now();
     lbc::k_totals<R, GS, FS, L><<<nblk, TPB, 0, stream>>>(box, Pd, B[cur], Ph[cur], Q[cur], sig, partial);
@@ -1080,6 +1084,55 @@ std::unique_ptr<Backend> make_backend(const lb_params& p, hipStream_t s) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Allocation-free centre.  Its block partials, chunk sums and final sums live
+// in `scratch`, a static device array of fixed size that each GPU the library
+// runs on holds until the process ends.  In host code `scratch` names only a
+// host-side stand-in: its device address on the current GPU is looked up once
+// per device with hipGetSymbolAddress and kept in g_na_ptr, and only that
+// address is ever passed to a kernel.
+constexpr int kNaMaxBlocks = LB_NOALLOC_MAX_SITES / 256;  // k_centre: one site per thread, 256 per block
+constexpr size_t kNaPartial = size_t(kNaMaxBlocks) * lbc::NCEN;
+constexpr size_t kNaMids = size_t(kSumChunks) * lbc::NCEN;
+constexpr size_t kNaDoubles = kNaPartial + kNaMids + lbc::NCEN;
+static_assert(kNaDoubles * sizeof(double) <= LB_NOALLOC_SCRATCH_BYTES, "scratch size stated in the header");
+static __device__ __align__(256) double scratch[kNaDoubles];
+
+namespace {
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mu;
+double* g_na_ptr[kNaMaxDevices] = {};
+
+// Device address of `scratch` on the current GPU (looked up on first use).
+double* noalloc_scratch() {
+  int dev = -1;
+  HIPCHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNaMaxDevices) fail(LB_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_na_mu);
+  if (!g_na_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) fail(LB_EDEVICE, "no device address for the scratch array");
+    g_na_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_na_ptr[dev];
+}
+
+template <class FS>
+void centre_noalloc(const lbc::Box& box, const FS* phi, double* out, hipStream_t stream) {
+  double* base = noalloc_scratch();
+  double* partial = base;
+  double* mids = base + kNaPartial;
+  double* sums = mids + kNaMids;
+  const int nblk = int((size_t(box.N) + TPB - 1) / TPB);
+  lbc::k_centre<FS><<<nblk, TPB, 0, stream>>>(box, phi, partial);
+  final_sum_into(stream, partial, nblk, lbc::NCEN, mids, sums);
+  lbc::k_centre_finish<<<1, 64, 0, stream>>>(box, sums, out);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) fail(LB_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+}  // namespace
+
 extern "C" {
 
 lb_status lb_init(const lb_params* p, const double* phi, const double* q5, const double* u0, void* hip_stream,
@@ -1177,6 +1230,29 @@ lb_status lb_centre(lb_ctx* c, double out[6], double* phi_total) {
       out[3 + a] = cc;
     }
     if (phi_total) *phi_total = v[3];
+  });
+}
+
+lb_status lb_centre_noalloc(int32_t nx, int32_t ny, int32_t nz, int32_t prec, const void* dev_phi,
+                            double* dev_out, void* hip_stream) {
+  return guarded([&] {
+    if (nx < 1 || ny < 1 || nz < 1) fail(LB_EINVAL, "box sides must be >= 1");
+    if (prec < LB_FP64 || prec > LB_FP16S) fail(LB_EINVAL, "unknown precision");
+    if (!dev_phi || !dev_out) fail(LB_EINVAL, "null device pointer");
+    const double n = double(nx) * double(ny) * double(nz);
+    if (n > double(LB_NOALLOC_MAX_SITES))
+      fail(LB_EINVAL, "box of " + std::to_string(int64_t(n)) + " sites exceeds the allocation-free maximum of " +
+                          std::to_string(LB_NOALLOC_MAX_SITES) + " sites");
+    lbc::Box box;
+    box.nx = nx;
+    box.ny = ny;
+    box.nz = nz;
+    box.N = int(size_t(nx) * ny * nz);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (prec == LB_FP64)
+      centre_noalloc(box, static_cast<const double*>(dev_phi), dev_out, s);
+    else
+      centre_noalloc(box, static_cast<const float*>(dev_phi), dev_out, s);
   });
 }
 
