@@ -33,6 +33,7 @@ ALGO_VALUES = {
     "k_collide": (1, 0),    # reads and writes the populations
     "k_order": (0, 6),      # writes Q, phi
     "k_lb_fused": (1, 6),   # populations + reads of Q, phi
+    "k_step_fused": (1, 12),  # the whole step: populations, Q and phi read and written
     "k_order_fused": (0, 6),
     # the paper's predictor-corrector (per launch: its own field reads + writes;
     # X*, Y, v and mu are traffic the stage split adds)
@@ -51,7 +52,7 @@ FS_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 4}
 
 
 # sources the 3D step kernels (and their launch configuration) are built from
-STEP_SOURCES = ("physics.hpp", "storage.hpp", "kernels_fused.hpp", "kernels_pc.hpp", "kernels_site.hpp",
+STEP_SOURCES = ("physics.hpp", "storage.hpp", "kernels_fused.hpp", "kernels_step.hpp", "kernels_pc.hpp", "kernels_site.hpp",
                 "kernels_reduce.hpp", "kernels_adjoint.hpp", "adjoint.hpp", "lb_api.hip")
 
 
@@ -82,12 +83,12 @@ def step_bytes(prec: str, lattice: str = "d3q19") -> int:
     return 2 * NQ[lattice] * GS_BYTES[prec] + 12 * FS_BYTES[prec]
 
 
-def time_precision(prec, p, phi, q5, steps, warmup, stream, lattice="d3q19", fd_scheme="euler2"):
+def time_precision(prec, p, phi, q5, steps, warmup, stream, lattice="d3q19", fd_scheme="euler2", tuning=None):
     import torch
     from paper_2011_00287_amd.sim import Sim
     if fd_scheme == "pc4":
         p = dict(p, M=PC4_M)
-    sim = Sim(p, phi, q5, precision=prec, stream=stream, lattice=lattice, fd_scheme=fd_scheme)
+    sim = Sim(p, phi, q5, precision=prec, stream=stream, lattice=lattice, fd_scheme=fd_scheme, tuning=tuning)
     sim.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -367,6 +368,10 @@ def main():
     ap.add_argument("--fd-scheme", default="euler2", choices=["euler2", "pc4"],
                     help="euler2: explicit Euler, 2nd-order stencils; pc4: the paper's predictor-corrector, "
                          f"upwind, 4th-order stencils (M = {PC4_M})")
+    ap.add_argument("--path", default="default", choices=["default", "one", "two"],
+                    help="launch path of the timed step: the two-launch split (default) or one kernel per step")
+    ap.add_argument("--step-tile", type=int, default=0, help="one-launch kernel tile (lb_tuning.step_tile)")
+    ap.add_argument("--tz-step", type=int, default=0, help="one-launch slab depth (lb_tuning.tz_step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side", action="store_true", help="skip the FP64 / FP16S side timings")
     ap.add_argument("--profile-steps", type=int, default=50)
@@ -400,8 +405,9 @@ def main():
     print(f"# workload {args.workload} {phi.shape} {args.precision} {args.lattice} {args.fd_scheme}: "
           f"warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
 
+    tuning = {"path": args.path, "step_tile": args.step_tile, "tz_step": args.tz_step}
     sim, dt = time_precision(args.precision, p, phi, q5, args.steps, args.warmup, stream, args.lattice,
-                             args.fd_scheme)
+                             args.fd_scheme, tuning)
     mlups = n * args.steps / dt / 1e6
     print(f"# {args.precision}: {mlups:.1f} MLUPS ({dt / args.steps * 1e3:.4f} ms/step)", file=sys.stderr, flush=True)
 

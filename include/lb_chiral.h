@@ -131,7 +131,52 @@ typedef struct lb_ctx lb_ctx;
 lb_status lb_init(const lb_params* p, const double* phi, const double* q5, const double* u0,
                   void* hip_stream, lb_ctx** out);
 
-/* Enqueue nsteps coupled steps on the context's stream (nsteps >= 0). */
+/* Launch configuration of a context, for tests and tuning.  lb_init uses the
+ * defaults; lb_init_tuned with t = NULL, or with a zero-initialised struct,
+ * reproduces them.  The configuration changes the launch shapes and, through
+ * them, the floating-point rounding order, never the method.  The library
+ * reads no environment variables. */
+typedef enum {
+  LB_PATH_DEFAULT = 0,      /* LB_PATH_TWO_LAUNCHES */
+  LB_PATH_ONE_LAUNCH = 1,   /* the whole step in one z-marching kernel: Q, phi read once, u and
+                               mu kept on chip, at the price of recomputing the stress on a
+                               frame two sites wide and the moments of the tile's edge sites
+                               (LB_FD_EULER2 only; slower than two launches on MI355X) */
+  LB_PATH_TWO_LAUNCHES = 2, /* stress + collision kernel (writes u, mu), then the
+                               order-parameter kernel (LB_FD_PC4: its four launches) */
+  LB_PATH_SITE = 3          /* site-parallel kernels, the reference the tiled kernels are
+                               tested against (adjoint only with LB_D3Q19 + LB_FD_EULER2) */
+} lb_path;
+
+typedef struct {
+  int32_t path;          /* lb_path */
+  int32_t lb_tile;       /* stress + collision kernel tile; 0 = default,
+                            1..5 = 32x8, 32x16, 64x4, 16x16, 16x8 (float64: 32x16 -> 16x16) */
+  int32_t order_tile;    /* order-parameter kernel tile; 0 = default,
+                            1..5 = 32x8, 64x4, 32x16, 64x8, 64x16 (float64: 64x16 -> 64x8) */
+  int32_t pc_tile;       /* LB_FD_PC4 stage kernel tile; 0 = default, 1..4 = 32x8, 32x16, 16x16, 64x8 */
+  int32_t pcmu_tile;     /* LB_FD_PC4 mu kernel tile; same table as pc_tile */
+  int32_t step_tile;     /* one-launch kernel tile; 0 = default, 1..3 = 32x8, 32x16, 64x8
+                            (float64: 32x8 only) */
+  int32_t tz_step;       /* z-slab depths in planes, 0 = automatic: one-launch kernel, */
+  int32_t tz_lb;         /* stress + collision kernel, */
+  int32_t tz_order;      /* order-parameter kernel, */
+  int32_t tz_pc;         /* LB_FD_PC4 stage kernel, */
+  int32_t tz_pcmu;       /* LB_FD_PC4 mu kernel, */
+  int32_t tz_adj;        /* fused stress + gather adjoint, */
+  int32_t tz_adj_order;  /* order-parameter adjoint */
+} lb_tuning;
+
+/* lb_init with an explicit launch configuration (t may be NULL).  Errors as
+ * lb_init, plus LB_EINVAL for an unknown path or tile index, a negative slab
+ * depth, or LB_PATH_ONE_LAUNCH with LB_FD_PC4. */
+lb_status lb_init_tuned(const lb_params* p, const lb_tuning* t, const double* phi, const double* q5,
+                        const double* u0, void* hip_stream, lb_ctx** out);
+
+/* Enqueue nsteps coupled steps on the context's stream (nsteps >= 0).  One
+ * step: mu and H of the Eq. (5) free energy, the stress of Eqs. (3)-(4), the
+ * BGK collision with its forcing and the pull stream (Eqs. (6)-(8), (10)-(11)),
+ * the Q update of Eq. (2) and the phi update of Eq. (1). */
 lb_status lb_step(lb_ctx* c, int32_t nsteps);
 
 /* Replace the model parameters that do not change the allocation (every
@@ -139,7 +184,9 @@ lb_status lb_step(lb_ctx* c, int32_t nsteps);
 lb_status lb_set_params(lb_ctx* c, const lb_params* p);
 
 /* Copy rho [N], u [3][N] (with F/2), phi [N] and q5 [5][N] at the current
- * time to host float64 arrays; any pointer may be NULL.  Synchronises.
+ * time to host float64 arrays; any pointer may be NULL.  rho and u are the
+ * moments of Eq. (8), u with half the force of the stress of Eqs. (3)-(4) in
+ * the forcing form of Eq. (10).  Synchronises.
  * Errors: LB_ENOMEM when device scratch for rho, u cannot be allocated. */
 lb_status lb_moments(lb_ctx* c, double* rho, double* u3, double* phi, double* q5);
 
@@ -212,7 +259,7 @@ lb_status lb_set_state(lb_ctx* c, const void* dev_src, size_t bytes);
  * (Eq. (10)).
  * The adjoint covers both lattices and both integrators (on LB_FD_PC4 it is
  * the reverse of Heun's two stages, Sec. 3).  Only when the library runs its
- * site-parallel test kernels (LBC_SITE_KERNELS=1) is it limited to LB_D3Q19
+ * site-parallel test kernels (LB_PATH_SITE) is it limited to LB_D3Q19
  * with LB_FD_EULER2: there, for the other schemes, lb_adjoint_bytes,
  * lb_record_bytes and lb_lean_record_bytes return 0 and the calls below
  * return LB_EINVAL.

@@ -33,6 +33,16 @@ class LbParams(ctypes.Structure):
     ]
 
 
+LB_PATH_DEFAULT, LB_PATH_ONE_LAUNCH, LB_PATH_TWO_LAUNCHES, LB_PATH_SITE = 0, 1, 2, 3
+PATHS = {"default": LB_PATH_DEFAULT, "one": LB_PATH_ONE_LAUNCH, "two": LB_PATH_TWO_LAUNCHES, "site": LB_PATH_SITE}
+
+
+class LbTuning(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int32) for name in (
+        "path", "lb_tile", "order_tile", "pc_tile", "pcmu_tile", "step_tile", "tz_step", "tz_lb", "tz_order", "tz_pc",
+        "tz_pcmu", "tz_adj", "tz_adj_order")]
+
+
 class LbTotals(ctypes.Structure):
     _fields_ = [
         ("mass", ctypes.c_double), ("momentum", ctypes.c_double * 3), ("phi_total", ctypes.c_double),
@@ -51,6 +61,8 @@ _D = ctypes.POINTER(ctypes.c_double)
 
 SIGNATURES = {
     "lb_init": (ctypes.c_int, [ctypes.POINTER(LbParams), _D, _D, _D, _P, ctypes.POINTER(_P)]),
+    "lb_init_tuned": (ctypes.c_int, [ctypes.POINTER(LbParams), ctypes.POINTER(LbTuning), _D, _D, _D, _P,
+                                     ctypes.POINTER(_P)]),
     "lb_step": (ctypes.c_int, [_P, ctypes.c_int32]),
     "lb_set_params": (ctypes.c_int, [_P, ctypes.POINTER(LbParams)]),
     "lb_moments": (ctypes.c_int, [_P, _D, _D, _D, _D]),

@@ -22,6 +22,7 @@
 #include "kernels_pc.hpp"
 #include "kernels_pc_adjoint.hpp"
 #include "kernels_reduce.hpp"
+#include "kernels_step.hpp"
 
 namespace {
 
@@ -74,23 +75,17 @@ void final_sum_into(hipStream_t stream, const double* part, int nblocks, int nv,
   lbc::k_final_sum<<<1, TPB, 0, stream>>>(mids, kSumChunks, nv, sums);
 }
 
-int env_int(const char* name, int dflt) {
-  const char* v = std::getenv(name);
-  return (v && *v) ? std::atoi(v) : dflt;
-}
-
 // x-y tiles of the fused kernels.  The stress kernel computes the stress on
 // the (TX+2) x (TY+2) frame of a TX x TY tile; LDS per workgroup is about
 // 20 (TX+4)(TY+4) + 10 (TX+2)(TY+2) values.  The variant is chosen at context
-// creation (LBC_LB_TILE / LBC_OR_TILE select another one for tuning; in
-// double, the 32 x 16 stress tile is replaced by 16 x 16 and the 64 x 16
-// order tile by 64 x 8).
+// creation (lb_tuning selects another one; in double, the 32 x 16 stress
+// tile is replaced by 16 x 16 and the 64 x 16 order tile by 64 x 8).
 struct TileCfg {
   int tx, ty;
 };
 constexpr TileCfg kLbTiles[] = {{32, 8}, {32, 16}, {64, 4}, {16, 16}, {16, 8}};
 constexpr TileCfg kOrTiles[] = {{32, 8}, {64, 4}, {32, 16}, {64, 8}, {64, 16}};
-// tiles of the z-marching predictor-corrector stage kernel (LBC_PC_TILE)
+// tiles of the z-marching predictor-corrector stage and mu kernels
 constexpr TileCfg kPcTiles[] = {{32, 8}, {32, 16}, {16, 16}, {64, 8}};
 
 // Deepest z-slab of at most tz_max planes (halved down to tz_min) that still
@@ -117,8 +112,7 @@ int auto_slab(int ntx, int nty, int nz, int tz_max, int tz_min, int per_cu) {
 // register and LDS footprint leaves one or two small workgroups per CU); the
 // slab is the deepest that still gives a workgroup per CU.  Order kernel
 // 64 x 8 with the deepest slab of at most 16 planes that gives two
-// workgroups per CU.  LBC_TZ_LB / LBC_TZ_ORDER fix a depth instead, and
-// LBC_TZ_ADJ / LBC_TZ_AO that of the fused stress + gather and order adjoints.
+// workgroups per CU.  lb_tuning can fix each depth instead.
 template <class R, class GS>
 struct DefaultTile {
   static constexpr int lb = 0, order = 3, tz_lb_max = 16;
@@ -151,6 +145,34 @@ void validate(const lb_params& p) {
   if (!(p.phi_cr != 0.0)) fail(LB_EINVAL, "phi_cr must be nonzero");
   const double n = double(p.nx) * double(p.ny) * double(p.nz);
   if (n > double(1 << 29)) fail(LB_ENOMEM, "box exceeds 2^29 sites");
+}
+
+// tiles of the one-launch step kernel (each keeps one halo stress slot or
+// edge job per thread and plane)
+constexpr TileCfg kStTiles[] = {{32, 8}, {32, 16}, {64, 8}};
+constexpr int kNStTiles = int(sizeof(kStTiles) / sizeof(kStTiles[0]));
+constexpr int kNLbTiles = int(sizeof(kLbTiles) / sizeof(kLbTiles[0]));
+constexpr int kNOrTiles = int(sizeof(kOrTiles) / sizeof(kOrTiles[0]));
+constexpr int kNPcTiles = int(sizeof(kPcTiles) / sizeof(kPcTiles[0]));
+
+// The one-launch step applies to the explicit Euler integrator.  It is never
+// the default: its halo recompute (the stress on a frame two sites wide, the
+// moments of the tile's edge sites) costs more than the u, mu round trip and
+// the second read of Q, phi that it saves (measured at 128^3 and 256^3).
+bool one_launch_applies(const lb_params& p) { return p.fd_scheme == LB_FD_EULER2; }
+
+void validate_tuning(const lb_params& p, const lb_tuning& t) {
+  if (t.path < LB_PATH_DEFAULT || t.path > LB_PATH_SITE) fail(LB_EINVAL, "unknown lb_path");
+  if (t.path == LB_PATH_ONE_LAUNCH && !one_launch_applies(p))
+    fail(LB_EINVAL, "LB_PATH_ONE_LAUNCH needs LB_FD_EULER2");
+  if (t.lb_tile < 0 || t.lb_tile > kNLbTiles) fail(LB_EINVAL, "lb_tile out of range");
+  if (t.order_tile < 0 || t.order_tile > kNOrTiles) fail(LB_EINVAL, "order_tile out of range");
+  if (t.pc_tile < 0 || t.pc_tile > kNPcTiles) fail(LB_EINVAL, "pc_tile out of range");
+  if (t.pcmu_tile < 0 || t.pcmu_tile > kNPcTiles) fail(LB_EINVAL, "pcmu_tile out of range");
+  if (t.step_tile < 0 || t.step_tile > kNStTiles) fail(LB_EINVAL, "step_tile out of range");
+  const int32_t tz[] = {t.tz_step, t.tz_lb, t.tz_order, t.tz_pc, t.tz_pcmu, t.tz_adj, t.tz_adj_order};
+  for (int32_t v : tz)
+    if (v < 0) fail(LB_EINVAL, "negative slab depth");
 }
 
 template <class R>
@@ -247,6 +269,8 @@ struct BackendT final : Backend {
   size_t apart_n = 0;        // doubles in apart
   bool apart_live = false;   // apart holds sums not yet fetched by the caller
   bool site_path = false;  // three site-parallel kernels instead of the fused pair
+  bool one_launch = false;  // the whole step in k_step_fused
+  int st_tile = 0, st_ntx = 1, st_nty = 1, st_tz = 1, st_blocks = 1;  // k_step_fused
   // predictor-corrector integrator of the order parameters: X* (Q then phi, in
   // FS) and the anchoring vector v [3][N]
   bool pc4 = false;
@@ -263,7 +287,7 @@ struct BackendT final : Backend {
   static constexpr int kAsTX = sizeof(R) == 4 ? 32 : 16, kAsTY = 8;
   int as_ntx, as_nty, as_tz, as_blocks;
 
-  BackendT(const lb_params& p, hipStream_t s) : stream(s) {
+  BackendT(const lb_params& p, const lb_tuning& t, hipStream_t s) : stream(s) {
     box.nx = p.nx;
     box.ny = p.ny;
     box.nz = p.nz;
@@ -271,25 +295,30 @@ struct BackendT final : Backend {
     box.N = int(N);
     nblk = unsigned((N + TPB - 1) / TPB);
     set_params(p);
-    site_path = env_int("LBC_SITE_KERNELS", 0) != 0;
+    site_path = t.path == LB_PATH_SITE;
     pc4 = p.fd_scheme == LB_FD_PC4;
-    pc_tile = env_int("LBC_PC_TILE", 0);
-    if (pc_tile < 0 || pc_tile >= int(sizeof(kPcTiles) / sizeof(kPcTiles[0]))) pc_tile = 0;
-    tz_pc = std::max(0, env_int("LBC_TZ_PC", 0));
+    one_launch = !pc4 && t.path == LB_PATH_ONE_LAUNCH;
+    pc_tile = t.pc_tile > 0 ? t.pc_tile - 1 : 0;
+    tz_pc = t.tz_pc;
     // mu kernel: 64 x 8 in float; in double that frame needs 150 KB of LDS, so 32 x 8
     const int pm_default = sizeof(R) == 4 ? 3 : 0;
-    pm_tile = env_int("LBC_PCMU_TILE", pm_default);
-    if (pm_tile < 0 || pm_tile >= int(sizeof(kPcTiles) / sizeof(kPcTiles[0]))) pm_tile = pm_default;
-    tz_pm = std::max(0, env_int("LBC_TZ_PCMU", 0));
+    pm_tile = t.pcmu_tile > 0 ? t.pcmu_tile - 1 : pm_default;
+    tz_pm = t.tz_pcmu;
     using D = DefaultTile<R, GS>;
-    tz_lb = std::max(0, env_int("LBC_TZ_LB", 0));
-    tz_or = std::max(0, env_int("LBC_TZ_ORDER", 0));
-    lb_tile = env_int("LBC_LB_TILE", D::lb);
-    or_tile = env_int("LBC_OR_TILE", D::order);
-    if (lb_tile < 0 || lb_tile >= int(sizeof(kLbTiles) / sizeof(kLbTiles[0]))) lb_tile = D::lb;
+    tz_lb = t.tz_lb;
+    tz_or = t.tz_order;
+    lb_tile = t.lb_tile > 0 ? t.lb_tile - 1 : D::lb;
+    or_tile = t.order_tile > 0 ? t.order_tile - 1 : D::order;
     if (sizeof(R) == 8 && lb_tile == 1) lb_tile = 3;  // 32 x 16 needs more than 160 KB of LDS in double
-    if (or_tile < 0 || or_tile >= int(sizeof(kOrTiles) / sizeof(kOrTiles[0]))) or_tile = D::order;
     if (sizeof(R) == 8 && or_tile == 4) or_tile = 3;  // 64 x 16 would spill in double
+    st_tile = (t.step_tile > 0 && sizeof(R) == 4) ? t.step_tile - 1 : 0;  // float64: 32 x 8 only
+    const TileCfg stt = kStTiles[st_tile];
+    st_ntx = (p.nx + stt.tx - 1) / stt.tx;
+    st_nty = (p.ny + stt.ty - 1) / stt.ty;
+    // workgroups per CU the LDS frame allows: two for the 32 x 8 tile in float, else one
+    const int st_per_cu = (sizeof(R) == 4 && st_tile == 0) ? 2 : 1;
+    st_tz = t.tz_step > 0 ? t.tz_step : auto_slab(st_ntx, st_nty, p.nz, 32, 1, st_per_cu);
+    st_blocks = st_ntx * st_nty * ((p.nz + st_tz - 1) / st_tz);
     const TileCfg lt = kLbTiles[lb_tile], ot = kOrTiles[or_tile];
     lb_ntx = (p.nx + lt.tx - 1) / lt.tx;
     lb_nty = (p.ny + lt.ty - 1) / lt.ty;
@@ -309,12 +338,12 @@ struct BackendT final : Backend {
     pm_blocks = pm_ntx * pm_nty * ((p.nz + tz_pm - 1) / tz_pm);
     ao_ntx = (p.nx + kAoTX - 1) / kAoTX;
     ao_nty = (p.ny + kAoTY - 1) / kAoTY;
-    ao_tz = std::max(0, env_int("LBC_TZ_AO", 0));
+    ao_tz = t.tz_adj_order;
     if (ao_tz == 0) ao_tz = auto_slab(ao_ntx, ao_nty, p.nz, 16, 1, 2);
     ao_blocks = ao_ntx * ao_nty * ((p.nz + ao_tz - 1) / ao_tz);
     as_ntx = (p.nx + kAsTX - 1) / kAsTX;
     as_nty = (p.ny + kAsTY - 1) / kAsTY;
-    as_tz = std::max(0, env_int("LBC_TZ_ADJ", 0));
+    as_tz = t.tz_adj;
     if (as_tz == 0) {
       // large boxes (four or more workgroups per CU at 64 planes or less): deeper
       // slabs, since each slab marches two planes more than it owns
@@ -482,8 +511,9 @@ struct BackendT final : Backend {
   // launches of the predictor-corrector)
   int n_lb() const { return site_path ? 2 : 1; }
   int n_pc() const { return site_path ? 6 : 4; }
-  int nkernels() const { return n_lb() + (pc4 ? n_pc() : 1); }
+  int nkernels() const { return one_launch ? 1 : n_lb() + (pc4 ? n_pc() : 1); }
   const char* kernel_name(int i) const override {
+    if (one_launch) return i == 0 ? "k_step_fused" : nullptr;
     static const char* site_names[3] = {"k_thermo", "k_collide", "k_order"};
     static const char* fused_names[2] = {"k_lb_fused", "k_order_fused"};
     static const char* pc_names[6] = {"k_pc_v", "k_pc_mu", "k_pc_predict", "k_pc_v (X*)", "k_pc_mu (X*)",
@@ -574,6 +604,11 @@ struct BackendT final : Backend {
       }
       return;
     }
+    if (one_launch) {
+      launch_step1(Io{B[cur], B[nx], Ph[cur], Q[cur], Ph[nx], Q[nx], nullptr, nullptr, nullptr});
+      cur = nx;
+      return;
+    }
     const Io io = cur_io();
     if (k == 0) {
       launch_lb_tile(io);
@@ -640,7 +675,29 @@ struct BackendT final : Backend {
     launch_pc_mu(phs, qs);
     launch_pc_stage<false>(phs, qs, io.phi_i, io.q_i, io.phi_o, io.q_o, io.u);
   }
+  // the whole step in one launch (u, F, drho written only where io asks for them)
+  void launch_step1(const Io& io) {
+    if constexpr (sizeof(R) == 8) {  // 158 KB of LDS on the 32 x 8 tile: one workgroup per CU
+      launch_step1_tile<32, 8, 1>(io);
+    } else {
+      switch (st_tile) {
+        case 1: launch_step1_tile<32, 16, 2>(io); break;
+        case 2: launch_step1_tile<64, 8, 2>(io); break;
+        default: launch_step1_tile<32, 8, 2>(io); break;
+      }
+    }
+  }
+  template <int TX, int TY, int MINW>
+  void launch_step1_tile(const Io& io) {
+    lbc::k_step_fused<R, GS, FS, L, TX, TY, MINW><<<st_blocks, TX * TY, 0, stream>>>(
+        box, P, st_tz, st_ntx, st_nty, io.Bi, io.Bo, io.phi_i, io.q_i, io.phi_o, io.q_o, io.u, io.F, io.drho,
+        io.step_in, io.step_out);
+  }
   void fused_step(const Io& io) {
+    if (one_launch) {
+      launch_step1(io);
+      return;
+    }
     launch_lb_tile(io);
     if (pc4)
       pc_update(io);
@@ -1068,17 +1125,17 @@ void need_adjoint_ctx(const lb_ctx* c) {
   if (c->be->adjoint_bytes() == 0) fail(LB_EINVAL, "no adjoint for this context (D3Q15: fused kernels only)");
 }
 
-std::unique_ptr<Backend> make_backend(const lb_params& p, hipStream_t s) {
+std::unique_ptr<Backend> make_backend(const lb_params& p, const lb_tuning& t, hipStream_t s) {
   switch (p.prec) {
     case LB_FP64:
-      if (p.lattice == LB_D3Q15) return std::unique_ptr<Backend>(new BackendT<double, double, double, lbc::D3Q15>(p, s));
-      return std::unique_ptr<Backend>(new BackendT<double, double, double, lbc::D3Q19>(p, s));
+      if (p.lattice == LB_D3Q15) return std::unique_ptr<Backend>(new BackendT<double, double, double, lbc::D3Q15>(p, t, s));
+      return std::unique_ptr<Backend>(new BackendT<double, double, double, lbc::D3Q19>(p, t, s));
     case LB_FP32:
-      if (p.lattice == LB_D3Q15) return std::unique_ptr<Backend>(new BackendT<float, float, float, lbc::D3Q15>(p, s));
-      return std::unique_ptr<Backend>(new BackendT<float, float, float, lbc::D3Q19>(p, s));
+      if (p.lattice == LB_D3Q15) return std::unique_ptr<Backend>(new BackendT<float, float, float, lbc::D3Q15>(p, t, s));
+      return std::unique_ptr<Backend>(new BackendT<float, float, float, lbc::D3Q19>(p, t, s));
     default:
-      if (p.lattice == LB_D3Q15) return std::unique_ptr<Backend>(new BackendT<float, __half, float, lbc::D3Q15>(p, s));
-      return std::unique_ptr<Backend>(new BackendT<float, __half, float, lbc::D3Q19>(p, s));
+      if (p.lattice == LB_D3Q15) return std::unique_ptr<Backend>(new BackendT<float, __half, float, lbc::D3Q15>(p, t, s));
+      return std::unique_ptr<Backend>(new BackendT<float, __half, float, lbc::D3Q19>(p, t, s));
   }
 }
 
@@ -1135,19 +1192,27 @@ void centre_noalloc(const lbc::Box& box, const FS* phi, double* out, hipStream_t
 
 extern "C" {
 
-lb_status lb_init(const lb_params* p, const double* phi, const double* q5, const double* u0, void* hip_stream,
-                  lb_ctx** out) {
+lb_status lb_init_tuned(const lb_params* p, const lb_tuning* t, const double* phi, const double* q5,
+                        const double* u0, void* hip_stream, lb_ctx** out) {
   if (out) *out = nullptr;
   return guarded([&] {
     if (!p || !phi || !q5 || !out) fail(LB_EINVAL, "null argument");
     validate(*p);
+    lb_tuning tt{};
+    if (t) tt = *t;
+    validate_tuning(*p, tt);
     std::unique_ptr<lb_ctx> c(new lb_ctx);
     c->p = *p;
     c->stream = static_cast<hipStream_t>(hip_stream);
-    c->be = make_backend(*p, c->stream);
+    c->be = make_backend(*p, tt, c->stream);
     c->be->upload(phi, q5, u0);
     *out = c.release();
   });
+}
+
+lb_status lb_init(const lb_params* p, const double* phi, const double* q5, const double* u0, void* hip_stream,
+                  lb_ctx** out) {
+  return lb_init_tuned(p, nullptr, phi, q5, u0, hip_stream, out);
 }
 
 lb_status lb_step(lb_ctx* c, int32_t nsteps) {

@@ -35,6 +35,19 @@ def make_params(p: dict, shape, precision: str = "fp64", lattice: str = "d3q19",
     return lp
 
 
+def make_tuning(tuning: Optional[dict]) -> "_lib.LbTuning":
+    """lb_tuning from a dict: path ('default', 'one', 'two', 'site' or the lb_path
+    value), tile indices (1-based, 0 = default) and slab depths (0 = automatic)."""
+    t = _lib.LbTuning()
+    for k, v in (tuning or {}).items():
+        if k == "path" and isinstance(v, str):
+            v = _lib.PATHS[v]
+        if k not in dict(_lib.LbTuning._fields_):
+            raise KeyError(f"unknown tuning field {k!r}")
+        setattr(t, k, int(v))
+    return t
+
+
 def _dptr(a: Optional[np.ndarray]):
     if a is None:
         return None
@@ -61,7 +74,8 @@ class Sim:
     forcing term) or 'd3q15' (symmetric stress in the equilibrium, antisymmetric
     stress as a forcing term; fp64 and fp32).  fd_scheme: 'euler2'
     (explicit Euler, second-order stencils) or 'pc4' (the paper's predictor-corrector
-    with upwind advection and fourth-order stencils).  stream: a torch.cuda.Stream,
+    with upwind advection and fourth-order stencils).  tuning: launch
+    configuration (see make_tuning; None = the defaults).  stream: a torch.cuda.Stream,
     a raw hipStream_t as int, or None for the default stream.  The device tensors
     this class allocates (state, adjoint and record buffers) are created and
     zero-filled on torch's current stream, so pass that stream (or None while
@@ -69,7 +83,7 @@ class Sim:
     """
 
     def __init__(self, params: dict, phi, q5, u0=None, precision: str = "fp64", stream=None,
-                 lattice: str = "d3q19", fd_scheme: str = "euler2"):
+                 lattice: str = "d3q19", fd_scheme: str = "euler2", tuning: Optional[dict] = None):
         phi = _c64(phi)
         q5 = _c64(q5)
         if q5.shape != (5,) + phi.shape:
@@ -86,8 +100,9 @@ class Sim:
         self._lp = make_params(params, phi.shape, precision, lattice, fd_scheme)
         self._stream = stream
         h = ctypes.c_void_p()
-        check(lib().lb_init(ctypes.byref(self._lp), _dptr(phi), _dptr(q5), _dptr(u0),
-                            _stream_handle(stream), ctypes.byref(h)))
+        self._tuning = make_tuning(tuning)
+        check(lib().lb_init_tuned(ctypes.byref(self._lp), ctypes.byref(self._tuning), _dptr(phi), _dptr(q5),
+                                  _dptr(u0), _stream_handle(stream), ctypes.byref(h)))
         self._h = h
 
     @property

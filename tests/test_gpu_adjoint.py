@@ -228,7 +228,7 @@ def test_recorded_rollout_equals_checkpointed():
 @pytest.mark.parametrize("shape", [(34, 18, 11), (33, 9, 5), (12, 6, 7), (64, 16, 5)])
 @pytest.mark.parametrize("tz", ["1", "3", "default"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
-def test_adjoint_site_and_tiled_kernels_agree(monkeypatch, prec, tol, tz, shape):
+def test_adjoint_site_and_tiled_kernels_agree(prec, tol, tz, shape):
     """The site-parallel and the z-marching tiled reverse kernels (the order kernel
     and the fused stress + gather kernel with its tile-face terms) give the same
     reverse step, for several slab depths.  Boxes: ragged tiles and slabs
@@ -239,14 +239,10 @@ def test_adjoint_site_and_tiled_kernels_agree(monkeypatch, prec, tol, tz, shape)
     p = _p(q0=2 * math.pi / 9, zeta=0.01)
     g, phi, q5 = inputs.random_fields(*shape, seed=21, g_amp=2e-3, q_amp=0.2)
     seed_vals = np.random.default_rng(4).normal(size=25 * phi.size)
-    if tz == "default":
-        monkeypatch.delenv("LBC_TZ_ADJ", raising=False)
-    else:
-        monkeypatch.setenv("LBC_TZ_ADJ", tz)
+    tz_adj = 0 if tz == "default" else int(tz)
     outs = []
-    for site in ("0", "1"):
-        monkeypatch.setenv("LBC_SITE_KERNELS", site)
-        with Sim(p, phi, q5, precision=prec) as sim:
+    for path in ("default", "site"):
+        with Sim(p, phi, q5, precision=prec, tuning={"path": path, "tz_adj": tz_adj}) as sim:
             sim.set_fields(g=g)
             state = sim.get_state()
             adj = sim.adjoint_buffer()
@@ -327,13 +323,12 @@ def test_lean_rollouts_equal_full_state_rollout():
         assert l2 < 1e-12 and mx < 1e-12, (l2, mx)
 
 
-def test_lean_records_refused_without_adjoint(monkeypatch):
+def test_lean_records_refused_without_adjoint():
     """A context without an adjoint (the pc4 integrator on the site-parallel test
     kernels) has no lean records either."""
     from paper_2011_00287_amd._lib import LB_EINVAL, LbError
     phi, q5 = inputs.droplet_fields(6, 6, 6, 2.0, 0.5)
-    monkeypatch.setenv("LBC_SITE_KERNELS", "1")
-    with Sim(_p(M=0.05), phi, q5, fd_scheme="pc4") as sim:
+    with Sim(_p(M=0.05), phi, q5, fd_scheme="pc4", tuning={"path": "site"}) as sim:
         assert sim.lean_record_buffer().numel() == 0
         with pytest.raises(LbError) as e:
             sim.step_record_lean(torch.empty(8, dtype=torch.uint8, device="cuda"))

@@ -105,23 +105,16 @@ def test_totals_match_oracle():
 @pytest.mark.parametrize("lb_tile,or_tile,tz", [(0, 0, "1"), (1, 1, "3"), (2, 2, "8"), (3, 3, "5"), (4, 4, "16"),
                                                 (0, 3, "default")])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_site_kernels_match_fused_kernels(monkeypatch, lb_tile, or_tile, tz, prec):
+def test_site_kernels_match_fused_kernels(lb_tile, or_tile, tz, prec):
     """Site-parallel and fused kernels of this scheme compute the same step for every
     tile variant and slab depth (ragged tiles and slabs included)."""
     p = _p(q0=2 * math.pi / 9, zeta=0.01)
     g, phi, q5 = _g15(34, 18, 11, 77)
-    if tz == "default":
-        monkeypatch.delenv("LBC_TZ_LB", raising=False)
-        monkeypatch.delenv("LBC_TZ_ORDER", raising=False)
-    else:
-        monkeypatch.setenv("LBC_TZ_LB", tz)
-        monkeypatch.setenv("LBC_TZ_ORDER", tz)
-    monkeypatch.setenv("LBC_LB_TILE", str(lb_tile))
-    monkeypatch.setenv("LBC_OR_TILE", str(or_tile))
+    tzv = 0 if tz == "default" else int(tz)
+    tuning = {"path": "two", "lb_tile": lb_tile + 1, "order_tile": or_tile + 1, "tz_lb": tzv, "tz_order": tzv}
     tol = 1e-13 if prec == "fp64" else 2e-5
-    with Sim(p, phi, q5, precision=prec, lattice="d3q15") as fused:
-        monkeypatch.setenv("LBC_SITE_KERNELS", "1")
-        with Sim(p, phi, q5, precision=prec, lattice="d3q15") as site:
+    with Sim(p, phi, q5, precision=prec, lattice="d3q15", tuning=tuning) as fused:
+        with Sim(p, phi, q5, precision=prec, lattice="d3q15", tuning={"path": "site"}) as site:
             for s in (fused, site):
                 s.set_fields(g=g)
                 s.step(4)
@@ -178,13 +171,12 @@ def test_bitwise_determinism_and_resume():
             assert np.array_equal(x, y)
 
 
-def test_site_kernel_adjoint_refused(monkeypatch):
+def test_site_kernel_adjoint_refused():
     """The D3Q15 adjoint runs on the fused kernels only: with the site-parallel test
     kernels it is refused with LB_EINVAL (the forward still runs)."""
     p = _p()
     phi, q5 = inputs.droplet_fields(6, 6, 6, 2.0, 0.5)
-    monkeypatch.setenv("LBC_SITE_KERNELS", "1")
-    with Sim(p, phi, q5, lattice="d3q15") as s:
+    with Sim(p, phi, q5, lattice="d3q15", tuning={"path": "site"}) as s:
         assert s.adjoint_buffer().numel() == 0 and s.record_buffer().numel() == 0
         with pytest.raises(LbError) as e:
             s.step_record(s.get_state(), s.get_state(), torch.empty(8, dtype=torch.uint8, device="cuda"))

@@ -297,7 +297,7 @@ def test_fp32_128_pc4_adjoint_sampled_sites_vs_oracle():
     assert worst <= 1e-4, worst
 
 
-def test_fp32_128_adjoint_tiled_equals_site_kernels(monkeypatch):
+def test_fp32_128_adjoint_tiled_equals_site_kernels():
     """One reverse step over the whole 128^3 box: the z-marching reverse kernels,
     whose tiles exchange terms across every tile face and the periodic wrap
     faces through face buffers, against the site-parallel reverse kernels,
@@ -306,9 +306,8 @@ def test_fp32_128_adjoint_tiled_equals_site_kernels(monkeypatch):
     phi, q5 = inputs.workload_fields("droplet128")
     n, nq = phi.shape[0], 19
     outs = []
-    for site in ("0", "1"):
-        monkeypatch.setenv("LBC_SITE_KERNELS", site)
-        with Sim(p, phi, q5, precision="fp32") as sim:
+    for path in ("default", "site"):
+        with Sim(p, phi, q5, precision="fp32", tuning={"path": path}) as sim:
             sim.step(3)  # a state with flow
             state = sim.get_state()
             adj = sim.adjoint_buffer()

@@ -196,24 +196,17 @@ def test_reduced_precision_accuracy_droplet16(prec, tol):
 @pytest.mark.parametrize("lb_tile,or_tile,tz", [(0, 0, "1"), (1, 1, "3"), (2, 2, "8"), (3, 3, "5"), (4, 4, "16"),
                                                 (0, 3, "default")])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_site_kernels_match_fused_kernels(monkeypatch, lb_tile, or_tile, tz, prec):
+def test_site_kernels_match_fused_kernels(lb_tile, or_tile, tz, prec):
     """The site-parallel and the fused (z-marching, LDS-tiled) kernels compute the same step,
     for every tile variant and slab depth (ragged tiles and slabs included; "default" is the
     slab depth chosen at context creation)."""
     p = _p(q0=2 * math.pi / 9, zeta=0.01)
     g, phi, q5 = inputs.random_fields(34, 18, 11, seed=77, g_amp=2e-3, q_amp=0.2)
-    if tz == "default":
-        monkeypatch.delenv("LBC_TZ_LB", raising=False)
-        monkeypatch.delenv("LBC_TZ_ORDER", raising=False)
-    else:
-        monkeypatch.setenv("LBC_TZ_LB", tz)
-        monkeypatch.setenv("LBC_TZ_ORDER", tz)
-    monkeypatch.setenv("LBC_LB_TILE", str(lb_tile))
-    monkeypatch.setenv("LBC_OR_TILE", str(or_tile))
+    tzv = 0 if tz == "default" else int(tz)
+    tuning = {"path": "two", "lb_tile": lb_tile + 1, "order_tile": or_tile + 1, "tz_lb": tzv, "tz_order": tzv}
     tol = 1e-13 if prec == "fp64" else 2e-5
-    with Sim(p, phi, q5, precision=prec) as fused:
-        monkeypatch.setenv("LBC_SITE_KERNELS", "1")
-        with Sim(p, phi, q5, precision=prec) as site:
+    with Sim(p, phi, q5, precision=prec, tuning=tuning) as fused:
+        with Sim(p, phi, q5, precision=prec, tuning={"path": "site"}) as site:
             for s in (fused, site):
                 s.set_fields(g=g)
                 s.step(4)

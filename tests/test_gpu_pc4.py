@@ -90,20 +90,15 @@ def test_fp64_d3q15_with_pc4():
 
 @pytest.mark.parametrize("pc_tile,tz", [(0, "1"), (1, "3"), (2, "5"), (3, "16"), (0, "default")])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_site_kernels_match_z_marching(monkeypatch, pc_tile, tz, prec):
+def test_site_kernels_match_z_marching(pc_tile, tz, prec):
     """Site-parallel and z-marching (LDS-tiled) stage kernels compute the same step for
     every tile and slab depth (ragged tiles and slabs included)."""
     p = _p(q0=2 * math.pi / 9, zeta=0.01)
     g, phi, q5 = inputs.random_fields(34, 18, 11, seed=77, g_amp=2e-3, q_amp=0.2)
     tol = 1e-13 if prec == "fp64" else 2e-5
-    monkeypatch.setenv("LBC_PC_TILE", str(pc_tile))
-    if tz == "default":
-        monkeypatch.delenv("LBC_TZ_PC", raising=False)
-    else:
-        monkeypatch.setenv("LBC_TZ_PC", tz)
-    with Sim(p, phi, q5, precision=prec, fd_scheme="pc4") as fused:
-        monkeypatch.setenv("LBC_SITE_KERNELS", "1")
-        with Sim(p, phi, q5, precision=prec, fd_scheme="pc4") as site:
+    tuning = {"pc_tile": pc_tile + 1, "tz_pc": 0 if tz == "default" else int(tz)}
+    with Sim(p, phi, q5, precision=prec, fd_scheme="pc4", tuning=tuning) as fused:
+        with Sim(p, phi, q5, precision=prec, fd_scheme="pc4", tuning={"path": "site"}) as site:
             for s in (fused, site):
                 s.set_fields(g=g)
                 s.step(4)
@@ -157,18 +152,16 @@ def test_bitwise_determinism_and_resume():
             assert np.array_equal(x, y)
 
 
-def test_adjoint_on_site_kernels_is_refused(monkeypatch):
+def test_adjoint_on_site_kernels_is_refused():
     """The pc4 reverse runs with the fused kernels only: with the site-parallel
     test kernels the adjoint calls are refused with LB_EINVAL."""
     p = _p()
     phi, q5 = inputs.droplet_fields(6, 6, 6, 2.0, 0.5)
-    monkeypatch.setenv("LBC_SITE_KERNELS", "1")
-    with Sim(p, phi, q5, fd_scheme="pc4") as s:
+    with Sim(p, phi, q5, fd_scheme="pc4", tuning={"path": "site"}) as s:
         assert s.adjoint_buffer().numel() == 0 and s.record_buffer().numel() == 0
         with pytest.raises(LbError) as e:
             s.step_record(s.get_state(), s.get_state(), torch.empty(8, dtype=torch.uint8, device="cuda"))
         assert e.value.status == LB_EINVAL
-    monkeypatch.delenv("LBC_SITE_KERNELS")
     with Sim(p, phi, q5, fd_scheme="pc4") as s:
         names = [k for k in s.profile(2)]
         assert names[-1] == "k_pc_stage_z (correct)" and "k_pc_stage_z (predict)" in names
