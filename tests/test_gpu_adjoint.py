@@ -156,18 +156,21 @@ def test_droplet32_adjoint_vs_central_differences(precision, tol):
     inside = np.argwhere(phi > p["phi_cr"])
     picks = inside[rng.choice(len(inside), 10, replace=False)]
     comps = rng.integers(0, 5, 10)
-    errs, norms = [], []
+    ads, fds = [], []
     for (z, y, x), c in zip(picks, comps):
         qp = q5.copy()
         qm = q5.copy()
         qp[c, z, y, x] += h
         qm[c, z, y, x] -= h
-        fd = (_loss_fwd(p, phi, qp, steps) - _loss_fwd(p, phi, qm, steps)) / (2 * h)
-        ad = qbar[c, z, y, x]
-        errs.append(abs(ad - fd))
-        norms.append(abs(fd))
-    errs, norms = np.array(errs), np.array(norms)
-    assert np.linalg.norm(errs) <= tol * np.linalg.norm(norms), (errs, norms)
+        fds.append((_loss_fwd(p, phi, qp, steps) - _loss_fwd(p, phi, qm, steps)) / (2 * h))
+        ads.append(qbar[c, z, y, x])
+    ads, fds = np.array(ads), np.array(fds)
+    # each entry on its own: tol relative to its own difference quotient, plus a
+    # floor for the quotients' rounding noise, ~1e-6 of the largest gradient
+    floor = 1e-6 * np.abs(fds).max()
+    ratio = np.abs(ads - fds) / (tol * np.abs(fds) + floor)
+    print(precision, "Q entries: ad", ads, "fd", fds, "worst |ad - fd| / bound", ratio.max())
+    assert np.all(ratio <= 1.0), (ads, fds, ratio)
 
 
 def test_parameter_sums_kept_on_device_between_fetches():
