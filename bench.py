@@ -197,6 +197,19 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True, lat
     return out
 
 
+def droplet_velocity(prec, p, phi, q5, steps, every, stream, window=1000):
+    """Velocity of the droplet (circular-mean centre, unwrapped) over the last `window` steps of `steps`."""
+    from paper_2011_00287_amd.sim import Sim
+    from paper_2011_00287_amd.study import Track
+    with Sim(p, phi, q5, precision=prec, stream=stream) as sim:
+        tr = Track(phi.shape)
+        for t in range(0, steps + 1, every):
+            if t:
+                sim.step(every)
+            tr.add(t, sim)
+    return [float(v) for v in tr.velocity(window)]
+
+
 def _oracle_mlups(workload, nsteps, threads, lattice="d3q19", fd_scheme="euler2"):
     """MLUPS of the FP64 oracle on `threads` host threads: `nsteps` timed steps after one warm-up."""
     import torch
@@ -461,6 +474,21 @@ def main():
         side["nematic512_fp32"] = {"mlups": n2d * 2000 / dt2 / 1e6, "ms_per_step": dt2 / 2000 * 1e3,
                                    "step_hbm_frac": n2d * 2000 / dt2 * STEP_VALUES_2D * 4 / (HBM_PEAK_GBS * 1e9)}
         print(f"# nematic512_fp32: {side['nematic512_fp32']['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
+        if (args.workload == "droplet128" and args.precision == "fp32" and args.lattice == "d3q19"
+                and args.fd_scheme == "euler2"):
+            # the accuracy the speed of each precision buys: droplet velocity over the last
+            # 1000 of 5000 steps, against FP64, with each precision's step time beside it
+            steps_v = inputs.WORKLOADS["droplet128"]["steps"]
+            vel = {prec: droplet_velocity(prec, p, phi, q5, steps_v, 100, stream) for prec in ("fp64", "fp32", "fp16s")}
+            ms = {"fp64": side["fp64"]["ms_per_step"], "fp16s": side["fp16s"]["ms_per_step"],
+                  "fp32": dt / args.steps * 1e3}
+            v64 = vel["fp64"][2]
+            side["droplet_velocity"] = {
+                "steps": steps_v, "window": 1000, "velocity_z": {k: v[2] for k, v in vel.items()},
+                "rel_diff_vs_fp64": {k: abs(v[2] - v64) / abs(v64) for k, v in vel.items() if k != "fp64"},
+                "ms_per_step": ms}
+            print(f"# droplet velocity (z, last 1000 of {steps_v} steps): "
+                  + ", ".join(f"{k} {v[2]:.4e}" for k, v in vel.items()), file=sys.stderr, flush=True)
         if args.workload != "droplet256":
             # the large box: 256^3 forward rate and the 50-step adjoint with checkpoint 10
             w5 = inputs.WORKLOADS["droplet256"]

@@ -134,6 +134,31 @@ class Sim:
     def sync(self):
         check(lib().lb_sync(self._h))
 
+    def run_logged(self, nsteps: int, every: int, path: str):
+        """Advance nsteps steps, appending one JSON line to `path` at the start and
+        every `every` steps: step, float64 totals (mass, momentum, sum phi, F_h,
+        kinetic energy) and the droplet centre (linear and circular mean).  A
+        non-finite total raises (LbError, LB_ENONFINITE) with the last good line
+        already written."""
+        import json
+        if every <= 0:
+            raise ValueError("every must be positive")
+        with open(path, "a") as fh:
+            done = 0
+            while True:
+                t = self.totals()
+                lin, circ, _ = self.centre()
+                fh.write(json.dumps({"step": t["step"], "mass": t["mass"], "momentum": t["momentum"],
+                                     "phi_total": t["phi_total"], "free_energy": t["free_energy"],
+                                     "kinetic_energy": t["kinetic_energy"], "centre_linear": lin.tolist(),
+                                     "centre_circular": circ.tolist()}) + "\n")
+                fh.flush()
+                if done >= nsteps:
+                    break
+                n = min(every, nsteps - done)
+                self.step(n)
+                done += n
+
     def set_params(self, **changes):
         """Change model parameters (not the box, precision, lattice or integrator); kept only if
         the library accepts them."""

@@ -216,3 +216,20 @@ def test_site_kernels_match_fused_kernels(lb_tile, or_tile, tz, prec):
             l2, mx = rel_err(fused.populations(), site.populations())
             assert l2 < tol and mx < tol
 
+
+
+def test_run_logged_writes_conserved_totals(tmp_path):
+    """Periodic totals and centre as JSON lines: one at the start and every 5 steps."""
+    import json
+    p = inputs.params_for("droplet16")
+    phi, q5 = inputs.workload_fields("droplet16")
+    out = tmp_path / "log.jsonl"
+    with Sim(p, phi, q5, precision="fp64") as s:
+        s.run_logged(20, 5, str(out))
+        assert s.totals()["step"] == 20
+    rows = [json.loads(line) for line in out.read_text().splitlines()]
+    assert [r["step"] for r in rows] == [0, 5, 10, 15, 20]
+    for r in rows:
+        assert abs(r["mass"] - rows[0]["mass"]) <= 1e-12 * rows[0]["mass"]
+        assert abs(r["phi_total"] - rows[0]["phi_total"]) <= 1e-12 * rows[0]["phi_total"]
+        assert len(r["centre_linear"]) == 3 and len(r["centre_circular"]) == 3

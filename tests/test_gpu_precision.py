@@ -14,6 +14,10 @@
   away from rest, so the advection and co-rotation terms are exercised.
   Measured max-abs: g 9e-9, Q 9e-8, phi 5e-7, rho 8e-8, u 3e-8; the bounds
   are about three times these.
+* droplet128 over its 5000 steps: the droplet velocity (circular-mean centre,
+  last 1000 steps) in float32 within 1 % of float64 and with float16
+  population storage within 2 %, the accuracy at which the faster precisions
+  are compared with float64.
 """
 import numpy as np
 import pytest
@@ -89,3 +93,24 @@ def test_fp32_droplet128_whole_box_vs_oracle():
         assert v <= TOL128[k], (k, v)
     for k, v in l2.items():
         assert v <= 5e-5, (k, v)
+
+
+def test_droplet_velocity_fp32_fp16s_vs_fp64():
+    from paper_2011_00287_amd.study import Track
+    p = inputs.params_for("droplet128")
+    phi, q5 = inputs.workload_fields("droplet128")
+    steps, every = inputs.WORKLOADS["droplet128"]["steps"], 100
+    vel = {}
+    for prec in ("fp64", "fp32", "fp16s"):
+        with Sim(p, phi, q5, precision=prec) as s:
+            tr = Track(phi.shape)
+            for t in range(0, steps + 1, every):
+                if t:
+                    s.step(every)
+                tr.add(t, s)
+        vel[prec] = tr.velocity(1000)
+    v64 = vel["fp64"][2]
+    print({k: float(v[2]) for k, v in vel.items()})
+    assert abs(v64) > 1e-5  # the droplet moves: a relative comparison means something
+    assert abs(vel["fp32"][2] - v64) <= 0.01 * abs(v64)
+    assert abs(vel["fp16s"][2] - v64) <= 0.02 * abs(v64)
