@@ -100,7 +100,7 @@ def time_precision(prec, p, phi, q5, steps, warmup, stream, lattice="d3q19", fd_
 
 
 def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True, lattice="d3q19", alternatives=True,
-                 fd_scheme="euler2"):
+                 fd_scheme="euler2", tuning=None):
     """(reverse pass incl. any segment replay) / (plain forward) over the same steps.
 
     Modes (lean records hold Q, phi, drho, u, F per step; full-state records hold
@@ -115,7 +115,7 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True, lat
                                                backward_segments_lean, backward_segments_overlapped, run_lean,
                                                run_recorded, run_segments)
     from paper_2011_00287_amd.sim import Sim
-    sim = Sim(p, phi, q5, precision=prec, stream=stream, lattice=lattice, fd_scheme=fd_scheme)
+    sim = Sim(p, phi, q5, precision=prec, stream=stream, lattice=lattice, fd_scheme=fd_scheme, tuning=tuning)
     s0 = sim.get_state()
     # the loss is the displacement of the centre from its position at time 0,
     # so the reference is read from the initial state (a reference taken at
@@ -167,7 +167,7 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True, lat
     # the same sweep with the replay of segment s-1 on a second context and stream
     # while segment s is reversed (the replay context exists before the timed region)
     replay_stream = torch.cuda.Stream()
-    rep = Sim(p, phi, q5, precision=prec, stream=replay_stream, lattice=lattice, fd_scheme=fd_scheme)
+    rep = Sim(p, phi, q5, precision=prec, stream=replay_stream, lattice=lattice, fd_scheme=fd_scheme, tuning=tuning)
     ck, _, t_bwd_ov = run_mode(lambda: run_segments(sim, steps, checkpoint),
                                lambda h, a: backward_segments_overlapped(sim, rep, h, steps, checkpoint, a,
                                                                          replay_stream))
@@ -385,6 +385,10 @@ def main():
                     help="launch path of the timed step: the two-launch split (default) or one kernel per step")
     ap.add_argument("--step-tile", type=int, default=0, help="one-launch kernel tile (lb_tuning.step_tile)")
     ap.add_argument("--tz-step", type=int, default=0, help="one-launch slab depth (lb_tuning.tz_step)")
+    ap.add_argument("--adj-tile", type=int, default=0, help="stress + gather adjoint tile (lb_tuning.adj_tile)")
+    ap.add_argument("--adj-order-tile", type=int, default=0, help="order adjoint tile (lb_tuning.adj_order_tile)")
+    ap.add_argument("--tz-adj", type=int, default=0, help="stress + gather adjoint slab depth (lb_tuning.tz_adj)")
+    ap.add_argument("--tz-adj-order", type=int, default=0, help="order adjoint slab depth (lb_tuning.tz_adj_order)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side", action="store_true", help="skip the FP64 / FP16S side timings")
     ap.add_argument("--profile-steps", type=int, default=50)
@@ -503,7 +507,8 @@ def main():
             print(f"# droplet256_fp32: {side['droplet256_fp32']['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
             if args.adjoint_steps > 0:
                 a5 = time_adjoint("fp32", p5, phi5, q55, w5["adjoint_steps"], w5["checkpoint"], stream,
-                                  recorded=False, alternatives=False)
+                                  recorded=False, alternatives=False,
+                                  tuning={"adj_tile": args.adj_tile, "adj_order_tile": args.adj_order_tile})
                 side["droplet256_fp32_adjoint"] = {k: a5[k] for k in ("adjoint_over_forward", "total_over_forward",
                                                                       "forward_ms", "backward_ms", "checkpoint",
                                                                       "steps", "loss")}
@@ -515,7 +520,9 @@ def main():
     if args.adjoint_steps > 0:
         pa = dict(p, M=PC4_M) if args.fd_scheme == "pc4" else p
         adjoint = time_adjoint(args.precision, pa, phi, q5, args.adjoint_steps, args.adjoint_checkpoint, stream,
-                               recorded=not args.no_adjoint_recorded, lattice=args.lattice, fd_scheme=args.fd_scheme)
+                               recorded=not args.no_adjoint_recorded, lattice=args.lattice, fd_scheme=args.fd_scheme,
+                               tuning=dict(tuning, adj_tile=args.adj_tile, adj_order_tile=args.adj_order_tile,
+                                           tz_adj=args.tz_adj, tz_adj_order=args.tz_adj_order))
         print(f"# adjoint/forward: {adjoint['adjoint_over_forward']:.2f} (checkpoint {args.adjoint_checkpoint}; "
               f"{adjoint['overlapped']['adjoint_over_forward']:.2f} with the replay overlapped)"
               + (f", {adjoint['recorded']['adjoint_over_forward']:.2f} (every step recorded, "

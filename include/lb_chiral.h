@@ -156,6 +156,9 @@ typedef struct {
                             1..5 = 32x8, 64x4, 32x16, 64x8, 64x16 (float64: 64x16 -> 64x8) */
   int32_t pc_tile;       /* LB_FD_PC4 stage kernel tile; 0 = default, 1..4 = 32x8, 32x16, 16x16, 64x8 */
   int32_t pcmu_tile;     /* LB_FD_PC4 mu kernel tile; same table as pc_tile */
+  int32_t adj_tile;      /* stress + gather adjoint tile; 0 = default (32x16; float64 16x8),
+                            1 = 32x8, 2 = 32x16 (float64: 16x8, 16x16) */
+  int32_t adj_order_tile; /* order-parameter adjoint tile; 0 = default (32x8), 1 = 32x8, 2 = 32x16 */
   int32_t step_tile;     /* one-launch kernel tile; 0 = default, 1..3 = 32x8, 32x16, 64x8
                             (float64: 32x8 only) */
   int32_t tz_step;       /* z-slab depths in planes, 0 = automatic: one-launch kernel, */
@@ -274,7 +277,10 @@ size_t lb_record_bytes(const lb_ctx* c);
 /* One forward step from the state buffer dev_state_in (time t, lb_get_state
  * format) into dev_state_out (time t+1, a different buffer), writing u, F and
  * drho of time t into dev_rec_out.  The context's own state is not touched.  This is
- * the replay of a checkpoint segment before its reverse steps. */
+ * the replay of a checkpoint segment before its reverse steps.  dev_state_out
+ * may be NULL: then only the record is written (the last step of a replayed
+ * segment, whose output state the reverse never reads), and the populations
+ * and order parameters of t+1 are not formed. */
 lb_status lb_step_record(lb_ctx* c, const void* dev_state_in, void* dev_state_out, void* dev_rec_out,
                          size_t state_bytes, size_t rec_bytes);
 

@@ -79,11 +79,14 @@ def backward_segments(sim: Sim, ckpts, steps: int, checkpoint: int, adj):
         n = min(checkpoint, steps - t0)
         states[0] = ckpts[s]
         for j in range(n):
-            if states[j + 1] is None:
-                states[j + 1] = torch.empty_like(ckpts[s])
             if recs[j] is None:
                 recs[j] = sim.record_buffer()
-            sim.step_record(states[j], states[j + 1], recs[j])
+            if j + 1 < n:
+                if states[j + 1] is None:
+                    states[j + 1] = torch.empty_like(ckpts[s])
+                sim.step_record(states[j], states[j + 1], recs[j])
+            else:  # the segment's end state is never read: record only
+                sim.step_record(states[j], None, recs[j])
         for j in reversed(range(n)):
             last = s == 0 and j == 0  # the parameter sums are fetched once, after the last reverse step
             zb, qb = sim.adjoint_step(states[j], cur, nxt, rec=recs[j], zeta_bar=zb, q0_bar=qb, fetch=last)
@@ -120,7 +123,7 @@ def backward_segments_overlapped(sim: Sim, replay: Sim, ckpts, steps: int, check
             n = min(checkpoint, steps - s * checkpoint)
             states[0] = ckpts[s]
             for j in range(n):
-                replay.step_record(states[j], states[j + 1], recs[j])
+                replay.step_record(states[j], states[j + 1] if j + 1 < n else None, recs[j])
             replayed[s].record(replay_stream)
 
     zb = qb = 0.0

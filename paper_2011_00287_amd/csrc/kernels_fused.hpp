@@ -5,9 +5,9 @@
 //               anchoring vector v = Q D0 phi taken from the stress pass); on
 //               D3Q15 the symmetric stress enters the equilibrium (Eq. (9))
 //               and the force is that of the antisymmetric stress;
-//               writes the post-collision populations, u and mu (and the
-//               force F and the density deviation when a recording step asks
-//               for them).
+//               writes the post-collision populations (unless Bout is null),
+//               u and mu (and the force F and the density deviation when a
+//               recording step asks for them).
 // k_order_fused: molecular field H (Eq. (5)), Beris-Edwards update of Q
 //               (Eq. (2)) and Cahn-Hilliard update of phi (Eq. (1)).
 //
@@ -292,8 +292,10 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
       else
         drho = collide_site(P, g, F, u);
       const uint32_t sg = uint32_t(zc) * plane_gs + own_g, sr = uint32_t(zc) * plane_r + own_r;
+      if (Bout) {  // null on a step that only records u, F and drho
 #pragma unroll
-      for (int i = 0; i < L::Q; ++i) GPolO<GS, L>::template st<R>(Bout + size_t(i) * N, sg, i, g[i]);
+        for (int i = 0; i < L::Q; ++i) GPolO<GS, L>::template st<R>(Bout + size_t(i) * N, sg, i, g[i]);
+      }
 #pragma unroll
       for (int a = 0; a < 3; ++a) sto(u_out + size_t(a) * N, sr, u[a]);
       if (F_out) {  // recording step (adjoint replay): keep the force of this plane

@@ -399,8 +399,10 @@ k_step_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict_
           drho = collide_site(P, g, F, ucol);
         if (active) {
           const uint32_t sg = uint32_t(pmod(pc, b.nz)) * plane_gs + own_g;
+          if (Bout) {  // null on a step that only records u, F and drho
 #pragma unroll
-          for (int i = 0; i < L::Q; ++i) GPolO<GS, L>::template st<R>(Bout + size_t(i) * N, sg, i, g[i]);
+            for (int i = 0; i < L::Q; ++i) GPolO<GS, L>::template st<R>(Bout + size_t(i) * N, sg, i, g[i]);
+          }
           const uint32_t sr = uint32_t(pmod(pc, b.nz)) * plane_r + own_r;
           if (u_rec) {
 #pragma unroll
@@ -456,8 +458,8 @@ k_step_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict_
       sUM[m3c][3][m] = eA[parc][ej] - P.W * eVz[r3p][ej];
     }
 
-    // ---- order parameters of plane p-2 at the own site
-    if (po >= z0 && po <= z1 - 1) {
+    // ---- order parameters of plane p-2 at the own site (skipped on a record-only step)
+    if (q_out != nullptr && po >= z0 && po <= z1 - 1) {
       const int m3o = pmod(po, 3), m3b = pmod(po - 1, 3);
       const R(*U0)[NU] = sUM[m3o];
       R W[3][3];

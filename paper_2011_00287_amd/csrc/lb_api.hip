@@ -170,6 +170,8 @@ void validate_tuning(const lb_params& p, const lb_tuning& t) {
   if (t.pc_tile < 0 || t.pc_tile > kNPcTiles) fail(LB_EINVAL, "pc_tile out of range");
   if (t.pcmu_tile < 0 || t.pcmu_tile > kNPcTiles) fail(LB_EINVAL, "pcmu_tile out of range");
   if (t.step_tile < 0 || t.step_tile > kNStTiles) fail(LB_EINVAL, "step_tile out of range");
+  if (t.adj_tile < 0 || t.adj_tile > 2) fail(LB_EINVAL, "adj_tile out of range");
+  if (t.adj_order_tile < 0 || t.adj_order_tile > 2) fail(LB_EINVAL, "adj_order_tile out of range");
   const int32_t tz[] = {t.tz_step, t.tz_lb, t.tz_order, t.tz_pc, t.tz_pcmu, t.tz_adj, t.tz_adj_order};
   for (int32_t v : tz)
     if (v < 0) fail(LB_EINVAL, "negative slab depth");
@@ -281,10 +283,14 @@ struct BackendT final : Backend {
   int tz_lb = 8, tz_or = 8;
   int lb_tile = 0, or_tile = 0;
   int lb_ntx, lb_nty, lb_blocks, or_ntx, or_nty, or_blocks;
-  static constexpr int kAoTX = 32, kAoTY = 8;  // tile of the z-marching adjoint order kernel
-  int ao_ntx, ao_nty, ao_tz, ao_blocks;
+  static constexpr int kAoTX = 32;  // tile of the z-marching adjoint order kernel: 32 x ao_ty
+  int ao_ty = 8, ao_ntx, ao_nty, ao_tz, ao_blocks;
   // tile of the fused stress + gather adjoint (double: 16 x 8, whose LDS frame is half as large)
-  static constexpr int kAsTX = sizeof(R) == 4 ? 32 : 16, kAsTY = 8;
+  static constexpr int kAsTX = sizeof(R) == 4 ? 32 : 16;
+  // rows of the stress + gather adjoint's tile: 16 in float (half the y tile faces
+  // of 8 rows, whose terms k_adj_faces adds: checkpointed adjoint/forward 3.21 ->
+  // 3.13 at 256^3, 3.00 -> 2.91 at 128^3), 8 in double
+  int as_ty = 8;
   int as_ntx, as_nty, as_tz, as_blocks;
 
   BackendT(const lb_params& p, const lb_tuning& t, hipStream_t s) : stream(s) {
@@ -336,19 +342,22 @@ struct BackendT final : Backend {
     pm_nty = (p.ny + kPcTiles[pm_tile].ty - 1) / kPcTiles[pm_tile].ty;
     if (tz_pm == 0) tz_pm = auto_slab(pm_ntx, pm_nty, p.nz, 16, 1, 2);
     pm_blocks = pm_ntx * pm_nty * ((p.nz + tz_pm - 1) / tz_pm);
+    ao_ty = t.adj_order_tile == 2 ? 16 : 8;
     ao_ntx = (p.nx + kAoTX - 1) / kAoTX;
-    ao_nty = (p.ny + kAoTY - 1) / kAoTY;
+    ao_nty = (p.ny + ao_ty - 1) / ao_ty;
     ao_tz = t.tz_adj_order;
-    if (ao_tz == 0) ao_tz = auto_slab(ao_ntx, ao_nty, p.nz, 16, 1, 2);
+    if (ao_tz == 0) ao_tz = auto_slab(ao_ntx, ao_nty, p.nz, 16, 1, ao_ty == 16 ? 1 : 2);
     ao_blocks = ao_ntx * ao_nty * ((p.nz + ao_tz - 1) / ao_tz);
+    as_ty = t.adj_tile == 2 || (t.adj_tile == 0 && sizeof(R) == 4) ? 16 : 8;
     as_ntx = (p.nx + kAsTX - 1) / kAsTX;
-    as_nty = (p.ny + kAsTY - 1) / kAsTY;
+    as_nty = (p.ny + as_ty - 1) / as_ty;
     as_tz = t.tz_adj;
     if (as_tz == 0) {
       // large boxes (four or more workgroups per CU at 64 planes or less): deeper
       // slabs, since each slab marches two planes more than it owns
-      as_tz = auto_slab(as_ntx, as_nty, p.nz, 64, 16, 4);
-      if (size_t(as_ntx) * as_nty * ((p.nz + as_tz - 1) / as_tz) < 4 * size_t(cu_count()))
+      const int per_cu = as_ty == 16 ? 2 : 4;  // 16 waves per CU either way
+      as_tz = auto_slab(as_ntx, as_nty, p.nz, 64, 16, per_cu);
+      if (size_t(as_ntx) * as_nty * ((p.nz + as_tz - 1) / as_tz) < size_t(per_cu) * cu_count())
         as_tz = auto_slab(as_ntx, as_nty, p.nz, 16, 1, 1);
     }
     as_blocks = as_ntx * as_nty * ((p.nz + as_tz - 1) / as_tz);
@@ -900,13 +909,18 @@ struct BackendT final : Backend {
   void step_record(const void* state_in, void* state_out, void* rec_out) override {
     need_adjoint();
     const StateView vi = view(state_in);
+    R* ru = static_cast<R*>(rec_out);
+    R* rF = ru + 3 * N;
+    R* rd = ru + 6 * N;
+    if (!state_out) {  // the record only
+      record_only(vi, ru, rF, rd);
+      check_launch();
+      return;
+    }
     char* co = static_cast<char*>(state_out);
     GS* Bo = reinterpret_cast<GS*>(co);
     FS* qo = reinterpret_cast<FS*>(co + off_q());
     FS* po = reinterpret_cast<FS*>(co + off_phi());
-    R* ru = static_cast<R*>(rec_out);
-    R* rF = ru + 3 * N;
-    R* rd = ru + 6 * N;
     int64_t* step_out = reinterpret_cast<int64_t*>(co + off_step());
     if (site_path) {
       ensure_thermo();
@@ -919,6 +933,20 @@ struct BackendT final : Backend {
       fused_step(Io{vi.B, Bo, vi.phi, vi.q, po, qo, ru, rF, rd, vi.step, step_out});  // k_lb_fused counts
     }
     check_launch();
+  }
+  // u, F and drho of the state at vi without forming the next state: the
+  // site path's force kernel, or the stress + collision kernel with no
+  // population output and no order-parameter update
+  void record_only(const StateView& vi, R* ru, R* rF, R* rd) {
+    if (site_path) {
+      ensure_thermo();
+      lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, vi.phi, vi.q, mu, H, sig);
+      lbc::k_fwd_force<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, vi.B, sig, rF, ru, rd);
+    } else if (one_launch) {
+      launch_step1(Io{vi.B, nullptr, vi.phi, vi.q, nullptr, nullptr, ru, rF, rd});
+    } else {
+      launch_lb_tile(Io{vi.B, nullptr, vi.phi, vi.q, nullptr, nullptr, ru, rF, rd});
+    }
   }
   // lean step record: Q [5][N], phi [N] (storage type) of time t, then drho,
   // u [3][N], F [3][N] of that step (arithmetic type), each 256-byte aligned
@@ -963,15 +991,28 @@ struct BackendT final : Backend {
   }
   // the fused stress + gather adjoint and its tile-face terms; aq: Q_bar(t+1)
   // for the Euler update's H_bar (zeros under pc4), mb: mu_bar
+  void launch_adj_order(const FS* phi_t, const FS* q_t, const R* uu, const R* pi, const R* qi) {
+    if (ao_ty == 16)
+      lbc::k_adj_order_fused<R, FS, kAoTX, 16><<<ao_blocks, kAoTX * 16, 0, stream>>>(
+          box, P, ao_tz, ao_ntx, ao_nty, phi_t, q_t, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp, ahxw, ahyw);
+    else
+      lbc::k_adj_order_fused<R, FS, kAoTX, 8><<<ao_blocks, kAoTX * 8, 0, stream>>>(
+          box, P, ao_tz, ao_ntx, ao_nty, phi_t, q_t, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp, ahxw, ahyw);
+  }
   void stress_gather(const FS* phi_t, const FS* q_t, const R* aq, const R* mb, R* po, R* qo) {
-    lbc::k_adj_sg_fused<R, FS, kAsTX, kAsTY, L::kStressInEq><<<as_blocks, kAsTX * kAsTY, 0, stream>>>(
-        box, P, as_tz, as_ntx, as_nty, phi_t, q_t, aFb, aq, mb, aqbp, aphibp, aSb, po, qo, ahx, ahy, apart,
-        apart_live ? 1 : 0);
+    if (as_ty == 16)
+      lbc::k_adj_sg_fused<R, FS, kAsTX, 16, L::kStressInEq><<<as_blocks, kAsTX * 16, 0, stream>>>(
+          box, P, as_tz, as_ntx, as_nty, phi_t, q_t, aFb, aq, mb, aqbp, aphibp, aSb, po, qo, ahx, ahy, apart,
+          apart_live ? 1 : 0);
+    else
+      lbc::k_adj_sg_fused<R, FS, kAsTX, 8, L::kStressInEq><<<as_blocks, kAsTX * 8, 0, stream>>>(
+          box, P, as_tz, as_ntx, as_nty, phi_t, q_t, aFb, aq, mb, aqbp, aphibp, aSb, po, qo, ahx, ahy, apart,
+          apart_live ? 1 : 0);
     // one thread per field and x-face row, then one per field and y-face column
     const size_t n = (as_ntx > 1 ? 6 * size_t(as_ntx) * box.nz * box.ny : 0) +
                      (as_nty > 1 ? 6 * size_t(as_nty) * box.nz * box.nx : 0);
     if (n > 0)
-      lbc::k_adj_faces<R><<<unsigned((n + TPB - 1) / TPB), TPB, 0, stream>>>(box, kAsTX, as_ntx, kAsTY, as_nty, ahx,
+      lbc::k_adj_faces<R><<<unsigned((n + TPB - 1) / TPB), TPB, 0, stream>>>(box, kAsTX, as_ntx, as_ty, as_nty, ahx,
                                                                              ahy, po, qo);
   }
   // Reverse of a step of the pc4 integrator: the predictor is replayed from
@@ -1028,13 +1069,12 @@ struct BackendT final : Backend {
     } else {
       // site path: W_bar [9][N] and the local u_bar part; fused: W_bar_az [3][N] (in aWb) and
       // u_bar with the in-plane transposes (in aubp), plus the tile-face terms
-      lbc::UbarIn<R> ubin{aWb, aubp, ahxw, ahyw, kAoTX, kAoTY, ao_ntx, ao_nty, site_path ? 0 : 1};
+      lbc::UbarIn<R> ubin{aWb, aubp, ahxw, ahyw, kAoTX, ao_ty, ao_ntx, ao_nty, site_path ? 0 : 1};
       if (site_path)
         lbc::k_adj_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phi_t, q_t, uu, pi, qi, amub, aWb, aubp, aqbp,
                                                            aphibp);
       else
-        lbc::k_adj_order_fused<R, FS, kAoTX, kAoTY><<<ao_blocks, kAoTX * kAoTY, 0, stream>>>(
-            box, P, ao_tz, ao_ntx, ao_nty, phi_t, q_t, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp, ahxw, ahyw);
+        launch_adj_order(phi_t, q_t, uu, pi, qi);
       if (Bt)
         lbc::k_adj_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, Bt, FF, ubin, gi, go, aFb, aSb);
       else
@@ -1349,7 +1389,7 @@ lb_status lb_step_record(lb_ctx* c, const void* dev_state_in, void* dev_state_ou
                          size_t state_bytes, size_t rec_bytes) {
   return guarded([&] {
     need_adjoint_ctx(c);
-    if (!dev_state_in || !dev_state_out || !dev_rec_out) fail(LB_EINVAL, "null buffer");
+    if (!dev_state_in || !dev_rec_out) fail(LB_EINVAL, "null buffer");
     if (dev_state_in == dev_state_out) fail(LB_EINVAL, "state_in and state_out must differ");
     if (state_bytes != c->be->state_bytes()) fail(LB_ESTATE, "state buffer size mismatch");
     if (rec_bytes != c->be->record_bytes()) fail(LB_ESTATE, "record buffer size mismatch");

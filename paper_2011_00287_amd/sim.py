@@ -261,9 +261,11 @@ class Sim:
         return torch.empty(nb // esz, dtype=self.compute_dtype, device="cuda")
 
     def step_record(self, state_in, state_out, rec_out):
-        """state_out <- one step of state_in; rec_out <- (u, F) of state_in's time."""
+        """state_out <- one step of state_in (None: record only); rec_out <- (u, F, drho) of
+        state_in's time."""
+        out = None if state_out is None else ctypes.c_void_p(state_out.data_ptr())
         check(lib().lb_step_record(self._h, ctypes.c_void_p(state_in.data_ptr()),
-                                   ctypes.c_void_p(state_out.data_ptr()), ctypes.c_void_p(rec_out.data_ptr()),
+                                   out, ctypes.c_void_p(rec_out.data_ptr()),
                                    state_in.numel() * state_in.element_size(),
                                    rec_out.numel() * rec_out.element_size()))
 
