@@ -51,19 +51,9 @@ GS_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 2}
 FS_BYTES = {"fp64": 8, "fp32": 4, "fp16s": 4}
 
 
-# sources the 3D step kernels (and their launch configuration) are built from
-STEP_SOURCES = ("physics.hpp", "storage.hpp", "kernels_fused.hpp", "kernels_step.hpp", "kernels_pc.hpp", "kernels_site.hpp",
-                "kernels_reduce.hpp", "kernels_adjoint.hpp", "adjoint.hpp", "lb_api.hip")
-
-
 def kernel_source_hash() -> str:
-    """Hash of the step's HIP sources; traffic counters are valid only for the source they were taken on."""
-    import hashlib
-    h = hashlib.sha256()
-    for f in STEP_SOURCES:
-        with open(os.path.join(ROOT, "paper_2011_00287_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_2011_00287_amd.build import kernel_source_hash as h
+    return h()
 
 
 def measured_traffic(kernel: str, workload: str, prec: str, lattice: str = "d3q19"):
@@ -383,6 +373,8 @@ def main():
                          f"upwind, 4th-order stencils (M = {PC4_M})")
     ap.add_argument("--path", default="default", choices=["default", "one", "two"],
                     help="launch path of the timed step: the two-launch split (default) or one kernel per step")
+    ap.add_argument("--lb-tile", type=int, default=0, help="stress + collision kernel tile (lb_tuning.lb_tile)")
+    ap.add_argument("--tz-lb", type=int, default=0, help="stress + collision slab depth (lb_tuning.tz_lb)")
     ap.add_argument("--step-tile", type=int, default=0, help="one-launch kernel tile (lb_tuning.step_tile)")
     ap.add_argument("--tz-step", type=int, default=0, help="one-launch slab depth (lb_tuning.tz_step)")
     ap.add_argument("--adj-tile", type=int, default=0, help="stress + gather adjoint tile (lb_tuning.adj_tile)")
@@ -422,7 +414,8 @@ def main():
     print(f"# workload {args.workload} {phi.shape} {args.precision} {args.lattice} {args.fd_scheme}: "
           f"warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
 
-    tuning = {"path": args.path, "step_tile": args.step_tile, "tz_step": args.tz_step}
+    tuning = {"path": args.path, "step_tile": args.step_tile, "tz_step": args.tz_step, "lb_tile": args.lb_tile,
+              "tz_lb": args.tz_lb}
     sim, dt = time_precision(args.precision, p, phi, q5, args.steps, args.warmup, stream, args.lattice,
                              args.fd_scheme, tuning)
     mlups = n * args.steps / dt / 1e6

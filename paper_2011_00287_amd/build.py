@@ -23,6 +23,22 @@ HIPCC_FLAGS = [
 ]
 
 
+# sources the 3D step's kernels and their launch configuration are built from
+STEP_SOURCES = ("physics.hpp", "storage.hpp", "kernels_fused.hpp", "kernels_step.hpp", "kernels_pc.hpp",
+                "kernels_site.hpp", "kernels_reduce.hpp", "kernels_adjoint.hpp", "kernels_pc_adjoint.hpp",
+                "adjoint.hpp", "lb_api.hip")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the 3D step's HIP sources: hardware counters are valid only for the source they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in STEP_SOURCES:
+        with open(os.path.join(PKG, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):

@@ -147,3 +147,49 @@ def test_header_is_plain_c_and_links():
     with tempfile.TemporaryDirectory() as d:
         exe = compile_c_consumer(d)
         assert os.path.exists(exe)
+
+
+def test_tuning_struct_layout():
+    """Field order of lb_tuning in the header equals the ctypes struct."""
+    from paper_2011_00287_amd import _lib
+    text = open(HEADER).read()
+    body = re.search(r"typedef struct \{([^{}]*)\} lb_tuning;", text).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = [d.strip().split(None, 1)[1].strip() for d in body.split(";") if d.strip()]
+    assert fields == [f[0] for f in _lib.LbTuning._fields_]
+
+
+@pytest.mark.parametrize("bad", [{"path": 4}, {"path": -1}, {"lb_tile": 6}, {"order_tile": -1}, {"pc_tile": 5},
+                                 {"pcmu_tile": 9}, {"step_tile": 4}, {"adj_tile": 3}, {"adj_order_tile": 3},
+                                 {"tz_step": -1}, {"tz_adj": -2}])
+def test_invalid_tuning_rejected_before_any_device_work(bad):
+    """lb_init_tuned validates the launch configuration on the host (LB_EINVAL)."""
+    import numpy as np
+    from paper_2011_00287_amd import _lib, inputs, sim
+    phi = np.zeros((4, 4, 4))
+    q5 = np.zeros((5, 4, 4, 4))
+    with pytest.raises(_lib.LbError) as e:
+        sim.Sim(dict(inputs.BASE_PARAMS), phi, q5, tuning=bad)
+    assert e.value.status == _lib.LB_EINVAL
+
+
+def test_one_launch_path_refused_with_the_pc4_integrator():
+    import numpy as np
+    from paper_2011_00287_amd import _lib, inputs, sim
+    phi = np.zeros((4, 4, 4))
+    q5 = np.zeros((5, 4, 4, 4))
+    with pytest.raises(_lib.LbError) as e:
+        sim.Sim(dict(inputs.BASE_PARAMS), phi, q5, fd_scheme="pc4", tuning={"path": "one"})
+    assert e.value.status == _lib.LB_EINVAL
+    with pytest.raises(KeyError):
+        sim.make_tuning({"no_such_field": 1})
+
+
+def test_centre_noalloc_rejects_bad_arguments_before_any_device_work():
+    """Sizes, precision and pointers are checked on the host (no GPU is touched)."""
+    from paper_2011_00287_amd import _lib
+    L = _lib.lib()
+    assert L.lb_centre_noalloc(1024, 1024, 33, _lib.LB_FP64, 16, 16, None) == _lib.LB_EINVAL
+    assert L.lb_centre_noalloc(0, 4, 4, _lib.LB_FP64, 16, 16, None) == _lib.LB_EINVAL
+    assert L.lb_centre_noalloc(4, 4, 4, 7, 16, 16, None) == _lib.LB_EINVAL
+    assert L.lb_centre_noalloc(4, 4, 4, _lib.LB_FP32, None, 16, None) == _lib.LB_EINVAL
