@@ -374,3 +374,27 @@ def test_overlapped_replay_equals_sequential(prec):
             res.append((zb, qb, adj.cpu().numpy().copy()))
     assert res[0][0] == res[1][0] and res[0][1] == res[1][1]
     assert np.array_equal(res[0][2], res[1][2])
+
+
+@pytest.mark.parametrize("adj_tile", [1, 2])
+def test_fp64_reverse_with_16_plane_slabs_equals_site_kernels(adj_tile):
+    """The reverse step with 16-plane slabs of both adjoint marches (the slab depth of the benchmark's
+    128^3 box), on a box whose last slabs are ragged, against the site-parallel reverse kernels."""
+    p = _p(q0=2 * math.pi / 9, zeta=0.01)
+    g, phi, q5 = inputs.random_fields(40, 24, 36, seed=31, g_amp=2e-3, q_amp=0.2)
+    seed_vals = np.random.default_rng(5).normal(size=25 * phi.size)
+    outs = []
+    for tuning in ({"tz_adj": 16, "tz_adj_order": 16, "adj_tile": adj_tile, "adj_order_tile": adj_tile},
+                   {"path": "site"}):
+        with Sim(p, phi, q5, precision="fp64", tuning=tuning) as sim:
+            sim.set_fields(g=g)
+            state = sim.get_state()
+            adj = sim.adjoint_buffer()
+            adj.copy_(torch.tensor(seed_vals, dtype=adj.dtype))
+            out = sim.adjoint_buffer()
+            zb, qb = sim.adjoint_step(state, adj, out)
+            outs.append((out.cpu().numpy(), zb, qb))
+    (a, za, qa), (b, zb_, qb_) = outs
+    l2, mx = rel_err(a, b)
+    assert l2 < 1e-13 and mx < 1e-13, (l2, mx)
+    assert abs(za - zb_) <= 1e-13 * abs(za) and abs(qa - qb_) <= 1e-13 * abs(qa)

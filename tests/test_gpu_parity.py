@@ -233,3 +233,18 @@ def test_run_logged_writes_conserved_totals(tmp_path):
         assert abs(r["mass"] - rows[0]["mass"]) <= 1e-12 * rows[0]["mass"]
         assert abs(r["phi_total"] - rows[0]["phi_total"]) <= 1e-12 * rows[0]["phi_total"]
         assert len(r["centre_linear"]) == 3 and len(r["centre_circular"]) == 3
+
+
+@pytest.mark.parametrize("shape", [(40, 24, 34), (64, 16, 33)])
+def test_fp64_benchmark_launch_shapes_vs_oracle(shape):
+    """The FP32 benchmark's launch shapes (32 x 8 stress tile, 64 x 8 order tile, 16-plane slabs, here with
+    ragged last slabs) run in float64 against the oracle: <= 1e-12 per field after 3 steps."""
+    nx, ny, nz = shape
+    p = _p(q0=2 * math.pi / 9, zeta=0.01, body_force=(1e-5, -2e-5, 3e-5))
+    g, phi, q5 = inputs.random_fields(nx, ny, nz, seed=nx + ny + nz, g_amp=2e-3, q_amp=0.2)
+    tuning = {"path": "two", "lb_tile": 1, "order_tile": 4, "tz_lb": 16, "tz_order": 16}
+    with Sim(p, phi, q5, precision="fp64", tuning=tuning) as s:
+        s.set_fields(g=g)
+        s.step(3)
+        g3, q3, p3 = oracle_run(p, g, q5, phi, 3)
+        _compare_state(s, p, g3, q3, p3)
