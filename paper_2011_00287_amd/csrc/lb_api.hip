@@ -108,7 +108,7 @@ int auto_slab(int ntx, int nty, int nz, int tz_max, int tz_min, int per_cu) {
 
 // Default tiles and slab depths per storage (measured on the 128^3 and
 // 256^3 droplets): stress kernel float 32 x 8 with slabs of up to 16 planes,
-// half populations 16 x 8 with up to 11, double 16 x 8 with up to 16 (its
+// half populations 32 x 8 with up to 11, double 16 x 8 with up to 16 (its
 // register and LDS footprint leaves one or two small workgroups per CU); the
 // slab is the deepest that still gives a workgroup per CU.  Order kernel
 // 64 x 8 with the deepest slab of at most 16 planes that gives two
@@ -119,7 +119,7 @@ struct DefaultTile {
 };
 template <>
 struct DefaultTile<float, __half> {
-  static constexpr int lb = 4, order = 3, tz_lb_max = 11;
+  static constexpr int lb = 0, order = 3, tz_lb_max = 11;
 };
 template <>
 struct DefaultTile<double, double> {
