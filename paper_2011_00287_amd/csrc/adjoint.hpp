@@ -495,6 +495,35 @@ __host__ __device__ __forceinline__ void corotation_site_bwd(R xi, const R q[5],
   full_to_stored(Qb, qb);
 }
 
+// The W part of corotation_site_bwd alone.  S is linear in W, so its W
+// adjoint depends on Q and on the adjoint s5b of S only:
+//   Wb = (xi+1)/2 Ab + (xi-1)/2 Ab^T + 2 xi cb Q,   Ab = Mb P,
+// with Mb the symmetric tensor whose diagonal is twice the trace-projected
+// diagonal of s5b and whose off-diagonals are those of s5b, and
+// cb = -(the diagonal and each off-diagonal of the projected s5b, once) : P.
+template <class R>
+__host__ __device__ __forceinline__ void corotation_wbar(R xi, const R q[5], const R s5b[5], R Wb[3][3]) {
+  const R xx = q[0], xy = q[1], xz = q[2], yy = q[3], yz = q[4], zz = -xx - yy;
+  const R Pm[3][3] = {{xx + C3<R>::third, xy, xz}, {xy, yy + C3<R>::third, yz}, {xz, yz, zz + C3<R>::third}};
+  const R Qm[3][3] = {{xx, xy, xz}, {xy, yy, yz}, {xz, yz, zz}};
+  const R tb = -(s5b[0] + s5b[3]) * C3<R>::third;
+  const R d[3] = {s5b[0] + tb, s5b[3] + tb, tb};
+  const R Mb[3][3] = {{R(2) * d[0], s5b[1], s5b[2]}, {s5b[1], R(2) * d[1], s5b[4]}, {s5b[2], s5b[4], R(2) * d[2]}};
+  const R cb = -((d[0] * Pm[0][0] + d[1] * Pm[1][1] + d[2] * Pm[2][2]) +
+                 (s5b[1] * Pm[0][1] + s5b[2] * Pm[0][2] + s5b[4] * Pm[1][2]));
+  R Ab[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Ab[a][b] = Mb[a][0] * Pm[b][0] + Mb[a][1] * Pm[b][1] + Mb[a][2] * Pm[b][2];
+  const R trb = R(2) * xi * cb;
+  const R cp = R(0.5) * (xi + R(1)), cm = R(0.5) * (xi - R(1));
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Wb[a][b] = (cp * Ab[a][b] + cm * Ab[b][a]) + trb * Qm[a][b];
+}
+
 // Reverse of collide_site from the moments of the pre-collision populations:
 // drho = sum g, u = (j + F/2)/rho (rho = rho0 + drho), the force F, the
 // adjoint of the post-collision populations gsb[19] and of the velocity

@@ -169,27 +169,26 @@ k_adj_order(Box b, Params<R> P, const FS* __restrict__ phi, const FS* __restrict
 // (q[5], u[3], phi adjoint, q adjoint[5]) on a TX x TY tile plus the halo the
 // stencils read (no corners), the owned column keeps planes z-1, z, z+1 in
 // registers, and the halo of plane z+1 is loaded while plane z is computed.
-// It also applies the in-plane part of the velocity-gradient transpose,
-// u_bar_a -= sum_{c = x, y} D0_c W_bar_ac, from the W_bar of the neighbours in
-// the tile (through LDS), and writes u_bar with it (ub_out [3][N]) and the
-// W_bar_az the z part needs (Wz_out [3][N]).  An edge site of the tile writes
-// its W_bar_ax (or W_bar_ay) to the face buffers hxw[a][side][face][z][y]
-// (hyw[a][side][face][z][x]), face k between tiles k and k+1, side 0 written
-// by tile k's last column (row), side 1 by tile k+1's first; the collision
-// adjoint adds those terms and the z part (ubar_fused).
+// It also applies the transpose of the velocity gradient,
+// u_bar_a -= sum_c D0_c W_bar_ac, and writes the whole u_bar (ub_out [3][N]).
+// W_bar at a site depends only on Q and Q_bar(t+1) there (the co-rotation is
+// linear in W), so the W_bar the transposes read beyond the owned sites (the
+// halo columns and rows of the plane, and the own column at z +- 1) is formed
+// from the staged fields (corotation_wbar) instead of being exchanged
+// between tiles or launches.
 template <class R, class FS, int TX, int TY>
 __global__ void __launch_bounds__(TX* TY)
 k_adj_order_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__ phi,
                   const FS* __restrict__ q, const R* __restrict__ u, const R* __restrict__ adj_phi,
-                  const R* __restrict__ adj_q, R* __restrict__ mub, R* __restrict__ Wz_out, R* __restrict__ ub_out,
-                  R* __restrict__ qbp, R* __restrict__ phibp, R* __restrict__ hxw, R* __restrict__ hyw) {
+                  const R* __restrict__ adj_q, R* __restrict__ mub, R* __restrict__ ub_out,
+                  R* __restrict__ qbp, R* __restrict__ phibp) {
   constexpr int NT = TX * TY;
   constexpr int SX = TX + 2, SY = TY + 2, NS = SX * SY;
   constexpr int NH = 2 * (TX + TY);
   static_assert(NH <= NT, "one halo slot per thread");
   constexpr int NV = 14;  // q[5], u[3], phi adjoint, q adjoint[5]
   __shared__ R sV[NV][NS];
-  __shared__ R sW[6][NT];  // W_bar_ax, then W_bar_ay (a = 0..2) of the owned sites
+  __shared__ R sW[6][NS];  // W_bar_ax, then W_bar_ay (a = 0..2) on the tile and its halo
   __shared__ int sGX[SX], sGY[SY];
 
   const int l = xcd_remap(blockIdx.x, gridDim.x);
@@ -205,6 +204,9 @@ k_adj_order_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __rest
   for (int k = tid; k < SX; k += NT) sGX[k] = pmod(x0 - 1 + k, b.nx);
   for (int k = tid; k < SY; k += NT) sGY[k] = pmod(y0 - 1 + k, b.ny);
   __syncthreads();
+  // every thread, active or not, stages the (wrapped) site of its slot: on a
+  // ragged tile the slot right of the last active column holds that
+  // column's neighbour
   const int col = sGY[ly + 1] * b.nx + sGX[lx + 1];
 
   auto load_at = [&](size_t k, R v[NV]) {
@@ -222,11 +224,14 @@ k_adj_order_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __rest
   load_col(z0, v0);
   load_col(z0 + 1, vp);
 
+  // halo slot of this thread: rows y0-1, y0+TY for tid < 2 TX (they need
+  // W_bar_ay), then columns x0-1, x0+TX (W_bar_ax)
   const bool has_halo = tid < NH;
+  const bool halo_row = tid < 2 * TX;
   int hs = 0, hcol = 0;
   if (has_halo) {
     int hx, hy;
-    if (tid < 2 * TX) {
+    if (halo_row) {
       hx = 1 + (tid % TX);
       hy = tid < TX ? 0 : SY - 1;
     } else {
@@ -240,17 +245,14 @@ k_adj_order_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __rest
   R hv[NV];
   if (has_halo) load_at(size_t(z0) * plane + hcol, hv);
 
-  // in-plane neighbours inside the tile (a lone tile along an axis wraps
-  // periodically inside itself); -1 where the neighbour is in another tile
-  const int w = min(TX, b.nx - x0), h = min(TY, b.ny - y0);
-  const int nxp = ntx == 1 ? (lx + 1) % w : (lx + 1 < w ? lx + 1 : -1);
-  const int nxm = ntx == 1 ? (lx + w - 1) % w : (lx > 0 ? lx - 1 : -1);
-  const int nyp = nty == 1 ? (ly + 1) % h : (ly + 1 < h ? ly + 1 : -1);
-  const int nym = nty == 1 ? (ly + h - 1) % h : (ly > 0 ? ly - 1 : -1);
-  const int sxp = nxp < 0 ? tid : ly * TX + nxp, sxm = nxm < 0 ? tid : ly * TX + nxm;
-  const int syp = nyp < 0 ? tid : nyp * TX + lx, sym = nym < 0 ? tid : nym * TX + lx;
-  const size_t fxs = size_t(ntx) * b.nz * b.ny, fys = size_t(nty) * b.nz * b.nx;  // one component-side block
-  const int kxm = (tx + ntx - 1) % ntx, kym = (ty + nty - 1) % nty;
+  // W_bar_az of the owned column at plane z - 1 (carried from the previous plane)
+  R wz_m[3];
+  {
+    R Wt[3][3];
+    corotation_wbar(P.xi, vm, vm + 9, Wt);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) wz_m[a] = Wt[a][2];
+  }
 
   const int sc = (ly + 1) * SX + (lx + 1);
   for (int zc = z0; zc < z1; ++zc) {
@@ -263,8 +265,7 @@ k_adj_order_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __rest
       if (zc + 1 < z1) load_at(size_t(zc + 1) * plane + hcol, hv);  // next plane's halo
     }
     __syncthreads();
-    R m = R(0), Wb[3][3] = {{R(0), R(0), R(0)}, {R(0), R(0), R(0)}, {R(0), R(0), R(0)}}, ub[3] = {R(0), R(0), R(0)};
-    R qb[5], pb = R(0);
+    R Wb[3][3] = {{R(0), R(0), R(0)}, {R(0), R(0), R(0)}, {R(0), R(0), R(0)}}, ub[3] = {R(0), R(0), R(0)};
     if (active) {
       const size_t site = size_t(zc) * plane + col;
       const R ph = R(phi[site]);
@@ -306,47 +307,55 @@ k_adj_order_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __rest
         aqn[2][0][k] = vp[9 + k];
         aqn[2][1][k] = vm[9 + k];
       }
+      R m, qb[5], pb;
       adj_order_site(P, qc, qbar, uc, ph, v0[8], pbn, un, qn, aqn, m, Wb, ub, qb, pb);
       mub[site] = m;
 #pragma unroll
       for (int k = 0; k < 5; ++k) qbp[k * N + site] = qb[k];
       phibp[site] = pb;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) Wz_out[a * N + site] = Wb[a][2];
-      const int gy = sGY[ly + 1], gx = sGX[lx + 1];
-      if (ntx > 1 && lx == w - 1) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) hxw[size_t(2 * a) * fxs + (size_t(tx) * b.nz + zc) * b.ny + gy] = Wb[a][0];
-      }
-      if (ntx > 1 && lx == 0) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) hxw[size_t(2 * a + 1) * fxs + (size_t(kxm) * b.nz + zc) * b.ny + gy] = Wb[a][0];
-      }
-      if (nty > 1 && ly == h - 1) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) hyw[size_t(2 * a) * fys + (size_t(ty) * b.nz + zc) * b.nx + gx] = Wb[a][1];
-      }
-      if (nty > 1 && ly == 0) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) hyw[size_t(2 * a + 1) * fys + (size_t(kym) * b.nz + zc) * b.nx + gx] = Wb[a][1];
-      }
+    } else {
+      corotation_wbar(P.xi, v0, v0 + 9, Wb);  // a neighbour of the tile's last column or row
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      sW[a][tid] = Wb[a][0];
-      sW[3 + a][tid] = Wb[a][1];
+      sW[a][sc] = Wb[a][0];
+      sW[3 + a][sc] = Wb[a][1];
     }
-    __syncthreads();  // the in-plane W_bar of the tile are in place
-    if (active) {
-      // u_bar_a -= D0_x W_bar_ax + D0_y W_bar_ay over the neighbours in this tile
-      const size_t site = size_t(zc) * plane + col;
+    if (has_halo) {  // the halo slot's W_bar_ay (rows) or W_bar_ax (columns), from its staged Q and Q_bar
+      R qh[5], sh[5], Wh[3][3];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        qh[k] = sV[k][hs];
+        sh[k] = sV[9 + k][hs];
+      }
+      corotation_wbar(P.xi, qh, sh, Wh);
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const R wxp = nxp >= 0 ? sW[a][sxp] : R(0), wxm = nxm >= 0 ? sW[a][sxm] : R(0);
-        const R wyp = nyp >= 0 ? sW[3 + a][syp] : R(0), wym = nym >= 0 ? sW[3 + a][sym] : R(0);
-        ub_out[a * N + site] = ub[a] - (R(0.5) * (wxp - wxm) + R(0.5) * (wyp - wym));
+        if (halo_row)
+          sW[3 + a][hs] = Wh[a][1];
+        else
+          sW[a][hs] = Wh[a][0];
       }
     }
+    // W_bar_az of the owned column at plane z + 1
+    R wz_p[3];
+    {
+      R Wt[3][3];
+      corotation_wbar(P.xi, vp, vp + 9, Wt);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) wz_p[a] = Wt[a][2];
+    }
+    __syncthreads();  // W_bar of the tile and its halo are in place
+    if (active) {
+      const size_t site = size_t(zc) * plane + col;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        ub_out[a * N + site] = ub[a] - ((R(0.5) * (sW[a][sc + 1] - sW[a][sc - 1]) +
+                                         R(0.5) * (sW[3 + a][sc + SX] - sW[3 + a][sc - SX])) +
+                                        R(0.5) * (wz_p[a] - wz_m[a]));
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) wz_m[a] = Wb[a][2];
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
       vm[c] = v0[c];
@@ -356,20 +365,15 @@ k_adj_order_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __rest
   }
 }
 
-// Where the velocity adjoint u_bar comes from.  Site path (fused == 0): the
+// Where the velocity adjoint u_bar comes from.  Site path (whole == 0): the
 // order kernel's local part u (ubp [3][N]) and W_bar (W [9][N]), and
 //   u_bar_a = ubp_a - sum_c D0_c W_bar_ac.
-// Fused path (fused == 1): k_adj_order_fused's u (u_bar with the in-plane
-// transposes from inside its TX x TY tiles) and W = W_bar_az [3][N]; the z
-// transpose and the tile-face terms (hx, hy: the edge sites' W_bar_ax,
-// W_bar_ay) are added here.  fused == 2: u is the whole u_bar (the pc4 reverse).
+// whole == 1: u is the whole u_bar (k_adj_order_fused, the pc4 reverse).
 template <class R>
 struct UbarIn {
   const R* W;
   const R* u;
-  const R* hx;
-  const R* hy;
-  int TX, TY, ntx, nty, fused;
+  int whole;
 };
 
 template <class R>
@@ -378,47 +382,13 @@ __device__ __forceinline__ void ubar_at(const Box& b, const UbarIn<R>& in, int s
   const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
 #pragma unroll
   for (int a = 0; a < 3; ++a) ub[a] = in.u[a * N + s];
-  if (in.fused == 2) return;
-  if (!in.fused) {
+  if (in.whole) return;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const int sp = sidx(b, x + off[c][0], y + off[c][1], z + off[c][2]);
-      const int sm = sidx(b, x - off[c][0], y - off[c][1], z - off[c][2]);
+  for (int c = 0; c < 3; ++c) {
+    const int sp = sidx(b, x + off[c][0], y + off[c][1], z + off[c][2]);
+    const int sm = sidx(b, x - off[c][0], y - off[c][1], z - off[c][2]);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) ub[a] -= R(0.5) * (in.W[(a * 3 + c) * N + sp] - in.W[(a * 3 + c) * N + sm]);
-    }
-    return;
-  }
-  const int sp = sidx(b, x, y, z + 1), sm = sidx(b, x, y, z - 1);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) ub[a] -= R(0.5) * (in.W[a * N + sp] - in.W[a * N + sm]);
-  if (in.ntx > 1) {
-    const int j = x / in.TX, lx = x - j * in.TX, w = min(in.TX, b.nx - j * in.TX);
-    const size_t fs = size_t(in.ntx) * b.nz * b.ny, zy = size_t(z) * b.ny + y, nzy = size_t(b.nz) * b.ny;
-    if (lx == 0) {  // the - neighbour's W_bar_ax, sent across face j-1 in the + direction
-      const size_t o = size_t((j + in.ntx - 1) % in.ntx) * nzy + zy;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) ub[a] += R(0.5) * in.hx[size_t(2 * a) * fs + o];
-    }
-    if (lx == w - 1) {  // the + neighbour's, sent across face j in the - direction
-      const size_t o = size_t(j) * nzy + zy;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) ub[a] -= R(0.5) * in.hx[size_t(2 * a + 1) * fs + o];
-    }
-  }
-  if (in.nty > 1) {
-    const int i = y / in.TY, ly = y - i * in.TY, h = min(in.TY, b.ny - i * in.TY);
-    const size_t fs = size_t(in.nty) * b.nz * b.nx, zx = size_t(z) * b.nx + x, nzx = size_t(b.nz) * b.nx;
-    if (ly == 0) {
-      const size_t o = size_t((i + in.nty - 1) % in.nty) * nzx + zx;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) ub[a] += R(0.5) * in.hy[size_t(2 * a) * fs + o];
-    }
-    if (ly == h - 1) {
-      const size_t o = size_t(i) * nzx + zx;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) ub[a] -= R(0.5) * in.hy[size_t(2 * a + 1) * fs + o];
-    }
+    for (int a = 0; a < 3; ++a) ub[a] -= R(0.5) * (in.W[(a * 3 + c) * N + sp] - in.W[(a * 3 + c) * N + sm]);
   }
 }
 

@@ -260,8 +260,6 @@ struct BackendT final : Backend {
   R* ahx = nullptr;  // face terms and edge-column adjoints of the fused stress + gather adjoint (x tiles > 1)
   R* ahy = nullptr;  // the same along y
   R* aSb = nullptr;  // D3Q15: adjoint of the symmetric stress S_ab in the collision, [6][N]
-  R* ahxw = nullptr;  // the order adjoint's W_bar_ax of tile-edge columns (x tiles > 1)
-  R* ahyw = nullptr;  // its W_bar_ay of tile-edge rows (y tiles > 1)
   R* apb = nullptr;    // pc4 reverse: per-site adjoints of one product's stencil data [NPB][N]
   R* axs = nullptr;    // pc4 reverse: X*_bar [6][N]
   R* aupc = nullptr;   // pc4 reverse: u_bar [3][N]
@@ -424,7 +422,7 @@ struct BackendT final : Backend {
     pcv = nullptr;
     mu = H = sig = u = nullptr;
     partial = sums = mids = nullptr;
-    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &ahxw, &ahyw, &apb, &axs, &aupc, &azero};
+    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &apb, &axs, &aupc, &azero};
     for (R** a : adj) {
       dfree(*a);
       *a = nullptr;
@@ -851,7 +849,7 @@ struct BackendT final : Backend {
     try {
       aF = dalloc<R>(3 * N);
       amub = dalloc<R>(N);
-      aWb = dalloc<R>(9 * N);
+      if (site_path) aWb = dalloc<R>(9 * N);  // the fused order kernel forms the whole u_bar
       aubp = dalloc<R>(3 * N);
       aqbp = dalloc<R>(5 * N);
       aphibp = dalloc<R>(N);
@@ -869,8 +867,6 @@ struct BackendT final : Backend {
         gz_blocks = ncb * ((box.nz + gz_tz - 1) / gz_tz);
       }
       if (!site_path && as_ntx > 1) ahx = dalloc<R>(24 * size_t(as_ntx) * box.nz * box.ny);
-      if (!site_path && ao_ntx > 1) ahxw = dalloc<R>(6 * size_t(ao_ntx) * box.nz * box.ny);
-      if (!site_path && ao_nty > 1) ahyw = dalloc<R>(6 * size_t(ao_nty) * box.nz * box.nx);
       if (!site_path && as_nty > 1) ahy = dalloc<R>(12 * size_t(as_nty) * box.nz * box.nx);
       // one (zeta, q0) pair per block of whichever reverse kernel writes them
       // pc4: the stress kernel's blocks, then those of k_pcb_local
@@ -880,7 +876,7 @@ struct BackendT final : Backend {
       HIPCHECK(hipMemsetAsync(apart, 0, npart * sizeof(double), stream));
       apart_live = false;
     } catch (...) {
-      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &ahxw, &ahyw, &apb, &axs, &aupc, &azero};
+      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &apb, &axs, &aupc, &azero};
       for (R** a : adj) {
         dfree(*a);
         *a = nullptr;
@@ -994,10 +990,10 @@ struct BackendT final : Backend {
   void launch_adj_order(const FS* phi_t, const FS* q_t, const R* uu, const R* pi, const R* qi) {
     if (ao_ty == 16)
       lbc::k_adj_order_fused<R, FS, kAoTX, 16><<<ao_blocks, kAoTX * 16, 0, stream>>>(
-          box, P, ao_tz, ao_ntx, ao_nty, phi_t, q_t, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp, ahxw, ahyw);
+          box, P, ao_tz, ao_ntx, ao_nty, phi_t, q_t, uu, pi, qi, amub, aubp, aqbp, aphibp);
     else
       lbc::k_adj_order_fused<R, FS, kAoTX, 8><<<ao_blocks, kAoTX * 8, 0, stream>>>(
-          box, P, ao_tz, ao_ntx, ao_nty, phi_t, q_t, uu, pi, qi, amub, aWb, aubp, aqbp, aphibp, ahxw, ahyw);
+          box, P, ao_tz, ao_ntx, ao_nty, phi_t, q_t, uu, pi, qi, amub, aubp, aqbp, aphibp);
   }
   void stress_gather(const FS* phi_t, const FS* q_t, const R* aq, const R* mb, R* po, R* qo) {
     if (as_ty == 16)
@@ -1045,7 +1041,7 @@ struct BackendT final : Backend {
                                                            xsp, R(1), aqbp, aphibp, aupc, 1);
     lbc::k_pcb_gather_z<R, FS><<<gz_blocks, 256, 0, stream>>>(box, gz_tz, phi_t, uu, xsq, xsp, R(1), apb, aqbp,
                                                                aphibp, aupc);
-    lbc::UbarIn<R> ubin{nullptr, aupc, nullptr, nullptr, 0, 0, 0, 0, 2};
+    lbc::UbarIn<R> ubin{nullptr, aupc, 1};
     if (Bt)
       lbc::k_adj_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, Bt, FF, ubin, gi, go, aFb, aSb);
     else
@@ -1067,9 +1063,8 @@ struct BackendT final : Backend {
     if (pc4) {
       reverse_pc4(phi_t, q_t, uu, FF, Bt, drho, gi, qi, pi, go, qo, po);
     } else {
-      // site path: W_bar [9][N] and the local u_bar part; fused: W_bar_az [3][N] (in aWb) and
-      // u_bar with the in-plane transposes (in aubp), plus the tile-face terms
-      lbc::UbarIn<R> ubin{aWb, aubp, ahxw, ahyw, kAoTX, ao_ty, ao_ntx, ao_nty, site_path ? 0 : 1};
+      // site path: W_bar [9][N] and the local u_bar part; fused: the whole u_bar (in aubp)
+      lbc::UbarIn<R> ubin{aWb, aubp, site_path ? 0 : 1};
       if (site_path)
         lbc::k_adj_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phi_t, q_t, uu, pi, qi, amub, aWb, aubp, aqbp,
                                                            aphibp);
