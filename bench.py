@@ -17,6 +17,7 @@ import argparse
 import json
 import os
 import sys
+import statistics
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -90,8 +91,11 @@ def time_precision(prec, p, phi, q5, steps, warmup, stream, lattice="d3q19", fd_
 
 
 def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True, lattice="d3q19", alternatives=True,
-                 fd_scheme="euler2", tuning=None):
+                 fd_scheme="euler2", tuning=None, reps=3):
     """(reverse pass incl. any segment replay) / (plain forward) over the same steps.
+
+    Every time is the median of `reps` runs from the same initial state (a
+    single run of a few tens of milliseconds varies by a few per cent).
 
     Modes (lean records hold Q, phi, drho, u, F per step; full-state records hold
     whole states plus u, F), as the autograd function runs them:
@@ -122,20 +126,28 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True, lat
         torch.cuda.synchronize()
         return out, time.perf_counter() - t0
 
-    _, t_fwd = timed(lambda: sim.step(steps))
+    def plain_forward():
+        sim.set_state(s0)
+        return timed(lambda: sim.step(steps))[1]
+
+    t_fwd = statistics.median(plain_forward() for _ in range(reps))
     losses = []
 
     def run_mode(fwd, bwd):
-        sim.set_state(s0)
-        hist, t_f = timed(fwd)
-        adj = sim.adjoint_buffer()
-        loss = sim.seed_centre(zc0, adj)
-        if not loss > 0.0:
-            raise RuntimeError(f"adjoint timing: displacement loss {loss!r} after {steps} steps; the reverse "
-                               "pass would run on a zero seed")
+        t_fs, t_bs = [], []
+        for _ in range(reps):
+            sim.set_state(s0)
+            hist, t_f = timed(fwd)
+            adj = sim.adjoint_buffer()
+            loss = sim.seed_centre(zc0, adj)
+            if not loss > 0.0:
+                raise RuntimeError(f"adjoint timing: displacement loss {loss!r} after {steps} steps; the reverse "
+                                   "pass would run on a zero seed")
+            _, t_b = timed(lambda: bwd(hist, adj))
+            t_fs.append(t_f)
+            t_bs.append(t_b)
         losses.append(loss)
-        _, t_b = timed(lambda: bwd(hist, adj))
-        return hist, t_f, t_b
+        return hist, statistics.median(t_fs), statistics.median(t_bs)
 
     ck, t_fwd_ck, t_bwd = run_mode(lambda: run_segments(sim, steps, checkpoint),
                                    lambda h, a: backward_segments(sim, h, steps, checkpoint, a))
@@ -144,7 +156,7 @@ def time_adjoint(prec, p, phi, q5, steps, checkpoint, stream, recorded=True, lat
            "fd_scheme": fd_scheme,
            "forward_ms": t_fwd * 1e3, "forward_with_checkpoints_ms": t_fwd_ck * 1e3, "backward_ms": t_bwd * 1e3,
            "adjoint_over_forward": t_bwd / t_fwd, "total_over_forward": (t_fwd_ck + t_bwd) / t_fwd,
-           "loss": losses[0]}
+           "loss": losses[0], "reps": reps}
     if not alternatives:
         if recorded:
             recs, t_fwd_rec, t_bwd_rec = run_mode(lambda: run_lean(sim, steps),
@@ -504,7 +516,7 @@ def main():
                                   tuning={"adj_tile": args.adj_tile, "adj_order_tile": args.adj_order_tile})
                 side["droplet256_fp32_adjoint"] = {k: a5[k] for k in ("adjoint_over_forward", "total_over_forward",
                                                                       "forward_ms", "backward_ms", "checkpoint",
-                                                                      "steps", "loss")}
+                                                                      "steps", "loss", "reps")}
                 print(f"# droplet256_fp32 adjoint/forward: {a5['adjoint_over_forward']:.2f} (checkpoint "
                       f"{w5['checkpoint']}, {w5['adjoint_steps']} steps)", file=sys.stderr, flush=True)
             del phi5, q55

@@ -209,16 +209,19 @@ k_adj_order_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __rest
   // column's neighbour
   const int col = sGY[ly + 1] * b.nx + sGX[lx + 1];
 
-  auto load_at = [&](size_t k, R v[NV]) {
+  // global accesses: uniform field base plus a 32-bit byte offset per lane
+  // (component arrays are below 4 GiB)
+  auto load_at = [&](uint32_t k, R v[NV]) {
+    const uint32_t kf = k * uint32_t(sizeof(FS)), kr = k * uint32_t(sizeof(R));
 #pragma unroll
-    for (int c = 0; c < 5; ++c) v[c] = R(q[c * N + k]);
+    for (int c = 0; c < 5; ++c) v[c] = R(ldo(q + c * N, kf));
 #pragma unroll
-    for (int a = 0; a < 3; ++a) v[5 + a] = u[a * N + k];
-    v[8] = adj_phi[k];
+    for (int a = 0; a < 3; ++a) v[5 + a] = ldo(u + a * N, kr);
+    v[8] = ldo(adj_phi, kr);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) v[9 + c] = adj_q[c * N + k];
+    for (int c = 0; c < 5; ++c) v[9 + c] = ldo(adj_q + c * N, kr);
   };
-  auto load_col = [&](int zz, R v[NV]) { load_at(size_t(pmod(zz, b.nz)) * plane + col, v); };
+  auto load_col = [&](int zz, R v[NV]) { load_at(uint32_t(pmod(zz, b.nz)) * uint32_t(plane) + uint32_t(col), v); };
   R vm[NV], v0[NV], vp[NV];
   load_col(z0 - 1, vm);
   load_col(z0, v0);
@@ -243,7 +246,7 @@ k_adj_order_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __rest
     hcol = sGY[hy] * b.nx + sGX[hx];
   }
   R hv[NV];
-  if (has_halo) load_at(size_t(z0) * plane + hcol, hv);
+  if (has_halo) load_at(uint32_t(z0) * uint32_t(plane) + uint32_t(hcol), hv);
 
   // W_bar_az of the owned column at plane z - 1 (carried from the previous plane)
   R wz_m[3];
@@ -262,13 +265,14 @@ k_adj_order_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __rest
     if (has_halo) {
 #pragma unroll
       for (int c = 0; c < NV; ++c) sV[c][hs] = hv[c];
-      if (zc + 1 < z1) load_at(size_t(zc + 1) * plane + hcol, hv);  // next plane's halo
+      if (zc + 1 < z1) load_at(uint32_t(zc + 1) * uint32_t(plane) + uint32_t(hcol), hv);  // next plane's halo
     }
     __syncthreads();
     R Wb[3][3] = {{R(0), R(0), R(0)}, {R(0), R(0), R(0)}, {R(0), R(0), R(0)}}, ub[3] = {R(0), R(0), R(0)};
+    const uint32_t site = uint32_t(zc) * uint32_t(plane) + uint32_t(col);
+    const uint32_t sr = site * uint32_t(sizeof(R));
     if (active) {
-      const size_t site = size_t(zc) * plane + col;
-      const R ph = R(phi[site]);
+      const R ph = R(ldo(phi, site * uint32_t(sizeof(FS))));
       R qc[5], qbar[5], uc[3];
 #pragma unroll
       for (int k = 0; k < 5; ++k) {
@@ -309,10 +313,10 @@ k_adj_order_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __rest
       }
       R m, qb[5], pb;
       adj_order_site(P, qc, qbar, uc, ph, v0[8], pbn, un, qn, aqn, m, Wb, ub, qb, pb);
-      mub[site] = m;
+      sto(mub, sr, m);
 #pragma unroll
-      for (int k = 0; k < 5; ++k) qbp[k * N + site] = qb[k];
-      phibp[site] = pb;
+      for (int k = 0; k < 5; ++k) sto(qbp + k * N, sr, qb[k]);
+      sto(phibp, sr, pb);
     } else {
       corotation_wbar(P.xi, v0, v0 + 9, Wb);  // a neighbour of the tile's last column or row
     }
@@ -347,12 +351,11 @@ k_adj_order_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __rest
     }
     __syncthreads();  // W_bar of the tile and its halo are in place
     if (active) {
-      const size_t site = size_t(zc) * plane + col;
 #pragma unroll
       for (int a = 0; a < 3; ++a)
-        ub_out[a * N + site] = ub[a] - ((R(0.5) * (sW[a][sc + 1] - sW[a][sc - 1]) +
-                                         R(0.5) * (sW[3 + a][sc + SX] - sW[3 + a][sc - SX])) +
-                                        R(0.5) * (wz_p[a] - wz_m[a]));
+        sto(ub_out + a * N, sr, ub[a] - ((R(0.5) * (sW[a][sc + 1] - sW[a][sc - 1]) +
+                                          R(0.5) * (sW[3 + a][sc + SX] - sW[3 + a][sc - SX])) +
+                                         R(0.5) * (wz_p[a] - wz_m[a])));
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) wz_m[a] = Wb[a][2];
@@ -381,7 +384,7 @@ __device__ __forceinline__ void ubar_at(const Box& b, const UbarIn<R>& in, int s
   const size_t N = b.N;
   const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
 #pragma unroll
-  for (int a = 0; a < 3; ++a) ub[a] = in.u[a * N + s];
+  for (int a = 0; a < 3; ++a) ub[a] = ldo(in.u + a * N, uint32_t(s) * uint32_t(sizeof(R)));
   if (in.whole) return;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -473,21 +476,24 @@ __global__ void __launch_bounds__(256) k_adj_collide_lean(Box b, Params<R> P, co
   const size_t N = b.N;
   R ub[3];
   ubar_at(b, ubin, s, x, y, z, ub);
+  // global accesses: uniform field base plus a 32-bit byte offset per lane
+  const uint32_t so = uint32_t(s) * uint32_t(sizeof(R));
   R gsb[L::Q], Fs[3], us[3];
 #pragma unroll
   for (int i = 0; i < L::Q; ++i)
-    gsb[i] = __builtin_nontemporal_load(adj_g + i * N + sidx(b, x + L::cx(i), y + L::cy(i), z + L::cz(i)));
+    gsb[i] = ldo_nt(adj_g + i * N,
+                    uint32_t(sidx(b, x + L::cx(i), y + L::cy(i), z + L::cz(i))) * uint32_t(sizeof(R)));
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    Fs[a] = F[a * N + s];
-    us[a] = u[a * N + s];
+    Fs[a] = ldo(F + a * N, so);
+    us[a] = ldo(u + a * N, so);
   }
   R gb[L::Q], Fb[3] = {R(0), R(0), R(0)};
-  collide_bwd_site_l<R, L>(P, drho[s], us, Fs, gsb, ub, gb, Fb, Sb_out, N, s);
+  collide_bwd_site_l<R, L>(P, ldo(drho, so), us, Fs, gsb, ub, gb, Fb, Sb_out, N, s);
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) __builtin_nontemporal_store(gb[i], g_out + i * N + s);
+  for (int i = 0; i < L::Q; ++i) sto_nt(g_out + i * N, so, gb[i]);
 #pragma unroll
-  for (int a = 0; a < 3; ++a) Fb_out[a * N + s] = Fb[a];
+  for (int a = 0; a < 3; ++a) sto(Fb_out + a * N, so, Fb[a]);
 }
 
 // Number of per-site gradient-data adjoint values stored between kernels.

@@ -344,20 +344,16 @@ struct BackendT final : Backend {
     ao_ntx = (p.nx + kAoTX - 1) / kAoTX;
     ao_nty = (p.ny + ao_ty - 1) / ao_ty;
     ao_tz = t.tz_adj_order;
-    if (ao_tz == 0) ao_tz = auto_slab(ao_ntx, ao_nty, p.nz, 16, 1, ao_ty == 16 ? 1 : 2);
+    if (ao_tz == 0) ao_tz = auto_slab(ao_ntx, ao_nty, p.nz, 32, 1, ao_ty == 16 ? 1 : 2);
     ao_blocks = ao_ntx * ao_nty * ((p.nz + ao_tz - 1) / ao_tz);
     as_ty = t.adj_tile == 2 || (t.adj_tile == 0 && sizeof(R) == 4) ? 16 : 8;
     as_ntx = (p.nx + kAsTX - 1) / kAsTX;
     as_nty = (p.ny + as_ty - 1) / as_ty;
     as_tz = t.tz_adj;
-    if (as_tz == 0) {
-      // large boxes (four or more workgroups per CU at 64 planes or less): deeper
-      // slabs, since each slab marches two planes more than it owns
-      const int per_cu = as_ty == 16 ? 2 : 4;  // 16 waves per CU either way
-      as_tz = auto_slab(as_ntx, as_nty, p.nz, 64, 16, per_cu);
-      if (size_t(as_ntx) * as_nty * ((p.nz + as_tz - 1) / as_tz) < size_t(per_cu) * cu_count())
-        as_tz = auto_slab(as_ntx, as_nty, p.nz, 16, 1, 1);
-    }
+    // the deepest slab of up to 128 planes that still gives every CU a
+    // workgroup (8 waves): each slab marches two planes more than it owns, and
+    // its LDS footprint allows one such workgroup per CU at a time
+    if (as_tz == 0) as_tz = auto_slab(as_ntx, as_nty, p.nz, 128, 1, as_ty == 16 ? 1 : 2);
     as_blocks = as_ntx * as_nty * ((p.nz + as_tz - 1) / as_tz);
     size_t need = 2 * (NQ * N * sizeof(GS) + 6 * N * sizeof(FS)) + 4 * N * sizeof(R);
     if (pc4) need += 6 * N * sizeof(FS) + (site_path ? 3 * N * sizeof(R) : 0);
