@@ -1013,35 +1013,38 @@ template <class R>
 __global__ void __launch_bounds__(256) k_adj_faces(Box b, int TX, int ntx, int TY, int nty,
                                                    const R* __restrict__ hx, const R* __restrict__ hy,
                                                    R* __restrict__ adj_phi, R* __restrict__ adj_q) {
-  const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const size_t nzy = size_t(b.nz) * b.ny, nzx = size_t(b.nz) * b.nx;
-  const size_t fxs = size_t(ntx) * nzy, fys = size_t(nty) * nzx;  // one field-side block of hx, hy
-  const size_t nxt = ntx > 1 ? 6 * fxs : 0, nyt = nty > 1 ? 6 * fys : 0;
+  // 32-bit index arithmetic: every index below is under 6 N < 2^32
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t nx = b.nx, ny = b.ny, nz = b.nz;
+  const uint32_t nzy = nz * ny, nzx = nz * nx;
+  const uint32_t fxs = uint32_t(ntx) * nzy, fys = uint32_t(nty) * nzx;  // one field-side block of hx, hy
+  const uint32_t nxt = ntx > 1 ? 6 * fxs : 0, nyt = nty > 1 ? 6 * fys : 0;
   if (t < nxt) {
-    const int f = int(t / fxs);
-    const size_t r = t % fxs;
-    const int j = int(r / nzy);
-    const size_t zy = r % nzy;
-    const int jn = j + 1 < ntx ? j + 1 : 0;
-    const int wj = min(TX, b.nx - j * TX), wn = min(TX, b.nx - jn * TX);
-    const int xf = jn > 0 ? jn * TX - 1 : b.nx - 1;  // first column of tile jn; tile j's last is xf - 1
-    R* out = (f == 0 ? adj_phi : adj_q + size_t(f - 1) * b.N) + zy * b.nx;  // row (z, y)
+    const uint32_t f = t / fxs;
+    const uint32_t r = t - f * fxs;
+    const uint32_t j = r / nzy;
+    const uint32_t zy = r - j * nzy;
+    const uint32_t jn = j + 1 < uint32_t(ntx) ? j + 1 : 0;
+    const int wj = min(TX, b.nx - int(j) * TX), wn = min(TX, b.nx - int(jn) * TX);
+    const uint32_t xf = jn > 0 ? jn * TX - 1 : nx - 1;  // first column of tile jn; tile j's last is xf - 1
+    R* out = (f == 0 ? adj_phi : adj_q + size_t(f - 1) * b.N) + size_t(zy) * nx;  // row (z, y)
     const R* hs = hx + size_t(4 * f) * fxs;
-    const size_t fj = size_t(j) * nzy + zy, fn = size_t(jn) * nzy + zy;
+    const uint32_t fj = j * nzy + zy, fn = jn * nzy + zy;
     R vl = hs[3 * fxs + fj] + hs[fxs + fj];
     R vf = hs[2 * fxs + fn] + hs[fj];
     if (wn == 1) vf += hs[fxs + fn];
     if (nty > 1) {  // the y-face terms of a first or last row of a y tile
-      const int z = int(zy / b.ny), y = int(zy % b.ny);
-      const int i = y / TY, ly = y - i * TY, h = min(TY, b.ny - i * TY);
-      const R* ys = hy + size_t(2 * f) * fys + size_t(z) * b.nx;
+      const uint32_t z = zy / ny, y = zy - z * ny;
+      const uint32_t i = y / TY, ly = y - i * TY;
+      const uint32_t h = min(uint32_t(TY), ny - i * TY);
+      const R* ys = hy + size_t(2 * f) * fys + z * nx;
       if (ly == 0) {
-        const R* s0 = ys + size_t((i + nty - 1) % nty) * nzx;
+        const R* s0 = ys + ((i + nty - 1) % nty) * nzx;
         vl += s0[xf - 1];
         vf += s0[xf];
       }
       if (ly == h - 1) {
-        const R* s1 = ys + fys + size_t(i) * nzx;
+        const R* s1 = ys + fys + i * nzx;
         vl += s1[xf - 1];
         vf += s1[xf];
       }
@@ -1051,19 +1054,19 @@ __global__ void __launch_bounds__(256) k_adj_faces(Box b, int TX, int ntx, int T
     return;
   }
   if (t - nxt >= nyt) return;
-  const size_t u = t - nxt;
-  const int f = int(u / fys);
-  const size_t r = u % fys;
-  const int i = int(r / nzx);
-  const size_t zx = r % nzx;
-  const int z = int(zx / b.nx), x = int(zx % b.nx);
+  const uint32_t u = t - nxt;
+  const uint32_t f = u / fys;
+  const uint32_t r = u - f * fys;
+  const uint32_t i = r / nzx;
+  const uint32_t zx = r - i * nzx;
+  const uint32_t z = zx / nx, x = zx - z * nx;
   // the x-edge columns (first and last of every x tile) belong to the first range
-  if (ntx > 1 && ((x + 1) % TX == 0 || (x + 2) % TX == 0 || x >= b.nx - 2)) return;
-  const int ya = i * TY, yb = min(ya + TY, b.ny) - 1;
-  R* out = (f == 0 ? adj_phi : adj_q + size_t(f - 1) * b.N) + size_t(z) * b.ny * b.nx + x;
+  if (ntx > 1 && ((x + 1) % TX == 0 || (x + 2) % TX == 0 || x + 2 >= nx)) return;
+  const uint32_t ya = i * TY, yb = min(ya + TY, ny) - 1;
+  R* out = (f == 0 ? adj_phi : adj_q + size_t(f - 1) * b.N) + size_t(z) * ny * nx + x;
   const R* hs = hy + size_t(2 * f) * fys;
-  out[size_t(ya) * b.nx] += hs[size_t((i + nty - 1) % nty) * nzx + zx];
-  out[size_t(yb) * b.nx] += hs[fys + size_t(i) * nzx + zx];
+  out[ya * nx] += hs[((i + nty - 1) % nty) * nzx + zx];
+  out[yb * nx] += hs[fys + i * nzx + zx];
 }
 
 // out = in + 1 for the step counter of a recorded state (one thread, vector memory).
