@@ -393,6 +393,8 @@ def main():
     ap.add_argument("--adj-order-tile", type=int, default=0, help="order adjoint tile (lb_tuning.adj_order_tile)")
     ap.add_argument("--tz-adj", type=int, default=0, help="stress + gather adjoint slab depth (lb_tuning.tz_adj)")
     ap.add_argument("--tz-adj-order", type=int, default=0, help="order adjoint slab depth (lb_tuning.tz_adj_order)")
+    ap.add_argument("--tz-pc-adj", type=int, default=0, help="pc4 reverse product slab depth (lb_tuning.tz_pc_adj)")
+    ap.add_argument("--pc-adj", type=int, default=0, help="pc4 reverse kernels (lb_tuning.pc_adj: 1 = site-parallel)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side", action="store_true", help="skip the FP64 / FP16S side timings")
     ap.add_argument("--profile-steps", type=int, default=50)
@@ -527,7 +529,8 @@ def main():
         adjoint = time_adjoint(args.precision, pa, phi, q5, args.adjoint_steps, args.adjoint_checkpoint, stream,
                                recorded=not args.no_adjoint_recorded, lattice=args.lattice, fd_scheme=args.fd_scheme,
                                tuning=dict(tuning, adj_tile=args.adj_tile, adj_order_tile=args.adj_order_tile,
-                                           tz_adj=args.tz_adj, tz_adj_order=args.tz_adj_order))
+                                           tz_adj=args.tz_adj, tz_adj_order=args.tz_adj_order,
+                                           tz_pc_adj=args.tz_pc_adj, pc_adj=args.pc_adj))
         print(f"# adjoint/forward: {adjoint['adjoint_over_forward']:.2f} (checkpoint {args.adjoint_checkpoint}; "
               f"{adjoint['overlapped']['adjoint_over_forward']:.2f} with the replay overlapped)"
               + (f", {adjoint['recorded']['adjoint_over_forward']:.2f} (every step recorded, "

@@ -167,12 +167,16 @@ typedef struct {
   int32_t tz_pc;         /* LB_FD_PC4 stage kernel, */
   int32_t tz_pcmu;       /* LB_FD_PC4 mu kernel, */
   int32_t tz_adj;        /* fused stress + gather adjoint, */
-  int32_t tz_adj_order;  /* order-parameter adjoint */
+  int32_t tz_adj_order;  /* order-parameter adjoint, */
+  int32_t tz_pc_adj;     /* LB_FD_PC4 reverse product kernel */
+  int32_t pc_adj;        /* LB_FD_PC4 reverse: 0 = default (one z-marching kernel per Heun
+                            product where every tile along a split axis is at least two sites
+                            wide, else the site-parallel kernels), 1 = site-parallel kernels */
 } lb_tuning;
 
 /* lb_init with an explicit launch configuration (t may be NULL).  Errors as
  * lb_init, plus LB_EINVAL for an unknown path or tile index, a negative slab
- * depth, or LB_PATH_ONE_LAUNCH with LB_FD_PC4. */
+ * depth, pc_adj other than 0 or 1, or LB_PATH_ONE_LAUNCH with LB_FD_PC4. */
 lb_status lb_init_tuned(const lb_params* p, const lb_tuning* t, const double* phi, const double* q5,
                         const double* u0, void* hip_stream, lb_ctx** out);
 

@@ -40,7 +40,7 @@ PATHS = {"default": LB_PATH_DEFAULT, "one": LB_PATH_ONE_LAUNCH, "two": LB_PATH_T
 class LbTuning(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in (
         "path", "lb_tile", "order_tile", "pc_tile", "pcmu_tile", "adj_tile", "adj_order_tile", "step_tile", "tz_step", "tz_lb", "tz_order", "tz_pc",
-        "tz_pcmu", "tz_adj", "tz_adj_order")]
+        "tz_pcmu", "tz_adj", "tz_adj_order", "tz_pc_adj", "pc_adj")]
 
 
 class LbTotals(ctypes.Structure):

@@ -270,17 +270,506 @@ k_pcb_gather(Box b, const FS* __restrict__ phi, const R* __restrict__ u, const R
   for (int a = 0; a < 3; ++a) ub_out[a * N + s] = accumulate ? ub_out[a * N + s] + ub[a] : ub[a];
 }
 
-// The z terms of one product (after k_pcb_gather<R, FS, 2>), added to q_out,
-// phi_out and ub_out.  One thread per (x, y) column marches the planes of a
-// slab of TZ; the 15 fields with a radius-2 z stencil (the adjoints of
-// D4_z Q, L4 Q, D4_z phi, L4 phi, W_az) sit in five-plane register rings, the
-// 8 with a radius-1 one (V, u_z, phi) in three-plane rings.
-template <class R, class FS>
-__global__ void __launch_bounds__(256) k_pcb_gather_z(Box b, int TZ, const FS* __restrict__ phi,
+// mu_bar = M vs L4 vphi of one product at every site: the adjoint of mu4,
+// which the fused product reads with a D4 stencil (v_bar = 2 W D4 mu_bar).
+template <class R>
+__global__ void __launch_bounds__(256) k_pcb_mub(Box b, Params<R> P, const R* __restrict__ vphi, R vs,
+                                                 R* __restrict__ mub) {
+  const int s = site_xcd();
+  if (s >= b.N) return;
+  int x, y, z;
+  coords(b, s, x, y, z);
+  int n[3][4];
+  star2(b, x, y, z, n);
+  R lapv = R(-7.5) * vphi[s];
+#pragma unroll
+  for (int g = 0; g < 3; ++g) lapv += l4c(vphi[n[g][0]], vphi[n[g][1]], vphi[n[g][2]], vphi[n[g][3]]);
+  mub[s] = P.M * vs * lapv;
+}
+
+// Coefficients of the transposed axis stencils: a site x gathers
+// L4^T f = sum_d l4w(d) f(x + d) (plus -7.5 f(x), once over the axes) and
+// D4^T f = -D4 f = sum_d d4w(d) f(x + d), d = -2, -1, 1, 2.
+template <class R>
+__device__ __forceinline__ R l4w(int d) {
+  return (d == 1 || d == -1) ? R(16.0 / 12.0) : R(-1.0 / 12.0);
+}
+template <class R>
+__device__ __forceinline__ R d4w(int d) {
+  return d == 1 ? R(-8.0 / 12.0) : d == -1 ? R(8.0 / 12.0) : d == 2 ? R(1.0 / 12.0) : R(-1.0 / 12.0);
+}
+
+// A face record: the 9 output fields of one owed term, padded to 12 values
+// so that it moves as three 16-byte (float) or six 16-byte (double) accesses.
+constexpr int kRec = 12;
+template <class R>
+__device__ __forceinline__ void st_rec(R* __restrict__ p, const R v[9]) {
+  if constexpr (sizeof(R) == 4) {
+    float4* q = reinterpret_cast<float4*>(p);
+    q[0] = make_float4(v[0], v[1], v[2], v[3]);
+    q[1] = make_float4(v[4], v[5], v[6], v[7]);
+    q[2] = make_float4(v[8], 0.0f, 0.0f, 0.0f);
+  } else {
+    double2* q = reinterpret_cast<double2*>(p);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = make_double2(v[2 * i], v[2 * i + 1]);
+    q[4] = make_double2(v[8], 0.0);
+  }
+}
+template <class R>
+__device__ __forceinline__ void add_rec(const R* __restrict__ p, R t[9]) {
+  if constexpr (sizeof(R) == 4) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+    const float4 a = q[0], c = q[1], d = q[2];
+    t[0] += a.x; t[1] += a.y; t[2] += a.z; t[3] += a.w;
+    t[4] += c.x; t[5] += c.y; t[6] += c.z; t[7] += c.w;
+    t[8] += d.x;
+  } else {
+    const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double2 a = q[i];
+      t[2 * i] += a.x;
+      t[2 * i + 1] += a.y;
+    }
+    t[8] += q[4].x;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_pcb_fused: one product R'(X)^T V of the pc4 reverse (k_pcb_local, k_pcb_v
+// and k_pcb_gather together) in one z-march over a TX x TY tile and a slab of
+// TZ planes, with the Heun combination out = c1 X_bar(t+1) + c2 Xs + R'^T V
+// and u_bar written (accumulate = 0) or added to (accumulate = 1).
+//   Per plane, LDS holds the 16 input fields (Q, phi, u, mu_bar for the
+//   stencils of the local reverse; V for the neighbour terms of the upwind
+//   and donor-cell operators) on the tile with an in-plane cross-shaped halo
+//   of 2; the owned column keeps Q, phi, u, mu_bar of planes z-2 .. z+2 in
+//   registers.  Each thread forms the local reverse of its own site (the
+//   stencil-data adjoints of H4, mu4, the co-rotation and the site's own
+//   upwind terms, with v_bar = -D4 (-2 W mu_bar) folded in) and puts the 24
+//   stencil-data adjoints the x and y transposes read in LDS.  A site then
+//   gathers the x and y transposes from the neighbours in its tile (a lone
+//   tile along an axis wraps inside itself).  Two kinds of terms are left to
+//   k_pcb_gather_z:
+//   * the z transposes: of the 15 stencil-data adjoints with z stencils, the
+//     9 that depend on the site's reverse go to zf[9][N] (D4_z Q adjoints,
+//     the D4_z phi adjoint, W_az adjoints); the L4 Q and L4 phi adjoints are
+//     K Gamma V_Q and -k_phi mu_bar, which k_pcb_gather_z forms from V and
+//     mu_bar itself;
+//   * the terms a site owes the two columns (rows) across a tile face: the
+//     last two columns of tile j send to the first two of tile j+1 and back.
+//     Per output field (q[5], phi, u[3]) and face, side 0 holds what tile j
+//     sends in the + direction, side 1 what tile j+1 sends in the -
+//     direction; entry 0 is the edge site's term for the first site across,
+//     entry 1 its term for the second, entry 2 the second-to-edge site's term
+//     for the first.  A record holds the 9 output fields of one entry:
+//     fx[((((side 3 + entry) ntx + j) nz + z) ny + y) kRec + f], fy likewise
+//     over (nty, z, x).  Every tile along a split axis is at least two sites wide
+//     (checked by the caller).
+// partial: one float64 (zeta, q0) pair per block, overwritten (pacc = 0) or
+// added to (pacc = 1).
+// ---------------------------------------------------------------------------
+template <class R, class FS, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 2 : 1)))
+k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__ phi, const FS* __restrict__ q,
+            const R* __restrict__ u, const R* __restrict__ vq, const R* __restrict__ vphi, R vs,
+            const R* __restrict__ mub, const R* __restrict__ xq1, const R* __restrict__ xp1, R c1,
+            const R* __restrict__ xsq, const R* __restrict__ xsp, R c2, R* __restrict__ q_out,
+            R* __restrict__ phi_out, R* __restrict__ ub_out, int accumulate, R* __restrict__ zf,
+            R* __restrict__ fx, R* __restrict__ fy, double* __restrict__ partial, int pacc) {
+  constexpr int NT = TX * TY;
+  constexpr int HR = 2;
+  constexpr int SX = TX + 2 * HR, SY = TY + 2 * HR, NS = SX * SY;
+  constexpr int NH = 2 * HR * (TX + TY);  // halo slots of the axis stencils (no corners)
+  static_assert(NH <= NT, "one halo slot per thread");
+  constexpr int NZ = 10;  // fields with z stencils: q[5], phi, u[3], mu_bar
+  constexpr int NV = 16;  // and V: vq[5], vphi
+  // x, y stencil-data adjoints: lapq[5], lapphi, dq_x[5], dq_y[5], dphi_x, dphi_y, W_ax[3], W_ay[3]
+  constexpr int XL = 0, XLP = 5, XDQ = 6, XDP = 16, XW = 18, NXF = 24;
+  __shared__ R sV[NV][NS];
+  __shared__ R sX[NXF][NT];
+  __shared__ int sGX[SX], sGY[SY];
+
+  const int l = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = l % ntx, ty = (l / ntx) % nty, sl = l / (ntx * nty);
+  const int x0 = tx * TX, y0 = ty * TY, z0 = sl * TZ;
+  const int z1 = min(z0 + TZ, b.nz);
+  const int w = min(TX, b.nx - x0), h = min(TY, b.ny - y0);
+  const int tid = threadIdx.x;
+  const int lx = tid % TX, ly = tid / TX;
+  const bool active = lx < w && ly < h;
+  const size_t N = b.N;
+  const int plane = b.nx * b.ny;
+
+  for (int k = tid; k < SX; k += NT) sGX[k] = pmod(x0 - HR + k, b.nx);
+  for (int k = tid; k < SY; k += NT) sGY[k] = pmod(y0 - HR + k, b.ny);
+  __syncthreads();
+  const int col = sGY[ly + HR] * b.nx + sGX[lx + HR];
+
+  // global accesses: uniform field base plus a 32-bit byte offset per lane
+  // (component arrays are below 4 GiB)
+  constexpr uint32_t SR = sizeof(R), SF = sizeof(FS);
+  auto load_z = [&](int zz, R v[NZ]) {
+    const uint32_t k = uint32_t(pmod(zz, b.nz)) * uint32_t(plane) + uint32_t(col);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) v[c] = R(ldo(q + c * N, k * SF));
+    v[5] = R(ldo(phi, k * SF));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[6 + a] = ldo(u + a * N, k * SR);
+    v[9] = ldo(mub, k * SR);
+  };
+  auto load_v = [&](uint32_t k, R v[6]) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) v[c] = ldo(vq + c * N, k * SR);
+    v[5] = ldo(vphi, k * SR);
+  };
+  // owned column: planes z-2 .. z+2 of the z-stencil fields
+  R zr[5][NZ];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) load_z(z0 - 2 + j, zr[j]);
+
+  // this thread's halo slot: 2 HR rows of TX, then 2 HR columns of TY
+  const bool has_halo = tid < NH;
+  int hs = 0, hcol = 0;
+  if (has_halo) {
+    int hx, hy;
+    if (tid < 2 * HR * TX) {
+      const int r = tid / TX;
+      hx = HR + tid % TX;
+      hy = r < HR ? r : TY + r;
+    } else {
+      const int t = tid - 2 * HR * TX;
+      const int c = t / TY;
+      hy = HR + t % TY;
+      hx = c < HR ? c : TX + c;
+    }
+    hs = hy * SX + hx;
+    hcol = sGY[hy] * b.nx + sGX[hx];
+  }
+  auto load_all = [&](int zz, R v[NV]) {
+    const uint32_t k = uint32_t(zz) * uint32_t(plane) + uint32_t(hcol);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) v[c] = R(ldo(q + c * N, k * SF));
+    v[5] = R(ldo(phi, k * SF));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[6 + a] = ldo(u + a * N, k * SR);
+    v[9] = ldo(mub, k * SR);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) v[10 + c] = ldo(vq + c * N, k * SR);
+    v[15] = ldo(vphi, k * SR);
+  };
+
+  // in-tile neighbour at offset d (|d| <= 2) along x (y); -1 where it is in
+  // another tile (a lone tile wraps: t in [-2, n + 1] folds into [0, n))
+  auto wrap2 = [](int t, int n) {
+    t += t < 0 ? n : 0;
+    t += t < 0 ? n : 0;
+    t -= t >= n ? n : 0;
+    t -= t >= n ? n : 0;
+    return t;
+  };
+  auto nbx = [&](int d) {
+    const int t = lx + d;
+    if (ntx == 1) return ly * TX + wrap2(t, w);
+    return (t >= 0 && t < w) ? ly * TX + t : -1;
+  };
+  auto nby = [&](int d) {
+    const int t = ly + d;
+    if (nty == 1) return wrap2(t, h) * TX + lx;
+    return (t >= 0 && t < h) ? t * TX + lx : -1;
+  };
+  const size_t fxs = size_t(ntx) * b.nz * b.ny * kRec, fys = size_t(nty) * b.nz * b.nx * kRec;  // one (side, entry) block
+  const int kxm = (tx + ntx - 1) % ntx, kym = (ty + nty - 1) % nty;
+
+  const int sc = (ly + HR) * SX + (lx + HR);
+  double v2[2] = {0.0, 0.0};
+  for (int zc = z0; zc < z1; ++zc) {
+    __syncthreads();  // the previous plane's reads are done
+#pragma unroll
+    for (int c = 0; c < NZ; ++c) sV[c][sc] = zr[2][c];
+    {  // V of the owned site
+      R vv[6];
+      load_v(uint32_t(zc) * uint32_t(plane) + uint32_t(col), vv);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sV[NZ + c][sc] = vv[c];
+    }
+    if (has_halo) {  // the halo of this plane (loads carried across the plane would exceed the registers)
+      R hv[NV];
+      load_all(zc, hv);
+#pragma unroll
+      for (int c = 0; c < NV; ++c) sV[c][hs] = hv[c];
+    }
+    __syncthreads();
+    // ---- local reverse at the own site
+    R qbl[5], pbl = R(0), ubl[3] = {R(0), R(0), R(0)};
+    if (active) {
+      auto nb = [&](int f, int g, R& m2, R& m1, R& p1, R& p2) {
+        if (g == 0) {
+          m2 = sV[f][sc - 2]; m1 = sV[f][sc - 1]; p1 = sV[f][sc + 1]; p2 = sV[f][sc + 2];
+        } else if (g == 1) {
+          m2 = sV[f][sc - 2 * SX]; m1 = sV[f][sc - SX]; p1 = sV[f][sc + SX]; p2 = sV[f][sc + 2 * SX];
+        } else {
+          m2 = zr[0][f]; m1 = zr[1][f]; p1 = zr[3][f]; p2 = zr[4][f];
+        }
+      };
+      Grad<R> G;
+      G.phi = zr[2][5];
+      G.lapphi = R(0);
+      G.divv = R(0);
+      R W[3][3], vb[3], VQ[5], uq[5] = {R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        G.q[k] = zr[2][k];
+        G.lapq[k] = R(-7.5) * G.q[k];
+        VQ[k] = vs * sV[NZ + k][sc];
+      }
+#pragma unroll
+      for (int g = 0; g < 3; ++g) {
+        R m2, m1, p1, p2;
+        nb(5, g, m2, m1, p1, p2);
+        G.dphi[g] = d4c(m2, m1, p1, p2);
+        // the site's own upwind terms along g: R_Q gets
+        // -max(u_g,0)(Q - Q(x-e_g)) - min(u_g,0)(Q(x+e_g) - Q)
+        const R ug = zr[2][6 + g], up = ug > R(0) ? ug : R(0), um = ug < R(0) ? ug : R(0);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          nb(k, g, m2, m1, p1, p2);
+          G.dq[g][k] = d4c(m2, m1, p1, p2);
+          G.lapq[k] += l4c(m2, m1, p1, p2);
+          const R a = -VQ[k];
+          const R back = G.q[k] - m1, fwd = p1 - G.q[k];
+          uq[k] += a * (up - um);
+          ubl[g] += a * ((ug >= R(0) ? back : R(0)) + (ug <= R(0) ? fwd : R(0)));
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          nb(6 + a, g, m2, m1, p1, p2);
+          W[a][g] = d4c(m2, m1, p1, p2);
+        }
+        // v = Q D4 phi: v_bar_g = -D4_g divv_bar with divv_bar = -2 W mu_bar
+        nb(9, g, m2, m1, p1, p2);
+        const R w2 = R(2) * P.W;
+        vb[g] = -d4c(-(w2 * m2), -(w2 * m1), -(w2 * p1), -(w2 * p2));
+      }
+      R hb[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) hb[k] = P.Gamma * VQ[k];
+      Local<R> Lc;
+      local_thermo(P, G, Lc);
+      GradBar<R> Gb;
+      Gb.zero();
+      ParBar<R> Pb{R(0), R(0), R(0)};
+      R lapphib = R(0), divvb = R(0), tr2b = R(0), tr3b = R(0);
+      mu_site_bwd_local(P, G.phi, Lc.tr2, zr[2][9], Gb.phi, lapphib, divvb, tr2b, tr3b);
+      local_thermo_bwd(P, G, Lc, hb, tr2b, tr3b, R(0), R(0), R(0), Gb, Pb);
+      R Wb[3][3] = {{R(0), R(0), R(0)}, {R(0), R(0), R(0)}, {R(0), R(0), R(0)}};
+#pragma unroll
+      for (int k = 0; k < 5; ++k) qbl[k] = Gb.q[k];
+      corotation_site_bwd(P.xi, G.q, W, VQ, qbl, Wb);
+      pbl = Gb.phi;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) qbl[k] += uq[k];
+      // v = Q D4 phi at the site: Q_bar_ab += v_bar_a D4_b phi, (D4 phi)_bar_b += Q_ab v_bar_a
+      {
+        const R xx = G.q[0], xy = G.q[1], xz = G.q[2], yy = G.q[3], yz = G.q[4], zz = -xx - yy;
+        const R Qm[3][3] = {{xx, xy, xz}, {xy, yy, yz}, {xz, yz, zz}};
+        R Qb[3][3], qv[5] = {R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) Qb[a][c] = vb[a] * G.dphi[c];
+          Gb.dphi[a] += Qm[a][0] * vb[0] + Qm[a][1] * vb[1] + Qm[a][2] * vb[2];
+        }
+        full_to_stored(Qb, qv);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) qbl[k] += qv[k];
+      }
+      par_adjoints(P, Pb, v2);
+      // x, y stencil-data adjoints to LDS; z ones to zf
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        sX[XL + k][tid] = Gb.lapq[k];
+        sX[XDQ + k][tid] = Gb.dq[0][k];
+        sX[XDQ + 5 + k][tid] = Gb.dq[1][k];
+      }
+      sX[XLP][tid] = lapphib;
+      sX[XDP][tid] = Gb.dphi[0];
+      sX[XDP + 1][tid] = Gb.dphi[1];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        sX[XW + a][tid] = Wb[a][0];
+        sX[XW + 3 + a][tid] = Wb[a][1];
+      }
+      const uint32_t so = (uint32_t(zc) * uint32_t(plane) + uint32_t(col)) * SR;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) sto(zf + k * N, so, Gb.dq[2][k]);
+      sto(zf + 5 * N, so, Gb.dphi[2]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) sto(zf + (6 + a) * N, so, Wb[a][2]);
+    }
+    __syncthreads();  // the stencil-data adjoints of the tile are in place
+    if (active) {
+      const uint32_t so = (uint32_t(zc) * uint32_t(plane) + uint32_t(col)) * SR;
+      const int dd[4] = {-2, -1, 1, 2};
+      int ix[4], iy[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        ix[k] = nbx(dd[k]);
+        iy[k] = nby(dd[k]);
+      }
+      auto vx = [&](int f, int k) { return ix[k] >= 0 ? sX[f][ix[k]] : R(0); };
+      auto vy = [&](int f, int k) { return iy[k] >= 0 ? sX[f][iy[k]] : R(0); };
+      auto l4x = [&](int f) { return l4c(vx(f, 0), vx(f, 1), vx(f, 2), vx(f, 3)); };
+      auto l4y = [&](int f) { return l4c(vy(f, 0), vy(f, 1), vy(f, 2), vy(f, 3)); };
+      auto d4x = [&](int f) { return -d4c(vx(f, 0), vx(f, 1), vx(f, 2), vx(f, 3)); };
+      auto d4y = [&](int f) { return -d4c(vy(f, 0), vy(f, 1), vy(f, 2), vy(f, 3)); };
+      R qo[5], po, ub[3];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        R r = qbl[k] + ((R(-7.5) * sX[XL + k][tid] + l4x(XL + k)) + l4y(XL + k));
+        r += d4x(XDQ + k);
+        r += d4y(XDQ + 5 + k);
+        qo[k] = r;
+      }
+      {
+        R r = pbl + ((R(-7.5) * sX[XLP][tid] + l4x(XLP)) + l4y(XLP));
+        r += d4x(XDP);
+        r += d4y(XDP + 1);
+        po = r;
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        R r = ubl[a];
+        r += d4x(XW + a);
+        r += d4y(XW + 3 + a);
+        ub[a] = r;
+      }
+      // the x and y neighbour terms of the upwind and donor-cell operators
+      const R ph = zr[2][5], vp0 = vs * sV[NZ + 5][sc];
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        const int m1 = g == 0 ? sc - 1 : sc - SX, p1 = g == 0 ? sc + 1 : sc + SX;
+        const R ugp = sV[6 + g][p1], ugm = sV[6 + g][m1], ugs = zr[2][6 + g];
+        const R upx = ugp > R(0) ? ugp : R(0), umx = ugm < R(0) ? ugm : R(0);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) qo[k] += (vs * sV[NZ + k][p1]) * upx - (vs * sV[NZ + k][m1]) * umx;
+        const R fp = R(0.5) * (ugs + ugp), fm = R(0.5) * (ugm + ugs);
+        const R cp = vs * sV[NZ + 5][p1] - vp0, cm = vp0 - vs * sV[NZ + 5][m1];
+        const R php = sV[5][p1], phm = sV[5][m1];
+        po += cp * (fp > R(0) ? fp : R(0)) + cm * (fm < R(0) ? fm : R(0));
+        const R dfp = (fp >= R(0) ? ph : R(0)) + (fp <= R(0) ? php : R(0));
+        const R dfm = (fm >= R(0) ? phm : R(0)) + (fm <= R(0) ? ph : R(0));
+        ub[g] += R(0.5) * (cp * dfp + cm * dfm);
+      }
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        R r = c1 * ldo(xq1 + k * N, so) + qo[k];
+        if (xsq) r += c2 * ldo(xsq + k * N, so);
+        sto(q_out + k * N, so, r);
+      }
+      {
+        R r = c1 * ldo(xp1, so) + po;
+        if (xsp) r += c2 * ldo(xsp, so);
+        sto(phi_out, so, r);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) sto(ub_out + a * N, so, accumulate ? ldo(ub_out + a * N, so) + ub[a] : ub[a]);
+      // the terms owed across a tile face: output fields q[5], phi, u[3] of
+      // the site at offset d from this one
+      auto owed = [&](int g, int d, R o[9]) {
+        const R lw = l4w<R>(-d), dw = d4w<R>(-d);  // this site is at offset -d from the receiver
+#pragma unroll
+        for (int k = 0; k < 5; ++k) o[k] = sX[XL + k][tid] * lw + sX[XDQ + 5 * g + k][tid] * dw;
+        o[5] = sX[XLP][tid] * lw + sX[XDP + g][tid] * dw;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) o[6 + a] = sX[XW + 3 * g + a][tid] * dw;
+      };
+      auto put = [&](R* buf, size_t fs, int side, int entry, size_t off, const R o[9]) {
+        st_rec(buf + size_t(side * 3 + entry) * fs + off * kRec, o);
+      };
+      const int pz = zc;
+      if (ntx > 1) {
+        const int gy = sGY[ly + HR];
+        R o[9];
+        if (lx == w - 1) {  // to the first two columns of tile tx + 1
+          const size_t off = (size_t(tx) * b.nz + pz) * b.ny + gy;
+          owed(0, 1, o);
+          put(fx, fxs, 0, 0, off, o);
+          owed(0, 2, o);
+          put(fx, fxs, 0, 1, off, o);
+        }
+        if (lx == w - 2) {
+          owed(0, 2, o);
+          put(fx, fxs, 0, 2, (size_t(tx) * b.nz + pz) * b.ny + gy, o);
+        }
+        if (lx == 0) {  // to the last two columns of tile tx - 1
+          const size_t off = (size_t(kxm) * b.nz + pz) * b.ny + gy;
+          owed(0, -1, o);
+          put(fx, fxs, 1, 0, off, o);
+          owed(0, -2, o);
+          put(fx, fxs, 1, 1, off, o);
+        }
+        if (lx == 1) {
+          owed(0, -2, o);
+          put(fx, fxs, 1, 2, (size_t(kxm) * b.nz + pz) * b.ny + gy, o);
+        }
+      }
+      if (nty > 1) {
+        const int gx = sGX[lx + HR];
+        R o[9];
+        if (ly == h - 1) {
+          const size_t off = (size_t(ty) * b.nz + pz) * b.nx + gx;
+          owed(1, 1, o);
+          put(fy, fys, 0, 0, off, o);
+          owed(1, 2, o);
+          put(fy, fys, 0, 1, off, o);
+        }
+        if (ly == h - 2) {
+          owed(1, 2, o);
+          put(fy, fys, 0, 2, (size_t(ty) * b.nz + pz) * b.nx + gx, o);
+        }
+        if (ly == 0) {
+          const size_t off = (size_t(kym) * b.nz + pz) * b.nx + gx;
+          owed(1, -1, o);
+          put(fy, fys, 1, 0, off, o);
+          owed(1, -2, o);
+          put(fy, fys, 1, 1, off, o);
+        }
+        if (ly == 1) {
+          owed(1, -2, o);
+          put(fy, fys, 1, 2, (size_t(kym) * b.nz + pz) * b.nx + gx, o);
+        }
+      }
+    }
+    if (zc + 1 < z1) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int c = 0; c < NZ; ++c) zr[j][c] = zr[j + 1][c];
+      load_z(zc + 3, zr[4]);
+    }
+  }
+  block_reduce_store<2>(v2, partial + size_t(blockIdx.x) * 2, pacc != 0);
+}
+
+// The z terms of one product (after k_pcb_gather<R, FS, 2> or k_pcb_fused),
+// added to q_out, phi_out and ub_out.  One thread per (x, y) column marches
+// the planes of a slab of TZ; the 15 fields with a radius-2 z stencil (the
+// adjoints of D4_z Q, L4 Q, D4_z phi, L4 phi, W_az: pb's fields, or zf of
+// k_pcb_fused, zstride apart) sit in five-plane register rings, the 8 with a
+// radius-1 one (V, u_z, phi) in three-plane rings.  After k_pcb_fused (fx or
+// fy not null) a column among the first or last two of its TX x TY tile also
+// takes the terms the neighbouring tile owes it across the face.
+template <class R, class FS, bool FACES>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? (FACES ? 2 : 3) : 1)))
+k_pcb_gather_z(Box b, Params<R> P, int TZ, const FS* __restrict__ phi,
                                                       const R* __restrict__ u, const R* __restrict__ vq,
                                                       const R* __restrict__ vphi, R vs, const R* __restrict__ pb,
                                                       R* __restrict__ q_out, R* __restrict__ phi_out,
-                                                      R* __restrict__ ub_out) {
+                                                      R* __restrict__ ub_out, const R* __restrict__ zf,
+                                                      const R* __restrict__ mub, int TX, int TY, int ntx, int nty,
+                                                      const R* __restrict__ fx, const R* __restrict__ fy) {
   const int plane = b.nx * b.ny;
   const int ncb = (plane + 255) / 256;
   const int col = (blockIdx.x % ncb) * 256 + threadIdx.x;
@@ -290,15 +779,83 @@ __global__ void __launch_bounds__(256) k_pcb_gather_z(Box b, int TZ, const FS* _
   constexpr int N2 = 15, N1 = 8;
   // radius-2 fields: D4_z Q adjoint (5), L4 Q adjoint (5), D4_z phi, L4 phi adjoints, W_az adjoint (3)
   const R* f2[N2];
+  if constexpr (FACES) {  // zf: D4_z Q (5), D4_z phi, W_az (3); L4 Q, L4 phi formed from V, mu_bar below
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    f2[k] = pb + size_t(PB_DQ + 10 + k) * N;
-    f2[5 + k] = pb + size_t(PB_LAPQ + k) * N;
+    for (int k = 0; k < 5; ++k) {
+      f2[k] = zf + size_t(k) * N;
+      f2[5 + k] = vq + size_t(k) * N;
+    }
+    f2[10] = zf + size_t(5) * N;
+    f2[11] = mub;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) f2[12 + a] = zf + size_t(6 + a) * N;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      f2[k] = pb + size_t(PB_DQ + 10 + k) * N;
+      f2[5 + k] = pb + size_t(PB_LAPQ + k) * N;
+    }
+    f2[10] = pb + size_t(PB_DPHI + 2) * N;
+    f2[11] = pb + size_t(PB_LAPPHI) * N;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) f2[12 + a] = pb + size_t(PB_W + 3 * a + 2) * N;
   }
-  f2[10] = pb + size_t(PB_DPHI + 2) * N;
-  f2[11] = pb + size_t(PB_LAPPHI) * N;
+  // face terms of this column (k_pcb_fused): per axis, up to two (face,
+  // side, entries) sources; the entry sums are formed per plane below
+  const int cx = col % b.nx, cy = col / b.nx;
+  int xsrc[2] = {-1, -1}, xent[2] = {0, 0}, ysrc[2] = {-1, -1}, yent[2] = {0, 0};
+  // entries: 0 -> entry 0 + entry 2 (the first site across), 1 -> entry 1 (the second)
+  if (FACES && ntx > 1) {
+    const int j = cx / TX, lx = cx - j * TX, wj = min(TX, b.nx - j * TX);
+    if (lx < 2) {  // sent by tile j - 1 in the + direction (side 0) across face j - 1
+      xsrc[0] = ((j + ntx - 1) % ntx) * 2 + 0;
+      xent[0] = lx;
+    }
+    if (lx >= wj - 2) {  // sent by tile j + 1 in the - direction (side 1) across face j
+      xsrc[1] = j * 2 + 1;
+      xent[1] = wj - 1 - lx;
+    }
+  }
+  if (FACES && nty > 1) {
+    const int i = cy / TY, ly = cy - i * TY, hi = min(TY, b.ny - i * TY);
+    if (ly < 2) {
+      ysrc[0] = ((i + nty - 1) % nty) * 2 + 0;
+      yent[0] = ly;
+    }
+    if (ly >= hi - 2) {
+      ysrc[1] = i * 2 + 1;
+      yent[1] = hi - 1 - ly;
+    }
+  }
+  // records of the 9 output fields: entry stride fxs (fys), one record per (face, z, line)
+  const size_t fxs = size_t(ntx) * b.nz * b.ny * kRec, fys = size_t(nty) * b.nz * b.nx * kRec;
+  // the owed terms of the 9 output fields at plane zz, added to t
+  auto face_terms = [&](int zz, R t[9]) {
 #pragma unroll
-  for (int a = 0; a < 3; ++a) f2[12 + a] = pb + size_t(PB_W + 3 * a + 2) * N;
+    for (int e = 0; e < 2; ++e) {
+      if (xsrc[e] >= 0) {
+        const int face = xsrc[e] >> 1, side = xsrc[e] & 1;
+        const R* r = fx + size_t(side * 3) * fxs + ((size_t(face) * b.nz + zz) * b.ny + cy) * kRec;
+        if (xent[e] == 0) {
+          add_rec(r, t);
+          add_rec(r + 2 * fxs, t);
+        } else {
+          add_rec(r + fxs, t);
+        }
+      }
+      if (ysrc[e] >= 0) {
+        const int face = ysrc[e] >> 1, side = ysrc[e] & 1;
+        const R* r = fy + size_t(side * 3) * fys + ((size_t(face) * b.nz + zz) * b.nx + cx) * kRec;
+        if (yent[e] == 0) {
+          add_rec(r, t);
+          add_rec(r + 2 * fys, t);
+        } else {
+          add_rec(r + fys, t);
+        }
+      }
+    }
+  };
+  const bool faces = xsrc[0] >= 0 || xsrc[1] >= 0 || ysrc[0] >= 0 || ysrc[1] >= 0;
   auto at = [&](int zz) { return size_t(pmod(zz, b.nz)) * plane + col; };
   auto ld1 = [&](int zz, R v[N1]) {
     const size_t k = at(zz);
@@ -309,20 +866,23 @@ __global__ void __launch_bounds__(256) k_pcb_gather_z(Box b, int TZ, const FS* _
     v[7] = R(phi[k]);
   };
   R r2[5][N2], r1[3][N1];
+  // a plane of the radius-2 ring; with FACES the L4 Q and L4 phi adjoints
+  // are K (Gamma (vs V_Q)) and -(k_phi mu_bar), as the local reverse forms them
+  auto ld2 = [&](size_t k, R v[N2]) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const size_t k = at(z0 - 2 + j);
+    for (int f = 0; f < N2; ++f) v[f] = f2[f][k];
+    if constexpr (FACES) {
 #pragma unroll
-    for (int f = 0; f < N2; ++f) r2[j][f] = f2[f][k];
-  }
+      for (int c = 0; c < 5; ++c) v[5 + c] = P.K * (P.Gamma * (vs * v[5 + c]));
+      v[11] = -(P.k_phi * v[11]);
+    }
+  };
+#pragma unroll
+  for (int j = 0; j < 4; ++j) ld2(at(z0 - 2 + j), r2[j]);
   ld1(z0 - 1, r1[0]);
   ld1(z0, r1[1]);
   for (int zc = z0; zc < z1; ++zc) {
-    {
-      const size_t k = at(zc + 2);
-#pragma unroll
-      for (int f = 0; f < N2; ++f) r2[4][f] = f2[f][k];
-    }
+    ld2(at(zc + 2), r2[4]);
     ld1(zc + 1, r1[2]);
     auto d4z = [&](int f) { return -d4c(r2[0][f], r2[1][f], r2[3][f], r2[4][f]); };
     auto l4z = [&](int f) { return l4c(r2[0][f], r2[1][f], r2[3][f], r2[4][f]); };
@@ -330,18 +890,20 @@ __global__ void __launch_bounds__(256) k_pcb_gather_z(Box b, int TZ, const FS* _
     // upwind terms of the z neighbours; donor-cell faces z + 1/2 and z - 1/2
     const R uzp = r1[2][6], uzm = r1[0][6], uz = r1[1][6];
     const R upx = uzp > R(0) ? uzp : R(0), umx = uzm < R(0) ? uzm : R(0);
+    R ft[9] = {R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
+    if (FACES && faces) face_terms(zc, ft);
 #pragma unroll
     for (int k = 0; k < 5; ++k)
-      q_out[k * N + s] += (d4z(k) + l4z(5 + k)) + (r1[2][k] * upx - r1[0][k] * umx);
+      q_out[k * N + s] += ((d4z(k) + l4z(5 + k)) + (r1[2][k] * upx - r1[0][k] * umx)) + ft[k];
     const R fp = R(0.5) * (uz + uzp), fm = R(0.5) * (uzm + uz);
     const R cp = r1[2][5] - r1[1][5], cm = r1[1][5] - r1[0][5];
     const R ph = r1[1][7], php = r1[2][7], phm = r1[0][7];
-    phi_out[s] += (d4z(10) + l4z(11)) + (cp * (fp > R(0) ? fp : R(0)) + cm * (fm < R(0) ? fm : R(0)));
+    phi_out[s] += ((d4z(10) + l4z(11)) + (cp * (fp > R(0) ? fp : R(0)) + cm * (fm < R(0) ? fm : R(0)))) + ft[5];
     const R dfp = (fp >= R(0) ? ph : R(0)) + (fp <= R(0) ? php : R(0));
     const R dfm = (fm >= R(0) ? phm : R(0)) + (fm <= R(0) ? ph : R(0));
-    ub_out[s] += d4z(12);
-    ub_out[N + s] += d4z(13);
-    ub_out[2 * N + s] += d4z(14) + R(0.5) * (cp * dfp + cm * dfm);
+    ub_out[s] += d4z(12) + ft[6];
+    ub_out[N + s] += d4z(13) + ft[7];
+    ub_out[2 * N + s] += (d4z(14) + R(0.5) * (cp * dfp + cm * dfm)) + ft[8];
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll

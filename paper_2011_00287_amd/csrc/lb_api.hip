@@ -172,7 +172,8 @@ void validate_tuning(const lb_params& p, const lb_tuning& t) {
   if (t.step_tile < 0 || t.step_tile > kNStTiles) fail(LB_EINVAL, "step_tile out of range");
   if (t.adj_tile < 0 || t.adj_tile > 2) fail(LB_EINVAL, "adj_tile out of range");
   if (t.adj_order_tile < 0 || t.adj_order_tile > 2) fail(LB_EINVAL, "adj_order_tile out of range");
-  const int32_t tz[] = {t.tz_step, t.tz_lb, t.tz_order, t.tz_pc, t.tz_pcmu, t.tz_adj, t.tz_adj_order};
+  if (t.pc_adj < 0 || t.pc_adj > 1) fail(LB_EINVAL, "pc_adj out of range");
+  const int32_t tz[] = {t.tz_step, t.tz_lb, t.tz_order, t.tz_pc, t.tz_pcmu, t.tz_adj, t.tz_adj_order, t.tz_pc_adj};
   for (int32_t v : tz)
     if (v < 0) fail(LB_EINVAL, "negative slab depth");
 }
@@ -265,6 +266,14 @@ struct BackendT final : Backend {
   R* aupc = nullptr;   // pc4 reverse: u_bar [3][N]
   R* azero = nullptr;  // pc4 reverse: zeros [6][N]
   int gz_tz = 0, gz_blocks = 0;  // pc4 reverse: slab depth and grid of k_pcb_gather_z
+  // pc4 reverse product in one z-march (k_pcb_fused) on kPfTX x 16 tiles, where
+  // every tile along a split axis is at least two sites wide; else the
+  // site-parallel k_pcb_local / k_pcb_v / k_pcb_gather
+  static constexpr int kPfTX = sizeof(R) == 4 ? 32 : 16, kPfTY = 16;
+  bool pf_fused = false;
+  int pf_ntx = 1, pf_nty = 1, pf_tz = 1, pf_blocks = 1;
+  R* apfx = nullptr;  // its face terms along x ([2][3][pf_ntx][nz][ny][kRec])
+  R* apfy = nullptr;  // along y ([2][3][pf_nty][nz][nx][kRec])
   double* apart = nullptr;   // per-block (zeta, q0) adjoint partials, kept across reverse steps
   size_t apart_n = 0;        // doubles in apart
   bool apart_live = false;   // apart holds sums not yet fetched by the caller
@@ -355,6 +364,12 @@ struct BackendT final : Backend {
     // its LDS footprint allows one such workgroup per CU at a time
     if (as_tz == 0) as_tz = auto_slab(as_ntx, as_nty, p.nz, 128, 1, as_ty == 16 ? 1 : 2);
     as_blocks = as_ntx * as_nty * ((p.nz + as_tz - 1) / as_tz);
+    pf_ntx = (p.nx + kPfTX - 1) / kPfTX;
+    pf_nty = (p.ny + kPfTY - 1) / kPfTY;
+    pf_fused = pc4 && t.pc_adj == 0 && (pf_ntx == 1 || p.nx % kPfTX != 1) && (pf_nty == 1 || p.ny % kPfTY != 1);
+    pf_tz = t.tz_pc_adj;
+    if (pf_tz == 0) pf_tz = auto_slab(pf_ntx, pf_nty, p.nz, 16, 1, 1);  // one workgroup per CU fits its LDS
+    pf_blocks = pf_ntx * pf_nty * ((p.nz + pf_tz - 1) / pf_tz);
     size_t need = 2 * (NQ * N * sizeof(GS) + 6 * N * sizeof(FS)) + 4 * N * sizeof(R);
     if (pc4) need += 6 * N * sizeof(FS) + (site_path ? 3 * N * sizeof(R) : 0);
     size_t free_b = 0, total_b = 0;
@@ -418,7 +433,7 @@ struct BackendT final : Backend {
     pcv = nullptr;
     mu = H = sig = u = nullptr;
     partial = sums = mids = nullptr;
-    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &apb, &axs, &aupc, &azero};
+    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &apb, &axs, &aupc, &azero, &apfx, &apfy};
     for (R** a : adj) {
       dfree(*a);
       *a = nullptr;
@@ -854,6 +869,8 @@ struct BackendT final : Backend {
       if (L::kStressInEq) aSb = dalloc<R>(6 * N);  // adjoint of the symmetric stress in the collision
       if (pc4) {
         apb = dalloc<R>(size_t(lbc::NPB) * N);  // per-site scratch of one R'^T V product
+        if (pf_fused && pf_ntx > 1) apfx = dalloc<R>(6 * lbc::kRec * size_t(pf_ntx) * box.nz * box.ny);
+        if (pf_fused && pf_nty > 1) apfy = dalloc<R>(6 * lbc::kRec * size_t(pf_nty) * box.nz * box.nx);
         axs = dalloc<R>(6 * N);                 // X*_bar: q [5][N], phi [N]
         aupc = dalloc<R>(3 * N);                // u_bar of both Heun stages
         azero = dalloc<R>(6 * N);               // zero Q_bar(t+1), mu_bar for the stress kernel
@@ -866,13 +883,14 @@ struct BackendT final : Backend {
       if (!site_path && as_nty > 1) ahy = dalloc<R>(12 * size_t(as_nty) * box.nz * box.nx);
       // one (zeta, q0) pair per block of whichever reverse kernel writes them
       // pc4: the stress kernel's blocks, then those of k_pcb_local
-      const size_t npart = size_t(pc4 ? as_blocks + int(nblk) : std::max<int>(int(nblk), as_blocks)) * 2;
+      const int pc_part = std::max<int>(int(nblk), pf_blocks);  // the pc4 product kernel's blocks
+      const size_t npart = size_t(pc4 ? as_blocks + pc_part : std::max<int>(int(nblk), as_blocks)) * 2;
       apart = dalloc<double>(npart);
       apart_n = npart;
       HIPCHECK(hipMemsetAsync(apart, 0, npart * sizeof(double), stream));
       apart_live = false;
     } catch (...) {
-      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &apb, &axs, &aupc, &azero};
+      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &apb, &axs, &aupc, &azero, &apfx, &apfy};
       for (R** a : adj) {
         dfree(*a);
         *a = nullptr;
@@ -1019,24 +1037,43 @@ struct BackendT final : Backend {
     FS* phs = pcs + 5 * N;
     launch_pc_mu(phi_t, q_t);
     launch_pc_stage<true>(phi_t, q_t, nullptr, nullptr, phs, qs, uu);
-    double* pl = apart + size_t(as_blocks) * 2;  // k_pcb_local's block partials follow the stress kernel's
+    double* pl = apart + size_t(as_blocks) * 2;  // the product kernel's block partials follow the stress kernel's
     R* xsq = axs;
     R* xsp = axs + 5 * N;
-    // X*_bar = X_bar(t+1)/2 + R'(X*)^T (X_bar(t+1)/2)
-    lbc::k_pcb_local<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phs, qs, uu, qi, pi, R(0.5), apb, pl,
-                                                       apart_live ? 1 : 0);
-    lbc::k_pcb_v<R, FS><<<nblk, TPB, 0, stream>>>(box, phs, qs, apb);
-    lbc::k_pcb_gather<R, FS, 2><<<nblk, TPB, 0, stream>>>(box, phs, uu, qi, pi, R(0.5), apb, qi, pi, R(0.5),
-                                                           nullptr, nullptr, R(0), xsq, xsp, aupc, 0);
-    lbc::k_pcb_gather_z<R, FS><<<gz_blocks, 256, 0, stream>>>(box, gz_tz, phs, uu, qi, pi, R(0.5), apb, xsq, xsp,
-                                                               aupc);
-    // X_bar = X_bar(t+1)/2 + X*_bar + R'(X)^T X*_bar
-    lbc::k_pcb_local<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phi_t, q_t, uu, xsq, xsp, R(1), apb, pl, 1);
-    lbc::k_pcb_v<R, FS><<<nblk, TPB, 0, stream>>>(box, phi_t, q_t, apb);
-    lbc::k_pcb_gather<R, FS, 2><<<nblk, TPB, 0, stream>>>(box, phi_t, uu, xsq, xsp, R(1), apb, qi, pi, R(0.5), xsq,
-                                                           xsp, R(1), aqbp, aphibp, aupc, 1);
-    lbc::k_pcb_gather_z<R, FS><<<gz_blocks, 256, 0, stream>>>(box, gz_tz, phi_t, uu, xsq, xsp, R(1), apb, aqbp,
-                                                               aphibp, aupc);
+    if (pf_fused) {
+      R* zf = apb;          // z-stencil adjoints [9][N]
+      R* mb = apb + 9 * N;  // mu_bar of the product
+      auto product = [&](const FS* ph, const FS* qq, const R* vq, const R* vp, R vs, R c2, const R* x2q,
+                         const R* x2p, R* oq, R* op, int acc, int pacc) {
+        lbc::k_pcb_mub<R><<<nblk, TPB, 0, stream>>>(box, P, vp, vs, mb);
+        lbc::k_pcb_fused<R, FS, kPfTX, kPfTY><<<pf_blocks, kPfTX * kPfTY, 0, stream>>>(
+            box, P, pf_tz, pf_ntx, pf_nty, ph, qq, uu, vq, vp, vs, mb, qi, pi, R(0.5), x2q, x2p, c2, oq, op, aupc,
+            acc, zf, apfx, apfy, pl, pacc);
+        lbc::k_pcb_gather_z<R, FS, true><<<gz_blocks, 256, 0, stream>>>(box, P, gz_tz, ph, uu, vq, vp, vs, nullptr,
+                                                                         oq, op, aupc, zf, mb, kPfTX, kPfTY, pf_ntx,
+                                                                         pf_nty, apfx, apfy);
+      };
+      // X*_bar = X_bar(t+1)/2 + R'(X*)^T (X_bar(t+1)/2)
+      product(phs, qs, qi, pi, R(0.5), R(0), nullptr, nullptr, xsq, xsp, 0, apart_live ? 1 : 0);
+      // X_bar = X_bar(t+1)/2 + X*_bar + R'(X)^T X*_bar
+      product(phi_t, q_t, xsq, xsp, R(1), R(1), xsq, xsp, aqbp, aphibp, 1, 1);
+    } else {
+      // X*_bar = X_bar(t+1)/2 + R'(X*)^T (X_bar(t+1)/2)
+      lbc::k_pcb_local<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phs, qs, uu, qi, pi, R(0.5), apb, pl,
+                                                         apart_live ? 1 : 0);
+      lbc::k_pcb_v<R, FS><<<nblk, TPB, 0, stream>>>(box, phs, qs, apb);
+      lbc::k_pcb_gather<R, FS, 2><<<nblk, TPB, 0, stream>>>(box, phs, uu, qi, pi, R(0.5), apb, qi, pi, R(0.5),
+                                                             nullptr, nullptr, R(0), xsq, xsp, aupc, 0);
+      lbc::k_pcb_gather_z<R, FS, false><<<gz_blocks, 256, 0, stream>>>(box, P, gz_tz, phs, uu, qi, pi, R(0.5), apb, xsq, xsp,
+                                                                 aupc, nullptr, nullptr, 0, 0, 1, 1, nullptr, nullptr);
+      // X_bar = X_bar(t+1)/2 + X*_bar + R'(X)^T X*_bar
+      lbc::k_pcb_local<R, FS><<<nblk, TPB, 0, stream>>>(box, P, phi_t, q_t, uu, xsq, xsp, R(1), apb, pl, 1);
+      lbc::k_pcb_v<R, FS><<<nblk, TPB, 0, stream>>>(box, phi_t, q_t, apb);
+      lbc::k_pcb_gather<R, FS, 2><<<nblk, TPB, 0, stream>>>(box, phi_t, uu, xsq, xsp, R(1), apb, qi, pi, R(0.5),
+                                                             xsq, xsp, R(1), aqbp, aphibp, aupc, 1);
+      lbc::k_pcb_gather_z<R, FS, false><<<gz_blocks, 256, 0, stream>>>(box, P, gz_tz, phi_t, uu, xsq, xsp, R(1), apb, aqbp,
+                                                                 aphibp, aupc, nullptr, nullptr, 0, 0, 1, 1, nullptr, nullptr);
+    }
     lbc::UbarIn<R> ubin{nullptr, aupc, 1};
     if (Bt)
       lbc::k_adj_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, Bt, FF, ubin, gi, go, aFb, aSb);
@@ -1054,7 +1091,8 @@ struct BackendT final : Backend {
     R* go = static_cast<R*>(adj_out);
     R* qo = go + NQ * N;
     R* po = go + (NQ + 5) * N;
-    const int npart_blocks = site_path ? int(nblk) : (pc4 ? as_blocks + int(nblk) : as_blocks);
+    const int npart_blocks =
+        site_path ? int(nblk) : (pc4 ? as_blocks + std::max<int>(int(nblk), pf_blocks) : as_blocks);
     if (size_t(npart_blocks) * 2 > apart_n) fail(LB_EDEVICE, "adjoint partial buffer smaller than the grid");
     if (pc4) {
       reverse_pc4(phi_t, q_t, uu, FF, Bt, drho, gi, qi, pi, go, qo, po);

@@ -67,8 +67,8 @@ def _inputs(shape, nq, seed):
     return g, phi, q5, ab
 
 
-def _gpu_vjp(p, g, phi, q5, ab, precision, lattice, record):
-    with Sim(p, phi, q5, precision=precision, lattice=lattice, fd_scheme="pc4") as sim:
+def _gpu_vjp(p, g, phi, q5, ab, precision, lattice, record, tuning=None):
+    with Sim(p, phi, q5, precision=precision, lattice=lattice, fd_scheme="pc4", tuning=tuning) as sim:
         sim.set_fields(g=g)
         state = sim.get_state()
         adj = sim.adjoint_buffer()
@@ -117,6 +117,36 @@ def test_d3q15_pc4_single_step_vjp_matches_oracle(record):
     g, phi, q5, ab = _inputs((9, 7, 6), 15, seed=63)
     ref = _oracle_vjp(_step15_pc4, p, g, q5, phi, ab)
     _check(_gpu_vjp(p, g, phi, q5, ab, "fp64", "d3q15", record), ref, 1e-10, 1e-10)
+
+
+# Boxes whose tiles exercise the one-kernel product of the reverse (tiles of
+# 32 x 16 in float, 16 x 16 in double): several tiles along both in-plane
+# axes, ragged last tiles two and more sites wide (the terms owed across a
+# tile face reach two sites), a lone tile along one axis wrapping inside itself.
+FUSED_SHAPES = [(70, 20, 9), (36, 18, 7), (34, 10, 6), (18, 12, 5), (40, 6, 7), (20, 40, 5)]
+
+
+@pytest.mark.parametrize("shape", FUSED_SHAPES)
+def test_pc4_fused_product_vjp_matches_oracle(shape):
+    p = _p(q0=2 * math.pi / 7, zeta=0.01)
+    g, phi, q5, ab = _inputs(shape, 19, seed=91 + shape[0] + shape[1])
+    ref = _oracle_vjp(pc4.step, p, g, q5, phi, ab)
+    _check(_gpu_vjp(p, g, phi, q5, ab, "fp64", "d3q19", True), ref, 1e-10, 1e-10)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", FUSED_SHAPES + [(33, 9, 5), (34, 17, 6)])
+def test_pc4_fused_product_equals_site_parallel_product(shape, prec):
+    """pc_adj = 0 (one z-marching kernel per Heun product where the tiling
+    allows it) against pc_adj = 1 (the site-parallel kernels); (33, 9, 5) and
+    (34, 17, 6) leave a one-column or one-row edge tile, where both settings
+    run the site-parallel kernels."""
+    p = _p(q0=2 * math.pi / 7, zeta=0.01)
+    g, phi, q5, ab = _inputs(shape, 19, seed=17 + shape[0])
+    a = _gpu_vjp(p, g, phi, q5, ab, prec, "d3q19", True, tuning={"pc_adj": 0})
+    b = _gpu_vjp(p, g, phi, q5, ab, prec, "d3q19", True, tuning={"pc_adj": 1})
+    tol = 1e-13 if prec == "fp64" else 2e-5
+    _check(a, b, tol, tol)
 
 
 def test_pc4_single_step_vjp_fp32():
