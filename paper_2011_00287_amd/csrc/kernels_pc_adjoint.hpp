@@ -299,41 +299,12 @@ __device__ __forceinline__ R d4w(int d) {
   return d == 1 ? R(-8.0 / 12.0) : d == -1 ? R(8.0 / 12.0) : d == 2 ? R(1.0 / 12.0) : R(-1.0 / 12.0);
 }
 
-// A face record: the 9 output fields of one owed term, padded to 12 values
-// so that it moves as three 16-byte (float) or six 16-byte (double) accesses.
-constexpr int kRec = 12;
-template <class R>
-__device__ __forceinline__ void st_rec(R* __restrict__ p, const R v[9]) {
-  if constexpr (sizeof(R) == 4) {
-    float4* q = reinterpret_cast<float4*>(p);
-    q[0] = make_float4(v[0], v[1], v[2], v[3]);
-    q[1] = make_float4(v[4], v[5], v[6], v[7]);
-    q[2] = make_float4(v[8], 0.0f, 0.0f, 0.0f);
-  } else {
-    double2* q = reinterpret_cast<double2*>(p);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) q[i] = make_double2(v[2 * i], v[2 * i + 1]);
-    q[4] = make_double2(v[8], 0.0);
-  }
-}
-template <class R>
-__device__ __forceinline__ void add_rec(const R* __restrict__ p, R t[9]) {
-  if constexpr (sizeof(R) == 4) {
-    const float4* q = reinterpret_cast<const float4*>(p);
-    const float4 a = q[0], c = q[1], d = q[2];
-    t[0] += a.x; t[1] += a.y; t[2] += a.z; t[3] += a.w;
-    t[4] += c.x; t[5] += c.y; t[6] += c.z; t[7] += c.w;
-    t[8] += d.x;
-  } else {
-    const double2* q = reinterpret_cast<const double2*>(p);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const double2 a = q[i];
-      t[2 * i] += a.x;
-      t[2 * i + 1] += a.y;
-    }
-    t[8] += q[4].x;
-  }
+// One 32-bit value per lane from global memory straight into LDS
+// (global_load_lds_dword): lane i of the wave writes lds_wave[i].  The data
+// is visible to the workgroup after s_waitcnt and a barrier.
+__device__ __forceinline__ void g2lds(const float* src, float* lds_wave) {
+  __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)(src),
+                                   (__attribute__((address_space(3))) void*)(lds_wave), 4, 0, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -359,14 +330,13 @@ __device__ __forceinline__ void add_rec(const R* __restrict__ p, R t[9]) {
 //     mu_bar itself;
 //   * the terms a site owes the two columns (rows) across a tile face: the
 //     last two columns of tile j send to the first two of tile j+1 and back.
-//     Per output field (q[5], phi, u[3]) and face, side 0 holds what tile j
-//     sends in the + direction, side 1 what tile j+1 sends in the -
-//     direction; entry 0 is the edge site's term for the first site across,
-//     entry 1 its term for the second, entry 2 the second-to-edge site's term
-//     for the first.  A record holds the 9 output fields of one entry:
-//     fx[((((side 3 + entry) ntx + j) nz + z) ny + y) kRec + f], fy likewise
-//     over (nty, z, x).  Every tile along a split axis is at least two sites wide
-//     (checked by the caller).
+//     The edge column sends, per output field (q[5], phi, u[3]), the whole
+//     term of the first site across (its own part and its inner neighbour's,
+//     read from LDS; pos 0) and of the second (pos 1); side 0 holds what
+//     tile j sends in the + direction across face j, side 1 what tile j+1
+//     sends in the - direction: fx[((((f 2 + side) 2 + pos) ntx + j) nz + z)
+//     ny + y], fy likewise over (nty, z, x).  Every tile along a split axis
+//     is at least two sites wide (checked by the caller).
 // partial: one float64 (zeta, q0) pair per block, overwritten (pacc = 0) or
 // added to (pacc = 1).
 // ---------------------------------------------------------------------------
@@ -390,6 +360,15 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
   __shared__ R sV[NV][NS];
   __shared__ R sX[NXF][NT];
   __shared__ int sGX[SX], sGY[SY];
+  // float: the next plane's V and halo, and this plane's inputs of the Heun
+  // combination, go from global memory to LDS staging buffers while the local
+  // reverse runs (global_load_lds, no registers); double loads them where used
+  constexpr bool kStage = sizeof(R) == 4;
+  constexpr int NHP = (NH + 63) / 64 * 64;  // whole waves of halo slots
+  constexpr int NO = 15;                    // xq1[5], xp1, xsq[5], xsp, ub_out[3]
+  __shared__ R sStV[kStage ? 6 : 1][kStage ? NT : 1];
+  __shared__ R sStH[kStage ? NV : 1][kStage ? NHP : 1];
+  __shared__ R sStO[kStage ? NO : 1][kStage ? NT : 1];
 
   const int l = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = l % ntx, ty = (l / ntx) % nty, sl = l / (ntx * nty);
@@ -479,28 +458,83 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
     if (nty == 1) return wrap2(t, h) * TX + lx;
     return (t >= 0 && t < h) ? t * TX + lx : -1;
   };
-  const size_t fxs = size_t(ntx) * b.nz * b.ny * kRec, fys = size_t(nty) * b.nz * b.nx * kRec;  // one (side, entry) block
+  const size_t fxs = size_t(ntx) * b.nz * b.ny, fys = size_t(nty) * b.nz * b.nx;  // one (field, side, pos) block
   const int kxm = (tx + ntx - 1) % ntx, kym = (ty + nty - 1) % nty;
 
   const int sc = (ly + HR) * SX + (lx + HR);
+  const int wb = (tid >> 6) << 6;  // first thread of this wave
+  // staging (float): V and the halo of plane zz; the combination inputs of plane zz
+  auto stage_vh = [&](int zz) {
+    if constexpr (kStage) {
+      const uint32_t k = uint32_t(zz) * uint32_t(plane) + uint32_t(col);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) g2lds(reinterpret_cast<const float*>(vq + c * N) + k, reinterpret_cast<float*>(&sStV[c][wb]));
+      g2lds(reinterpret_cast<const float*>(vphi) + k, reinterpret_cast<float*>(&sStV[5][wb]));
+      if (has_halo) {
+        const uint32_t kh = uint32_t(zz) * uint32_t(plane) + uint32_t(hcol);
+        const float* src[NV] = {};
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          src[c] = reinterpret_cast<const float*>(q + c * N);
+          src[10 + c] = reinterpret_cast<const float*>(vq + c * N);
+        }
+        src[5] = reinterpret_cast<const float*>(phi);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) src[6 + a] = reinterpret_cast<const float*>(u + a * N);
+        src[9] = reinterpret_cast<const float*>(mub);
+        src[15] = reinterpret_cast<const float*>(vphi);
+#pragma unroll
+        for (int c = 0; c < NV; ++c) g2lds(src[c] + kh, reinterpret_cast<float*>(&sStH[c][wb]));
+      }
+    }
+  };
+  auto stage_o = [&](int zz) {
+    if constexpr (kStage) {
+      const uint32_t k = uint32_t(zz) * uint32_t(plane) + uint32_t(col);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) g2lds(reinterpret_cast<const float*>(xq1 + c * N) + k, reinterpret_cast<float*>(&sStO[c][wb]));
+      g2lds(reinterpret_cast<const float*>(xp1) + k, reinterpret_cast<float*>(&sStO[5][wb]));
+      if (xsq) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) g2lds(reinterpret_cast<const float*>(xsq + c * N) + k, reinterpret_cast<float*>(&sStO[6 + c][wb]));
+        g2lds(reinterpret_cast<const float*>(xsp) + k, reinterpret_cast<float*>(&sStO[11][wb]));
+      }
+      if (accumulate) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g2lds(reinterpret_cast<const float*>(ub_out + a * N) + k, reinterpret_cast<float*>(&sStO[12 + a][wb]));
+      }
+    }
+  };
+  stage_vh(z0);
   double v2[2] = {0.0, 0.0};
   for (int zc = z0; zc < z1; ++zc) {
-    __syncthreads();  // the previous plane's reads are done
+    if constexpr (kStage) __builtin_amdgcn_s_waitcnt(0);  // this thread's staging loads have landed
+    __syncthreads();  // the previous plane's reads are done; the staged V and halo are in place
 #pragma unroll
     for (int c = 0; c < NZ; ++c) sV[c][sc] = zr[2][c];
-    {  // V of the owned site
-      R vv[6];
+    if constexpr (kStage) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sV[NZ + c][sc] = sStV[c][tid];
+      if (has_halo) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) sV[c][hs] = sStH[c][tid];
+      }
+    } else {
+      R vv[6];  // V of the owned site
       load_v(uint32_t(zc) * uint32_t(plane) + uint32_t(col), vv);
 #pragma unroll
       for (int c = 0; c < 6; ++c) sV[NZ + c][sc] = vv[c];
-    }
-    if (has_halo) {  // the halo of this plane (loads carried across the plane would exceed the registers)
-      R hv[NV];
-      load_all(zc, hv);
+      if (has_halo) {  // the halo of this plane
+        R hv[NV];
+        load_all(zc, hv);
 #pragma unroll
-      for (int c = 0; c < NV; ++c) sV[c][hs] = hv[c];
+        for (int c = 0; c < NV; ++c) sV[c][hs] = hv[c];
+      }
     }
     __syncthreads();
+    // in flight during the local reverse: the combination inputs of this plane, V and halo of the next
+    stage_o(zc);
+    if (zc + 1 < z1) stage_vh(zc + 1);
     // ---- local reverse at the own site
     R qbl[5], pbl = R(0), ubl[3] = {R(0), R(0), R(0)};
     if (active) {
@@ -608,7 +642,8 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
 #pragma unroll
       for (int a = 0; a < 3; ++a) sto(zf + (6 + a) * N, so, Wb[a][2]);
     }
-    __syncthreads();  // the stencil-data adjoints of the tile are in place
+    if constexpr (kStage) __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();  // the stencil-data adjoints of the tile (and the staged inputs) are in place
     if (active) {
       const uint32_t so = (uint32_t(zc) * uint32_t(plane) + uint32_t(col)) * SR;
       const int dd[4] = {-2, -1, 1, 2};
@@ -662,83 +697,83 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
         const R dfm = (fm >= R(0) ? phm : R(0)) + (fm <= R(0) ? ph : R(0));
         ub[g] += R(0.5) * (cp * dfp + cm * dfm);
       }
+      // the combination inputs of this site: staged (float) or loaded
+      auto in_o = [&](int c, const R* base) { return kStage ? sStO[c][tid] : ldo(base, so); };
 #pragma unroll
       for (int k = 0; k < 5; ++k) {
-        R r = c1 * ldo(xq1 + k * N, so) + qo[k];
-        if (xsq) r += c2 * ldo(xsq + k * N, so);
+        R r = c1 * in_o(k, xq1 + k * N) + qo[k];
+        if (xsq) r += c2 * in_o(6 + k, xsq + k * N);
         sto(q_out + k * N, so, r);
       }
       {
-        R r = c1 * ldo(xp1, so) + po;
-        if (xsp) r += c2 * ldo(xsp, so);
+        R r = c1 * in_o(5, xp1) + po;
+        if (xsp) r += c2 * in_o(11, xsp);
         sto(phi_out, so, r);
       }
 #pragma unroll
-      for (int a = 0; a < 3; ++a) sto(ub_out + a * N, so, accumulate ? ldo(ub_out + a * N, so) + ub[a] : ub[a]);
+      for (int a = 0; a < 3; ++a) sto(ub_out + a * N, so, accumulate ? in_o(12 + a, ub_out + a * N) + ub[a] : ub[a]);
       // the terms owed across a tile face: output fields q[5], phi, u[3] of
       // the site at offset d from this one
-      auto owed = [&](int g, int d, R o[9]) {
-        const R lw = l4w<R>(-d), dw = d4w<R>(-d);  // this site is at offset -d from the receiver
+      // the terms owed across a tile face, per output field q[5], phi, u[3]:
+      // the edge site sends, for the first site across, its own term and that
+      // of its inner neighbour (read from LDS), and its own for the second
+      auto owed = [&](int t, int g, int d, R o[9], bool add) {
+        const R lw = l4w<R>(-d), dw = d4w<R>(-d);  // the sender is at offset -d from the receiver
 #pragma unroll
-        for (int k = 0; k < 5; ++k) o[k] = sX[XL + k][tid] * lw + sX[XDQ + 5 * g + k][tid] * dw;
-        o[5] = sX[XLP][tid] * lw + sX[XDP + g][tid] * dw;
+        for (int k = 0; k < 5; ++k) {
+          const R v = sX[XL + k][t] * lw + sX[XDQ + 5 * g + k][t] * dw;
+          o[k] = add ? o[k] + v : v;
+        }
+        const R v5 = sX[XLP][t] * lw + sX[XDP + g][t] * dw;
+        o[5] = add ? o[5] + v5 : v5;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) o[6 + a] = sX[XW + 3 * g + a][tid] * dw;
+        for (int a = 0; a < 3; ++a) {
+          const R v = sX[XW + 3 * g + a][t] * dw;
+          o[6 + a] = add ? o[6 + a] + v : v;
+        }
       };
-      auto put = [&](R* buf, size_t fs, int side, int entry, size_t off, const R o[9]) {
-        st_rec(buf + size_t(side * 3 + entry) * fs + off * kRec, o);
+      auto put = [&](R* buf, size_t fs, int side, int pos, size_t off, const R o[9]) {
+#pragma unroll
+        for (int f = 0; f < 9; ++f) buf[size_t((f * 2 + side) * 2 + pos) * fs + off] = o[f];
       };
-      const int pz = zc;
       if (ntx > 1) {
         const int gy = sGY[ly + HR];
         R o[9];
         if (lx == w - 1) {  // to the first two columns of tile tx + 1
-          const size_t off = (size_t(tx) * b.nz + pz) * b.ny + gy;
-          owed(0, 1, o);
+          const size_t off = (size_t(tx) * b.nz + zc) * b.ny + gy;
+          owed(tid, 0, 1, o, false);
+          owed(tid - 1, 0, 2, o, true);
           put(fx, fxs, 0, 0, off, o);
-          owed(0, 2, o);
+          owed(tid, 0, 2, o, false);
           put(fx, fxs, 0, 1, off, o);
         }
-        if (lx == w - 2) {
-          owed(0, 2, o);
-          put(fx, fxs, 0, 2, (size_t(tx) * b.nz + pz) * b.ny + gy, o);
-        }
         if (lx == 0) {  // to the last two columns of tile tx - 1
-          const size_t off = (size_t(kxm) * b.nz + pz) * b.ny + gy;
-          owed(0, -1, o);
+          const size_t off = (size_t(kxm) * b.nz + zc) * b.ny + gy;
+          owed(tid, 0, -1, o, false);
+          owed(tid + 1, 0, -2, o, true);
           put(fx, fxs, 1, 0, off, o);
-          owed(0, -2, o);
+          owed(tid, 0, -2, o, false);
           put(fx, fxs, 1, 1, off, o);
-        }
-        if (lx == 1) {
-          owed(0, -2, o);
-          put(fx, fxs, 1, 2, (size_t(kxm) * b.nz + pz) * b.ny + gy, o);
         }
       }
       if (nty > 1) {
         const int gx = sGX[lx + HR];
         R o[9];
-        if (ly == h - 1) {
-          const size_t off = (size_t(ty) * b.nz + pz) * b.nx + gx;
-          owed(1, 1, o);
+        if (ly == h - 1) {  // to the first two rows of tile ty + 1
+          const size_t off = (size_t(ty) * b.nz + zc) * b.nx + gx;
+          owed(tid, 1, 1, o, false);
+          owed(tid - TX, 1, 2, o, true);
           put(fy, fys, 0, 0, off, o);
-          owed(1, 2, o);
+          owed(tid, 1, 2, o, false);
           put(fy, fys, 0, 1, off, o);
         }
-        if (ly == h - 2) {
-          owed(1, 2, o);
-          put(fy, fys, 0, 2, (size_t(ty) * b.nz + pz) * b.nx + gx, o);
-        }
-        if (ly == 0) {
-          const size_t off = (size_t(kym) * b.nz + pz) * b.nx + gx;
-          owed(1, -1, o);
+        if (ly == 0) {  // to the last two rows of tile ty - 1
+          const size_t off = (size_t(kym) * b.nz + zc) * b.nx + gx;
+          owed(tid, 1, -1, o, false);
+          owed(tid + TX, 1, -2, o, true);
           put(fy, fys, 1, 0, off, o);
-          owed(1, -2, o);
+          owed(tid, 1, -2, o, false);
           put(fy, fys, 1, 1, off, o);
-        }
-        if (ly == 1) {
-          owed(1, -2, o);
-          put(fy, fys, 1, 2, (size_t(kym) * b.nz + pz) * b.nx + gx, o);
         }
       }
     }
@@ -800,58 +835,36 @@ k_pcb_gather_z(Box b, Params<R> P, int TZ, const FS* __restrict__ phi,
 #pragma unroll
     for (int a = 0; a < 3; ++a) f2[12 + a] = pb + size_t(PB_W + 3 * a + 2) * N;
   }
-  // face terms of this column (k_pcb_fused): per axis, up to two (face,
-  // side, entries) sources; the entry sums are formed per plane below
+  // face terms of this column (k_pcb_fused): up to one source per side and
+  // axis, each a (face, side, pos) block of fx or fy
   const int cx = col % b.nx, cy = col / b.nx;
-  int xsrc[2] = {-1, -1}, xent[2] = {0, 0}, ysrc[2] = {-1, -1}, yent[2] = {0, 0};
-  // entries: 0 -> entry 0 + entry 2 (the first site across), 1 -> entry 1 (the second)
+  int xsrc[2] = {-1, -1}, ysrc[2] = {-1, -1};  // ((face 2 + side) 2 + pos)
   if (FACES && ntx > 1) {
     const int j = cx / TX, lx = cx - j * TX, wj = min(TX, b.nx - j * TX);
-    if (lx < 2) {  // sent by tile j - 1 in the + direction (side 0) across face j - 1
-      xsrc[0] = ((j + ntx - 1) % ntx) * 2 + 0;
-      xent[0] = lx;
-    }
-    if (lx >= wj - 2) {  // sent by tile j + 1 in the - direction (side 1) across face j
-      xsrc[1] = j * 2 + 1;
-      xent[1] = wj - 1 - lx;
-    }
+    if (lx < 2) xsrc[0] = ((((j + ntx - 1) % ntx) * 2 + 0) * 2) + lx;  // sent by tile j - 1 across face j - 1
+    if (lx >= wj - 2) xsrc[1] = ((j * 2 + 1) * 2) + (wj - 1 - lx);     // sent by tile j + 1 across face j
   }
   if (FACES && nty > 1) {
     const int i = cy / TY, ly = cy - i * TY, hi = min(TY, b.ny - i * TY);
-    if (ly < 2) {
-      ysrc[0] = ((i + nty - 1) % nty) * 2 + 0;
-      yent[0] = ly;
-    }
-    if (ly >= hi - 2) {
-      ysrc[1] = i * 2 + 1;
-      yent[1] = hi - 1 - ly;
-    }
+    if (ly < 2) ysrc[0] = ((((i + nty - 1) % nty) * 2 + 0) * 2) + ly;
+    if (ly >= hi - 2) ysrc[1] = ((i * 2 + 1) * 2) + (hi - 1 - ly);
   }
-  // records of the 9 output fields: entry stride fxs (fys), one record per (face, z, line)
-  const size_t fxs = size_t(ntx) * b.nz * b.ny * kRec, fys = size_t(nty) * b.nz * b.nx * kRec;
+  const size_t fxs = size_t(ntx) * b.nz * b.ny, fys = size_t(nty) * b.nz * b.nx;
   // the owed terms of the 9 output fields at plane zz, added to t
   auto face_terms = [&](int zz, R t[9]) {
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       if (xsrc[e] >= 0) {
-        const int face = xsrc[e] >> 1, side = xsrc[e] & 1;
-        const R* r = fx + size_t(side * 3) * fxs + ((size_t(face) * b.nz + zz) * b.ny + cy) * kRec;
-        if (xent[e] == 0) {
-          add_rec(r, t);
-          add_rec(r + 2 * fxs, t);
-        } else {
-          add_rec(r + fxs, t);
-        }
+        const int face = xsrc[e] >> 2, sp = xsrc[e] & 3;  // sp = side 2 + pos
+        const R* r = fx + size_t(sp) * fxs + (size_t(face) * b.nz + zz) * b.ny + cy;
+#pragma unroll
+        for (int f = 0; f < 9; ++f) t[f] += r[size_t(4 * f) * fxs];
       }
       if (ysrc[e] >= 0) {
-        const int face = ysrc[e] >> 1, side = ysrc[e] & 1;
-        const R* r = fy + size_t(side * 3) * fys + ((size_t(face) * b.nz + zz) * b.nx + cx) * kRec;
-        if (yent[e] == 0) {
-          add_rec(r, t);
-          add_rec(r + 2 * fys, t);
-        } else {
-          add_rec(r + fys, t);
-        }
+        const int face = ysrc[e] >> 2, sp = ysrc[e] & 3;
+        const R* r = fy + size_t(sp) * fys + (size_t(face) * b.nz + zz) * b.nx + cx;
+#pragma unroll
+        for (int f = 0; f < 9; ++f) t[f] += r[size_t(4 * f) * fys];
       }
     }
   };
