@@ -275,7 +275,9 @@ size_t lb_adjoint_bytes(const lb_ctx* c);
 
 /* Size of a step record: u [3][N], F [3][N] and drho [N] (the velocity with
  * F/2, the force of Eq. (3) and rho - rho0 = sum g) of one time t, in the
- * context's arithmetic type. */
+ * context's arithmetic type; with LB_FD_PC4 followed by the predictor stage
+ * X* = (Q* [5][N], phi* [N]) of that step in the storage type, which the
+ * reverse of the step then reads instead of recomputing it. */
 size_t lb_record_bytes(const lb_ctx* c);
 
 /* One forward step from the state buffer dev_state_in (time t, lb_get_state
@@ -308,8 +310,9 @@ lb_status lb_adjoint_step(lb_ctx* c, const void* dev_state_t, size_t state_bytes
 
 /* Size of a lean step record: Q [5][N] and phi [N] of time t in the storage
  * type, then drho [N] (the sum of the population deviations), u [3][N] and
- * F [3][N] of the step from t, in the arithmetic type; each part starts on a
- * 256-byte boundary (about 52 B per site in float32).  The populations enter
+ * F [3][N] of the step from t, in the arithmetic type, and with LB_FD_PC4 the
+ * predictor stage Q* [5][N], phi* [N] (storage type); each part starts on a
+ * 256-byte boundary (about 52 B per site in float32, 76 B with LB_FD_PC4).  The populations enter
  * the collision only through drho and u, so a lean record holds everything
  * the reverse of its step reads: a reverse sweep over lean records needs no
  * state buffers and no replay. */

@@ -648,6 +648,8 @@ struct BackendT final : Backend {
     R* drho;
     const int64_t* step_in = nullptr;  // step counters of a recording step's states
     int64_t* step_out = nullptr;
+    FS* xs_q = nullptr;  // pc4 recording step: the predictor's X* goes here (record) instead of pcs
+    FS* xs_phi = nullptr;
   };
   Io cur_io() { return Io{B[cur], B[cur ^ 1], Ph[cur], Q[cur], Ph[cur ^ 1], Q[cur ^ 1], u, nullptr, nullptr}; }
   void launch_lb_tile(const Io& io) {
@@ -686,8 +688,8 @@ struct BackendT final : Backend {
   // the fused pair on explicit buffers
   // the whole Heun update of one step on the buffers of io (z-marching kernels)
   void pc_update(const Io& io) {
-    FS* qs = pcs;
-    FS* phs = pcs + 5 * N;
+    FS* qs = io.xs_q ? io.xs_q : pcs;
+    FS* phs = io.xs_phi ? io.xs_phi : pcs + 5 * N;
     launch_pc_mu(io.phi_i, io.q_i);
     launch_pc_stage<true>(io.phi_i, io.q_i, nullptr, nullptr, phs, qs, io.u);
     launch_pc_mu(phs, qs);
@@ -902,7 +904,15 @@ struct BackendT final : Backend {
   }
   // record buffer: u [3][N] and F [3][N] of the step that leaves the state
   // step record: u [3][N], F [3][N] and drho [N] of the step that leaves the state
-  size_t record_bytes() const override { return has_adjoint() ? 7 * N * sizeof(R) : 0; }
+  // pc4: then the predictor's X* = (Q* [5][N], phi* [N]) in the storage type, which the
+  // reverse of the step reads instead of recomputing the predictor
+  size_t record_bytes() const override {
+    return has_adjoint() ? 7 * N * sizeof(R) + (pc4 ? 6 * N * sizeof(FS) : 0) : 0;
+  }
+  FS* rec_xs(void* rec) const { return pc4 ? reinterpret_cast<FS*>(static_cast<char*>(rec) + 7 * N * sizeof(R)) : nullptr; }
+  const FS* rec_xs(const void* rec) const {
+    return pc4 ? reinterpret_cast<const FS*>(static_cast<const char*>(rec) + 7 * N * sizeof(R)) : nullptr;
+  }
   struct StateView {
     const GS* B;
     const FS* q;
@@ -922,8 +932,9 @@ struct BackendT final : Backend {
     R* ru = static_cast<R*>(rec_out);
     R* rF = ru + 3 * N;
     R* rd = ru + 6 * N;
+    FS* xs = rec_xs(rec_out);
     if (!state_out) {  // the record only
-      record_only(vi, ru, rF, rd);
+      record_only(vi, ru, rF, rd, xs);
       check_launch();
       return;
     }
@@ -940,14 +951,14 @@ struct BackendT final : Backend {
       lbc::k_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, vi.phi, vi.q, ru, H, mu, po, qo);
       lbc::k_step_count<<<1, 64, 0, stream>>>(vi.step, step_out);
     } else {
-      fused_step(Io{vi.B, Bo, vi.phi, vi.q, po, qo, ru, rF, rd, vi.step, step_out});  // k_lb_fused counts
+      fused_step(Io{vi.B, Bo, vi.phi, vi.q, po, qo, ru, rF, rd, vi.step, step_out, xs, xs ? xs + 5 * N : nullptr});
     }
     check_launch();
   }
   // u, F and drho of the state at vi without forming the next state: the
   // site path's force kernel, or the stress + collision kernel with no
   // population output and no order-parameter update
-  void record_only(const StateView& vi, R* ru, R* rF, R* rd) {
+  void record_only(const StateView& vi, R* ru, R* rF, R* rd, FS* xs = nullptr) {
     if (site_path) {
       ensure_thermo();
       lbc::k_thermo<R, FS><<<nblk, TPB, 0, stream>>>(box, P, vi.phi, vi.q, mu, H, sig);
@@ -956,6 +967,10 @@ struct BackendT final : Backend {
       launch_step1(Io{vi.B, nullptr, vi.phi, vi.q, nullptr, nullptr, ru, rF, rd});
     } else {
       launch_lb_tile(Io{vi.B, nullptr, vi.phi, vi.q, nullptr, nullptr, ru, rF, rd});
+      if (xs) {  // pc4: the predictor stage of the step (its X* is what the reverse reads)
+        launch_pc_mu(vi.phi, vi.q);
+        launch_pc_stage<true>(vi.phi, vi.q, nullptr, nullptr, xs + 5 * N, xs, ru);
+      }
     }
   }
   // lean step record: Q [5][N], phi [N] (storage type) of time t, then drho,
@@ -964,7 +979,10 @@ struct BackendT final : Backend {
   size_t lr_drho() const { return lr_phi() + align256(N * sizeof(FS)); }
   size_t lr_u() const { return lr_drho() + align256(N * sizeof(R)); }
   size_t lr_F() const { return lr_u() + align256(3 * N * sizeof(R)); }
-  size_t lean_record_bytes() const override { return has_adjoint() ? lr_F() + align256(3 * N * sizeof(R)) : 0; }
+  size_t lr_xs() const { return lr_F() + align256(3 * N * sizeof(R)); }  // pc4: Q* [5][N], then phi* [N]
+  size_t lean_record_bytes() const override {
+    return has_adjoint() ? lr_xs() + (pc4 ? align256(5 * N * sizeof(FS)) + align256(N * sizeof(FS)) : 0) : 0;
+  }
   // Record time t into a lean record and advance the context's state by one step.
   void step_record_lean(void* rec_out) override {
     need_adjoint();
@@ -982,7 +1000,9 @@ struct BackendT final : Backend {
       lbc::k_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, B[cur], B[nx], sig, ru);
       lbc::k_order<R, FS><<<nblk, TPB, 0, stream>>>(box, P, Ph[cur], Q[cur], ru, H, mu, Ph[nx], Q[nx]);
     } else {
-      fused_step(Io{B[cur], B[nx], Ph[cur], Q[cur], Ph[nx], Q[nx], ru, rF, rd});
+      FS* xq = pc4 ? reinterpret_cast<FS*>(c + lr_xs()) : nullptr;
+      FS* xp = pc4 ? reinterpret_cast<FS*>(c + lr_xs() + align256(5 * N * sizeof(FS))) : nullptr;
+      fused_step(Io{B[cur], B[nx], Ph[cur], Q[cur], Ph[nx], Q[nx], ru, rF, rd, nullptr, nullptr, xq, xp});
     }
     cur = nx;
     check_launch();
@@ -997,7 +1017,9 @@ struct BackendT final : Backend {
     const R* rd = reinterpret_cast<const R*>(c + lr_drho());
     const R* ru = reinterpret_cast<const R*>(c + lr_u());
     const R* rF = reinterpret_cast<const R*>(c + lr_F());
-    reverse_kernels(rphi, rq, ru, rF, nullptr, rd, adj_in, adj_out, zeta_bar, q0_bar);
+    const FS* xq = pc4 ? reinterpret_cast<const FS*>(c + lr_xs()) : nullptr;
+    const FS* xp = pc4 ? reinterpret_cast<const FS*>(c + lr_xs() + align256(5 * N * sizeof(FS))) : nullptr;
+    reverse_kernels(rphi, rq, ru, rF, nullptr, rd, adj_in, adj_out, zeta_bar, q0_bar, xq, xp);
   }
   // the fused stress + gather adjoint and its tile-face terms; aq: Q_bar(t+1)
   // for the Euler update's H_bar (zeros under pc4), mb: mu_bar
@@ -1032,11 +1054,15 @@ struct BackendT final : Backend {
   // the stress reverses (the stress kernel without the Euler update's H_bar
   // and mu_bar, which pc4 does not use).
   void reverse_pc4(const FS* phi_t, const FS* q_t, const R* uu, const R* FF, const GS* Bt, const R* drho,
-                   const R* gi, const R* qi, const R* pi, R* go, R* qo, R* po) {
-    FS* qs = pcs;
-    FS* phs = pcs + 5 * N;
-    launch_pc_mu(phi_t, q_t);
-    launch_pc_stage<true>(phi_t, q_t, nullptr, nullptr, phs, qs, uu);
+                   const R* gi, const R* qi, const R* pi, R* go, R* qo, R* po, const FS* xs_q, const FS* xs_phi) {
+    const FS* qs = xs_q;
+    const FS* phs = xs_phi;
+    if (!qs) {  // no recorded X*: replay the predictor
+      launch_pc_mu(phi_t, q_t);
+      launch_pc_stage<true>(phi_t, q_t, nullptr, nullptr, pcs + 5 * N, pcs, uu);
+      qs = pcs;
+      phs = pcs + 5 * N;
+    }
     double* pl = apart + size_t(as_blocks) * 2;  // the product kernel's block partials follow the stress kernel's
     R* xsq = axs;
     R* xsp = axs + 5 * N;
@@ -1084,7 +1110,8 @@ struct BackendT final : Backend {
   // the reverse kernels of one step; the collision adjoint reads the
   // populations B, or (B == nullptr) the recorded density deviation drho
   void reverse_kernels(const FS* phi_t, const FS* q_t, const R* uu, const R* FF, const GS* Bt, const R* drho,
-                       const void* adj_in, void* adj_out, double* zeta_bar, double* q0_bar) {
+                       const void* adj_in, void* adj_out, double* zeta_bar, double* q0_bar,
+                       const FS* xs_q = nullptr, const FS* xs_phi = nullptr) {
     const R* gi = static_cast<const R*>(adj_in);
     const R* qi = gi + NQ * N;
     const R* pi = gi + (NQ + 5) * N;
@@ -1095,7 +1122,7 @@ struct BackendT final : Backend {
         site_path ? int(nblk) : (pc4 ? as_blocks + std::max<int>(int(nblk), pf_blocks) : as_blocks);
     if (size_t(npart_blocks) * 2 > apart_n) fail(LB_EDEVICE, "adjoint partial buffer smaller than the grid");
     if (pc4) {
-      reverse_pc4(phi_t, q_t, uu, FF, Bt, drho, gi, qi, pi, go, qo, po);
+      reverse_pc4(phi_t, q_t, uu, FF, Bt, drho, gi, qi, pi, go, qo, po, xs_q, xs_phi);
     } else {
       // site path: W_bar [9][N] and the local u_bar part; fused: the whole u_bar (in aubp)
       lbc::UbarIn<R> ubin{aWb, aubp, site_path ? 0 : 1};
@@ -1135,7 +1162,9 @@ struct BackendT final : Backend {
     const StateView v = view(state);
     if (rec) {  // the collision adjoint reads the recorded drho and u, not the populations
       const R* uu = static_cast<const R*>(rec);
-      reverse_kernels(v.phi, v.q, uu, uu + 3 * N, nullptr, uu + 6 * N, adj_in, adj_out, zeta_bar, q0_bar);
+      const FS* xs = rec_xs(rec);
+      reverse_kernels(v.phi, v.q, uu, uu + 3 * N, nullptr, uu + 6 * N, adj_in, adj_out, zeta_bar, q0_bar, xs,
+                      xs ? xs + 5 * N : nullptr);
       return;
     }
     // recompute u and F of time t

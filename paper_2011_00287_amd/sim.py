@@ -254,7 +254,8 @@ class Sim:
         return loss.value
 
     def record_buffer(self):
-        """Device tensor for one step record (u [3][N], F [3][N])."""
+        """Device tensor for one step record (u [3][N], F [3][N], drho [N]; with the pc4
+        integrator also the predictor state X*)."""
         import torch
         nb = int(lib().lb_record_bytes(self._h))
         esz = 8 if self.precision == "fp64" else 4
@@ -288,7 +289,8 @@ class Sim:
         return zb.value, qb.value
 
     def lean_record_buffer(self):
-        """uint8 device tensor for one lean step record (Q, phi of time t; drho, u, F of its step)."""
+        """uint8 device tensor for one lean step record (Q, phi of time t; drho, u, F of its step;
+        with the pc4 integrator also the predictor state X*)."""
         import torch
         return torch.empty(int(lib().lb_lean_record_bytes(self._h)), dtype=torch.uint8, device="cuda")
 
