@@ -870,25 +870,37 @@ k_pcb_gather_z(Box b, Params<R> P, int TZ, const FS* __restrict__ phi,
   };
   const bool faces = xsrc[0] >= 0 || xsrc[1] >= 0 || ysrc[0] >= 0 || ysrc[1] >= 0;
   auto at = [&](int zz) { return size_t(pmod(zz, b.nz)) * plane + col; };
+  // the radius-1 fields (vs V_Q, vs V_phi, u_z, phi); with FACES vs V_Q is
+  // formed from the radius-2 ring, which holds V_Q itself
   auto ld1 = [&](int zz, R v[N1]) {
     const size_t k = at(zz);
+    if constexpr (!FACES) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) v[c] = vs * vq[c * N + k];
+      for (int c = 0; c < 5; ++c) v[c] = vs * vq[c * N + k];
+    }
     v[5] = vs * vphi[k];
     v[6] = u[2 * N + k];
     v[7] = R(phi[k]);
   };
   R r2[5][N2], r1[3][N1];
-  // a plane of the radius-2 ring; with FACES the L4 Q and L4 phi adjoints
-  // are K (Gamma (vs V_Q)) and -(k_phi mu_bar), as the local reverse forms them
+  // a plane of the radius-2 ring; with FACES its L4 Q and L4 phi slots hold
+  // V_Q and mu_bar, whose adjoints K (Gamma (vs V_Q)) and -(k_phi mu_bar) (as
+  // the local reverse forms them) are taken where the stencil reads them
   auto ld2 = [&](size_t k, R v[N2]) {
 #pragma unroll
     for (int f = 0; f < N2; ++f) v[f] = f2[f][k];
+  };
+  auto r2v = [&](int j, int f) {
     if constexpr (FACES) {
-#pragma unroll
-      for (int c = 0; c < 5; ++c) v[5 + c] = P.K * (P.Gamma * (vs * v[5 + c]));
-      v[11] = -(P.k_phi * v[11]);
+      if (f >= 5 && f < 10) return P.K * (P.Gamma * (vs * r2[j][f]));
+      if (f == 11) return -(P.k_phi * r2[j][f]);
     }
+    return r2[j][f];
+  };
+  // vs V_Q at planes zc - 1, zc, zc + 1 (j = 0, 1, 2)
+  auto vq1 = [&](int j, int c) {
+    if constexpr (FACES) return vs * r2[1 + j][5 + c];
+    return r1[j][c];
   };
 #pragma unroll
   for (int j = 0; j < 4; ++j) ld2(at(z0 - 2 + j), r2[j]);
@@ -898,7 +910,7 @@ k_pcb_gather_z(Box b, Params<R> P, int TZ, const FS* __restrict__ phi,
     ld2(at(zc + 2), r2[4]);
     ld1(zc + 1, r1[2]);
     auto d4z = [&](int f) { return -d4c(r2[0][f], r2[1][f], r2[3][f], r2[4][f]); };
-    auto l4z = [&](int f) { return l4c(r2[0][f], r2[1][f], r2[3][f], r2[4][f]); };
+    auto l4z = [&](int f) { return l4c(r2v(0, f), r2v(1, f), r2v(3, f), r2v(4, f)); };
     const size_t s = size_t(zc) * plane + col;
     // upwind terms of the z neighbours; donor-cell faces z + 1/2 and z - 1/2
     const R uzp = r1[2][6], uzm = r1[0][6], uz = r1[1][6];
@@ -907,7 +919,7 @@ k_pcb_gather_z(Box b, Params<R> P, int TZ, const FS* __restrict__ phi,
     if (FACES && faces) face_terms(zc, ft);
 #pragma unroll
     for (int k = 0; k < 5; ++k)
-      q_out[k * N + s] += ((d4z(k) + l4z(5 + k)) + (r1[2][k] * upx - r1[0][k] * umx)) + ft[k];
+      q_out[k * N + s] += ((d4z(k) + l4z(5 + k)) + (vq1(2, k) * upx - vq1(0, k) * umx)) + ft[k];
     const R fp = R(0.5) * (uz + uzp), fm = R(0.5) * (uzm + uz);
     const R cp = r1[2][5] - r1[1][5], cm = r1[1][5] - r1[0][5];
     const R ph = r1[1][7], php = r1[2][7], phm = r1[0][7];
