@@ -10,7 +10,9 @@
 // Order (each a launch; the forward u and F of time t come from a recording
 // step, or are recomputed by k_thermo and k_fwd_force):
 //   k_adj_order   : phi, Q updates (Eqs. (1), (2))  -> mu_bar, W_bar, partial u_bar, Q_bar, phi_bar
-//                   (site-parallel, or z-marching over LDS tiles: k_adj_order_fused)
+//                   (site-parallel, or z-marching over LDS tiles: k_adj_order_fused,
+//                   which also applies the transpose of the velocity gradient
+//                   and writes the whole u_bar)
 //   k_adj_collide : collision + stream (Eqs. (6)-(8), (10)-(11)) -> g_bar(t), F_bar
 //   k_adj_stress  : stress, H, mu (Eqs. (3)-(5)), including the anchoring
 //                   divergence D0_a(Q_ab D0_b phi) of mu, whose adjoint

@@ -11,7 +11,12 @@
 //   X*_bar = X_bar(t+1)/2 + R'(X*)^T V2,          V2 = X_bar(t+1)/2,
 //   X_bar  = X_bar(t+1)/2 + X*_bar + R'(X)^T X*_bar,
 //   u_bar  = the u parts of both products.
-// One product R'(X)^T V takes three site-parallel passes:
+// One product R'(X)^T V is, by default, k_pcb_mub (mu_bar = M L4 V_phi),
+// k_pcb_fused (the local reverses and the x, y transposes in one z-march, with
+// the terms owed across tile faces handed to the next pass) and
+// k_pcb_gather_z (the z transposes and those face terms).  Where the tiling
+// leaves a tile one site wide, and on request (lb_tuning.pc_adj = 1), it takes
+// three site-parallel passes and the z pass instead:
 //   k_pcb_local: the local reverses at each site (H4 through local_thermo_bwd
 //     with H_bar = Gamma V_Q, the co-rotation, mu4 with mu_bar = M L4 V_phi, the
 //     site's own upwind terms) -> the adjoints of the site's stencil data

@@ -1021,8 +1021,7 @@ struct BackendT final : Backend {
     const FS* xp = pc4 ? reinterpret_cast<const FS*>(c + lr_xs() + align256(5 * N * sizeof(FS))) : nullptr;
     reverse_kernels(rphi, rq, ru, rF, nullptr, rd, adj_in, adj_out, zeta_bar, q0_bar, xq, xp);
   }
-  // the fused stress + gather adjoint and its tile-face terms; aq: Q_bar(t+1)
-  // for the Euler update's H_bar (zeros under pc4), mb: mu_bar
+  // the z-marching order adjoint: mu_bar, the whole u_bar and the site-local Q, phi adjoints
   void launch_adj_order(const FS* phi_t, const FS* q_t, const R* uu, const R* pi, const R* qi) {
     if (ao_ty == 16)
       lbc::k_adj_order_fused<R, FS, kAoTX, 16><<<ao_blocks, kAoTX * 16, 0, stream>>>(
@@ -1031,6 +1030,8 @@ struct BackendT final : Backend {
       lbc::k_adj_order_fused<R, FS, kAoTX, 8><<<ao_blocks, kAoTX * 8, 0, stream>>>(
           box, P, ao_tz, ao_ntx, ao_nty, phi_t, q_t, uu, pi, qi, amub, aubp, aqbp, aphibp);
   }
+  // the fused stress + gather adjoint and its tile-face terms; aq: Q_bar(t+1)
+  // for the Euler update's H_bar (zeros under pc4), mb: mu_bar
   void stress_gather(const FS* phi_t, const FS* q_t, const R* aq, const R* mb, R* po, R* qo) {
     if (as_ty == 16)
       lbc::k_adj_sg_fused<R, FS, kAsTX, 16, L::kStressInEq><<<as_blocks, kAsTX * 16, 0, stream>>>(
