@@ -312,6 +312,45 @@ __device__ __forceinline__ void g2lds(const float* src, float* lds_wave) {
                                    (__attribute__((address_space(3))) void*)(lds_wave), 4, 0, 0);
 }
 
+// A face record along x: the 9 output fields of one owed term, padded to 12
+// values so that it moves as three 16-byte (float) or six 16-byte (double)
+// accesses (a receiving site of an x face reads its record alone; y faces are
+// whole rows and keep one array per field).
+constexpr int kRec = 12;
+template <class R>
+__device__ __forceinline__ void st_rec(R* __restrict__ p, const R v[9]) {
+  if constexpr (sizeof(R) == 4) {
+    float4* q = reinterpret_cast<float4*>(p);
+    q[0] = make_float4(v[0], v[1], v[2], v[3]);
+    q[1] = make_float4(v[4], v[5], v[6], v[7]);
+    q[2] = make_float4(v[8], 0.0f, 0.0f, 0.0f);
+  } else {
+    double2* q = reinterpret_cast<double2*>(p);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = make_double2(v[2 * i], v[2 * i + 1]);
+    q[4] = make_double2(v[8], 0.0);
+  }
+}
+template <class R>
+__device__ __forceinline__ void add_rec(const R* __restrict__ p, R t[9]) {
+  if constexpr (sizeof(R) == 4) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+    const float4 a = q[0], c = q[1], d = q[2];
+    t[0] += a.x; t[1] += a.y; t[2] += a.z; t[3] += a.w;
+    t[4] += c.x; t[5] += c.y; t[6] += c.z; t[7] += c.w;
+    t[8] += d.x;
+  } else {
+    const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double2 a = q[i];
+      t[2 * i] += a.x;
+      t[2 * i + 1] += a.y;
+    }
+    t[8] += q[4].x;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // k_pcb_fused: one product R'(X)^T V of the pc4 reverse (k_pcb_local, k_pcb_v
 // and k_pcb_gather together) in one z-march over a TX x TY tile and a slab of
@@ -339,9 +378,11 @@ __device__ __forceinline__ void g2lds(const float* src, float* lds_wave) {
 //     term of the first site across (its own part and its inner neighbour's,
 //     read from LDS; pos 0) and of the second (pos 1); side 0 holds what
 //     tile j sends in the + direction across face j, side 1 what tile j+1
-//     sends in the - direction: fx[((((f 2 + side) 2 + pos) ntx + j) nz + z)
-//     ny + y], fy likewise over (nty, z, x).  Every tile along a split axis
-//     is at least two sites wide (checked by the caller).
+//     sends in the - direction.  x faces as records of the 9 fields,
+//     fx[(((((side 2 + pos) ntx + j) nz + z) ny + y) kRec + f], y faces one
+//     array per field, fy[((((f 2 + side) 2 + pos) nty + i) nz + z) nx + x].
+//     Every tile along a split axis is at least two sites wide (checked by
+//     the caller).
 // partial: one float64 (zeta, q0) pair per block, overwritten (pacc = 0) or
 // added to (pacc = 1).
 // ---------------------------------------------------------------------------
@@ -463,7 +504,7 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
     if (nty == 1) return wrap2(t, h) * TX + lx;
     return (t >= 0 && t < h) ? t * TX + lx : -1;
   };
-  const size_t fxs = size_t(ntx) * b.nz * b.ny, fys = size_t(nty) * b.nz * b.nx;  // one (field, side, pos) block
+  const size_t fxs = size_t(ntx) * b.nz * b.ny, fys = size_t(nty) * b.nz * b.nx;  // one (side, pos) block of records / of a field
   const int kxm = (tx + ntx - 1) % ntx, kym = (ty + nty - 1) % nty;
 
   const int sc = (ly + HR) * SX + (lx + HR);
@@ -737,9 +778,12 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
           o[6 + a] = add ? o[6 + a] + v : v;
         }
       };
-      auto put = [&](R* buf, size_t fs, int side, int pos, size_t off, const R o[9]) {
+      auto put = [&](R* buf, size_t fs, int side, int pos, size_t off, const R o[9]) {  // y: per field
 #pragma unroll
         for (int f = 0; f < 9; ++f) buf[size_t((f * 2 + side) * 2 + pos) * fs + off] = o[f];
+      };
+      auto put_rec = [&](int side, int pos, size_t off, const R o[9]) {  // x: one record
+        st_rec(fx + (size_t(side * 2 + pos) * fxs + off) * kRec, o);
       };
       if (ntx > 1) {
         const int gy = sGY[ly + HR];
@@ -748,17 +792,17 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
           const size_t off = (size_t(tx) * b.nz + zc) * b.ny + gy;
           owed(tid, 0, 1, o, false);
           owed(tid - 1, 0, 2, o, true);
-          put(fx, fxs, 0, 0, off, o);
+          put_rec(0, 0, off, o);
           owed(tid, 0, 2, o, false);
-          put(fx, fxs, 0, 1, off, o);
+          put_rec(0, 1, off, o);
         }
         if (lx == 0) {  // to the last two columns of tile tx - 1
           const size_t off = (size_t(kxm) * b.nz + zc) * b.ny + gy;
           owed(tid, 0, -1, o, false);
           owed(tid + 1, 0, -2, o, true);
-          put(fx, fxs, 1, 0, off, o);
+          put_rec(1, 0, off, o);
           owed(tid, 0, -2, o, false);
-          put(fx, fxs, 1, 1, off, o);
+          put_rec(1, 1, off, o);
         }
       }
       if (nty > 1) {
@@ -861,9 +905,7 @@ k_pcb_gather_z(Box b, Params<R> P, int TZ, const FS* __restrict__ phi,
     for (int e = 0; e < 2; ++e) {
       if (xsrc[e] >= 0) {
         const int face = xsrc[e] >> 2, sp = xsrc[e] & 3;  // sp = side 2 + pos
-        const R* r = fx + size_t(sp) * fxs + (size_t(face) * b.nz + zz) * b.ny + cy;
-#pragma unroll
-        for (int f = 0; f < 9; ++f) t[f] += r[size_t(4 * f) * fxs];
+        add_rec(fx + (size_t(sp) * fxs + (size_t(face) * b.nz + zz) * b.ny + cy) * kRec, t);
       }
       if (ysrc[e] >= 0) {
         const int face = ysrc[e] >> 2, sp = ysrc[e] & 3;

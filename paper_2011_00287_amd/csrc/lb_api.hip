@@ -272,7 +272,7 @@ struct BackendT final : Backend {
   static constexpr int kPfTX = sizeof(R) == 4 ? 32 : 16, kPfTY = 16;
   bool pf_fused = false;
   int pf_ntx = 1, pf_nty = 1, pf_tz = 1, pf_blocks = 1;
-  R* apfx = nullptr;  // its face terms along x ([9][2][2][pf_ntx][nz][ny])
+  R* apfx = nullptr;  // its face terms along x ([2][2][pf_ntx][nz][ny][kRec])
   R* apfy = nullptr;  // along y ([9][2][2][pf_nty][nz][nx])
   double* apart = nullptr;   // per-block (zeta, q0) adjoint partials, kept across reverse steps
   size_t apart_n = 0;        // doubles in apart
@@ -871,7 +871,7 @@ struct BackendT final : Backend {
       if (L::kStressInEq) aSb = dalloc<R>(6 * N);  // adjoint of the symmetric stress in the collision
       if (pc4) {
         apb = dalloc<R>(size_t(lbc::NPB) * N);  // per-site scratch of one R'^T V product
-        if (pf_fused && pf_ntx > 1) apfx = dalloc<R>(36 * size_t(pf_ntx) * box.nz * box.ny);
+        if (pf_fused && pf_ntx > 1) apfx = dalloc<R>(4 * lbc::kRec * size_t(pf_ntx) * box.nz * box.ny);
         if (pf_fused && pf_nty > 1) apfy = dalloc<R>(36 * size_t(pf_nty) * box.nz * box.nx);
         axs = dalloc<R>(6 * N);                 // X*_bar: q [5][N], phi [N]
         aupc = dalloc<R>(3 * N);                // u_bar of both Heun stages
