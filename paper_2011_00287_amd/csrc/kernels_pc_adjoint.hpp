@@ -690,6 +690,10 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
     }
     if constexpr (kStage) __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();  // the stencil-data adjoints of the tile (and the staged inputs) are in place
+    // the own column's plane zc + 3, loaded while the transposes are gathered
+    // (planes zc - 2 and zc +- 1, +2 of the ring are not read after the local reverse)
+    R zn[NZ];
+    if (zc + 1 < z1) load_z(zc + 3, zn);
     if (active) {
       const uint32_t so = (uint32_t(zc) * uint32_t(plane) + uint32_t(col)) * SR;
       const int dd[4] = {-2, -1, 1, 2};
@@ -831,7 +835,8 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
       for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int c = 0; c < NZ; ++c) zr[j][c] = zr[j + 1][c];
-      load_z(zc + 3, zr[4]);
+#pragma unroll
+      for (int c = 0; c < NZ; ++c) zr[4][c] = zn[c];
     }
   }
   block_reduce_store<2>(v2, partial + size_t(blockIdx.x) * 2, pacc != 0);
@@ -846,7 +851,7 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
 // fy not null) a column among the first or last two of its TX x TY tile also
 // takes the terms the neighbouring tile owes it across the face.
 template <class R, class FS, bool FACES>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? (FACES ? 2 : 3) : 1)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 2 : 1)))
 k_pcb_gather_z(Box b, Params<R> P, int TZ, const FS* __restrict__ phi,
                                                       const R* __restrict__ u, const R* __restrict__ vq,
                                                       const R* __restrict__ vphi, R vs, const R* __restrict__ pb,
@@ -953,9 +958,35 @@ k_pcb_gather_z(Box b, Params<R> P, int TZ, const FS* __restrict__ phi,
   for (int j = 0; j < 4; ++j) ld2(at(z0 - 2 + j), r2[j]);
   ld1(z0 - 1, r1[0]);
   ld1(z0, r1[1]);
+  // the loads of a plane are issued one iteration ahead: the ring planes
+  // zc + 2 (radius 2) and zc + 1 (radius 1), and the 9 outputs at zc it adds to
+  R n2[N2], n1[N1], no[9];
+  auto ld_out = [&](int zz, R o[9]) {
+    const size_t k = size_t(zz) * plane + col;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) o[c] = q_out[c * N + k];
+    o[5] = phi_out[k];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o[6 + a] = ub_out[a * N + k];
+  };
+  if (z0 < z1) {
+    ld_out(z0, no);
+    ld2(at(z0 + 2), n2);
+    ld1(z0 + 1, n1);
+  }
   for (int zc = z0; zc < z1; ++zc) {
-    ld2(at(zc + 2), r2[4]);
-    ld1(zc + 1, r1[2]);
+    R o[9];
+#pragma unroll
+    for (int f = 0; f < N2; ++f) r2[4][f] = n2[f];
+#pragma unroll
+    for (int f = 0; f < N1; ++f) r1[2][f] = n1[f];
+#pragma unroll
+    for (int f = 0; f < 9; ++f) o[f] = no[f];
+    if (zc + 1 < z1) {
+      ld_out(zc + 1, no);
+      ld2(at(zc + 3), n2);
+      ld1(zc + 2, n1);
+    }
     auto d4z = [&](int f) { return -d4c(r2[0][f], r2[1][f], r2[3][f], r2[4][f]); };
     auto l4z = [&](int f) { return l4c(r2v(0, f), r2v(1, f), r2v(3, f), r2v(4, f)); };
     const size_t s = size_t(zc) * plane + col;
@@ -966,16 +997,16 @@ k_pcb_gather_z(Box b, Params<R> P, int TZ, const FS* __restrict__ phi,
     if (FACES && faces) face_terms(zc, ft);
 #pragma unroll
     for (int k = 0; k < 5; ++k)
-      q_out[k * N + s] += ((d4z(k) + l4z(5 + k)) + (vq1(2, k) * upx - vq1(0, k) * umx)) + ft[k];
+      q_out[k * N + s] = o[k] + (((d4z(k) + l4z(5 + k)) + (vq1(2, k) * upx - vq1(0, k) * umx)) + ft[k]);
     const R fp = R(0.5) * (uz + uzp), fm = R(0.5) * (uzm + uz);
     const R cp = r1[2][5] - r1[1][5], cm = r1[1][5] - r1[0][5];
     const R ph = r1[1][7], php = r1[2][7], phm = r1[0][7];
-    phi_out[s] += ((d4z(10) + l4z(11)) + (cp * (fp > R(0) ? fp : R(0)) + cm * (fm < R(0) ? fm : R(0)))) + ft[5];
+    phi_out[s] = o[5] + (((d4z(10) + l4z(11)) + (cp * (fp > R(0) ? fp : R(0)) + cm * (fm < R(0) ? fm : R(0)))) + ft[5]);
     const R dfp = (fp >= R(0) ? ph : R(0)) + (fp <= R(0) ? php : R(0));
     const R dfm = (fm >= R(0) ? phm : R(0)) + (fm <= R(0) ? ph : R(0));
-    ub_out[s] += d4z(12) + ft[6];
-    ub_out[N + s] += d4z(13) + ft[7];
-    ub_out[2 * N + s] += (d4z(14) + R(0.5) * (cp * dfp + cm * dfm)) + ft[8];
+    ub_out[s] = o[6] + (d4z(12) + ft[6]);
+    ub_out[N + s] = o[7] + (d4z(13) + ft[7]);
+    ub_out[2 * N + s] = o[8] + ((d4z(14) + R(0.5) * (cp * dfp + cm * dfm)) + ft[8]);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
