@@ -277,19 +277,55 @@ k_pcb_gather(Box b, const FS* __restrict__ phi, const R* __restrict__ u, const R
 
 // mu_bar = M vs L4 vphi of one product at every site: the adjoint of mu4,
 // which the fused product reads with a D4 stencil (v_bar = 2 W D4 mu_bar).
-template <class R>
-__global__ void __launch_bounds__(256) k_pcb_mub(Box b, Params<R> P, const R* __restrict__ vphi, R vs,
-                                                 R* __restrict__ mub) {
-  const int s = site_xcd();
-  if (s >= b.N) return;
-  int x, y, z;
-  coords(b, s, x, y, z);
-  int n[3][4];
-  star2(b, x, y, z, n);
-  R lapv = R(-7.5) * vphi[s];
+// A workgroup covers a TX x TY tile of NP planes: it loads the NP + 4 planes
+// of vphi the stencils read (the tile with an in-plane halo of 2) at once,
+// puts them in LDS and forms the laplacian of its NP planes, summing the x,
+// y, z stencils in that order.
+template <class R, int TX, int TY, int NP>
+__global__ void __launch_bounds__(TX* TY) k_pcb_mub(Box b, Params<R> P, int ntx, int nty,
+                                                   const R* __restrict__ vphi, R vs, R* __restrict__ mub) {
+  constexpr int NT = TX * TY, SX = TX + 4, SY = TY + 4, NF = SX * SY, KR = (NF + NT - 1) / NT;
+  constexpr int NL = NP + 4;  // planes z0 - 2 .. z0 + NP + 1
+  __shared__ R sF[NL][NF];
+  const int l = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = l % ntx, ty = (l / ntx) % nty, sl = l / (ntx * nty);
+  const int x0 = tx * TX, y0 = ty * TY, z0 = sl * NP;
+  const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
+  const uint32_t plane = uint32_t(b.nx) * uint32_t(b.ny);
+  R v[NL][KR];
 #pragma unroll
-  for (int g = 0; g < 3; ++g) lapv += l4c(vphi[n[g][0]], vphi[n[g][1]], vphi[n[g][2]], vphi[n[g][3]]);
-  mub[s] = P.M * vs * lapv;
+  for (int j = 0; j < KR; ++j) {
+    const int k = tid + j * NT;
+    if (k < NF) {
+      const uint32_t col = uint32_t(pmod(y0 - 2 + k / SX, b.ny) * b.nx + pmod(x0 - 2 + k % SX, b.nx));
+#pragma unroll
+      for (int i = 0; i < NL; ++i)
+        v[i][j] = ldo(vphi, (uint32_t(pmod(z0 - 2 + i, b.nz)) * plane + col) * uint32_t(sizeof(R)));
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < KR; ++j) {
+    const int k = tid + j * NT;
+    if (k < NF) {
+#pragma unroll
+      for (int i = 0; i < NL; ++i) sF[i][k] = v[i][j];
+    }
+  }
+  __syncthreads();
+  if (x0 + lx >= b.nx || y0 + ly >= b.ny) return;
+  const int c = (ly + 2) * SX + (lx + 2);
+  const uint32_t own = (uint32_t(y0 + ly) * uint32_t(b.nx) + uint32_t(x0 + lx)) * uint32_t(sizeof(R));
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const int p = z0 + i;
+    if (p >= b.nz) break;
+    const R* f = sF[i + 2];
+    R lapv = R(-7.5) * f[c];
+    lapv += l4c(f[c - 2], f[c - 1], f[c + 1], f[c + 2]);
+    lapv += l4c(f[c - 2 * SX], f[c - SX], f[c + SX], f[c + 2 * SX]);
+    lapv += l4c(sF[i][c], sF[i + 1][c], sF[i + 3][c], sF[i + 4][c]);
+    sto(mub, uint32_t(p) * plane * uint32_t(sizeof(R)) + own, P.M * vs * lapv);
+  }
 }
 
 // Coefficients of the transposed axis stencils: a site x gathers
@@ -762,11 +798,15 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
       }
 #pragma unroll
       for (int a = 0; a < 3; ++a) sto(ub_out + a * N, so, accumulate ? in_o(12 + a, ub_out + a * N) + ub[a] : ub[a]);
-      // the terms owed across a tile face: output fields q[5], phi, u[3] of
-      // the site at offset d from this one
-      // the terms owed across a tile face, per output field q[5], phi, u[3]:
-      // the edge site sends, for the first site across, its own term and that
-      // of its inner neighbour (read from LDS), and its own for the second
+    }
+    // the terms owed across the tile faces, per output field q[5], phi, u[3]:
+    // an edge site sends, for the first site across, its own term and that of
+    // its inner neighbour, and its own for the second.  They are formed from
+    // the stencil-data adjoints in LDS as one work item per (row, side, pos)
+    // of the x faces and (column, side, pos) of the y faces, spread evenly
+    // over the waves (an edge lane of every row would leave the other lanes
+    // of its wave idle through the whole branch).
+    {
       auto owed = [&](int t, int g, int d, R o[9], bool add) {
         const R lw = l4w<R>(-d), dw = d4w<R>(-d);  // the sender is at offset -d from the receiver
 #pragma unroll
@@ -782,51 +822,48 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
           o[6 + a] = add ? o[6 + a] + v : v;
         }
       };
-      auto put = [&](R* buf, size_t fs, int side, int pos, size_t off, const R o[9]) {  // y: per field
+      // side 0: sent in the + direction by the last column (row) of the tile,
+      // side 1: in the - direction by the first; pos 0 / 1: the first / second
+      // site across
+      auto owed_item = [&](int t, int g, int side, int pos, int step, R o[9]) {
+        const int dir = side == 0 ? 1 : -1;
+        if (pos == 0) {
+          owed(t, g, dir, o, false);
+          owed(t - dir * step, g, 2 * dir, o, true);
+        } else {
+          owed(t, g, 2 * dir, o, false);
+        }
+      };
+      constexpr int NXI = 4 * TY, NYI = 4 * TX, NW = NT / 64;
+      constexpr int NWI = (NXI + NYI + NW - 1) / NW;  // items per wave
+      static_assert(NWI <= 64, "face items fit the lanes");
+      // the item of this lane, formed from the thread id in each plane (an
+      // empty asm keeps it from being hoisted and held across the march)
+      int tf = tid;
+      asm volatile("" : "+v"(tf));
+      const int lane = tf & 63, it = (tf >> 6) * NWI + lane;
+      if (lane < NWI) {
+        if (it < NXI) {
+          const int r = it >> 2, side = (it >> 1) & 1, pos = it & 1;
+          if (ntx > 1 && r < h) {
+            R o[9];
+            owed_item(r * TX + (side == 0 ? w - 1 : 0), 0, side, pos, 1, o);
+            const size_t off = (size_t(side == 0 ? tx : kxm) * b.nz + zc) * b.ny + sGY[r + HR];
+            st_rec(fx + (size_t(side * 2 + pos) * fxs + off) * kRec, o);
+          }
+        } else if (it < NXI + NYI) {
+          const int i2 = it - NXI;
+          const int cc = i2 >> 2, side = (i2 >> 1) & 1, pos = i2 & 1;
+          if (nty > 1 && cc < w) {
+            R o[9];
+            owed_item((side == 0 ? h - 1 : 0) * TX + cc, 1, side, pos, TX, o);
+            // uniform field base plus a 32-bit byte offset (one field block of fy is below 4 GiB)
+            const uint32_t off = (uint32_t(side * 2 + pos) * uint32_t(fys) +
+                                  (uint32_t(side == 0 ? ty : kym) * uint32_t(b.nz) + uint32_t(zc)) * uint32_t(b.nx) +
+                                  uint32_t(sGX[cc + HR])) * SR;
 #pragma unroll
-        for (int f = 0; f < 9; ++f) buf[size_t((f * 2 + side) * 2 + pos) * fs + off] = o[f];
-      };
-      auto put_rec = [&](int side, int pos, size_t off, const R o[9]) {  // x: one record
-        st_rec(fx + (size_t(side * 2 + pos) * fxs + off) * kRec, o);
-      };
-      if (ntx > 1) {
-        const int gy = sGY[ly + HR];
-        R o[9];
-        if (lx == w - 1) {  // to the first two columns of tile tx + 1
-          const size_t off = (size_t(tx) * b.nz + zc) * b.ny + gy;
-          owed(tid, 0, 1, o, false);
-          owed(tid - 1, 0, 2, o, true);
-          put_rec(0, 0, off, o);
-          owed(tid, 0, 2, o, false);
-          put_rec(0, 1, off, o);
-        }
-        if (lx == 0) {  // to the last two columns of tile tx - 1
-          const size_t off = (size_t(kxm) * b.nz + zc) * b.ny + gy;
-          owed(tid, 0, -1, o, false);
-          owed(tid + 1, 0, -2, o, true);
-          put_rec(1, 0, off, o);
-          owed(tid, 0, -2, o, false);
-          put_rec(1, 1, off, o);
-        }
-      }
-      if (nty > 1) {
-        const int gx = sGX[lx + HR];
-        R o[9];
-        if (ly == h - 1) {  // to the first two rows of tile ty + 1
-          const size_t off = (size_t(ty) * b.nz + zc) * b.nx + gx;
-          owed(tid, 1, 1, o, false);
-          owed(tid - TX, 1, 2, o, true);
-          put(fy, fys, 0, 0, off, o);
-          owed(tid, 1, 2, o, false);
-          put(fy, fys, 0, 1, off, o);
-        }
-        if (ly == 0) {  // to the last two rows of tile ty - 1
-          const size_t off = (size_t(kym) * b.nz + zc) * b.nx + gx;
-          owed(tid, 1, -1, o, false);
-          owed(tid + TX, 1, -2, o, true);
-          put(fy, fys, 1, 0, off, o);
-          owed(tid, 1, -2, o, false);
-          put(fy, fys, 1, 1, off, o);
+            for (int f = 0; f < 9; ++f) sto(fy + size_t(4 * f) * fys, off, o[f]);
+          }
         }
       }
     }
