@@ -844,7 +844,8 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
       const int lane = tf & 63, it = (tf >> 6) * NWI + lane;
       if (lane < NWI) {
         if (it < NXI) {
-          const int r = it >> 2, side = (it >> 1) & 1, pos = it & 1;
+          // consecutive lanes take consecutive rows of one (side, pos): whole runs of records
+          const int r = it % TY, side = it / (2 * TY), pos = (it / TY) & 1;
           if (ntx > 1 && r < h) {
             R o[9];
             owed_item(r * TX + (side == 0 ? w - 1 : 0), 0, side, pos, 1, o);
@@ -853,7 +854,7 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
           }
         } else if (it < NXI + NYI) {
           const int i2 = it - NXI;
-          const int cc = i2 >> 2, side = (i2 >> 1) & 1, pos = i2 & 1;
+          const int cc = i2 % TX, side = i2 / (2 * TX), pos = (i2 / TX) & 1;
           if (nty > 1 && cc < w) {
             R o[9];
             owed_item((side == 0 ? h - 1 : 0) * TX + cc, 1, side, pos, TX, o);
