@@ -368,6 +368,25 @@ __device__ __forceinline__ void st_rec(R* __restrict__ p, const R v[9]) {
   }
 }
 template <class R>
+__device__ __forceinline__ void ld_rec(const R* __restrict__ p, R t[9]) {
+  if constexpr (sizeof(R) == 4) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+    const float4 a = q[0], c = q[1], d = q[2];
+    t[0] = a.x; t[1] = a.y; t[2] = a.z; t[3] = a.w;
+    t[4] = c.x; t[5] = c.y; t[6] = c.z; t[7] = c.w;
+    t[8] = d.x;
+  } else {
+    const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double2 a = q[i];
+      t[2 * i] = a.x;
+      t[2 * i + 1] = a.y;
+    }
+    t[8] = q[4].x;
+  }
+}
+template <class R>
 __device__ __forceinline__ void add_rec(const R* __restrict__ p, R t[9]) {
   if constexpr (sizeof(R) == 4) {
     const float4* q = reinterpret_cast<const float4*>(p);
@@ -942,20 +961,23 @@ k_pcb_gather_z(Box b, Params<R> P, int TZ, const FS* __restrict__ phi,
     if (ly >= hi - 2) ysrc[1] = ((i * 2 + 1) * 2) + (hi - 1 - ly);
   }
   const size_t fxs = size_t(ntx) * b.nz * b.ny, fys = size_t(nty) * b.nz * b.nx;
-  // the owed terms of the 9 output fields at plane zz, added to t
-  auto face_terms = [&](int zz, R t[9]) {
+  // the owed terms at plane zz: a record of fx, or 9 values of one fy row
+  // (sp = side 2 + pos)
+  auto xrec = [&](int src, int zz) {
+    return fx + (size_t(src & 3) * fxs + (size_t(src >> 2) * b.nz + zz) * b.ny + cy) * kRec;
+  };
+  auto yrow = [&](int src, int zz) { return fy + size_t(src & 3) * fys + (size_t(src >> 2) * b.nz + zz) * b.nx + cx; };
+  // the first x and the first y source of the column are loaded one plane
+  // ahead; a second one along an axis (tiles under four sites wide) is
+  // loaded where it is added
+  const int xa = xsrc[0] >= 0 ? xsrc[0] : xsrc[1], xb = xsrc[0] >= 0 ? xsrc[1] : -1;
+  const int ya = ysrc[0] >= 0 ? ysrc[0] : ysrc[1], yb = ysrc[0] >= 0 ? ysrc[1] : -1;
+  auto ld_faces = [&](int zz, R px[9], R py[9]) {
+    if (xa >= 0) ld_rec(xrec(xa, zz), px);
+    if (ya >= 0) {
+      const R* r = yrow(ya, zz);
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      if (xsrc[e] >= 0) {
-        const int face = xsrc[e] >> 2, sp = xsrc[e] & 3;  // sp = side 2 + pos
-        add_rec(fx + (size_t(sp) * fxs + (size_t(face) * b.nz + zz) * b.ny + cy) * kRec, t);
-      }
-      if (ysrc[e] >= 0) {
-        const int face = ysrc[e] >> 2, sp = ysrc[e] & 3;
-        const R* r = fy + size_t(sp) * fys + (size_t(face) * b.nz + zz) * b.nx + cx;
-#pragma unroll
-        for (int f = 0; f < 9; ++f) t[f] += r[size_t(4 * f) * fys];
-      }
+      for (int f = 0; f < 9; ++f) py[f] = r[size_t(4 * f) * fys];
     }
   };
   const bool faces = xsrc[0] >= 0 || xsrc[1] >= 0 || ysrc[0] >= 0 || ysrc[1] >= 0;
@@ -999,6 +1021,7 @@ k_pcb_gather_z(Box b, Params<R> P, int TZ, const FS* __restrict__ phi,
   // the loads of a plane are issued one iteration ahead: the ring planes
   // zc + 2 (radius 2) and zc + 1 (radius 1), and the 9 outputs at zc it adds to
   R n2[N2], n1[N1], no[9];
+  R nfx[9], nfy[9];  // the face sources of the next plane
   auto ld_out = [&](int zz, R o[9]) {
     const size_t k = size_t(zz) * plane + col;
 #pragma unroll
@@ -1011,6 +1034,7 @@ k_pcb_gather_z(Box b, Params<R> P, int TZ, const FS* __restrict__ phi,
     ld_out(z0, no);
     ld2(at(z0 + 2), n2);
     ld1(z0 + 1, n1);
+    if constexpr (FACES) ld_faces(z0, nfx, nfy);
   }
   for (int zc = z0; zc < z1; ++zc) {
     R o[9];
@@ -1020,10 +1044,29 @@ k_pcb_gather_z(Box b, Params<R> P, int TZ, const FS* __restrict__ phi,
     for (int f = 0; f < N1; ++f) r1[2][f] = n1[f];
 #pragma unroll
     for (int f = 0; f < 9; ++f) o[f] = no[f];
+    // the face terms of this plane: the prefetched sources, then any second one
+    R ft[9] = {R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
+    if (FACES && faces) {
+      if (xa >= 0) {
+#pragma unroll
+        for (int f = 0; f < 9; ++f) ft[f] += nfx[f];
+      }
+      if (ya >= 0) {
+#pragma unroll
+        for (int f = 0; f < 9; ++f) ft[f] += nfy[f];
+      }
+      if (xb >= 0) add_rec(xrec(xb, zc), ft);
+      if (yb >= 0) {
+        const R* r = yrow(yb, zc);
+#pragma unroll
+        for (int f = 0; f < 9; ++f) ft[f] += r[size_t(4 * f) * fys];
+      }
+    }
     if (zc + 1 < z1) {
       ld_out(zc + 1, no);
       ld2(at(zc + 3), n2);
       ld1(zc + 2, n1);
+      if constexpr (FACES) ld_faces(zc + 1, nfx, nfy);
     }
     auto d4z = [&](int f) { return -d4c(r2[0][f], r2[1][f], r2[3][f], r2[4][f]); };
     auto l4z = [&](int f) { return l4c(r2v(0, f), r2v(1, f), r2v(3, f), r2v(4, f)); };
@@ -1031,8 +1074,6 @@ k_pcb_gather_z(Box b, Params<R> P, int TZ, const FS* __restrict__ phi,
     // upwind terms of the z neighbours; donor-cell faces z + 1/2 and z - 1/2
     const R uzp = r1[2][6], uzm = r1[0][6], uz = r1[1][6];
     const R upx = uzp > R(0) ? uzp : R(0), umx = uzm < R(0) ? uzm : R(0);
-    R ft[9] = {R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
-    if (FACES && faces) face_terms(zc, ft);
 #pragma unroll
     for (int k = 0; k < 5; ++k)
       q_out[k * N + s] = o[k] + (((d4z(k) + l4z(5 + k)) + (vq1(2, k) * upx - vq1(0, k) * umx)) + ft[k]);
