@@ -122,8 +122,10 @@ def test_d3q15_pc4_single_step_vjp_matches_oracle(record):
 # Boxes whose tiles exercise the one-kernel product of the reverse (tiles of
 # 32 x 16 in float, 16 x 16 in double): several tiles along both in-plane
 # axes, ragged last tiles two and more sites wide (the terms owed across a
-# tile face reach two sites), a lone tile along one axis wrapping inside itself.
-FUSED_SHAPES = [(70, 20, 9), (36, 18, 7), (34, 10, 6), (18, 12, 5), (40, 6, 7), (20, 40, 5)]
+# tile face reach two sites: in a tile two or three sites wide a column or
+# row receives from both faces), a lone tile along one axis wrapping inside
+# itself.
+FUSED_SHAPES = [(70, 20, 9), (36, 18, 7), (34, 10, 6), (18, 12, 5), (40, 6, 7), (20, 40, 5), (35, 19, 6)]
 
 
 @pytest.mark.parametrize("shape", FUSED_SHAPES)
