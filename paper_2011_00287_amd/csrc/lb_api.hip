@@ -272,7 +272,7 @@ struct BackendT final : Backend {
   static constexpr int kPfTX = sizeof(R) == 4 ? 32 : 16, kPfTY = 16;
   bool pf_fused = false;
   int pf_ntx = 1, pf_nty = 1, pf_tz = 1, pf_blocks = 1;
-  int mb_ntx = 1, mb_nty = 1, mb_blocks = 1;  // its mu_bar kernel (k_pcb_mub: 32 x 8 tiles of four planes)
+  int mb_ntx = 1, mb_nty = 1, mb_blocks = 1;  // its mu_bar kernel (k_pcb_mub: 32 x 8 tiles of eight planes)
   R* apfx = nullptr;  // its face terms along x ([2][2][pf_ntx][nz][ny][kRec])
   R* apfy = nullptr;  // along y ([9][2][2][pf_nty][nz][nx])
   double* apart = nullptr;   // per-block (zeta, q0) adjoint partials, kept across reverse steps
@@ -373,7 +373,7 @@ struct BackendT final : Backend {
     pf_blocks = pf_ntx * pf_nty * ((p.nz + pf_tz - 1) / pf_tz);
     mb_ntx = (p.nx + 31) / 32;
     mb_nty = (p.ny + 7) / 8;
-    mb_blocks = mb_ntx * mb_nty * ((p.nz + 3) / 4);
+    mb_blocks = mb_ntx * mb_nty * ((p.nz + 7) / 8);
     size_t need = 2 * (NQ * N * sizeof(GS) + 6 * N * sizeof(FS)) + 4 * N * sizeof(R);
     if (pc4) need += 6 * N * sizeof(FS) + (site_path ? 3 * N * sizeof(R) : 0);
     size_t free_b = 0, total_b = 0;
@@ -1076,7 +1076,7 @@ struct BackendT final : Backend {
       R* mb = apb + 9 * N;  // mu_bar of the product
       auto product = [&](const FS* ph, const FS* qq, const R* vq, const R* vp, R vs, R c2, const R* x2q,
                          const R* x2p, R* oq, R* op, int acc, int pacc) {
-        lbc::k_pcb_mub<R, 32, 8, 4><<<mb_blocks, 256, 0, stream>>>(box, P, mb_ntx, mb_nty, vp, vs, mb);
+        lbc::k_pcb_mub<R, 32, 8, 8><<<mb_blocks, 256, 0, stream>>>(box, P, mb_ntx, mb_nty, vp, vs, mb);
         lbc::k_pcb_fused<R, FS, kPfTX, kPfTY><<<pf_blocks, kPfTX * kPfTY, 0, stream>>>(
             box, P, pf_tz, pf_ntx, pf_nty, ph, qq, uu, vq, vp, vs, mb, qi, pi, R(0.5), x2q, x2p, c2, oq, op, aupc,
             acc, zf, apfx, apfy, pl, pacc);
