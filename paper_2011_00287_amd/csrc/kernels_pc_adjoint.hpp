@@ -33,6 +33,7 @@
 // w; at w = 0 their w-derivative is taken as a + b (both one-sided parts), the
 // convention of the clamp form the oracle writes them in.
 #pragma once
+#include <type_traits>
 #include "adjoint.hpp"
 #include "kernels_pc.hpp"
 #include "kernels_reduce.hpp"
@@ -459,7 +460,12 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
   // x, y stencil-data adjoints: lapq[5], lapphi, dq_x[5], dq_y[5], dphi_x, dphi_y, W_ax[3], W_ay[3]
   constexpr int XL = 0, XLP = 5, XDQ = 6, XDP = 16, XW = 18, NXF = 24;
   __shared__ R sV[NV][NS];
-  __shared__ R sX[NXF][NT];
+  // the tile's x, y stencil-data adjoints, each row padded with two zero
+  // columns on both sides: the x transposes read fixed offsets, and a site
+  // beyond the tile's last column (or a ragged tile's width) reads zeros (a
+  // lone x tile wraps inside itself instead)
+  constexpr int PX = TX + 4, NTP = TY * PX;
+  __shared__ R sX[NXF][NTP];
   __shared__ int sGX[SX], sGY[SY];
   // float: the next plane's V and halo, and this plane's inputs of the Heun
   // combination, go from global memory to LDS staging buffers while the local
@@ -484,6 +490,7 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
 
   for (int k = tid; k < SX; k += NT) sGX[k] = pmod(x0 - HR + k, b.nx);
   for (int k = tid; k < SY; k += NT) sGY[k] = pmod(y0 - HR + k, b.ny);
+  for (int k = tid; k < NXF * NTP; k += NT) (&sX[0][0])[k] = R(0);  // pads and inactive sites stay zero
   __syncthreads();
   const int col = sGY[ly + HR] * b.nx + sGX[lx + HR];
 
@@ -549,16 +556,18 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
     t -= t >= n ? n : 0;
     return t;
   };
+  // (indices into the padded rows of sX)
   auto nbx = [&](int d) {
     const int t = lx + d;
-    if (ntx == 1) return ly * TX + wrap2(t, w);
-    return (t >= 0 && t < w) ? ly * TX + t : -1;
+    if (ntx == 1) return ly * PX + wrap2(t, w) + 2;
+    return (t >= 0 && t < w) ? ly * PX + t + 2 : -1;
   };
   auto nby = [&](int d) {
     const int t = ly + d;
-    if (nty == 1) return wrap2(t, h) * TX + lx;
-    return (t >= 0 && t < h) ? t * TX + lx : -1;
+    if (nty == 1) return wrap2(t, h) * PX + lx + 2;
+    return (t >= 0 && t < h) ? t * PX + lx + 2 : -1;
   };
+  const int xs = ly * PX + lx + 2;  // this site's slot in sX
   const size_t fxs = size_t(ntx) * b.nz * b.ny, fys = size_t(nty) * b.nz * b.nx;  // one (side, pos) block of records / of a field
   const int kxm = (tx + ntx - 1) % ntx, kym = (ty + nty - 1) % nty;
 
@@ -724,17 +733,17 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
       // x, y stencil-data adjoints to LDS; z ones to zf
 #pragma unroll
       for (int k = 0; k < 5; ++k) {
-        sX[XL + k][tid] = Gb.lapq[k];
-        sX[XDQ + k][tid] = Gb.dq[0][k];
-        sX[XDQ + 5 + k][tid] = Gb.dq[1][k];
+        sX[XL + k][xs] = Gb.lapq[k];
+        sX[XDQ + k][xs] = Gb.dq[0][k];
+        sX[XDQ + 5 + k][xs] = Gb.dq[1][k];
       }
-      sX[XLP][tid] = lapphib;
-      sX[XDP][tid] = Gb.dphi[0];
-      sX[XDP + 1][tid] = Gb.dphi[1];
+      sX[XLP][xs] = lapphib;
+      sX[XDP][xs] = Gb.dphi[0];
+      sX[XDP + 1][xs] = Gb.dphi[1];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        sX[XW + a][tid] = Wb[a][0];
-        sX[XW + 3 + a][tid] = Wb[a][1];
+        sX[XW + a][xs] = Wb[a][0];
+        sX[XW + 3 + a][xs] = Wb[a][1];
       }
       const uint32_t so = (uint32_t(zc) * uint32_t(plane) + uint32_t(col)) * SR;
 #pragma unroll
@@ -751,40 +760,56 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
     if (zc + 1 < z1) load_z(zc + 3, zn);
     if (active) {
       const uint32_t so = (uint32_t(zc) * uint32_t(plane) + uint32_t(col)) * SR;
-      const int dd[4] = {-2, -1, 1, 2};
-      int ix[4], iy[4];
+      constexpr int dd[4] = {-2, -1, 1, 2};
+      int iy[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        ix[k] = nbx(dd[k]);
-        iy[k] = nby(dd[k]);
-      }
-      auto vx = [&](int f, int k) { return ix[k] >= 0 ? sX[f][ix[k]] : R(0); };
+      for (int k = 0; k < 4; ++k) iy[k] = nby(dd[k]);
       auto vy = [&](int f, int k) { return iy[k] >= 0 ? sX[f][iy[k]] : R(0); };
-      auto l4x = [&](int f) { return l4c(vx(f, 0), vx(f, 1), vx(f, 2), vx(f, 3)); };
       auto l4y = [&](int f) { return l4c(vy(f, 0), vy(f, 1), vy(f, 2), vy(f, 3)); };
-      auto d4x = [&](int f) { return -d4c(vx(f, 0), vx(f, 1), vx(f, 2), vx(f, 3)); };
       auto d4y = [&](int f) { return -d4c(vy(f, 0), vy(f, 1), vy(f, 2), vy(f, 3)); };
       R qo[5], po, ub[3];
+      // the transposes; x neighbours at fixed offsets in the padded rows, or
+      // wrapped inside a lone x tile (two copies of the code, one branch)
+      auto transposes = [&](auto lone) {
+        constexpr bool LONE = decltype(lone)::value;
+        int ix[4];
+        if constexpr (LONE) {
 #pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        R r = qbl[k] + ((R(-7.5) * sX[XL + k][tid] + l4x(XL + k)) + l4y(XL + k));
-        r += d4x(XDQ + k);
-        r += d4y(XDQ + 5 + k);
-        qo[k] = r;
-      }
-      {
-        R r = pbl + ((R(-7.5) * sX[XLP][tid] + l4x(XLP)) + l4y(XLP));
-        r += d4x(XDP);
-        r += d4y(XDP + 1);
-        po = r;
-      }
+          for (int k = 0; k < 4; ++k) ix[k] = nbx(dd[k]);
+        }
+        auto vx = [&](int f, int k) {
+          if constexpr (LONE)
+            return sX[f][ix[k]];
+          else
+            return sX[f][xs + dd[k]];
+        };
+        auto l4x = [&](int f) { return l4c(vx(f, 0), vx(f, 1), vx(f, 2), vx(f, 3)); };
+        auto d4x = [&](int f) { return -d4c(vx(f, 0), vx(f, 1), vx(f, 2), vx(f, 3)); };
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        R r = ubl[a];
-        r += d4x(XW + a);
-        r += d4y(XW + 3 + a);
-        ub[a] = r;
-      }
+        for (int k = 0; k < 5; ++k) {
+          R r = qbl[k] + ((R(-7.5) * sX[XL + k][xs] + l4x(XL + k)) + l4y(XL + k));
+          r += d4x(XDQ + k);
+          r += d4y(XDQ + 5 + k);
+          qo[k] = r;
+        }
+        {
+          R r = pbl + ((R(-7.5) * sX[XLP][xs] + l4x(XLP)) + l4y(XLP));
+          r += d4x(XDP);
+          r += d4y(XDP + 1);
+          po = r;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          R r = ubl[a];
+          r += d4x(XW + a);
+          r += d4y(XW + 3 + a);
+          ub[a] = r;
+        }
+      };
+      if (ntx == 1)
+        transposes(std::true_type{});
+      else
+        transposes(std::false_type{});
       // the x and y neighbour terms of the upwind and donor-cell operators
       const R ph = zr[2][5], vp0 = vs * sV[NZ + 5][sc];
 #pragma unroll
@@ -867,7 +892,7 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
           const int r = it % TY, side = it / (2 * TY), pos = (it / TY) & 1;
           if (ntx > 1 && r < h) {
             R o[9];
-            owed_item(r * TX + (side == 0 ? w - 1 : 0), 0, side, pos, 1, o);
+            owed_item(r * PX + (side == 0 ? w - 1 : 0) + 2, 0, side, pos, 1, o);
             const size_t off = (size_t(side == 0 ? tx : kxm) * b.nz + zc) * b.ny + sGY[r + HR];
             st_rec(fx + (size_t(side * 2 + pos) * fxs + off) * kRec, o);
           }
@@ -876,7 +901,7 @@ k_pcb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__
           const int cc = i2 % TX, side = i2 / (2 * TX), pos = (i2 / TX) & 1;
           if (nty > 1 && cc < w) {
             R o[9];
-            owed_item((side == 0 ? h - 1 : 0) * TX + cc, 1, side, pos, TX, o);
+            owed_item((side == 0 ? h - 1 : 0) * PX + cc + 2, 1, side, pos, PX, o);
             // uniform field base plus a 32-bit byte offset (one field block of fy is below 4 GiB)
             const uint32_t off = (uint32_t(side * 2 + pos) * uint32_t(fys) +
                                   (uint32_t(side == 0 ? ty : kym) * uint32_t(b.nz) + uint32_t(zc)) * uint32_t(b.nx) +
