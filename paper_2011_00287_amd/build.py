@@ -30,12 +30,17 @@ STEP_SOURCES = ("physics.hpp", "storage.hpp", "kernels_fused.hpp", "kernels_step
 
 
 def kernel_source_hash() -> str:
-    """Hash of the 3D step's HIP sources: hardware counters are valid only for the source they were taken on."""
+    """Hash of the 3D step's HIP sources without comments and blank lines: hardware counters are valid only
+    for the code they were taken on, and an edit of a comment leaves that code as it was."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in STEP_SOURCES:
-        with open(os.path.join(PKG, "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(PKG, "csrc", f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update("\n".join(line.rstrip() for line in text.splitlines() if line.strip()).encode())
     return h.hexdigest()[:16]
 
 

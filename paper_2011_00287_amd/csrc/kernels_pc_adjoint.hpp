@@ -430,11 +430,12 @@ __device__ __forceinline__ void add_rec(const R* __restrict__ p, R t[9]) {
 //     mu_bar itself;
 //   * the terms a site owes the two columns (rows) across a tile face: the
 //     last two columns of tile j send to the first two of tile j+1 and back.
-//     The edge column sends, per output field (q[5], phi, u[3]), the whole
+//     Per output field (q[5], phi, u[3]) the edge column owes the whole
 //     term of the first site across (its own part and its inner neighbour's,
 //     read from LDS; pos 0) and of the second (pos 1); side 0 holds what
 //     tile j sends in the + direction across face j, side 1 what tile j+1
-//     sends in the - direction.  x faces as records of the 9 fields,
+//     sends in the - direction.  These terms are formed as work items spread
+//     over the waves after the transposes.  x faces as records of the 9 fields,
 //     fx[(((((side 2 + pos) ntx + j) nz + z) ny + y) kRec + f], y faces one
 //     array per field, fy[((((f 2 + side) 2 + pos) nty + i) nz + z) nx + x].
 //     Every tile along a split axis is at least two sites wide (checked by
