@@ -816,6 +816,22 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
       }
     }
   };
+  // float, D3Q19: the next plane is loaded into registers before the stress
+  // adjoint of this plane (which hides the loads) and stored after it
+  constexpr bool kEarly = sizeof(R) == 4 && !SYM;
+  auto fill_load = [&](int wp, R v[KI][NF]) {
+    const size_t base = size_t(pmod(wp, b.nz)) * plane;
+#pragma unroll
+    for (int j = 0; j < KI; ++j) {
+      const size_t g = base + icol[j];
+      v[j][0] = R(phi[g]);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) v[j][1 + c] = R(q[c * N + g]);
+      v[j][6] = mub[g];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) v[j][7 + a] = Fb[a * N + g];
+    }
+  };
 
   // in-plane neighbours inside the tile (a lone tile along an axis wraps
   // periodically inside itself); -1 where the neighbour is in another tile
@@ -912,6 +928,10 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
   for (int p = z0 - 1; p <= z1; ++p) {
     const bool more = p < z1;
     __syncthreads();  // plane p+1 in place; the previous plane's reads of sGB are done
+    R fv[kEarly ? KI : 1][kEarly ? NF : 1];
+    if constexpr (kEarly) {
+      if (more) fill_load(p + 2, fv);
+    }
     GradBar<R> Gb;
     ParBar<R> Pb;
     site_adjoint(rm, r0, rp, aq_o, ss_o, Gb, Pb);
@@ -983,7 +1003,18 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
     if (more) {
       // plane p-1 is read by no one any more (all passed the barrier above):
       // plane p+2 takes its slot; the site inputs of plane p+1
-      fill_plane(p + 2, rm);
+      if constexpr (kEarly) {
+#pragma unroll
+        for (int j = 0; j < KI; ++j) {
+          const int k = tid + j * NT;
+          if (k < NI) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) sIn[rm][f][k] = fv[j][f];
+          }
+        }
+      } else {
+        fill_plane(p + 2, rm);
+      }
       load_site(p + 1, aq_o, qp_o, pp_o, ss_o);
     }
     const int t = rm;
