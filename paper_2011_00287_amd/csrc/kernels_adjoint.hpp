@@ -890,14 +890,14 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
     G.divv = R(0);
     adj_stress_site<R, SYM>(P, G, Fn, mbn, sIn[r0][6][f], aq, Gb, Pb, ssb);
   };
-  auto load_site = [&](int wp, R aq[5], R qp[5], R& pp, R ssb[6]) {
+  auto load_site = [&](int wp, R aq[5], R qp[5], R& pp, R ssb[6], bool with_s = true) {
     const size_t k = size_t(pmod(wp, b.nz)) * plane + col;
 #pragma unroll
     for (int c = 0; c < 5; ++c) aq[c] = adj_q[c * N + k];
 #pragma unroll
     for (int c = 0; c < 5; ++c) qp[c] = qbp[c * N + k];
     pp = phibp[k];
-    if constexpr (SYM) {
+    if (SYM && with_s) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) ssb[c] = Sbar[c * N + k];
     }
@@ -931,6 +931,15 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
     R fv[kEarly ? KI : 1][kEarly ? NF : 1];
     if constexpr (kEarly) {
       if (more) fill_load(p + 2, fv);
+    }
+    // D3Q15: the next plane's collision S adjoint, loaded before this plane's stress adjoint
+    R ss_n[SYM ? 6 : 1];
+    if constexpr (SYM) {
+      if (more) {
+        const size_t k = size_t(pmod(p + 1, b.nz)) * plane + col;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) ss_n[c] = Sbar[c * N + k];
+      }
     }
     GradBar<R> Gb;
     ParBar<R> Pb;
@@ -1015,7 +1024,11 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
       } else {
         fill_plane(p + 2, rm);
       }
-      load_site(p + 1, aq_o, qp_o, pp_o, ss_o);
+      load_site(p + 1, aq_o, qp_o, pp_o, ss_o, false);
+      if constexpr (SYM) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) ss_o[c] = ss_n[c];
+      }
     }
     const int t = rm;
     rm = r0;
