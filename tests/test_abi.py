@@ -193,3 +193,23 @@ def test_centre_noalloc_rejects_bad_arguments_before_any_device_work():
     assert L.lb_centre_noalloc(0, 4, 4, _lib.LB_FP64, 16, 16, None) == _lib.LB_EINVAL
     assert L.lb_centre_noalloc(4, 4, 4, 7, 16, 16, None) == _lib.LB_EINVAL
     assert L.lb_centre_noalloc(4, 4, 4, _lib.LB_FP32, None, 16, None) == _lib.LB_EINVAL
+
+
+def test_kernel_source_hash_ignores_comments_only(tmp_path, monkeypatch):
+    """The counter records are valid for the kernel code they were taken on: an
+    edited comment or blank line keeps the hash, an edited statement changes it."""
+    import shutil
+
+    from paper_2011_00287_amd import build
+
+    base = build.kernel_source_hash()
+    csrc = tmp_path / "csrc"
+    shutil.copytree(os.path.join(build.PKG, "csrc"), csrc)
+    monkeypatch.setattr(build, "PKG", str(tmp_path))
+    assert build.kernel_source_hash() == base
+    f = csrc / "kernels_fused.hpp"
+    text = f.read_text()
+    f.write_text("// an added comment\n\n" + text.replace("namespace lbc {", "namespace lbc {  /* note */", 1))
+    assert build.kernel_source_hash() == base
+    f.write_text(text.replace("R(0.5)", "R(0.25)", 1))
+    assert build.kernel_source_hash() != base
