@@ -1038,7 +1038,8 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
   block_reduce_store<2>(v, partial + size_t(blockIdx.x) * 2, accumulate != 0);
 }
 
-// The face terms of k_adj_sg_fused, in one launch of two thread ranges.
+// The face terms of k_adj_sg_fused, in one launch of two block ranges (grid
+// x: the rows or columns of a plane, y: the (field, face) pairs, z: the plane).
 // Fields f = 0..5: phi, q[5].
 // * x faces, one thread per (field, face j, z, y) when there are several x
 //   tiles.  Tile j covers the columns j TX - 1 .. j TX + w_j - 2 (mod nx), so
@@ -1059,38 +1060,39 @@ template <class R>
 __global__ void __launch_bounds__(256) k_adj_faces(Box b, int TX, int ntx, int TY, int nty,
                                                    const R* __restrict__ hx, const R* __restrict__ hy,
                                                    R* __restrict__ adj_phi, R* __restrict__ adj_q) {
-  // 32-bit index arithmetic: every index below is under 6 N < 2^32
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  // grid: x = the rows (columns) of a plane in blocks (of up to 256), y = (field,
+  // face) of the x faces then of the y faces, z = the plane: the indices
+  // come from the block, no division per thread.  32-bit index arithmetic:
+  // every index below is under 6 N < 2^32.
   const uint32_t nx = b.nx, ny = b.ny, nz = b.nz;
-  const uint32_t nzy = nz * ny, nzx = nz * nx;
-  const uint32_t fxs = uint32_t(ntx) * nzy, fys = uint32_t(nty) * nzx;  // one field-side block of hx, hy
-  const uint32_t nxt = ntx > 1 ? 6 * fxs : 0, nyt = nty > 1 ? 6 * fys : 0;
-  if (t < nxt) {
-    const uint32_t f = t / fxs;
-    const uint32_t r = t - f * fxs;
-    const uint32_t j = r / nzy;
-    const uint32_t zy = r - j * nzy;
+  const uint32_t z = blockIdx.z;
+  const uint32_t nxb = ntx > 1 ? 6u * uint32_t(ntx) : 0u;
+  const uint32_t fxs = uint32_t(ntx) * nz * ny, fys = uint32_t(nty) * nz * nx;  // one field-side block of hx, hy
+  if (blockIdx.y < nxb) {
+    const uint32_t y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= ny) return;
+    const uint32_t f = blockIdx.y / uint32_t(ntx), j = blockIdx.y - f * uint32_t(ntx);
+    const uint32_t zy = z * ny + y;
     const uint32_t jn = j + 1 < uint32_t(ntx) ? j + 1 : 0;
     const int wj = min(TX, b.nx - int(j) * TX), wn = min(TX, b.nx - int(jn) * TX);
     const uint32_t xf = jn > 0 ? jn * TX - 1 : nx - 1;  // first column of tile jn; tile j's last is xf - 1
     R* out = (f == 0 ? adj_phi : adj_q + size_t(f - 1) * b.N) + size_t(zy) * nx;  // row (z, y)
     const R* hs = hx + size_t(4 * f) * fxs;
-    const uint32_t fj = j * nzy + zy, fn = jn * nzy + zy;
+    const uint32_t fj = j * nz * ny + zy, fn = jn * nz * ny + zy;
     R vl = hs[3 * fxs + fj] + hs[fxs + fj];
     R vf = hs[2 * fxs + fn] + hs[fj];
     if (wn == 1) vf += hs[fxs + fn];
     if (nty > 1) {  // the y-face terms of a first or last row of a y tile
-      const uint32_t z = zy / ny, y = zy - z * ny;
-      const uint32_t i = y / TY, ly = y - i * TY;
-      const uint32_t h = min(uint32_t(TY), ny - i * TY);
+      const uint32_t i = y / uint32_t(TY), ly = y - i * uint32_t(TY);
+      const uint32_t h = min(uint32_t(TY), ny - i * uint32_t(TY));
       const R* ys = hy + size_t(2 * f) * fys + z * nx;
       if (ly == 0) {
-        const R* s0 = ys + ((i + nty - 1) % nty) * nzx;
+        const R* s0 = ys + ((i + nty - 1) % nty) * nz * nx;
         vl += s0[xf - 1];
         vf += s0[xf];
       }
       if (ly == h - 1) {
-        const R* s1 = ys + fys + i * nzx;
+        const R* s1 = ys + fys + i * nz * nx;
         vl += s1[xf - 1];
         vf += s1[xf];
       }
@@ -1099,20 +1101,18 @@ __global__ void __launch_bounds__(256) k_adj_faces(Box b, int TX, int ntx, int T
     out[xf] = vf;
     return;
   }
-  if (t - nxt >= nyt) return;
-  const uint32_t u = t - nxt;
-  const uint32_t f = u / fys;
-  const uint32_t r = u - f * fys;
-  const uint32_t i = r / nzx;
-  const uint32_t zx = r - i * nzx;
-  const uint32_t z = zx / nx, x = zx - z * nx;
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nx) return;
+  const uint32_t fi = blockIdx.y - nxb;
+  const uint32_t f = fi / uint32_t(nty), i = fi - f * uint32_t(nty);
   // the x-edge columns (first and last of every x tile) belong to the first range
   if (ntx > 1 && ((x + 1) % TX == 0 || (x + 2) % TX == 0 || x + 2 >= nx)) return;
+  const uint32_t zx = z * nx + x;
   const uint32_t ya = i * TY, yb = min(ya + TY, ny) - 1;
   R* out = (f == 0 ? adj_phi : adj_q + size_t(f - 1) * b.N) + size_t(z) * ny * nx + x;
   const R* hs = hy + size_t(2 * f) * fys;
-  out[ya * nx] += hs[((i + nty - 1) % nty) * nzx + zx];
-  out[yb * nx] += hs[fys + i * nzx + zx];
+  out[ya * nx] += hs[((i + nty - 1) % nty) * nz * nx + zx];
+  out[yb * nx] += hs[fys + i * nz * nx + zx];
 }
 
 // out = in + 1 for the step counter of a recorded state (one thread, vector memory).

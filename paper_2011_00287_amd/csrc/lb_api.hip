@@ -1045,12 +1045,15 @@ struct BackendT final : Backend {
       lbc::k_adj_sg_fused<R, FS, kAsTX, 8, L::kStressInEq><<<as_blocks, kAsTX * 8, 0, stream>>>(
           box, P, as_tz, as_ntx, as_nty, phi_t, q_t, aFb, aq, mb, aqbp, aphibp, aSb, po, qo, ahx, ahy, apart,
           apart_live ? 1 : 0);
-    // one thread per field and x-face row, then one per field and y-face column
-    const size_t n = (as_ntx > 1 ? 6 * size_t(as_ntx) * box.nz * box.ny : 0) +
-                     (as_nty > 1 ? 6 * size_t(as_nty) * box.nz * box.nx : 0);
-    if (n > 0)
-      lbc::k_adj_faces<R><<<unsigned((n + TPB - 1) / TPB), TPB, 0, stream>>>(box, kAsTX, as_ntx, as_ty, as_nty, ahx,
-                                                                             ahy, po, qo);
+    // blocks of up to 256 rows (columns) per plane and per (field, x face),
+    // then per (field, y face)
+    const unsigned gy = (as_ntx > 1 ? 6u * unsigned(as_ntx) : 0u) + (as_nty > 1 ? 6u * unsigned(as_nty) : 0u);
+    if (gy > 0) {
+      const int line = std::max(box.nx, box.ny);
+      const unsigned tpb = unsigned(std::min(256, (line + 63) / 64 * 64));
+      const dim3 grid(unsigned((line + int(tpb) - 1) / int(tpb)), gy, unsigned(box.nz));
+      lbc::k_adj_faces<R><<<grid, tpb, 0, stream>>>(box, kAsTX, as_ntx, as_ty, as_nty, ahx, ahy, po, qo);
+    }
   }
   // Reverse of a step of the pc4 integrator: the predictor is replayed from
   // X = (phi_t, q_t) with the step's velocity uu, the two Heun products
