@@ -270,6 +270,30 @@ def test_adjoint_site_and_tiled_kernels_agree(prec, tol, tz, shape, adj_tile):
     assert abs(za - zb_) <= tol * abs(za) and abs(qa - qb_) <= tol * abs(qa)
 
 
+@pytest.mark.parametrize("shape", [(290, 20, 4), (20, 290, 4)])
+def test_adjoint_tiled_kernels_on_lines_longer_than_a_face_block(shape):
+    """Rows (columns) longer than the 256 lines one block of the face fix-up
+    covers, with a two-column (four-row) last tile: the tiled reverse equals
+    the site-parallel one in FP64."""
+    p = _p(q0=2 * math.pi / 9, zeta=0.01)
+    g, phi, q5 = inputs.random_fields(*shape, seed=23, g_amp=2e-3, q_amp=0.2)
+    seed_vals = np.random.default_rng(5).normal(size=25 * phi.size)
+    outs = []
+    for path in ("default", "site"):
+        with Sim(p, phi, q5, precision="fp64", tuning={"path": path}) as sim:
+            sim.set_fields(g=g)
+            state = sim.get_state()
+            adj = sim.adjoint_buffer()
+            adj.copy_(torch.tensor(seed_vals, dtype=adj.dtype))
+            out = sim.adjoint_buffer()
+            zb, qb = sim.adjoint_step(state, adj, out)
+            outs.append((out.double().cpu().numpy(), zb, qb))
+    (a, za, qa), (b, zb_, qb_) = outs
+    l2, mx = rel_err(a, b)
+    assert l2 < 1e-13 and mx < 1e-13, (l2, mx)
+    assert abs(za - zb_) <= 1e-13 * abs(za) and abs(qa - qb_) <= 1e-13 * abs(qa)
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
 def test_lean_reverse_step_equals_full_state_step(prec, tol):
     """The reverse of a step from its lean record (Q, phi, drho, u, F) equals the reverse
