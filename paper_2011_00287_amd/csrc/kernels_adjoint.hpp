@@ -177,9 +177,10 @@ k_adj_order(Box b, Params<R> P, const FS* __restrict__ phi, const FS* __restrict
 // linear in W), so the W_bar the transposes read beyond the owned sites (the
 // halo columns and rows of the plane, and the own column at z +- 1) is formed
 // from the staged fields (corotation_wbar) instead of being exchanged
-// between tiles or launches.
+// between tiles or launches.  In float it fits 128 registers without spills,
+// so four waves per SIMD hide the latency of the plane loads.
 template <class R, class FS, int TX, int TY>
-__global__ void __launch_bounds__(TX* TY)
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
 k_adj_order_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__ phi,
                   const FS* __restrict__ q, const R* __restrict__ u, const R* __restrict__ adj_phi,
                   const R* __restrict__ adj_q, R* __restrict__ mub, R* __restrict__ ub_out,

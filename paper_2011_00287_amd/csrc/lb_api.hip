@@ -354,7 +354,11 @@ struct BackendT final : Backend {
     ao_ntx = (p.nx + kAoTX - 1) / kAoTX;
     ao_nty = (p.ny + ao_ty - 1) / ao_ty;
     ao_tz = t.tz_adj_order;
-    if (ao_tz == 0) ao_tz = auto_slab(ao_ntx, ao_nty, p.nz, 32, 1, ao_ty == 16 ? 1 : 2);
+    // float 32 x 8 holds four workgroups per CU (124 registers): slabs of up
+    // to 16 planes, deep enough to fill them (8 planes at 128^3, 16 at 256^3)
+    if (ao_tz == 0)
+      ao_tz = sizeof(R) == 4 && ao_ty == 8 ? auto_slab(ao_ntx, ao_nty, p.nz, 16, 1, 4)
+                                           : auto_slab(ao_ntx, ao_nty, p.nz, 32, 1, ao_ty == 16 ? 1 : 2);
     ao_blocks = ao_ntx * ao_nty * ((p.nz + ao_tz - 1) / ao_tz);
     as_ty = t.adj_tile == 2 || (t.adj_tile == 0 && sizeof(R) == 4) ? 16 : 8;
     as_ntx = (p.nx + kAsTX - 1) / kAsTX;
