@@ -158,7 +158,8 @@ typedef struct {
   int32_t pcmu_tile;     /* LB_FD_PC4 mu kernel tile; same table as pc_tile */
   int32_t adj_tile;      /* stress + gather adjoint tile; 0 = default (32x16; float64 16x8),
                             1 = 32x8, 2 = 32x16 (float64: 16x8, 16x16) */
-  int32_t adj_order_tile; /* order-parameter adjoint tile; 0 = default (32x8), 1 = 32x8, 2 = 32x16 */
+  int32_t adj_order_tile; /* order-parameter adjoint tile; 0 = default (float 32x16, float64 32x8),
+                             1 = 32x8, 2 = 32x16 */
   int32_t step_tile;     /* one-launch kernel tile; 0 = default, 1..3 = 32x8, 32x16, 64x8
                             (float64: 32x8 only) */
   int32_t tz_step;       /* z-slab depths in planes, 0 = automatic: one-launch kernel, */

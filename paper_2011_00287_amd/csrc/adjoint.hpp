@@ -242,8 +242,9 @@ __host__ __device__ __forceinline__ void mu_site_bwd_local(const Params<R>& P, R
 // molecular field output (hb_out[5], e.g. from the Beris-Edwards update) and
 // of the chemical potential mu_site at the same site (mub; its divv adjoint
 // goes to Gb.divv) -> gradient-data adjoint and parameter adjoints.  mu shares
-// tr(Q^2) and tr(Q^3) with H, so their reverse through Q runs once.
-template <class R>
+// tr(Q^2) and tr(Q^3) with H, so their reverse through Q runs once.  MU =
+// false: no mu adjoint (mub is ignored and its terms are not formed).
+template <class R, bool MU = true>
 __host__ __device__ __forceinline__ void sigma_site_bwd(const Params<R>& P, const Grad<R>& G, const R sb[9],
                                                         const R hb_out[5], GradBar<R>& Gb, ParBar<R>& Pb,
                                                         R mub = R(0)) {
@@ -413,7 +414,7 @@ __host__ __device__ __forceinline__ void sigma_site_bwd(const Params<R>& P, cons
   // H -> stored components, plus the adjoint of the molecular-field output
   R hb[5] = {hb_out[0], hb_out[1], hb_out[2], hb_out[3], hb_out[4]};
   full_to_stored(Hmb, hb);
-  mu_site_bwd_local(P, G.phi, L.tr2, mub, Gb.phi, Gb.lapphi, Gb.divv, tr2b, tr3b);
+  if constexpr (MU) mu_site_bwd_local(P, G.phi, L.tr2, mub, Gb.phi, Gb.lapphi, Gb.divv, tr2b, tr3b);
   // back through local_thermo
   local_thermo_bwd(P, G, L, hb, tr2b, tr3b, qcb, dp2b, chib, Gb, Pb);
 }

@@ -530,8 +530,10 @@ __device__ __forceinline__ void store_gb(const GradBar<R>& Gb, R* __restrict__ o
 // symmetric part S enters the site's own collision, whose adjoint Ssb (6
 // stored components) is added here.  Gb gets the gradient-data adjoints
 // (without the order kernel's site-local Q and phi adjoints), Pb the
-// parameter adjoints.
-template <class R, bool SYM = false>
+// parameter adjoints.  HM = false (the pc4 reverse, whose order-parameter
+// update takes neither this H nor this mu): mu_bar and Q_bar(t+1) are zero,
+// mbn, mb0 and aq are not read, and their terms are not formed.
+template <class R, bool SYM = false, bool HM = true>
 __device__ __forceinline__ void adj_stress_site(const Params<R>& P, const Grad<R>& G, const R Fn[3][2][3],
                                                 const R mbn[3][2], R mb0, const R aq[5], GradBar<R>& Gb,
                                                 ParBar<R>& Pb, const R* Ssb = nullptr) {
@@ -541,7 +543,7 @@ __device__ __forceinline__ void adj_stress_site(const Params<R>& P, const Grad<R
   for (int c = 0; c < 3; ++c) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) sb[3 * a + c] = -R(0.5) * (Fn[c][0][a] - Fn[c][1][a]);
-    vb[c] = P.W * (mbn[c][0] - mbn[c][1]);
+    if constexpr (HM) vb[c] = P.W * (mbn[c][0] - mbn[c][1]);
   }
   if constexpr (SYM) {
     // A_ac = (sigma_ac - sigma_ca)/2, S_ac = (sigma_ac + sigma_ca)/2 (S stored xx, xy, xz, yy, yz, zz)
@@ -564,10 +566,11 @@ __device__ __forceinline__ void adj_stress_site(const Params<R>& P, const Grad<R
   }
   R hbs[5];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) hbs[k] = P.Gamma * aq[k];
+  for (int k = 0; k < 5; ++k) hbs[k] = HM ? P.Gamma * aq[k] : R(0);
   Gb.zero();
   Pb = ParBar<R>{R(0), R(0), R(0)};
-  sigma_site_bwd(P, G, sb, hbs, Gb, Pb, mb0);
+  sigma_site_bwd<R, HM>(P, G, sb, hbs, Gb, Pb, HM ? mb0 : R(0));
+  if constexpr (!HM) return;
   // anchoring divergence: v_a = Q_ab D0_b phi  ->  Q_bar_ab += v_bar_a D0_b phi,
   // (D0_b phi)_bar += Q_ab v_bar_a
   R Qb[3][3];
@@ -753,9 +756,10 @@ k_adj_gather(Box b, const R* __restrict__ gbar, R* __restrict__ adj_phi, R* __re
 // tile k without its face terms.  Those columns are left out of adj_phi and
 // adj_qo here, and k_adj_faces writes them whole (a plain store instead of
 // a read-modify-write of every cache line that holds a tile edge).
-// The (zeta, q0) partials count owned sites only.
+// The (zeta, q0) partials count owned sites only.  HM = false (the pc4
+// reverse): no mu_bar or Q_bar(t+1) seeds; mub and adj_q are not read.
 // ---------------------------------------------------------------------------
-template <class R, class FS, int TX, int TY, bool SYM = false>
+template <class R, class FS, int TX, int TY, bool SYM = false, bool HM = true>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(1, 2)))
 k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restrict__ phi,
                const FS* __restrict__ q, const R* __restrict__ Fb, const R* __restrict__ adj_q,
@@ -808,12 +812,13 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
       v[0] = R(phi[g]);
 #pragma unroll
       for (int c = 0; c < 5; ++c) v[1 + c] = R(q[c * N + g]);
-      v[6] = mub[g];
+      v[6] = HM ? mub[g] : R(0);
 #pragma unroll
       for (int a = 0; a < 3; ++a) v[7 + a] = Fb[a * N + g];
       if (k < NI) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) sIn[slot][f][k] = v[f];
+        for (int f = 0; f < NF; ++f)
+          if (HM || f != 6) sIn[slot][f][k] = v[f];
       }
     }
   };
@@ -828,7 +833,7 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
       v[j][0] = R(phi[g]);
 #pragma unroll
       for (int c = 0; c < 5; ++c) v[j][1 + c] = R(q[c * N + g]);
-      v[j][6] = mub[g];
+      v[j][6] = HM ? mub[g] : R(0);
 #pragma unroll
       for (int a = 0; a < 3; ++a) v[j][7 + a] = Fb[a * N + g];
     }
@@ -880,7 +885,7 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
       }
 #pragma unroll
       for (int d = 0; d < 2; ++d) {
-        mbn[g][d] = at(6, g, d);
+        mbn[g][d] = HM ? at(6, g, d) : R(0);
 #pragma unroll
         for (int a = 0; a < 3; ++a) Fn[g][d][a] = at(7 + a, g, d);
       }
@@ -889,12 +894,12 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
 #pragma unroll
     for (int k = 0; k < 5; ++k) G.lapq[k] -= R(6) * G.q[k];
     G.divv = R(0);
-    adj_stress_site<R, SYM>(P, G, Fn, mbn, sIn[r0][6][f], aq, Gb, Pb, ssb);
+    adj_stress_site<R, SYM, HM>(P, G, Fn, mbn, HM ? sIn[r0][6][f] : R(0), aq, Gb, Pb, ssb);
   };
   auto load_site = [&](int wp, R aq[5], R qp[5], R& pp, R ssb[6], bool with_s = true) {
     const size_t k = size_t(pmod(wp, b.nz)) * plane + col;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) aq[c] = adj_q[c * N + k];
+    for (int c = 0; c < 5; ++c) aq[c] = HM ? adj_q[c * N + k] : R(0);
 #pragma unroll
     for (int c = 0; c < 5; ++c) qp[c] = qbp[c * N + k];
     pp = phibp[k];
@@ -1019,7 +1024,8 @@ k_adj_sg_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const FS* __restric
           const int k = tid + j * NT;
           if (k < NI) {
 #pragma unroll
-            for (int f = 0; f < NF; ++f) sIn[rm][f][k] = fv[j][f];
+            for (int f = 0; f < NF; ++f)
+              if (HM || f != 6) sIn[rm][f][k] = fv[j][f];
           }
         }
       } else {

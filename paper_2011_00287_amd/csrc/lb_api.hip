@@ -264,7 +264,6 @@ struct BackendT final : Backend {
   R* apb = nullptr;    // pc4 reverse: per-site adjoints of one product's stencil data [NPB][N]
   R* axs = nullptr;    // pc4 reverse: X*_bar [6][N]
   R* aupc = nullptr;   // pc4 reverse: u_bar [3][N]
-  R* azero = nullptr;  // pc4 reverse: zeros [6][N]
   int gz_tz = 0, gz_blocks = 0;  // pc4 reverse: slab depth and grid of k_pcb_gather_z
   // pc4 reverse product in one z-march (k_pcb_fused) on kPfTX x 16 tiles, where
   // every tile along a split axis is at least two sites wide; else the
@@ -350,15 +349,18 @@ struct BackendT final : Backend {
     pm_nty = (p.ny + kPcTiles[pm_tile].ty - 1) / kPcTiles[pm_tile].ty;
     if (tz_pm == 0) tz_pm = auto_slab(pm_ntx, pm_nty, p.nz, 16, 1, 2);
     pm_blocks = pm_ntx * pm_nty * ((p.nz + tz_pm - 1) / tz_pm);
-    ao_ty = t.adj_order_tile == 2 ? 16 : 8;
+    // order adjoint tile: float 32 x 16 (two workgroups of 512 threads per
+    // CU at 124 registers), double 32 x 8 (32 x 16 spills there)
+    ao_ty = t.adj_order_tile == 2 || (t.adj_order_tile == 0 && sizeof(R) == 4) ? 16 : 8;
     ao_ntx = (p.nx + kAoTX - 1) / kAoTX;
     ao_nty = (p.ny + ao_ty - 1) / ao_ty;
     ao_tz = t.tz_adj_order;
-    // float 32 x 8 holds four workgroups per CU (124 registers): slabs of up
-    // to 16 planes, deep enough to fill them (8 planes at 128^3, 16 at 256^3)
+    // float holds four waves per SIMD (124 registers: four workgroups of a
+    // 32 x 8 tile per CU, or two of 32 x 16): slabs of up to 16 planes, deep
+    // enough to fill them (8 planes at 128^3, 16 at 256^3)
     if (ao_tz == 0)
-      ao_tz = sizeof(R) == 4 && ao_ty == 8 ? auto_slab(ao_ntx, ao_nty, p.nz, 16, 1, 4)
-                                           : auto_slab(ao_ntx, ao_nty, p.nz, 32, 1, ao_ty == 16 ? 1 : 2);
+      ao_tz = sizeof(R) == 4 ? auto_slab(ao_ntx, ao_nty, p.nz, 16, 1, ao_ty == 16 ? 2 : 4)
+                             : auto_slab(ao_ntx, ao_nty, p.nz, 32, 1, ao_ty == 16 ? 1 : 2);
     ao_blocks = ao_ntx * ao_nty * ((p.nz + ao_tz - 1) / ao_tz);
     as_ty = t.adj_tile == 2 || (t.adj_tile == 0 && sizeof(R) == 4) ? 16 : 8;
     as_ntx = (p.nx + kAsTX - 1) / kAsTX;
@@ -441,7 +443,7 @@ struct BackendT final : Backend {
     pcv = nullptr;
     mu = H = sig = u = nullptr;
     partial = sums = mids = nullptr;
-    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &apb, &axs, &aupc, &azero, &apfx, &apfy};
+    R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &apb, &axs, &aupc, &apfx, &apfy};
     for (R** a : adj) {
       dfree(*a);
       *a = nullptr;
@@ -883,8 +885,6 @@ struct BackendT final : Backend {
         if (pf_fused && pf_nty > 1) apfy = dalloc<R>(36 * size_t(pf_nty) * box.nz * box.nx);
         axs = dalloc<R>(6 * N);                 // X*_bar: q [5][N], phi [N]
         aupc = dalloc<R>(3 * N);                // u_bar of both Heun stages
-        azero = dalloc<R>(6 * N);               // zero Q_bar(t+1), mu_bar for the stress kernel
-        HIPCHECK(hipMemsetAsync(azero, 0, 6 * N * sizeof(R), stream));
         const int ncb = (box.nx * box.ny + 255) / 256;  // column blocks of a plane
         gz_tz = auto_slab(ncb, 1, box.nz, 16, 1, 2);
         gz_blocks = ncb * ((box.nz + gz_tz - 1) / gz_tz);
@@ -900,7 +900,7 @@ struct BackendT final : Backend {
       HIPCHECK(hipMemsetAsync(apart, 0, npart * sizeof(double), stream));
       apart_live = false;
     } catch (...) {
-      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &apb, &axs, &aupc, &azero, &apfx, &apfy};
+      R** adj[] = {&aF, &amub, &aWb, &aubp, &aqbp, &aphibp, &aFb, &agbar, &ahx, &ahy, &aSb, &apb, &axs, &aupc, &apfx, &apfy};
       for (R** a : adj) {
         dfree(*a);
         *a = nullptr;
@@ -1040,15 +1040,26 @@ struct BackendT final : Backend {
   }
   // the fused stress + gather adjoint and its tile-face terms; aq: Q_bar(t+1)
   // for the Euler update's H_bar (zeros under pc4), mb: mu_bar
+  // aq == mb == nullptr: no Q_bar(t+1) or mu_bar seeds (the pc4 reverse)
   void stress_gather(const FS* phi_t, const FS* q_t, const R* aq, const R* mb, R* po, R* qo) {
-    if (as_ty == 16)
-      lbc::k_adj_sg_fused<R, FS, kAsTX, 16, L::kStressInEq><<<as_blocks, kAsTX * 16, 0, stream>>>(
-          box, P, as_tz, as_ntx, as_nty, phi_t, q_t, aFb, aq, mb, aqbp, aphibp, aSb, po, qo, ahx, ahy, apart,
-          apart_live ? 1 : 0);
-    else
-      lbc::k_adj_sg_fused<R, FS, kAsTX, 8, L::kStressInEq><<<as_blocks, kAsTX * 8, 0, stream>>>(
-          box, P, as_tz, as_ntx, as_nty, phi_t, q_t, aFb, aq, mb, aqbp, aphibp, aSb, po, qo, ahx, ahy, apart,
-          apart_live ? 1 : 0);
+    const int acc = apart_live ? 1 : 0;
+    if (as_ty == 16) {
+      if (aq)
+        lbc::k_adj_sg_fused<R, FS, kAsTX, 16, L::kStressInEq><<<as_blocks, kAsTX * 16, 0, stream>>>(
+            box, P, as_tz, as_ntx, as_nty, phi_t, q_t, aFb, aq, mb, aqbp, aphibp, aSb, po, qo, ahx, ahy, apart, acc);
+      else
+        lbc::k_adj_sg_fused<R, FS, kAsTX, 16, L::kStressInEq, false><<<as_blocks, kAsTX * 16, 0, stream>>>(
+            box, P, as_tz, as_ntx, as_nty, phi_t, q_t, aFb, nullptr, nullptr, aqbp, aphibp, aSb, po, qo, ahx, ahy,
+            apart, acc);
+    } else {
+      if (aq)
+        lbc::k_adj_sg_fused<R, FS, kAsTX, 8, L::kStressInEq><<<as_blocks, kAsTX * 8, 0, stream>>>(
+            box, P, as_tz, as_ntx, as_nty, phi_t, q_t, aFb, aq, mb, aqbp, aphibp, aSb, po, qo, ahx, ahy, apart, acc);
+      else
+        lbc::k_adj_sg_fused<R, FS, kAsTX, 8, L::kStressInEq, false><<<as_blocks, kAsTX * 8, 0, stream>>>(
+            box, P, as_tz, as_ntx, as_nty, phi_t, q_t, aFb, nullptr, nullptr, aqbp, aphibp, aSb, po, qo, ahx, ahy,
+            apart, acc);
+    }
     // blocks of up to 256 rows (columns) per plane and per (field, x face),
     // then per (field, y face)
     const unsigned gy = (as_ntx > 1 ? 6u * unsigned(as_ntx) : 0u) + (as_nty > 1 ? 6u * unsigned(as_nty) : 0u);
@@ -1117,7 +1128,7 @@ struct BackendT final : Backend {
       lbc::k_adj_collide<R, GS, L><<<nblk, TPB, 0, stream>>>(box, P, Bt, FF, ubin, gi, go, aFb, aSb);
     else
       lbc::k_adj_collide_lean<R, L><<<nblk, TPB, 0, stream>>>(box, P, drho, uu, FF, ubin, gi, go, aFb, aSb);
-    stress_gather(phi_t, q_t, azero, azero + 5 * N, po, qo);
+    stress_gather(phi_t, q_t, nullptr, nullptr, po, qo);
   }
   // the reverse kernels of one step; the collision adjoint reads the
   // populations B, or (B == nullptr) the recorded density deviation drho
