@@ -119,6 +119,17 @@ def test_d3q15_pc4_single_step_vjp_matches_oracle(record):
     _check(_gpu_vjp(p, g, phi, q5, ab, "fp64", "d3q15", record), ref, 1e-10, 1e-10)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_d3q15_pc4_multi_tile_vjp_matches_oracle(prec, tol):
+    """The paper's full scheme on a box of several ragged tiles along x and y
+    (the stress reverse, compiled without the Euler update's seeds, with its
+    tile-face terms, and the one-kernel Heun products), in FP64 and FP32."""
+    p = _p(q0=2 * math.pi / 7, zeta=0.01)
+    g, phi, q5, ab = _inputs((35, 19, 6), 15, seed=67)
+    ref = _oracle_vjp(_step15_pc4, p, g, q5, phi, ab)
+    _check(_gpu_vjp(p, g, phi, q5, ab, prec, "d3q15", True), ref, tol, 10 * tol)
+
+
 # Boxes whose tiles exercise the one-kernel product of the reverse (tiles of
 # 32 x 16 in float, 16 x 16 in double): several tiles along both in-plane
 # axes, ragged last tiles two and more sites wide (the terms owed across a
