@@ -131,7 +131,7 @@ k_lb_fused(Box b, Params<R> P, int TZ, int ntx, int nty, const GS* __restrict__ 
   for (int p = z0 - 1; p <= z1; ++p) {
     __syncthreads();  // rings for plane p are complete; last plane's stress reads are done
     const int rm = r0 == 0 ? 4 : r0 - 1, rp = r0 == 4 ? 0 : r0 + 1;
-    const int rm2 = rm == 0 ? 4 : rm - 1, rp2 = rp == 4 ? 0 : rp + 1;
+    const int rm2 = rm == 0 ? 4 : rm - 1;
     const int cm = c0 == 0 ? 2 : c0 - 1, cp = c0 == 2 ? 0 : c0 + 1;
     const int zc = p - 1;
     const bool collide = active && zc >= z0 && zc < z1;

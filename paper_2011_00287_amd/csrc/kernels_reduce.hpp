@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(256) k_final_sum(const double* __restrict__ pa
     buf[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-      if (threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
+      if (int(threadIdx.x) < w) buf[threadIdx.x] += buf[threadIdx.x + w];
       __syncthreads();
     }
     if (threadIdx.x == 0) out[size_t(blockIdx.x) * nv + k] = buf[0];

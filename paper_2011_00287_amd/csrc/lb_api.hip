@@ -663,13 +663,14 @@ struct BackendT final : Backend {
   };
   Io cur_io() { return Io{B[cur], B[cur ^ 1], Ph[cur], Q[cur], Ph[cur ^ 1], Q[cur ^ 1], u, nullptr, nullptr}; }
   void launch_lb_tile(const Io& io) {
+    constexpr int W2 = sizeof(R) == 4 ? 2 : 1;  // double's registers allow one wave per SIMD on these tiles
     switch (lb_tile) {
-      case 0: launch_lb<32, 8, 2>(io); break;
+      case 0: launch_lb<32, 8, W2>(io); break;
       case 1:  // float only: the double 32 x 16 frame does not fit the LDS (mapped to 16 x 16 at creation)
         if constexpr (sizeof(R) == 4) launch_lb<32, 16, 2>(io);
         break;
-      case 2: launch_lb<64, 4, 2>(io); break;
-      case 3: launch_lb<16, 16, 2>(io); break;
+      case 2: launch_lb<64, 4, W2>(io); break;
+      case 3: launch_lb<16, 16, W2>(io); break;
       default: launch_lb<16, 8, 1>(io); break;
     }
   }
