@@ -162,11 +162,13 @@ def test_pc4_fused_product_equals_site_parallel_product(shape, prec):
     _check(a, b, tol, tol)
 
 
-def test_pc4_single_step_vjp_fp32():
+@pytest.mark.parametrize("adj_tile", [0, 1])
+def test_pc4_single_step_vjp_fp32(adj_tile):
+    """adj_tile 0: the default 32 x 16 stress-adjoint tile; 1: 32 x 8."""
     p = _p(q0=2 * math.pi / 7, zeta=0.01)
     g, phi, q5, ab = _inputs((35, 10, 6), 19, seed=78)
     ref = _oracle_vjp(pc4.step, p, g, q5, phi, ab)
-    _check(_gpu_vjp(p, g, phi, q5, ab, "fp32", "d3q19", True), ref, 1e-5, 1e-4)
+    _check(_gpu_vjp(p, g, phi, q5, ab, "fp32", "d3q19", True, tuning={"adj_tile": adj_tile}), ref, 1e-5, 1e-4)
 
 
 def _oracle_rollout_grad(p, phi, q5, steps):
