@@ -8,7 +8,9 @@ M = 0.05), through the C ABI, against the autograd of the pc4 oracle step:
 * the same with the paper's D3Q15 LB scheme underneath (the paper's full
   scheme), and in FP32 (1e-5 relative);
 * a rollout's gradient w.r.t. zeta, q0 and the initial Q field == the oracle's
-  autograd gradient of the same rollout, with checkpoints and with lean records.
+  autograd gradient of the same rollout, with checkpoints and with lean records;
+* the 32^3 droplet over 400 steps (checkpoints every 20), D3Q19 and D3Q15,
+  FP64: the gradient against central differences.
 
 The inputs are random states with flow, so no velocity (or face velocity) is
 exactly zero: there the upwind switch has a kink, whose w-derivative the
@@ -204,3 +206,79 @@ def test_pc4_rollout_gradient_matches_oracle_autograd(checkpoint):
     assert abs(float(q0.grad) - dq0_o) <= 1e-9 * abs(dq0_o)
     l2, mx = rel_err(q5t.grad.numpy(), dq5_o)
     assert l2 < 1e-9 and mx < 1e-9, (l2, mx)
+
+
+def _pc4_loss(p, phi, q5, steps, lattice):
+    with Sim(p, phi, q5, precision="fp64", lattice=lattice, fd_scheme="pc4") as s:
+        zc0 = s.centre()[0][2]
+        s.step(steps)
+        zc = s.centre()[0][2]
+    return (zc - zc0) ** 2
+
+
+@pytest.mark.parametrize("lattice", ["d3q19", "d3q15"])
+def test_droplet32_pc4_adjoint_vs_central_differences(lattice):
+    """The 32^3 droplet (400 steps, checkpoints every 20) with the pc4 integrator
+    (M = 0.05), on the D3Q19 and on the paper's D3Q15 scheme, in FP64: dL/dzeta,
+    dL/dq0 and five Q entries inside the droplet against central differences of
+    the forward rollout, each within 1e-4 of its difference quotient.  (In FP32
+    the gradients of this small-displacement loss differ from FP64's by up to a
+    few 1e-4, and by more for q0's small gradient, as the Euler integrator's do
+    at the same mobility: the rounding of the FP32 trajectory; the FP32 reverse
+    step itself is held to the oracle's VJP above.)
+
+    The first-order upwind switch makes the loss only piecewise smooth in the
+    parameters: a velocity that changes sign at some site and step puts a kink
+    in L(zeta), and a central difference with step h averages the slopes of the
+    kinks it straddles.  On this rollout, with h = 1e-6, that leaves a few 1e-5
+    between the quotient for zeta and the adjoint, and the quotient converges
+    to the adjoint as h shrinks (1e-6 at h = 1e-8) until its own rounding noise
+    (~1e-17 absolute in L) dominates; zeta therefore takes h = 1e-8.  q0's
+    gradient is small (~5e-7), so its quotient is noise-limited below
+    h = 1e-6 and takes that step.  The Q entries take h = 1e-6 with a floor of
+    three times the quotients' change from h to 2h, as in the Euler rollout
+    check."""
+    from paper_2011_00287_amd.autograd import backward_segments, run_segments
+    w = inputs.WORKLOADS["droplet32_adjoint"]
+    p = inputs.params_for("droplet32_adjoint", M=0.05)
+    phi, q5 = inputs.workload_fields("droplet32_adjoint")
+    steps, ck = w["steps"], w["checkpoint"]
+    with Sim(p, phi, q5, precision="fp64", lattice=lattice, fd_scheme="pc4") as sim:
+        zc0 = sim.centre()[0][2]
+        ckpts = run_segments(sim, steps, ck)
+        adj = sim.adjoint_buffer()
+        L = sim.seed_centre(zc0, adj)
+        dz, dq0 = backward_segments(sim, ckpts, steps, ck, adj)
+        _, qbar, _ = sim.adjoint_parts(adj)
+        qbar = qbar.double().cpu().numpy()
+    assert L > 0
+    hz, hq = 1e-8, 1e-6
+    fd_z = (_pc4_loss(dict(p, zeta=p["zeta"] + hz), phi, q5, steps, lattice) -
+            _pc4_loss(dict(p, zeta=p["zeta"] - hz), phi, q5, steps, lattice)) / (2 * hz)
+    fd_q0 = (_pc4_loss(dict(p, q0=p["q0"] + hq), phi, q5, steps, lattice) -
+             _pc4_loss(dict(p, q0=p["q0"] - hq), phi, q5, steps, lattice)) / (2 * hq)
+    print(lattice, "zeta ad", dz, "fd", fd_z, "q0 ad", dq0, "fd", fd_q0)
+    assert abs(dz - fd_z) <= 1e-4 * abs(fd_z), (dz, fd_z)
+    assert abs(dq0 - fd_q0) <= 1e-4 * abs(fd_q0), (dq0, fd_q0)
+    rng = np.random.default_rng(1)
+    inside = np.argwhere(phi > p["phi_cr"])
+    picks = inside[rng.choice(len(inside), 5, replace=False)]
+    comps = rng.integers(0, 5, 5)
+
+    def fd_q(c, z, y, x, hh):
+        qp = q5.copy()
+        qm = q5.copy()
+        qp[c, z, y, x] += hh
+        qm[c, z, y, x] -= hh
+        return (_pc4_loss(p, phi, qp, steps, lattice) - _pc4_loss(p, phi, qm, steps, lattice)) / (2 * hh)
+
+    ads, fds, fds2 = [], [], []
+    for (z, y, x), c in zip(picks, comps):
+        fds.append(fd_q(c, z, y, x, hq))
+        fds2.append(fd_q(c, z, y, x, 2 * hq))
+        ads.append(qbar[c, z, y, x])
+    ads, fds, fds2 = np.array(ads), np.array(fds), np.array(fds2)
+    noise = np.abs(fds - fds2).max()
+    ratio = np.abs(ads - fds) / (1e-4 * np.abs(fds) + 3 * noise)
+    print("Q entries: ad", ads, "fd", fds, "fd noise", noise, "worst |ad - fd| / bound", ratio.max())
+    assert np.all(ratio <= 1.0), (ads, fds, ratio)
